@@ -1,0 +1,206 @@
+"""Seeded synthetic inputs shared by the GPU library's tests and the oracle's tests.
+
+This module only draws random numbers and lays out geometry and case
+parameters.  It holds none of the lattice-Boltzmann, turbulence-model or
+wall-model arithmetic: both the HIP library and the CPU oracle receive the
+arrays produced here and do all of the method's work themselves.
+
+The paper's own benchmarks (the TMR NACA 0012 and the MD-30P30N geometries)
+are not available, so seeded airfoil-like polylines with the paper's
+thickness, Reynolds number, Mach number and angle of attack stand in for them
+(Section 3.1.1 and Section 3.2 of the paper).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+# Boundary-condition codes shared by both configuration structs.
+BC_PERIODIC = 0
+BC_INLET = 1
+BC_OUTLET = 2
+BC_SYMMETRY = 3
+BC_WALL = 4
+
+WALL_VN = 0
+WALL_NISHIMURA = 1
+WALL_NOSLIP = 2
+WALL_PRESCRIBED = 3
+
+BB_AUTO = 0      # Yu's interpolated scheme at every cut link (step 6 of the VN procedure)
+BB_YU = 1        # same as BB_AUTO
+BB_HALFWAY = 2   # half-way rule eq (24) at every cut link
+
+BODY_SOLID = 0   # bodies are walls
+BODY_REFINE = 1  # bodies only mark where the grid is refined
+
+SA_FROZEN = 0
+SA_LW = 1
+SA_UPWIND1 = 2
+
+
+def _thickness_coeffs(rng: np.random.Generator):
+    """Draw the coefficients of a symmetric thickness polynomial.
+
+    y_t(x) = a0 sqrt(x) + a1 x + a2 x^2 + a3 x^3 + a4 x^4 with a1 chosen so that
+    y_t(1) = 0 (sharp trailing edge).  Draws that are negative anywhere on
+    (0, 1) are rejected.
+    """
+    xs = np.linspace(1e-6, 1.0 - 1e-6, 4001)
+    while True:
+        a0 = rng.uniform(0.26, 0.32)
+        a2 = rng.uniform(-0.40, -0.30)
+        a3 = rng.uniform(0.20, 0.32)
+        a4 = rng.uniform(-0.12, -0.08)
+        a1 = -(a0 + a2 + a3 + a4)
+        yt = a0 * np.sqrt(xs) + a1 * xs + a2 * xs**2 + a3 * xs**3 + a4 * xs**4
+        if np.all(yt > 0.0):
+            return np.array([a0, a1, a2, a3, a4])
+
+
+def _thickness(coef, x):
+    a0, a1, a2, a3, a4 = coef
+    return a0 * np.sqrt(x) + a1 * x + a2 * x**2 + a3 * x**3 + a4 * x**4
+
+
+def rotate(xy: np.ndarray, alpha_deg: float, pivot=(0.25, 0.0)) -> np.ndarray:
+    """Rotate points by -alpha about the pivot (positive alpha = nose up in a +x stream)."""
+    a = -math.radians(alpha_deg)
+    c, s = math.cos(a), math.sin(a)
+    p = np.asarray(xy, dtype=np.float64) - np.asarray(pivot)
+    out = np.empty_like(p)
+    out[:, 0] = c * p[:, 0] - s * p[:, 1]
+    out[:, 1] = s * p[:, 0] + c * p[:, 1]
+    return out + np.asarray(pivot)
+
+
+def airfoil_polyline(seed: int, n_side: int = 2048, thickness: float = 0.12,
+                     alpha_deg: float = 0.0, camber: float = 0.0,
+                     camber_pos: float = 0.4) -> np.ndarray:
+    """Closed counter-clockwise polyline of a seeded airfoil-like section.
+
+    Unit chord from (0, 0) to (1, 0) before rotation; ``n_side`` points per side
+    with cosine spacing, rounded leading edge (sqrt term) and a sharp trailing
+    edge.  The first point is the trailing edge; the upper surface runs to the
+    leading edge and the lower surface back, so the fluid lies to the right of
+    the direction of travel.  The polyline is returned without repeating the
+    first point (shape (2 * n_side, 2)).
+    """
+    rng = np.random.default_rng(seed)
+    coef = _thickness_coeffs(rng)
+    xs = np.linspace(0.0, 1.0, 20001)
+    scale = 0.5 * thickness / _thickness(coef, xs).max()
+    j = np.arange(n_side)
+    xu = 0.5 * (1.0 + np.cos(np.pi * j / n_side))        # 1 -> ~0
+    xl = 0.5 * (1.0 - np.cos(np.pi * j / n_side))        # 0 -> ~1
+    ytu = scale * _thickness(coef, xu)
+    ytl = scale * _thickness(coef, xl)
+    if camber != 0.0:
+        def yc(x):
+            p = camber_pos
+            return np.where(x < p, camber / p**2 * (2 * p * x - x**2),
+                            camber / (1 - p)**2 * ((1 - 2 * p) + 2 * p * x - x**2))
+        ycu, ycl = yc(xu), yc(xl)
+    else:
+        ycu = np.zeros_like(xu)
+        ycl = np.zeros_like(xl)
+    upper = np.stack([xu, ycu + ytu], axis=1)
+    lower = np.stack([xl, ycl - ytl], axis=1)
+    upper[0, 1] = 0.0 + (ycu[0] if camber != 0.0 else 0.0)   # exact sharp trailing edge
+    xy = np.concatenate([upper, lower], axis=0)
+    if alpha_deg != 0.0:
+        xy = rotate(xy, alpha_deg)
+    return np.ascontiguousarray(xy)
+
+
+def channel_noise(seed: int, nx: int, ny: int):
+    """Uniform noise in (-1, 1) for the two velocity components of an nx-by-ny channel."""
+    rng = np.random.default_rng(seed)
+    xi_x = rng.uniform(-1.0, 1.0, size=(ny, nx))
+    xi_y = rng.uniform(-1.0, 1.0, size=(ny, nx))
+    return xi_x, xi_y
+
+
+def random_populations(seed: int, n: int, amplitude: float = 0.02):
+    """Random positive D2Q9-like population sets (n, 9) for kernel-level checks."""
+    rng = np.random.default_rng(seed)
+    w = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+    return w[None, :] * (1.0 + amplitude * rng.uniform(-1, 1, size=(n, 9)))
+
+
+# ---------------------------------------------------------------------------
+# Case definitions (pure data).  Lengths are in chord units; the lattice is
+# defined by the level-0 cell size dx0 and the number of refinement levels.
+# ---------------------------------------------------------------------------
+
+def case_channel(nx: int = 256, ny: int = 64, steps: int = 2000):
+    """Periodic plane channel driven by a body force, walls at halfway links.
+
+    Lattice values for Re_tau = 2000 with a bulk velocity of 0.1 c_s
+    (u_tau from the bulk velocity divided by the mean of the wall function over
+    the half channel, nu = u_tau h / Re_tau, F = u_tau^2 / h, h = ny / 2).
+    """
+    return dict(
+        name="channel", nx0=nx, ny0=ny, n_levels=1, dx0=1.0, origin=(0.0, 0.0),
+        bc=(BC_PERIODIC, BC_PERIODIC, BC_WALL, BC_WALL), wall_y=(0.0, float(ny)),
+        bands=(), u_ref=0.05773502691896258, nu0=4.372943019927448e-05,
+        force=(2.3343054999428939e-07, 0.0), mach=0.1, reynolds=0.0, ref_length=float(ny),
+        chi_init=3.0, chi_inlet=3.0, omega_b=1.0, d_wr=2.0, d_wv=1.0,
+        wall_model=WALL_VN, bb_mode=BB_AUTO, sa_mode=SA_LW, steps=steps,
+        noise_seed=1234, noise_amplitude=1e-3, bodies=[],
+    )
+
+
+def case_airfoil(seed: int = 0, finest_cells_per_chord: int = 1024, n_levels: int = 8,
+                 domain_chords: float = 40.0, band_finest: float = 0.25,
+                 mach: float = 0.15, reynolds: float = 6e6, alpha_deg: float = 10.0,
+                 n_side: int = 2048, thickness: float = 0.12):
+    """Single airfoil-like body in a square domain with distance-band refinement.
+
+    Level l (l = 0 coarsest) has cell size dx0 / 2^l; cells of level l-1 whose
+    centre lies within bands[l] of the body are refined, with bands doubling
+    towards the coarse levels (band_finest at the finest level).
+    """
+    dx_f = 1.0 / finest_cells_per_chord
+    dx0 = dx_f * 2 ** (n_levels - 1)
+    n0 = int(round(domain_chords / dx0))
+    half = 0.5 * n0 * dx0
+    bands = tuple([0.0] + [band_finest * 2 ** (n_levels - 1 - l) for l in range(1, n_levels)])
+    xy = airfoil_polyline(seed, n_side=n_side, thickness=thickness, alpha_deg=alpha_deg)
+    return dict(
+        name="airfoil", nx0=n0, ny0=n0, n_levels=n_levels, dx0=dx0,
+        origin=(0.5 - half, -half), bc=(BC_INLET, BC_OUTLET, BC_SYMMETRY, BC_SYMMETRY),
+        wall_y=(0.0, 0.0), bands=bands, u_ref=0.0, nu0=0.0, force=(0.0, 0.0),
+        mach=mach, reynolds=reynolds, ref_length=1.0, chi_init=3.0, chi_inlet=3.0,
+        omega_b=1.0, d_wr=2.0, d_wv=1.0, wall_model=WALL_VN, bb_mode=BB_AUTO,
+        sa_mode=SA_LW, alpha_deg=alpha_deg, bodies=[xy],
+    )
+
+
+def case_airfoil_small(seed: int = 0, alpha_deg: float = 10.0, n_side: int = 256):
+    """Down-scaled airfoil case the oracle steps in seconds: 3 levels, finest c/64, 8c domain."""
+    return case_airfoil(seed=seed, finest_cells_per_chord=64, n_levels=3, domain_chords=8.0,
+                        band_finest=0.25, alpha_deg=alpha_deg, n_side=n_side)
+
+
+def case_airfoil_cfg1(seed: int = 0):
+    """Single body, FP32: Re 6e6, Mach 0.15, 10 deg, finest c/1024, 40-chord domain."""
+    return case_airfoil(seed=seed)
+
+
+def channel_initial_velocity(case):
+    """Laminar profile 1.5 U_b (1 - ((y - h) / h)^2) plus seeded uniform noise on both components.
+
+    Returns (ux, uy), each of shape (ny, nx), at the cell centres y = j + 1/2.
+    """
+    nx, ny = case["nx0"], case["ny0"]
+    h = 0.5 * ny
+    ub = case["u_ref"]
+    y = np.arange(ny) + 0.5
+    prof = 1.5 * ub * (1.0 - ((y - h) / h) ** 2)
+    xi_x, xi_y = channel_noise(case["noise_seed"], nx, ny)
+    amp = case["noise_amplitude"] * ub
+    ux = prof[:, None] + amp * xi_x
+    uy = amp * xi_y
+    return np.ascontiguousarray(ux), np.ascontiguousarray(uy)

@@ -1,0 +1,269 @@
+"""Whole-step pins of the oracle: invariants and textbook flows it must reproduce."""
+import math
+
+import numpy as np
+import pytest
+
+import lbr_inputs as LI
+import oracle
+
+
+def box_case(nx, ny, **kw):
+    c = LI.case_channel(nx=nx, ny=ny)
+    c.update(bc=(LI.BC_PERIODIC,) * 4, wall_y=(0.0, 0.0), sa_mode=LI.SA_FROZEN, chi_init=0.0,
+             force=(0.0, 0.0), u_ref=0.05, nu0=0.01)
+    c.update(kw)
+    return c
+
+
+def channel_case(ny, **kw):
+    c = LI.case_channel(nx=4, ny=ny)
+    c.update(wall_model=LI.WALL_NOSLIP, sa_mode=LI.SA_FROZEN, chi_init=0.0, nu0=0.1,
+             force=(1e-6, 0.0), u_ref=0.0)
+    c.update(kw)
+    return c
+
+
+def test_periodic_box_conserves_mass_and_gains_force_momentum():
+    F = (2e-6, -1e-6)
+    c = box_case(24, 16, force=F, sa_mode=LI.SA_LW, chi_init=3.0, nu0=1e-4)
+    s = oracle.Sim(c)
+    rng = np.random.default_rng(7)
+    sh = (16, 24)
+    s.init(0, rho=1 + 0.01 * rng.uniform(-1, 1, sh), ux=0.05 + 0.02 * rng.uniform(-1, 1, sh),
+           uy=0.02 * rng.uniform(-1, 1, sh))
+
+    def totals():
+        r = s.field(0, oracle.F_RHO)
+        u = s.field(0, oracle.F_UX)
+        v = s.field(0, oracle.F_UY)
+        # the stored velocity carries the half-force shift: rho u = sum c f + F/2
+        return r.sum(), (r * u).sum() - 0.5 * F[0] * r.size, (r * v).sum() - 0.5 * F[1] * r.size
+    m0, px0, py0 = totals()
+    n = 25
+    s.advance(n)
+    m1, px1, py1 = totals()
+    assert abs(m1 - m0) / m0 < 1e-14
+    assert px1 - px0 == pytest.approx(n * F[0] * 24 * 16, rel=1e-9)
+    assert py1 - py0 == pytest.approx(n * F[1] * 24 * 16, rel=1e-9)
+
+
+def _tg_rate(N, nu, chi=0.0, steps=(100, 300)):
+    c = box_case(N, N, nu0=nu, chi_init=chi)
+    s = oracle.Sim(c)
+    k = 2 * math.pi / N
+    x = np.arange(N) + 0.5
+    X, Y = np.meshgrid(x, x)
+    U0 = 0.02
+    ux = U0 * np.sin(k * X) * np.cos(k * Y)
+    uy = -U0 * np.cos(k * X) * np.sin(k * Y)
+    rho = 1.0 - 3 * U0**2 / 4 * (np.cos(2 * k * X) + np.cos(2 * k * Y))
+    s.init(0, rho=rho, ux=ux, uy=uy, chi=np.full((N, N), chi))
+    mode = np.sin(k * X) * np.cos(k * Y)
+    amp = []
+    done = 0
+    for t in steps:
+        s.advance(t - done)
+        done = t
+        amp.append(np.sum(s.field(0, oracle.F_UX) * mode) / np.sum(mode * mode))
+    return -math.log(amp[1] / amp[0]) / (steps[1] - steps[0]), 2 * nu * k * k
+
+
+def test_taylor_green_decay_matches_eq9_viscosity():
+    errs = []
+    for N in (16, 32):
+        rate, expect = _tg_rate(N, 0.02)
+        errs.append(abs(rate / expect - 1))
+    # a wrong relaxation-viscosity mapping would be off by O(1); the lattice error is ~0.1%
+    assert errs[0] < 3e-3
+    assert errs[1] < 1.5e-3
+
+
+def test_taylor_green_decay_with_frozen_eddy_viscosity():
+    nu, chi = 0.004, 8.0
+    fv1 = chi**3 / (chi**3 + 7.1**3)
+    rate, _ = _tg_rate(32, nu, chi=chi)
+    nu_eff = nu * (1 + chi * fv1)          # eq. (11): nu_t = nu chi f_v1
+    k = 2 * math.pi / 32
+    assert rate == pytest.approx(2 * nu_eff * k * k, rel=0.01)
+
+
+def _steady_profile(c, steps):
+    s = oracle.Sim(c)
+    ny = c["ny0"]
+    s.init(0, rho=np.ones((ny, 4)), ux=np.zeros((ny, 4)), uy=np.zeros((ny, 4)),
+           chi=np.zeros((ny, 4)))
+    s.advance(steps)
+    return s.field(0, oracle.F_UX)[:, 0]
+
+
+def test_poiseuille_half_way_bounce_back():
+    ny, nu, F = 16, 0.1, 1e-6
+    u = _steady_profile(channel_case(ny, bb_mode=LI.BB_HALFWAY, nu0=nu), 12000)
+    y = np.arange(ny) + 0.5
+    exact = F / (2 * nu) * y * (ny - y)
+    assert np.max(np.abs(u - exact)) / exact.max() < 5e-3
+
+
+@pytest.mark.parametrize("q", [0.1, 0.3, 0.7, 0.9])
+def test_interpolated_bounce_back_poiseuille_converges(q):
+    errs = []
+    for ny in (8, 16):
+        nu, F = 0.1, 1e-6
+        c = channel_case(ny, bb_mode=LI.BB_YU, nu0=nu, wall_y=(0.5 - q, ny - 0.5 + q))
+        u = _steady_profile(c, int(60 * ny * ny))
+        y = np.arange(ny) + 0.5
+        ylo, yhi = 0.5 - q, ny - 0.5 + q
+        exact = F / (2 * nu) * (y - ylo) * (yhi - y)
+        errs.append(np.sqrt(np.mean((u - exact) ** 2)) / exact.max())
+    assert errs[1] < 0.02
+    assert errs[1] < errs[0] / 2.5          # at least ~second order
+
+
+def test_couette_with_prescribed_wall_velocity():
+    ny, U = 12, 0.01
+    c = channel_case(ny, wall_model=LI.WALL_PRESCRIBED, force=(0.0, 0.0), nu0=0.1,
+                     bb_mode=LI.BB_HALFWAY, u_wall=(0.0, 0.0, U, 0.0))
+    u = _steady_profile(c, 6000)
+    y = np.arange(ny) + 0.5
+    np.testing.assert_allclose(u, U * y / ny, atol=2e-6 * U / 0.01)
+
+
+def _refined_box():
+    c = LI.case_airfoil_small(alpha_deg=0.0)
+    c.update(bc=(LI.BC_PERIODIC,) * 4, body_mode=LI.BODY_REFINE, sa_mode=LI.SA_FROZEN,
+             chi_init=0.0, u_ref=0.05, nu0=0.002)
+    return c
+
+
+def test_multilevel_mass_is_conserved_exactly():
+    c = _refined_box()
+    s = oracle.Sim(c)
+    rng = np.random.default_rng(11)
+    for l in range(c["n_levels"]):
+        inf = s.level_info(l)
+        sh = (inf["ny"], inf["nx"])
+        s.init(l, rho=1 + 0.01 * rng.uniform(-1, 1, sh), ux=0.05 + 0.01 * rng.uniform(-1, 1, sh),
+               uy=0.01 * rng.uniform(-1, 1, sh), chi=np.zeros(sh))
+
+    def mass():
+        return sum(np.nansum(s.field(l, oracle.F_RHO)) * 4.0**-l for l in range(c["n_levels"]))
+    m0 = mass()
+    s.advance(6)
+    assert abs(mass() - m0) / m0 < 1e-14
+
+
+def test_multilevel_preserves_uniform_flow():
+    c = _refined_box()
+    s = oracle.Sim(c)
+    s.advance(4)
+    for l in range(c["n_levels"]):
+        assert np.nanmax(np.abs(s.field(l, oracle.F_UX) - 0.05)) < 1e-14
+        assert np.nanmax(np.abs(s.field(l, oracle.F_UY))) < 1e-14
+        assert np.nanmax(np.abs(s.field(l, oracle.F_RHO) - 1.0)) < 1e-14
+
+
+def test_channel_friction_velocity_is_uniform_along_flat_walls():
+    c = LI.case_channel()
+    s = oracle.Sim(c)
+    ux, uy = LI.channel_initial_velocity(c)
+    s.init(0, rho=np.ones_like(ux), ux=ux, uy=uy, chi=np.full_like(ux, 3.0))
+    s.advance(100)
+    w = s.wall(0)
+    assert len(w) == 2 * c["nx0"]
+    assert np.all(w[:, 7] == 3)                         # three cut links per wall node
+    np.testing.assert_allclose(w[:, 6], 0.5)            # half-way walls
+    ut = w[:, 8]
+    assert ut.std() / ut.mean() < 5e-3                  # spread at the noise level
+    # the reference stencil reduces to the mean of the two rows straddling y = 2
+    u = s.field(0, oracle.F_UX)
+    lower = w[w[:, 1] == 0]
+    gi = lower[:, 0].astype(int)
+    np.testing.assert_allclose(lower[:, 12], 0.5 * (u[1, gi] + u[2, gi]), rtol=1e-12)
+
+
+def test_uniform_pressure_gives_no_pressure_force():
+    c = LI.case_airfoil_small(alpha_deg=7.0)
+    s = oracle.Sim(c)
+    for l in range(c["n_levels"]):
+        inf = s.level_info(l)
+        sh = (inf["ny"], inf["nx"])
+        s.init(l, rho=np.full(sh, 1.01), ux=np.zeros(sh), uy=np.zeros(sh))
+    f = s.forces()
+    # C_P = -(1/c) sum Cp n ds = 0 for constant Cp on a closed polyline
+    assert abs(f[1]) < 1e-12 and abs(f[3]) < 1e-12
+
+
+def test_symmetric_body_at_zero_incidence_has_no_lift():
+    c = LI.case_airfoil_small(alpha_deg=0.0)
+    s = oracle.Sim(c)
+    s.advance(20)
+    f = s.forces()
+    assert abs(f[3]) < 1e-9 * max(1.0, abs(f[2]))
+
+
+def _point_in_polygon(P, x, y):
+    n = len(P)
+    inside = False
+    for k in range(n):
+        ax, ay = P[k]
+        bx, by = P[(k + 1) % n]
+        if (ay > y) != (by > y):
+            if x < ax + (y - ay) * (bx - ax) / (by - ay):
+                inside = not inside
+    return inside
+
+
+def test_cut_link_fractions_by_bisection():
+    """Independent re-check of q: bisect each cut link with a point-in-polygon test."""
+    c = LI.case_airfoil_small(alpha_deg=10.0)
+    s = oracle.Sim(c)
+    lf = c["n_levels"] - 1
+    w = s.wall(lf)
+    scale = 2.0**lf / c["dx0"]
+    P = (c["bodies"][0] - np.array(c["origin"])) * scale          # finest-level lattice units
+    cx = [0, 1, -1, 0, 0, 1, -1, 1, -1]
+    cy = [0, 0, 0, 1, -1, 1, -1, -1, 1]
+    rng = np.random.default_rng(0)
+    checked = 0
+    for k in rng.choice(len(w), size=40, replace=False):
+        gi, gj = w[k, 0], w[k, 1]
+        x0, y0 = gi + 0.5, gj + 0.5
+        assert not _point_in_polygon(P, x0, y0)
+        for o in range(1, 9):
+            q = w[k, 18 + o]
+            if q < 0:
+                continue
+            x1, y1 = x0 + cx[o], y0 + cy[o]
+            if not _point_in_polygon(P, x1, y1):
+                continue            # a link through a thin part of the body: q is still checked below
+            lo, hi = 0.0, 1.0
+            for _ in range(60):
+                mid = 0.5 * (lo + hi)
+                if _point_in_polygon(P, x0 + mid * cx[o], y0 + mid * cy[o]):
+                    hi = mid
+                else:
+                    lo = mid
+            assert q == pytest.approx(hi, abs=1e-9)
+            checked += 1
+    assert checked > 40
+
+
+def test_wall_distance_field_by_brute_force():
+    c = LI.case_airfoil_small(alpha_deg=10.0)
+    s = oracle.Sim(c)
+    lf = c["n_levels"] - 1
+    inf = s.level_info(lf)
+    d = s.field(lf, oracle.F_DIST)
+    scale = 2.0**lf / c["dx0"]
+    P = (c["bodies"][0] - np.array(c["origin"])) * scale
+    A, B = P, np.roll(P, -1, axis=0)
+    rng = np.random.default_rng(2)
+    js, is_ = np.where(np.isfinite(d))
+    for k in rng.choice(len(js), 200, replace=False):
+        x = inf["gx0"] + is_[k] + 0.5
+        y = inf["gy0"] + js[k] + 0.5
+        e = B - A
+        t = np.clip(((x - A[:, 0]) * e[:, 0] + (y - A[:, 1]) * e[:, 1]) / (e**2).sum(1), 0, 1)
+        dist = np.hypot(A[:, 0] + t * e[:, 0] - x, A[:, 1] + t * e[:, 1] - y).min()
+        assert d[js[k], is_[k]] == pytest.approx(dist, rel=1e-12)

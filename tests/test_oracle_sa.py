@@ -1,0 +1,134 @@
+"""Pins of the oracle's SA-neg terms (Section 2.2) and its interpolation helpers."""
+import numpy as np
+import pytest
+
+import oracle
+from tests.golden.load import constants
+
+SA = constants("sa_constants.txt")
+K = SA["kappa"]
+
+
+def cw1():
+    return SA["c_b1"] / K**2 + (1.0 + SA["c_b2"]) / SA["sigma"]
+
+
+def fv1(chi):
+    return chi**3 / (chi**3 + SA["c_v1"] ** 3)
+
+
+@pytest.mark.parametrize("yplus", [2.0, 5.0, 10.0, 30.0, 100.0, 1000.0, 1e4])
+def test_log_layer_solution(yplus):
+    """eq. (20): chi = kappa y+ with the eq. (19) gradient gives S~ = u_tau^2/(nu kappa y+), r = 1."""
+    nu, utau = 1.5e-5, 4e-3
+    y = yplus * nu / utau
+    nt = K * utau * y
+    chi = nt / nu
+    omega = utau**2 / (nu * (1.0 + chi * fv1(chi)))       # (nu + nu_t) du/dy = u_tau^2
+    src = oracle.sa_source(nt, nu, omega, y)
+    assert src["S_tilde"] == pytest.approx(utau**2 / (nu * K * yplus), rel=1e-12)
+    assert src["r"] == pytest.approx(1.0, rel=1e-12)
+    assert src["f_w"] == pytest.approx(1.0, rel=1e-12)
+    # budget: P - D + (1/sigma)[d/dy((nu + nt) dnt/dy) + c_b2 (dnt/dy)^2] = 0 because
+    # c_w1 = c_b1/kappa^2 + (1 + c_b2)/sigma
+    diffusion = (K * utau) ** 2 * (1.0 + SA["c_b2"]) / SA["sigma"]
+    assert (src["P"] - src["D"] + diffusion) / diffusion == pytest.approx(0.0, abs=1e-12)
+
+
+def test_cw1_value():
+    assert cw1() == pytest.approx(3.2390678167757, rel=1e-12)
+
+
+def test_modified_vorticity_is_continuous_at_branch_switch():
+    # at S-bar = -c_v2 Omega both branches of eq. (14) give (1 - c_v2) Omega
+    nu, omega, d = 1e-5, 3e-3, 0.02
+    chi = 3.0                                     # f_v2 < 0 here
+    nt = chi * nu
+    fv2 = 1 - chi / (1 + chi * fv1(chi))
+    d_switch = np.sqrt(nt * fv2 / (-SA["c_v2"] * omega * K**2))
+    for eps in (1e-9, -1e-9):
+        st = oracle.sa_source(nt, nu, omega, d_switch * (1 + eps))["S_tilde"]
+        assert st == pytest.approx((1 - SA["c_v2"]) * omega, rel=1e-6)
+
+
+@pytest.mark.parametrize("chi", [-0.5, -2.0, -10.0])
+def test_negative_branch(chi):
+    nu, omega, d = 1e-5, 2e-3, 0.01
+    nt = chi * nu
+    src = oracle.sa_source(nt, nu, omega, d)
+    assert src["nu_t"] == 0.0                         # eq. (11)
+    assert src["P"] - src["D"] > 0.0                  # both terms drive nt back towards zero
+    assert src["P"] > 0.0 and -src["D"] > 0.0
+    # continuity of the diffusivity at nt = 0
+    assert oracle.sa_source(-1e-14 * nu, nu, omega, d)["mu"] == pytest.approx(nu, rel=1e-12)
+    assert oracle.sa_source(1e-14 * nu, nu, omega, d)["mu"] == pytest.approx(nu, rel=1e-12)
+
+
+def test_destruction_vanishes_far_from_walls():
+    src = oracle.sa_source(3e-5, 1e-5, 1e-4, 1e12)
+    assert src["D"] < 1e-30
+
+
+def _stencil(fun):
+    return np.array([[fun(dx, dy) for dx in (-1, 0, 1)] for dy in (-1, 0, 1)])
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_cell_update_exact_for_linear_fields(mode):
+    """Linear nt and uniform u: every discrete operator is exact, so the update equals
+    -u.grad nt + P - D + (1/sigma)(1 + c_b2)|grad nt|^2 from the continuous equation."""
+    nu, d = 1e-5, 0.5
+    a, bx, by = 4e-4, 3e-6, -2e-6
+    u, v = 0.04, -0.015
+    nt = _stencil(lambda dx, dy: a + bx * dx + by * dy)
+    ux = _stencil(lambda dx, dy: u)
+    uy = _stencil(lambda dx, dy: v)
+    got = oracle.sa_cell(nt, ux, uy, nu, d, mode)
+    src = oracle.sa_source(a, nu, 0.0, d)
+    expect = a - (u * bx + v * by) + src["P"] - src["D"] + (1 + SA["c_b2"]) * (bx**2 + by**2) / SA["sigma"]
+    assert got == pytest.approx(expect, rel=1e-12)
+
+
+def test_vorticity_from_least_squares_gradients():
+    """A linear shear u = (g y, 0) has vorticity |g| exactly; it enters through S~ = Omega + S-bar."""
+    nu, d, g = 1e-5, 1e9, 2e-3
+    nt0 = 3e-5
+    nt = _stencil(lambda dx, dy: nt0)
+    ux = _stencil(lambda dx, dy: g * dy)
+    uy = _stencil(lambda dx, dy: 0.0)
+    got = oracle.sa_cell(nt, ux, uy, nu, d, 1)
+    src = oracle.sa_source(nt0, nu, g, d)
+    assert got == pytest.approx(nt0 + src["P"] - src["D"], rel=1e-12)
+    assert src["S_tilde"] == pytest.approx(g, rel=1e-6)
+
+
+def test_lax_wendroff_advects_quadratics_exactly():
+    """For nt = c x^2 with uniform u, Lax-Wendroff gives c (x - u)^2 at x = 0 (exact advection);
+    the diffusion of the quadratic is removed by taking the difference of two velocities."""
+    nu, d, c = 1e-5, 1e12, 1e-4
+    nt = _stencil(lambda dx, dy: 1e-3 + c * dx * dx)
+    zero = _stencil(lambda dx, dy: 0.0)
+    for u in (0.03, -0.07):
+        ux = _stencil(lambda dx, dy: u)
+        diff = oracle.sa_cell(nt, ux, zero, nu, d, 1) - oracle.sa_cell(nt, zero, zero, nu, d, 1)
+        assert diff == pytest.approx(c * u * u, rel=1e-9)
+
+
+def test_lsq_exact_for_linear_fields():
+    rng = np.random.default_rng(0)
+    for n in (3, 4, 9, 16):
+        px, py = rng.uniform(-2, 2, n), rng.uniform(-2, 2, n)
+        v = 0.3 + 1.7 * px - 0.4 * py
+        x, y = 0.37, -0.61
+        assert oracle.lsq_point(px, py, v, x, y) == pytest.approx(0.3 + 1.7 * x - 0.4 * y, rel=1e-12)
+    assert np.isnan(oracle.lsq_point([0, 1, 2], [0, 1, 2], [1, 2, 3], 0.5, 0.5))  # collinear
+
+
+def test_idw_exact_for_constants_and_at_nodes():
+    rng = np.random.default_rng(1)
+    px, py = rng.uniform(-1, 1, 5), rng.uniform(-1, 1, 5)
+    assert oracle.idw_point(px, py, np.full(5, 2.5), 0.1, 0.2) == pytest.approx(2.5, rel=1e-15)
+    v = rng.uniform(0, 1, 5)
+    assert oracle.idw_point(px, py, v, px[2], py[2]) == v[2]
+    got = oracle.idw_point(px, py, v, 0.1, 0.2)
+    assert v.min() <= got <= v.max()
