@@ -1,0 +1,235 @@
+/*
+ * liblbr: MI355X (gfx950) implementation of the time step of the LBM-RANS
+ * method with the virtual-node slip-velocity bounce-back of Ponsin & Lozano,
+ * "Enhanced wall boundary modeling for turbulent flows using the lattice
+ * Boltzmann method with adaptive Cartesian grids".
+ *
+ * The problem is stated the way the paper states it (Sections 2.1-2.3 and
+ * 3.1.1): closed wall polylines, a multilevel Cartesian grid given by the
+ * level-0 resolution and the refinement bands, the flow parameters (Mach,
+ * Reynolds, reference density, inlet turbulence level), a number of time
+ * steps, and the outputs the paper reports (macroscopic fields, surface Cp
+ * and Cf, integrated force coefficients).
+ *
+ * Conventions for every entry point:
+ *  - Return value 0 on success, a negative LBR_ERR_* code on failure.  The
+ *    message of the last failure of a context is returned by
+ *    lbr_last_error(); no C++ exception crosses this interface.
+ *  - Host arrays passed in are read during the call and not retained.  Host
+ *    arrays passed out are written during the call (the call synchronises
+ *    the context's stream first).
+ *  - Device memory is owned by the library.  It is obtained from the
+ *    allocator callbacks in the config (for example PyTorch's caching
+ *    allocator) or, when those are NULL, from hipMalloc.
+ *  - All device work of a context is enqueued on the stream given in the
+ *    config (NULL: the default stream).  One context per host thread.
+ *
+ * Units: geometry in physical units (chord lengths); level l has cell size
+ * dx0 / 2^l; lattice values (velocities, viscosity, force) refer to level 0
+ * and are rescaled to finer levels with acoustic scaling (Section 2.1).
+ */
+#ifndef LBR_H
+#define LBR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBR_ABI_VERSION 1
+#define LBR_MAX_LEVELS 12
+
+enum lbr_status {
+    LBR_OK = 0,
+    LBR_ERR_INVALID_ARG = -1,
+    LBR_ERR_OOM = -2,
+    LBR_ERR_HIP = -3,
+    LBR_ERR_GEOMETRY = -4,
+    LBR_ERR_DIVERGED = -5,
+    LBR_ERR_STATE = -6
+};
+
+/* Population storage.  Populations are stored shifted by their lattice
+   weight (f_i - w_i); arithmetic is FP64 for LBR_STORE_F64 and FP32
+   otherwise.  The friction-velocity Newton solve, the wall-distance field and
+   the force sums are always FP64. */
+enum lbr_storage { LBR_STORE_F64 = 0, LBR_STORE_F32 = 1, LBR_STORE_F16 = 2, LBR_STORE_BF16 = 3 };
+
+/* Domain sides: x-lo, x-hi, y-lo, y-hi. */
+enum lbr_bc { LBR_BC_PERIODIC = 0, LBR_BC_INLET = 1, LBR_BC_OUTLET = 2, LBR_BC_SYMMETRY = 3,
+              LBR_BC_WALL = 4 };
+
+/* Wall treatment: the virtual-node slip velocity (Section 2.3), Nishimura's
+   linear extrapolation from R (eq. (31)), no slip, or a prescribed wall
+   velocity (for laminar checks). */
+enum lbr_wall_model { LBR_WALL_VN = 0, LBR_WALL_NISHIMURA = 1, LBR_WALL_NOSLIP = 2,
+                      LBR_WALL_PRESCRIBED = 3 };
+
+/* Link-wise bounce-back: Yu's interpolated scheme eq. (27) at every cut link
+   (AUTO and YU), or the half-way rule eq. (24) at every cut link. */
+enum lbr_bb { LBR_BB_AUTO = 0, LBR_BB_YU = 1, LBR_BB_HALFWAY = 2 };
+
+/* SA-neg convection: frozen (no SA update), Lax-Wendroff, first-order upwind. */
+enum lbr_sa { LBR_SA_FROZEN = 0, LBR_SA_LW = 1, LBR_SA_UPWIND1 = 2 };
+
+enum lbr_body { LBR_BODY_SOLID = 0, LBR_BODY_REFINE_ONLY = 1 };
+
+/* Fields for lbr_read_field. */
+enum lbr_field { LBR_FIELD_RHO = 0, LBR_FIELD_UX = 1, LBR_FIELD_UY = 2, LBR_FIELD_CHI = 3,
+                 LBR_FIELD_NUT = 4, LBR_FIELD_TYPE = 5, LBR_FIELD_DIST = 6 };
+
+/* Cell types reported through LBR_FIELD_TYPE. */
+enum lbr_cell { LBR_CELL_INACTIVE = 0, LBR_CELL_FLUID = 1, LBR_CELL_SOLID = 2,
+                LBR_CELL_GHOST = 3, LBR_CELL_COVERED = 4 };
+
+typedef void* (*lbr_alloc_fn)(size_t bytes, void* user);
+typedef void (*lbr_free_fn)(void* ptr, void* user);
+
+typedef struct lbr_config {
+    int32_t version;               /* LBR_ABI_VERSION */
+    int32_t storage;               /* enum lbr_storage */
+    int32_t nx0, ny0;              /* level-0 cells */
+    int32_t n_levels;              /* 1..LBR_MAX_LEVELS */
+    int32_t bc[4];                 /* enum lbr_bc for x-lo, x-hi, y-lo, y-hi */
+    int32_t wall_model;            /* enum lbr_wall_model */
+    int32_t bb;                    /* enum lbr_bb */
+    int32_t sa;                    /* enum lbr_sa */
+    int32_t body_mode;             /* enum lbr_body */
+    int32_t reserved0;
+    double origin[2];              /* physical position of the level-0 box corner */
+    double dx0;                    /* physical size of a level-0 cell */
+    double band[LBR_MAX_LEVELS];   /* band[l] (l >= 1): level l-1 cells closer than this
+                                      physical distance to a body are refined */
+    double wall_y[2];              /* physical y of the channel walls (bc = WALL) */
+    double mach, reynolds;         /* freestream Mach and Reynolds number */
+    double ref_length;             /* physical reference length (chord) */
+    double u_ref;                  /* level-0 lattice reference velocity (<= 0: mach c_s) */
+    double nu0;                    /* level-0 lattice viscosity (<= 0: from reynolds) */
+    double rho_ref;                /* reference density (lattice units, normally 1) */
+    double chi_inlet;              /* nu-tilde / nu at the inlet (paper: 3) */
+    double chi_init;               /* initial nu-tilde / nu (paper: 3) */
+    double force[2];               /* level-0 lattice body force per unit volume */
+    double omega_b;                /* bulk relaxation frequency (paper: 1) */
+    double d_wr, d_wv;             /* reference / virtual node distances in cells (2, 1) */
+    double u_wall[4];              /* LBR_WALL_PRESCRIBED: (ux, uy) lower, (ux, uy) upper */
+    lbr_alloc_fn alloc_fn;         /* optional device allocator */
+    lbr_free_fn free_fn;
+    void* alloc_user;
+    void* stream;                  /* hipStream_t, NULL = default stream */
+} lbr_config;
+
+typedef struct lbr_ctx lbr_ctx;
+
+/* Level description: the I/O box is the bounding box of the level's owned and
+   ghost cells, in global cell indices of the level (cell (i, j) of level l
+   spans [i, i+1] x [j, j+1] * dx0 / 2^l from the origin). */
+typedef struct lbr_level_desc {
+    int64_t gx0, gy0, nx, ny;      /* I/O box */
+    int64_t n_fluid;               /* owned fluid cells (the cells counted in MLUPS) */
+    int64_t n_wall_nodes;          /* boundary nodes B */
+    int64_t n_cut_links;
+    int64_t n_ghost;
+    int64_t n_tiles;               /* active 64 x 4 tiles launched per step */
+    int64_t bytes;                 /* device bytes held by the level */
+} lbr_level_desc;
+
+/* Number of doubles per wall-node record from lbr_read_wall: gi, gj, IW (x,y),
+   normal (x,y), d_WB, number of cut links, u_tau, u_W (x,y), rho_W, |u_Rt|,
+   Cp, Cf, body, chi_B, u_Rt (x,y), q[1..8] (-1: not cut), spare.  Positions
+   and distances are in lattice units of the node's level. */
+#define LBR_WALL_STRIDE 28
+
+/* Creates a context and validates the config (Section 2.1 parameters:
+   omega_b, d_WR = 2, d_WV = 1 unless changed).  cfg is copied.
+   Errors: LBR_ERR_INVALID_ARG for an inconsistent config. */
+int lbr_create(const lbr_config* cfg, lbr_ctx** out);
+
+/* Wall geometry (Section 2.3: surface segments in 2D): n_bodies closed
+   polylines, counter-clockwise (fluid on the right), given as consecutive
+   (x, y) pairs without repeating the first point; n_pts[b] >= 3.
+   Must be called before lbr_build (it may be called with n_bodies = 0). */
+int lbr_set_geometry(lbr_ctx* ctx, int32_t n_bodies, const int32_t* n_pts, const double* xy);
+
+/* Builds the multilevel grid, the cut-link list with wall fractions q, the
+   wall records (IW, normal, R-stencil weights), the FP64 wall-distance field,
+   and allocates device state (Sections 2.1 and 2.3).  Initialises every level
+   to the uniform reference state.  Errors: LBR_ERR_GEOMETRY when a refined
+   level reaches the domain edge or an interface comes too close to a body or
+   to another interface; LBR_ERR_OOM; LBR_ERR_HIP. */
+int lbr_build(lbr_ctx* ctx);
+
+/* Level layout after lbr_build. */
+int lbr_level_info(lbr_ctx* ctx, int32_t level, lbr_level_desc* out);
+
+/* Equilibrium initialisation of one level from host arrays over its I/O box
+   (row-major, ny x nx doubles).  NULL arrays take rho_ref, (u_ref, 0) and
+   chi_init. */
+int lbr_init_fields(lbr_ctx* ctx, int32_t level, const double* rho, const double* ux,
+                    const double* uy, const double* chi);
+
+/* Advances n coarse (level-0) steps: the recursive multilevel cycle of
+   Section 2.1, in which level l takes 2^l sub-steps.  Asynchronous on the
+   context's stream. */
+int lbr_advance(lbr_ctx* ctx, int64_t n_coarse_steps);
+
+/* Waits for the context's stream. */
+int lbr_synchronize(lbr_ctx* ctx);
+
+/* Copies one field of one level into a host array over the level's I/O box
+   (ny x nx doubles); cells that are not owned fluid read NaN (TYPE reads the
+   cell type for every cell). */
+int lbr_read_field(lbr_ctx* ctx, int32_t level, int32_t field, double* dst);
+
+/* Number of wall nodes on a level, and their records (LBR_WALL_STRIDE doubles
+   each, in row-major cell order).  The records hold the wall model evaluated
+   on the current state (steps 1-5 of the VN procedure, Section 2.3) and the
+   surface coefficients Cp and Cf of eq. (29). */
+int lbr_wall_count(lbr_ctx* ctx, int32_t level);
+int lbr_read_wall(lbr_ctx* ctx, int32_t level, double* dst);
+
+/* Surface Cp and sign-corrected Cf at the centroids of the segments of one
+   body (eq. (30) and the interpolation described after it).  cp and cf hold
+   n_pts[body] doubles each. */
+int lbr_surface(lbr_ctx* ctx, int32_t body, double* cp, double* cf);
+
+/* Integrated coefficients of eq. (30) for one body (body = -1: all bodies):
+   out = {C_Df, C_Dp, C_D, C_L (pressure only, as in eq. (30)), C_F . e_y}.
+   Sums are FP64 and deterministic. */
+int lbr_forces(lbr_ctx* ctx, int32_t body, double out[5]);
+
+/* Relative velocity change ||u(t) - u(t - n)||_2 / (n ||u(t)||_2) over all
+   owned fluid cells weighted by cell area, since the previous call (the first
+   call returns 1 and only records the state). */
+int lbr_residual(lbr_ctx* ctx, double* residual);
+
+/* Steps until lbr_residual (evaluated every check_every coarse steps) drops
+   below tol or max_steps is reached; returns the steps taken and the last
+   residual.  Returns LBR_ERR_DIVERGED if the state becomes non-finite. */
+int lbr_run_to_steady(lbr_ctx* ctx, double tol, int64_t max_steps, int64_t check_every,
+                      int64_t* steps_done, double* residual);
+
+/* Cell updates per coarse step: sum over levels of n_fluid * 2^l. */
+int64_t lbr_lups_per_coarse_step(lbr_ctx* ctx);
+
+/* Captures one coarse step in a HIP graph and replays it in lbr_advance
+   (enable != 0), or returns to direct launches (enable == 0). */
+int lbr_use_graph(lbr_ctx* ctx, int32_t enable);
+
+/* Average device time per launch of each kernel family over the last
+   lbr_advance (measured with HIP events on the context's stream), in
+   microseconds: out[0] main step (all levels), out[1] finest-level main step,
+   out[2] wall model, out[3] level transfers; enable turns the timing on. */
+int lbr_profile(lbr_ctx* ctx, int32_t enable, double out[4]);
+
+/* Last error message of the context (never NULL). */
+const char* lbr_last_error(const lbr_ctx* ctx);
+
+/* Frees every device and host resource of the context (NULL is allowed). */
+void lbr_destroy(lbr_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,252 @@
+"""Python binding of liblbr, the MI355X LBM-RANS library (include/lbr.h).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+PyTorch provides device memory (through the allocator callbacks of the
+config) and the stream.  Importing the package loads liblbr.so and raises if
+it has not been built (``python -m paper_2601_18443_amd.build``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbr.so")
+
+ABI_VERSION = 1
+MAX_LEVELS = 12
+WALL_STRIDE = 28
+
+STORE_F64, STORE_F32, STORE_F16, STORE_BF16 = 0, 1, 2, 3
+STORAGE = {"f64": STORE_F64, "f32": STORE_F32, "f16": STORE_F16, "bf16": STORE_BF16}
+FIELD_RHO, FIELD_UX, FIELD_UY, FIELD_CHI, FIELD_NUT, FIELD_TYPE, FIELD_DIST = range(7)
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class lbr_config(C.Structure):
+    _fields_ = [
+        ("version", C.c_int32), ("storage", C.c_int32), ("nx0", C.c_int32), ("ny0", C.c_int32),
+        ("n_levels", C.c_int32), ("bc", C.c_int32 * 4), ("wall_model", C.c_int32),
+        ("bb", C.c_int32), ("sa", C.c_int32), ("body_mode", C.c_int32), ("reserved0", C.c_int32),
+        ("origin", C.c_double * 2), ("dx0", C.c_double), ("band", C.c_double * MAX_LEVELS),
+        ("wall_y", C.c_double * 2), ("mach", C.c_double), ("reynolds", C.c_double),
+        ("ref_length", C.c_double), ("u_ref", C.c_double), ("nu0", C.c_double),
+        ("rho_ref", C.c_double), ("chi_inlet", C.c_double), ("chi_init", C.c_double),
+        ("force", C.c_double * 2), ("omega_b", C.c_double), ("d_wr", C.c_double),
+        ("d_wv", C.c_double), ("u_wall", C.c_double * 4),
+        ("alloc_fn", ALLOC_FN), ("free_fn", FREE_FN), ("alloc_user", C.c_void_p),
+        ("stream", C.c_void_p),
+    ]
+
+
+class lbr_level_desc(C.Structure):
+    _fields_ = [(k, C.c_int64) for k in ("gx0", "gy0", "nx", "ny", "n_fluid", "n_wall_nodes",
+                                         "n_cut_links", "n_ghost", "n_tiles", "bytes")]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded liblbr.so; raises when the HIP library is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("liblbr.so is not built: run `python -m paper_2601_18443_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        p, i32, i64, dp = C.c_void_p, C.c_int32, C.c_int64, C.POINTER(C.c_double)
+        L.lbr_create.argtypes = [C.POINTER(lbr_config), C.POINTER(p)]
+        L.lbr_set_geometry.argtypes = [p, i32, C.POINTER(C.c_int32), dp]
+        L.lbr_build.argtypes = [p]
+        L.lbr_level_info.argtypes = [p, i32, C.POINTER(lbr_level_desc)]
+        L.lbr_init_fields.argtypes = [p, i32, dp, dp, dp, dp]
+        L.lbr_advance.argtypes = [p, i64]
+        L.lbr_synchronize.argtypes = [p]
+        L.lbr_read_field.argtypes = [p, i32, i32, dp]
+        L.lbr_wall_count.argtypes = [p, i32]
+        L.lbr_read_wall.argtypes = [p, i32, dp]
+        L.lbr_surface.argtypes = [p, i32, dp, dp]
+        L.lbr_forces.argtypes = [p, i32, dp]
+        L.lbr_residual.argtypes = [p, dp]
+        L.lbr_run_to_steady.argtypes = [p, C.c_double, i64, i64, C.POINTER(C.c_int64), dp]
+        L.lbr_lups_per_coarse_step.argtypes = [p]
+        L.lbr_lups_per_coarse_step.restype = i64
+        L.lbr_use_graph.argtypes = [p, i32]
+        L.lbr_profile.argtypes = [p, i32, dp]
+        L.lbr_last_error.argtypes = [p]
+        L.lbr_last_error.restype = C.c_char_p
+        L.lbr_destroy.argtypes = [p]
+        L.lbr_destroy.restype = None
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return None if a is None else a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+class LbrError(RuntimeError):
+    pass
+
+
+class _TorchAllocator:
+    """Device memory for the library from PyTorch's caching allocator."""
+
+    def __init__(self, device):
+        import torch
+        self.torch = torch
+        self.device = device
+        self.live = {}
+        self.alloc_cb = ALLOC_FN(self._alloc)
+        self.free_cb = FREE_FN(self._free)
+
+    def _alloc(self, nbytes, user):
+        try:
+            t = self.torch.empty(int(nbytes), dtype=self.torch.uint8, device=self.device)
+        except Exception:
+            return None
+        ptr = t.data_ptr()
+        self.live[ptr] = t
+        return ptr
+
+    def _free(self, ptr, user):
+        self.live.pop(ptr, None)
+
+
+def make_config(case, storage="f32", stream=None, allocator=None) -> lbr_config:
+    c = lbr_config()
+    c.version = ABI_VERSION
+    c.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
+    c.nx0, c.ny0, c.n_levels = case["nx0"], case["ny0"], case["n_levels"]
+    for k in range(4):
+        c.bc[k] = case["bc"][k]
+    c.wall_model, c.bb, c.sa = case["wall_model"], case["bb_mode"], case["sa_mode"]
+    c.body_mode = case.get("body_mode", 0)
+    c.origin[0], c.origin[1] = case["origin"]
+    c.dx0 = case["dx0"]
+    for l, b in enumerate(case.get("bands", ())):
+        c.band[l] = b
+    c.wall_y[0], c.wall_y[1] = case.get("wall_y", (0.0, 0.0))
+    c.mach, c.reynolds, c.ref_length = case["mach"], case["reynolds"], case["ref_length"]
+    c.u_ref, c.nu0 = case["u_ref"], case["nu0"]
+    c.rho_ref = case.get("rho_ref", 1.0)
+    c.chi_inlet, c.chi_init = case["chi_inlet"], case["chi_init"]
+    c.force[0], c.force[1] = case["force"]
+    c.omega_b, c.d_wr, c.d_wv = case["omega_b"], case["d_wr"], case["d_wv"]
+    for k, v in enumerate(case.get("u_wall", (0.0, 0.0, 0.0, 0.0))):
+        c.u_wall[k] = v
+    if allocator is not None:
+        c.alloc_fn, c.free_fn = allocator.alloc_cb, allocator.free_cb
+    c.stream = stream
+    return c
+
+
+class Solver:
+    """One liblbr context: lbr_create + lbr_set_geometry + lbr_build from a case dict."""
+
+    def __init__(self, case, storage="f32", device="cuda:0", use_torch_memory=True):
+        import torch
+        L = lib()
+        if not torch.cuda.is_available():
+            raise LbrError("liblbr needs a GPU (torch.cuda.is_available() is False)")
+        self.device = torch.device(device)
+        torch.cuda.set_device(self.device)
+        self.torch_stream = torch.cuda.current_stream(self.device)
+        self.alloc = _TorchAllocator(self.device) if use_torch_memory else None
+        self.case = case
+        self.cfg = make_config(case, storage, C.c_void_p(self.torch_stream.cuda_stream), self.alloc)
+        h = C.c_void_p()
+        rc = L.lbr_create(C.byref(self.cfg), C.byref(h))
+        if rc != 0:
+            raise LbrError(f"lbr_create failed ({rc})")
+        self.h = h
+        bodies = case.get("bodies", [])
+        npts = (C.c_int32 * max(1, len(bodies)))(*[len(b) for b in bodies])
+        xy = np.ascontiguousarray(np.concatenate(bodies, 0) if bodies else np.zeros((1, 2)))
+        self._check(L.lbr_set_geometry(self.h, len(bodies), npts, _dp(xy)))
+        self._check(L.lbr_build(self.h))
+        self.n_levels = case["n_levels"]
+
+    def _check(self, rc):
+        if rc != 0:
+            raise LbrError(f"liblbr error {rc}: {lib().lbr_last_error(self.h).decode()}")
+        return rc
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().lbr_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def level_info(self, level):
+        d = lbr_level_desc()
+        self._check(lib().lbr_level_info(self.h, level, C.byref(d)))
+        return {k: int(getattr(d, k)) for k, _ in lbr_level_desc._fields_}
+
+    def init(self, level, rho=None, ux=None, uy=None, chi=None):
+        arrs = [None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+                for a in (rho, ux, uy, chi)]
+        self._check(lib().lbr_init_fields(self.h, level, *[_dp(a) for a in arrs]))
+
+    def advance(self, n):
+        self._check(lib().lbr_advance(self.h, int(n)))
+
+    def synchronize(self):
+        self._check(lib().lbr_synchronize(self.h))
+
+    def field(self, level, which):
+        inf = self.level_info(level)
+        out = np.empty((inf["ny"], inf["nx"]))
+        self._check(lib().lbr_read_field(self.h, level, which, _dp(out)))
+        return out
+
+    def wall(self, level):
+        n = lib().lbr_wall_count(self.h, level)
+        if n < 0:
+            self._check(n)
+        out = np.empty((max(n, 1), WALL_STRIDE))
+        if n > 0:
+            self._check(lib().lbr_read_wall(self.h, level, _dp(out)))
+        return out[:n]
+
+    def forces(self, body=-1):
+        out = np.zeros(5)
+        self._check(lib().lbr_forces(self.h, body, _dp(out)))
+        return out
+
+    def surface(self, body=0):
+        n = len(self.case["bodies"][body])
+        cp, cf = np.zeros(n), np.zeros(n)
+        self._check(lib().lbr_surface(self.h, body, _dp(cp), _dp(cf)))
+        return cp, cf
+
+    def residual(self):
+        r = C.c_double()
+        self._check(lib().lbr_residual(self.h, C.byref(r)))
+        return r.value
+
+    def run_to_steady(self, tol, max_steps, check_every=100):
+        done, r = C.c_int64(), C.c_double()
+        self._check(lib().lbr_run_to_steady(self.h, tol, max_steps, check_every, C.byref(done), C.byref(r)))
+        return done.value, r.value
+
+    def lups_per_coarse_step(self):
+        return int(lib().lbr_lups_per_coarse_step(self.h))
+
+    def use_graph(self, enable=True):
+        self._check(lib().lbr_use_graph(self.h, 1 if enable else 0))
+
+    def profile(self, enable=None):
+        out = np.zeros(4)
+        cur = 1 if enable else 0
+        self._check(lib().lbr_profile(self.h, cur, _dp(out)))
+        return out

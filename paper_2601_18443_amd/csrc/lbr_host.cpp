@@ -1,0 +1,1349 @@
+// Host side of liblbr: grid construction, wall records, the recursive
+// multilevel schedule and the C entry points declared in include/lbr.h.
+#include "lbr.h"
+#include "lbr_impl.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace lbr;
+
+namespace {
+
+constexpr int G = 2;   // guard ring of every storage box
+constexpr int CXH[9] = {0, 1, -1, 0, 0, 1, -1, 1, -1};
+constexpr int CYH[9] = {0, 0, 0, 1, -1, 1, -1, -1, 1};
+constexpr double KAPPA_H = 0.41;
+
+struct Node {
+    int gi, gj, body;
+    long cell;
+    double q[9];
+    double iw[2], nrm[2], dwb;
+};
+
+struct Level {
+    int l = 0;
+    Box box{};
+    int bx0 = 0, by0 = 0, bnx = 0, bny = 0;   // I/O box
+    double scale = 1, nu = 0, fx = 0, fy = 0;
+    std::vector<uint8_t> flag;
+    std::vector<double> dbody, d;
+    std::vector<uint8_t> inside;
+    std::vector<int32_t> bidx;
+    std::vector<Node> nodes;
+    std::vector<uint32_t> tiles;
+    std::vector<int32_t> owned, ghosts, covb;
+    int64_t n_fluid = 0, n_ghost = 0, n_cut = 0;
+    // device
+    void* f[2] = {nullptr, nullptr};
+    void* mac[2] = {nullptr, nullptr};
+    void* chi[2] = {nullptr, nullptr};
+    double* dist_dev = nullptr;
+    uint8_t* flag_dev = nullptr;
+    int32_t* bidx_dev = nullptr;
+    uint32_t* tiles_dev = nullptr;
+    int32_t* ghosts_dev = nullptr;
+    int32_t* covb_dev = nullptr;
+    int32_t* owned_dev = nullptr;
+    void* bq = nullptr;
+    void* bw = nullptr;
+    int32_t* bcell = nullptr;
+    double* bgeo = nullptr;
+    int32_t* st_cell = nullptr;
+    double* st_wr = nullptr;
+    double* st_wu = nullptr;
+    double* bstate = nullptr;
+    double* snap = nullptr;
+    int cur = 0;
+    size_t bytes = 0;
+
+    long idx(int gx, int gy) const {
+        const int lx = gx - box.gx0, ly = gy - box.gy0;
+        if (lx < 0 || ly < 0 || lx >= box.pitch || ly >= box.ny) return -1;
+        return (long)ly * box.pitch + lx;
+    }
+    uint8_t type_at(int gx, int gy) const {
+        const long c = idx(gx, gy);
+        return c < 0 ? T_INACTIVE : (flag[c] & F_TYPE);
+    }
+};
+
+struct SurfaceBody {
+    int nseg = 0;
+    double* seg = nullptr;
+    int32_t* near = nullptr;
+    double* wgt = nullptr;
+};
+
+}  // namespace
+
+struct lbr_ctx {
+    lbr_config cfg{};
+    std::string err = "";
+    hipStream_t stream = nullptr;
+    Prec prec = P_F32;
+    size_t ssize = 4, csize = 4;
+    double u_ref = 0, nu0 = 0;
+    std::vector<double> polyflat;   // level-0 lattice coordinates
+    std::vector<int> npts, off;
+    double wall_lat[2] = {0, 0};
+    std::vector<Level> lv;
+    int wall_level = -1;
+    std::vector<SurfaceBody> surf;
+    double* surf_cp = nullptr;
+    double* surf_cf = nullptr;
+    double* partial = nullptr;
+    int partial_n = 0;
+    bool built = false;
+    std::vector<void*> allocs;
+    int64_t resid_steps = 0;
+    bool resid_init = false;
+    // graph replay of one coarse step (two when level 0 alternates buffers)
+    bool use_graph = false;
+    hipGraphExec_t graph = nullptr;
+    int graph_steps = 0;
+    // profiling
+    bool prof = false;
+    std::vector<hipEvent_t> ev;
+    std::vector<int> ev_kind;
+    size_t ev_used = 0;
+    double prof_out[4] = {0, 0, 0, 0};
+};
+
+namespace {
+
+int set_err(lbr_ctx* c, int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return code;
+}
+
+#define HIPCHK(ctx, expr)                                                                  \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return set_err(ctx, LBR_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_));      \
+    } while (0)
+
+void* dalloc(lbr_ctx* c, size_t bytes) {
+    if (bytes == 0) bytes = 256;
+    void* p = nullptr;
+    if (c->cfg.alloc_fn) {
+        p = c->cfg.alloc_fn(bytes, c->cfg.alloc_user);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+        p = nullptr;
+    }
+    if (p) c->allocs.push_back(p);
+    return p;
+}
+
+void dfree(lbr_ctx* c, void* p) {
+    auto it = std::find(c->allocs.begin(), c->allocs.end(), p);
+    if (it == c->allocs.end()) return;
+    c->allocs.erase(it);
+    if (c->cfg.free_fn) c->cfg.free_fn(p, c->cfg.alloc_user);
+    else (void)hipFree(p);
+}
+
+template <class T>
+int upload(lbr_ctx* c, T** dst, const std::vector<T>& v, size_t* acct) {
+    size_t bytes = std::max<size_t>(v.size(), 1) * sizeof(T);
+    *dst = static_cast<T*>(dalloc(c, bytes));
+    if (!*dst) return set_err(c, LBR_ERR_OOM, "device allocation of %zu bytes failed", bytes);
+    if (acct) *acct += bytes;
+    if (!v.empty())
+        HIPCHK(c, hipMemcpyAsync(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, c->stream));
+    return 0;
+}
+
+double seg_closest(double px, double py, double ax, double ay, double bx, double by, double* qx,
+                   double* qy) {
+    const double ex = bx - ax, ey = by - ay, l2 = ex * ex + ey * ey;
+    double t = l2 > 0 ? ((px - ax) * ex + (py - ay) * ey) / l2 : 0.0;
+    t = std::min(1.0, std::max(0.0, t));
+    *qx = ax + t * ex;
+    *qy = ay + t * ey;
+    return std::hypot(px - *qx, py - *qy);
+}
+
+// parameter t in (0, 1] where p + t e crosses segment ab, or -1
+double crossing(double px, double py, double ex, double ey, double ax, double ay, double bx,
+                double by) {
+    const double sx = bx - ax, sy = by - ay;
+    const double den = ex * sy - ey * sx;
+    if (den == 0.0) return -1.0;
+    const double t = ((ax - px) * sy - (ay - py) * sx) / den;
+    const double u = ((ax - px) * ey - (ay - py) * ex) / den;
+    return (t > 0.0 && t <= 1.0 && u >= 0.0 && u <= 1.0) ? t : -1.0;
+}
+
+// Segments of all bodies bucketed on a uniform grid (in lattice units of one level).
+struct Buckets {
+    double x0 = 0, y0 = 0, h = 4;
+    int nx = 0, ny = 0;
+    std::vector<std::vector<int>> cell;   // segment ids
+    void build(const std::vector<double>& seg, double scale, double pad) {
+        const size_t ns = seg.size() / 5;
+        double xlo = 1e300, ylo = 1e300, xhi = -1e300, yhi = -1e300;
+        for (size_t k = 0; k < ns; ++k) {
+            for (int e = 0; e < 2; ++e) {
+                xlo = std::min(xlo, seg[5 * k + 2 * e] * scale);
+                xhi = std::max(xhi, seg[5 * k + 2 * e] * scale);
+                ylo = std::min(ylo, seg[5 * k + 2 * e + 1] * scale);
+                yhi = std::max(yhi, seg[5 * k + 2 * e + 1] * scale);
+            }
+        }
+        if (ns == 0) { nx = ny = 0; return; }
+        x0 = xlo - pad - h; y0 = ylo - pad - h;
+        nx = (int)((xhi - xlo + 2 * pad) / h) + 3;
+        ny = (int)((yhi - ylo + 2 * pad) / h) + 3;
+        cell.assign((size_t)nx * ny, {});
+        for (size_t k = 0; k < ns; ++k) {
+            const double ax = seg[5 * k] * scale, ay = seg[5 * k + 1] * scale;
+            const double bx = seg[5 * k + 2] * scale, by = seg[5 * k + 3] * scale;
+            const int i0 = (int)((std::min(ax, bx) - pad - x0) / h), i1 = (int)((std::max(ax, bx) + pad - x0) / h);
+            const int j0 = (int)((std::min(ay, by) - pad - y0) / h), j1 = (int)((std::max(ay, by) + pad - y0) / h);
+            for (int j = std::max(0, j0); j <= std::min(ny - 1, j1); ++j)
+                for (int i = std::max(0, i0); i <= std::min(nx - 1, i1); ++i)
+                    cell[(size_t)j * nx + i].push_back((int)k);
+        }
+    }
+    const std::vector<int>* at(double x, double y) const {
+        static const std::vector<int> none;
+        const int i = (int)std::floor((x - x0) / h), j = (int)std::floor((y - y0) / h);
+        if (nx == 0 || i < 0 || j < 0 || i >= nx || j >= ny) return &none;
+        return &cell[(size_t)j * nx + i];
+    }
+};
+
+int round_up(int v, int m) { return (v + m - 1) / m * m; }
+
+// Runs the FP64 geometry kernel over a level's storage box.
+int level_geometry(lbr_ctx* c, Level& L, const double* poly_dev, const int* off_dev) {
+    const long n = (long)L.box.pitch * L.box.ny;
+    double* dd = static_cast<double*>(dalloc(c, n * sizeof(double)));
+    uint8_t* id = static_cast<uint8_t*>(dalloc(c, n));
+    if (!dd || !id) return set_err(c, LBR_ERR_OOM, "geometry scratch allocation failed");
+    HIPCHK(c, launch_geometry(L.box.pitch, L.box.ny, L.box.gx0, L.box.gy0, L.scale,
+                              (int)c->npts.size(), off_dev, poly_dev,
+                              c->cfg.body_mode == LBR_BODY_SOLID, dd, id, c->stream));
+    L.dbody.resize(n);
+    L.inside.resize(n);
+    HIPCHK(c, hipMemcpyAsync(L.dbody.data(), dd, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(L.inside.data(), id, n, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    dfree(c, dd);
+    dfree(c, id);
+    return 0;
+}
+
+void set_box(Level& L, int gx0, int gy0, int nx, int ny) {
+    L.box.gx0 = gx0;
+    L.box.gy0 = gy0;
+    L.box.pitch = round_up(nx, TILE_X);
+    L.box.ny = round_up(ny, TILE_Y);
+    L.box.plane = (long)L.box.pitch * L.box.ny;
+    L.flag.assign(L.box.plane, T_INACTIVE);
+}
+
+int build_levels(lbr_ctx* c, const double* poly_dev, const int* off_dev) {
+    const lbr_config& cfg = c->cfg;
+    const int nl = cfg.n_levels;
+    c->lv.assign(nl, Level());
+    for (int l = 0; l < nl; ++l) {
+        Level& L = c->lv[l];
+        L.l = l;
+        L.scale = std::ldexp(1.0, l);
+        L.nu = c->nu0 * L.scale;
+        L.fx = cfg.force[0] / L.scale;
+        L.fy = cfg.force[1] / L.scale;
+        if (l == 0) {
+            set_box(L, -G, -G, cfg.nx0 + 2 * G, cfg.ny0 + 2 * G);
+            if (int r = level_geometry(c, L, poly_dev, off_dev)) return r;
+            for (int gy = 0; gy < cfg.ny0; ++gy)
+                for (int gx = 0; gx < cfg.nx0; ++gx) {
+                    const long k = L.idx(gx, gy);
+                    L.flag[k] = L.inside[k] ? T_SOLID : T_FLUID;
+                }
+            continue;
+        }
+        Level& P = c->lv[l - 1];
+        const double band = cfg.band[l] / cfg.dx0 * P.scale;
+        const long np = P.box.plane;
+        bool any = false;
+        for (long k = 0; k < np; ++k) {
+            const int t = P.flag[k] & F_TYPE;
+            if ((t == T_FLUID || t == T_SOLID) && P.dbody[k] < band) {
+                P.flag[k] = T_COVERED;
+                any = true;
+            }
+        }
+        if (!any) return set_err(c, LBR_ERR_GEOMETRY, "level %d: no cells refined", l);
+        int lo_x = 1 << 30, lo_y = 1 << 30, hi_x = -(1 << 30), hi_y = -(1 << 30);
+        for (long k = 0; k < np; ++k) {
+            const int gx = (int)(k % P.box.pitch) + P.box.gx0, gy = (int)(k / P.box.pitch) + P.box.gy0;
+            const int t = P.flag[k] & F_TYPE;
+            bool near_cov = false, near_fluid = false;
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const int tn = P.type_at(gx + dx, gy + dy);
+                    near_cov |= tn == T_COVERED;
+                    near_fluid |= tn == T_FLUID;
+                }
+            if (t == T_FLUID && near_cov) P.flag[k] |= F_IFACE;
+            if (t == T_COVERED && near_fluid) P.flag[k] |= F_COVB;
+            if (t == T_COVERED || (P.flag[k] & F_IFACE)) {
+                lo_x = std::min(lo_x, gx); hi_x = std::max(hi_x, gx);
+                lo_y = std::min(lo_y, gy); hi_y = std::max(hi_y, gy);
+            }
+        }
+        set_box(L, 2 * lo_x - G, 2 * lo_y - G, 2 * (hi_x - lo_x + 1) + 2 * G,
+                2 * (hi_y - lo_y + 1) + 2 * G);
+        if (int r = level_geometry(c, L, poly_dev, off_dev)) return r;
+        for (long k = 0; k < L.box.plane; ++k) {
+            const int gx = (int)(k % L.box.pitch) + L.box.gx0, gy = (int)(k / L.box.pitch) + L.box.gy0;
+            const long pk = P.idx(gx >> 1, gy >> 1);
+            if (pk < 0) continue;
+            if ((P.flag[pk] & F_TYPE) == T_COVERED) L.flag[k] = L.inside[k] ? T_SOLID : T_FLUID;
+            else if (P.flag[pk] & F_IFACE) L.flag[k] = T_GHOST;
+        }
+    }
+    return 0;
+}
+
+// Clearances the transfer needs between interfaces, bodies and the domain edge.
+int check_levels(lbr_ctx* c) {
+    const int nl = (int)c->lv.size();
+    for (int l = 0; l < nl; ++l) {
+        const Level& L = c->lv[l];
+        for (long k = 0; k < L.box.plane; ++k) {
+            const int t = L.flag[k] & F_TYPE;
+            if (t != T_COVERED && t != T_GHOST && !(l > 0 && t != T_INACTIVE)) continue;
+            const int gx = (int)(k % L.box.pitch) + L.box.gx0, gy = (int)(k / L.box.pitch) + L.box.gy0;
+            if (l > 0 && t != T_INACTIVE) {
+                const int nxd = c->cfg.nx0 << l, nyd = c->cfg.ny0 << l;
+                if (gx < 4 || gy < 4 || gx >= nxd - 4 || gy >= nyd - 4)
+                    return set_err(c, LBR_ERR_GEOMETRY, "level %d reaches the domain edge", l);
+            }
+            if (t == T_COVERED) {
+                for (int dy = -2; dy <= 2; ++dy)
+                    for (int dx = -2; dx <= 2; ++dx) {
+                        const int tn = L.type_at(gx + dx, gy + dy);
+                        if (tn != T_FLUID && tn != T_COVERED)
+                            return set_err(c, LBR_ERR_GEOMETRY,
+                                           "level %d: refined region too close to a body or edge", l);
+                    }
+                if ((L.flag[k] & F_COVB) && l + 1 < nl) {
+                    const Level& F = c->lv[l + 1];
+                    for (int dy = -3; dy <= 4; ++dy)
+                        for (int dx = -3; dx <= 4; ++dx) {
+                            const int tn = F.type_at(2 * gx + dx, 2 * gy + dy);
+                            if (tn == T_SOLID || tn == T_COVERED)
+                                return set_err(c, LBR_ERR_GEOMETRY,
+                                               "level %d: interface too close to a body or a finer "
+                                               "interface", l + 1);
+                        }
+                }
+            }
+            if (t == T_GHOST) {
+                for (int dy = -4; dy <= 4; ++dy)
+                    for (int dx = -4; dx <= 4; ++dx) {
+                        const int tn = L.type_at(gx + dx, gy + dy);
+                        if (tn == T_SOLID || tn == T_COVERED)
+                            return set_err(c, LBR_ERR_GEOMETRY,
+                                           "level %d: ghost band too close to a body or a finer level", l);
+                    }
+            }
+        }
+    }
+    return 0;
+}
+
+// Flags, distance field, lists and tiles of one level.
+void finish_level(lbr_ctx* c, Level& L) {
+    const lbr_config& cfg = c->cfg;
+    const int nxd = cfg.nx0 << L.l, nyd = cfg.ny0 << L.l;
+    L.d.assign(L.box.plane, 0.0);
+    L.bidx.assign(L.box.plane, -1);
+    L.owned.clear();
+    L.ghosts.clear();
+    L.covb.clear();
+    int lo_x = 1 << 30, lo_y = 1 << 30, hi_x = -(1 << 30), hi_y = -(1 << 30);
+    for (long k = 0; k < L.box.plane; ++k) {
+        const int gx = (int)(k % L.box.pitch) + L.box.gx0, gy = (int)(k / L.box.pitch) + L.box.gy0;
+        const int t = L.flag[k] & F_TYPE;
+        if (t == T_FLUID || t == T_SOLID || t == T_COVERED || t == T_GHOST) {
+            lo_x = std::min(lo_x, gx); hi_x = std::max(hi_x, gx);
+            lo_y = std::min(lo_y, gy); hi_y = std::max(hi_y, gy);
+        }
+        if (t == T_GHOST) { L.ghosts.push_back((int32_t)k); L.n_ghost++; }
+        if (t == T_COVERED && (L.flag[k] & F_COVB)) L.covb.push_back((int32_t)k);
+        if (t != T_FLUID) continue;
+        L.owned.push_back((int32_t)k);
+        L.n_fluid++;
+        if (L.l == 0 && (gx == 0 || gy == 0 || gx == nxd - 1 || gy == nyd - 1)) L.flag[k] |= F_EDGE;
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx)
+                if (L.type_at(gx + dx, gy + dy) == T_GHOST) L.flag[k] |= F_NEARGHOST;
+        const double py = gy + 0.5;
+        double d = (cfg.body_mode == LBR_BODY_SOLID && !c->npts.empty()) ? L.dbody[k] : 1e300;
+        if (cfg.bc[2] == LBR_BC_WALL) d = std::min(d, py - c->wall_lat[0] * L.scale);
+        if (cfg.bc[3] == LBR_BC_WALL) d = std::min(d, c->wall_lat[1] * L.scale - py);
+        L.d[k] = d;
+    }
+    L.bx0 = lo_x; L.by0 = lo_y; L.bnx = hi_x - lo_x + 1; L.bny = hi_y - lo_y + 1;
+}
+
+// Cut links, wall points and normals (Sections 2.1 and 2.3).
+int build_walls(lbr_ctx* c, Level& L, const std::vector<double>& seg) {
+    const lbr_config& cfg = c->cfg;
+    const int nxd = cfg.nx0 << L.l, nyd = cfg.ny0 << L.l;
+    const bool bodies = cfg.body_mode == LBR_BODY_SOLID && !seg.empty();
+    Buckets bk;
+    if (bodies) bk.build(seg, L.scale, 2.0);
+    const bool perx = cfg.bc[0] == LBR_BC_PERIODIC;
+    L.nodes.clear();
+    for (int32_t k : L.owned) {
+        if (L.d[k] > 1.5) continue;
+        const int gx = (int)(k % L.box.pitch) + L.box.gx0, gy = (int)(k / L.box.pitch) + L.box.gy0;
+        const double px = gx + 0.5, py = gy + 0.5;
+        Node nd{};
+        nd.gi = gx; nd.gj = gy; nd.cell = k;
+        int ncut = 0;
+        const std::vector<int>* cand = bodies ? bk.at(px, py) : nullptr;
+        for (int o = 0; o < 9; ++o) nd.q[o] = -1.0;
+        for (int o = 1; o < 9; ++o) {
+            const int tx = gx + CXH[o], ty = gy + CYH[o];
+            bool solid = false;
+            double t = -1.0;
+            if (L.l == 0 && ((ty < 0 && cfg.bc[2] == LBR_BC_WALL) || (ty >= nyd && cfg.bc[3] == LBR_BC_WALL))) {
+                const double yw = (ty < 0 ? c->wall_lat[0] : c->wall_lat[1]) * L.scale;
+                solid = true;
+                t = (yw - py) / (double)CYH[o];
+            } else {
+                int txx = tx;
+                if (L.l == 0 && perx) txx = ((tx % nxd) + nxd) % nxd;
+                solid = L.type_at(txx, ty) == T_SOLID;
+            }
+            double tb = -1.0;
+            if (cand)
+                for (int s : *cand) {
+                    const double tt = crossing(px, py, CXH[o], CYH[o], seg[5 * s] * L.scale,
+                                               seg[5 * s + 1] * L.scale, seg[5 * s + 2] * L.scale,
+                                               seg[5 * s + 3] * L.scale);
+                    if (tt >= 0.0 && (tb < 0.0 || tt < tb)) tb = tt;
+                }
+            if (tb >= 0.0 && (t < 0.0 || tb < t)) t = tb;
+            if (solid || tb >= 0.0) {
+                nd.q[o] = t > 0.0 ? t : 0.5;
+                ncut++;
+            }
+        }
+        if (!ncut) continue;
+        L.n_cut += ncut;
+        // closest wall point
+        double best = 1e300, qx = px, qy = py;
+        int body = -1, bseg = -1;
+        if (bodies) {
+            for (size_t s = 0; s < seg.size() / 5; ++s) {
+                double cx, cy;
+                const double dd = seg_closest(px, py, seg[5 * s] * L.scale, seg[5 * s + 1] * L.scale,
+                                              seg[5 * s + 2] * L.scale, seg[5 * s + 3] * L.scale, &cx, &cy);
+                if (dd < best) { best = dd; qx = cx; qy = cy; body = (int)seg[5 * s + 4]; bseg = (int)s; }
+            }
+        }
+        if (cfg.bc[2] == LBR_BC_WALL && L.l == 0) {
+            const double yw = c->wall_lat[0] * L.scale;
+            if (py - yw < best) { best = py - yw; qx = px; qy = yw; body = -1; bseg = -1; }
+        }
+        if (cfg.bc[3] == LBR_BC_WALL && L.l == 0) {
+            const double yw = c->wall_lat[1] * L.scale;
+            if (yw - py < best) { best = yw - py; qx = px; qy = yw; body = -2; bseg = -1; }
+        }
+        nd.iw[0] = qx; nd.iw[1] = qy; nd.dwb = best; nd.body = body;
+        if (best > 1e-12) {
+            nd.nrm[0] = (px - qx) / best;
+            nd.nrm[1] = (py - qy) / best;
+        } else if (bseg >= 0) {
+            const double tx = seg[5 * bseg + 2] - seg[5 * bseg], ty = seg[5 * bseg + 3] - seg[5 * bseg + 1];
+            const double tl = std::hypot(tx, ty);
+            nd.nrm[0] = ty / tl; nd.nrm[1] = -tx / tl;
+        } else {
+            nd.nrm[0] = 0.0; nd.nrm[1] = body == -1 ? 1.0 : -1.0;
+        }
+        L.bidx[k] = (int32_t)L.nodes.size();
+        L.flag[k] |= F_WALL;
+        L.nodes.push_back(nd);
+    }
+    return 0;
+}
+
+// Interpolation weights at R (step 1 of the VN procedure): IDW (power 2) for
+// rho over the enclosing 2 x 2 block without boundary nodes, linear least
+// squares for u over its fluid cells, both grown to 4 x 4 when too few cells
+// remain.  Weights are stored so the device only gathers.
+int stencils(lbr_ctx* c, Level& L, std::vector<int32_t>& sc, std::vector<double>& wr,
+             std::vector<double>& wu) {
+    const lbr_config& cfg = c->cfg;
+    const int nb = (int)L.nodes.size();
+    const int nxd = cfg.nx0 << L.l, nyd = cfg.ny0 << L.l;
+    const bool perx = cfg.bc[0] == LBR_BC_PERIODIC && L.l == 0;
+    const double dwr = cfg.wall_model == LBR_WALL_NISHIMURA ? 1.75 : cfg.d_wr;
+    sc.assign((size_t)nb * MAX_STENCIL, -1);
+    wr.assign((size_t)nb * MAX_STENCIL, 0.0);
+    wu.assign((size_t)nb * MAX_STENCIL, 0.0);
+    for (int b = 0; b < nb; ++b) {
+        const Node& nd = L.nodes[b];
+        const double rx = nd.iw[0] + dwr * nd.nrm[0], ry = nd.iw[1] + dwr * nd.nrm[1];
+        const int i0 = (int)std::floor(rx - 0.5), j0 = (int)std::floor(ry - 0.5);
+        struct Pt { long cell; double x, y; bool rho_ok; };
+        auto gather = [&](int grow, std::vector<Pt>& pts) {
+            pts.clear();
+            for (int dj = -grow; dj <= 1 + grow; ++dj)
+                for (int di = -grow; di <= 1 + grow; ++di) {
+                    const int gi = i0 + di, gj = j0 + dj;
+                    int gis = gi;
+                    if (perx) gis = ((gi % nxd) + nxd) % nxd;
+                    if (L.l == 0 && (gj < 0 || gj >= nyd)) continue;
+                    const long k = L.idx(gis, gj);
+                    if (k < 0) continue;
+                    const int t = L.flag[k] & F_TYPE;
+                    if (t == T_FLUID)
+                        pts.push_back({k, gi + 0.5, gj + 0.5, L.bidx[k] < 0});
+                    else if (t != T_SOLID)
+                        return false;
+                }
+            return true;
+        };
+        std::vector<Pt> pts;
+        std::vector<double> w_rho, w_u;
+        std::vector<long> cells;
+        bool rho_done = false, u_done = false;
+        std::vector<std::pair<long, double>> rw, uw;
+        for (int grow = 0; grow <= 1 && !(rho_done && u_done); ++grow) {
+            if (!gather(grow, pts))
+                return set_err(c, LBR_ERR_GEOMETRY, "level %d: wall stencil reaches a non-owned cell", L.l);
+            if (!rho_done) {
+                double sw = 0;
+                rw.clear();
+                for (const Pt& p : pts) {
+                    if (!p.rho_ok) continue;
+                    const double d2 = (p.x - rx) * (p.x - rx) + (p.y - ry) * (p.y - ry);
+                    if (d2 < 1e-24) { rw.assign(1, {p.cell, 1.0}); sw = 1.0; break; }
+                    rw.push_back({p.cell, 1.0 / d2});
+                    sw += 1.0 / d2;
+                }
+                if (!rw.empty()) {
+                    for (auto& e : rw) e.second /= sw;
+                    rho_done = true;
+                }
+            }
+            if (!u_done && pts.size() >= 3) {
+                double A[3][3] = {{0}};
+                for (const Pt& p : pts) {
+                    const double r[3] = {1.0, p.x - rx, p.y - ry};
+                    for (int a = 0; a < 3; ++a)
+                        for (int b2 = 0; b2 < 3; ++b2) A[a][b2] += r[a] * r[b2];
+                }
+                const double det = A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) -
+                                   A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
+                                   A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+                if (std::fabs(det) >= 1e-9) {
+                    // first row of A^-1 (cofactors / det)
+                    const double r0[3] = {(A[1][1] * A[2][2] - A[1][2] * A[2][1]) / det,
+                                          -(A[0][1] * A[2][2] - A[0][2] * A[2][1]) / det,
+                                          (A[0][1] * A[1][2] - A[0][2] * A[1][1]) / det};
+                    uw.clear();
+                    for (const Pt& p : pts)
+                        uw.push_back({p.cell, r0[0] + r0[1] * (p.x - rx) + r0[2] * (p.y - ry)});
+                    u_done = true;
+                }
+            }
+        }
+        if (!rho_done) rw.assign(1, {nd.cell, 1.0});
+        if (!u_done) uw.assign(1, {nd.cell, 1.0});
+        // merge into one list of cells
+        std::vector<long> cl;
+        for (auto& e : rw) cl.push_back(e.first);
+        for (auto& e : uw) cl.push_back(e.first);
+        std::sort(cl.begin(), cl.end());
+        cl.erase(std::unique(cl.begin(), cl.end()), cl.end());
+        if ((int)cl.size() > MAX_STENCIL) return set_err(c, LBR_ERR_GEOMETRY, "wall stencil too large");
+        for (size_t j = 0; j < cl.size(); ++j) {
+            sc[(size_t)b * MAX_STENCIL + j] = (int32_t)cl[j];
+            for (auto& e : rw) if (e.first == cl[j]) wr[(size_t)b * MAX_STENCIL + j] += e.second;
+            for (auto& e : uw) if (e.first == cl[j]) wu[(size_t)b * MAX_STENCIL + j] += e.second;
+        }
+    }
+    return 0;
+}
+
+void make_tiles(Level& L) {
+    L.tiles.clear();
+    const int ntx = L.box.pitch / TILE_X, nty = L.box.ny / TILE_Y;
+    for (int ty = 0; ty < nty; ++ty)
+        for (int tx = 0; tx < ntx; ++tx) {
+            bool act = false;
+            for (int y = 0; y < TILE_Y && !act; ++y)
+                for (int x = 0; x < TILE_X && !act; ++x) {
+                    const int t = L.flag[(long)(ty * TILE_Y + y) * L.box.pitch + tx * TILE_X + x] & F_TYPE;
+                    act = (t == T_FLUID || t == T_GHOST);
+                }
+            if (act) L.tiles.push_back((uint32_t)tx | ((uint32_t)ty << 16));
+        }
+}
+
+int alloc_level(lbr_ctx* c, Level& L) {
+    const size_t n = L.box.plane;
+    for (int b = 0; b < 2; ++b) {
+        L.f[b] = dalloc(c, 9 * n * c->ssize);
+        L.mac[b] = dalloc(c, 3 * n * c->csize);
+        L.chi[b] = dalloc(c, n * c->csize);
+        if (!L.f[b] || !L.mac[b] || !L.chi[b]) return set_err(c, LBR_ERR_OOM, "level %d: out of device memory", L.l);
+        HIPCHK(c, hipMemsetAsync(L.f[b], 0, 9 * n * c->ssize, c->stream));
+        HIPCHK(c, hipMemsetAsync(L.mac[b], 0, 3 * n * c->csize, c->stream));
+        HIPCHK(c, hipMemsetAsync(L.chi[b], 0, n * c->csize, c->stream));
+    }
+    L.bytes += 2 * n * (9 * c->ssize + 4 * c->csize);
+    std::vector<double> dclamp(L.d);
+    if (c->prec != P_F64)
+        for (double& v : dclamp) v = std::min(v, 1e18);
+    if (int r = upload(c, &L.dist_dev, dclamp, &L.bytes)) return r;
+    if (int r = upload(c, &L.flag_dev, L.flag, &L.bytes)) return r;
+    if (int r = upload(c, &L.bidx_dev, L.bidx, &L.bytes)) return r;
+    if (int r = upload(c, &L.tiles_dev, L.tiles, &L.bytes)) return r;
+    if (int r = upload(c, &L.ghosts_dev, L.ghosts, &L.bytes)) return r;
+    if (int r = upload(c, &L.covb_dev, L.covb, &L.bytes)) return r;
+    if (int r = upload(c, &L.owned_dev, L.owned, &L.bytes)) return r;
+    L.snap = static_cast<double*>(dalloc(c, std::max<size_t>(L.owned.size(), 1) * 2 * sizeof(double)));
+    // wall records
+    const int nb = (int)L.nodes.size();
+    std::vector<int32_t> bcell(nb);
+    std::vector<double> geo((size_t)nb * 6), qd((size_t)nb * 8);
+    for (int b = 0; b < nb; ++b) {
+        const Node& nd = L.nodes[b];
+        bcell[b] = (int32_t)nd.cell;
+        geo[6 * b + 0] = nd.iw[0]; geo[6 * b + 1] = nd.iw[1];
+        geo[6 * b + 2] = nd.nrm[0]; geo[6 * b + 3] = nd.nrm[1];
+        geo[6 * b + 4] = nd.dwb; geo[6 * b + 5] = nd.body;
+        for (int o = 1; o < 9; ++o) qd[8 * b + o - 1] = nd.q[o];
+    }
+    if (int r = upload(c, &L.bcell, bcell, &L.bytes)) return r;
+    if (int r = upload(c, &L.bgeo, geo, &L.bytes)) return r;
+    if (c->prec == P_F64) {
+        double* p;
+        if (int r = upload(c, &p, qd, &L.bytes)) return r;
+        L.bq = p;
+    } else {
+        std::vector<float> qf(qd.begin(), qd.end());
+        float* p;
+        if (int r = upload(c, &p, qf, &L.bytes)) return r;
+        L.bq = p;
+    }
+    L.bw = dalloc(c, std::max(nb, 1) * 4 * c->csize);
+    L.bstate = static_cast<double*>(dalloc(c, std::max(nb, 1) * 8 * sizeof(double)));
+    if (!L.bw || !L.bstate) return set_err(c, LBR_ERR_OOM, "wall state allocation failed");
+    HIPCHK(c, hipMemsetAsync(L.bw, 0, std::max(nb, 1) * 4 * c->csize, c->stream));
+    HIPCHK(c, hipMemsetAsync(L.bstate, 0, std::max(nb, 1) * 8 * sizeof(double), c->stream));
+    std::vector<int32_t> sc;
+    std::vector<double> wr, wu;
+    if (int r = stencils(c, L, sc, wr, wu)) return r;
+    if (int r = upload(c, &L.st_cell, sc, &L.bytes)) return r;
+    if (int r = upload(c, &L.st_wr, wr, &L.bytes)) return r;
+    if (int r = upload(c, &L.st_wu, wu, &L.bytes)) return r;
+    return 0;
+}
+
+template <class ST, class CT>
+void fill_step_args(lbr_ctx* c, int l, int substep, StepArgs<ST, CT>& a) {
+    Level& L = c->lv[l];
+    const lbr_config& cfg = c->cfg;
+    a.fsrc = (const ST*)L.f[L.cur];
+    a.fdst = (ST*)L.f[1 - L.cur];
+    a.msrc = (const CT*)L.mac[L.cur];
+    a.mdst = (CT*)L.mac[1 - L.cur];
+    a.csrc = (const CT*)L.chi[L.cur];
+    a.cdst = (CT*)L.chi[1 - L.cur];
+    a.dist = L.dist_dev;
+    a.flag = L.flag_dev;
+    a.bidx = L.bidx_dev;
+    a.bq = (const CT*)L.bq;
+    a.bw = (const CT*)L.bw;
+    a.tiles = L.tiles_dev;
+    a.ntiles = (int)L.tiles.size();
+    a.box = L.box;
+    a.dom.nxd = cfg.nx0 << l;
+    a.dom.nyd = cfg.ny0 << l;
+    for (int k = 0; k < 4; ++k) a.dom.bc[k] = cfg.bc[k];
+    a.dom.periodic_x = cfg.bc[0] == LBR_BC_PERIODIC;
+    a.nu = (CT)L.nu;
+    a.fx = (CT)L.fx;
+    a.fy = (CT)L.fy;
+    a.omega_b = (CT)cfg.omega_b;
+    a.u_in = (CT)c->u_ref;
+    a.chi_in = (CT)cfg.chi_inlet;
+    a.sa_mode = cfg.sa;
+    a.frozen = cfg.sa == LBR_SA_FROZEN;
+    a.bb_halfway = cfg.bb == LBR_BB_HALFWAY;
+    a.substep = substep;
+    if (l > 0) {
+        Level& P = c->lv[l - 1];
+        a.fcoarse = (const ST*)P.f[P.cur];
+        a.cbox = P.box;
+    } else {
+        a.fcoarse = nullptr;
+        a.cbox = Box{};
+    }
+    if (l + 1 < (int)c->lv.size()) {
+        Level& F = c->lv[l + 1];
+        a.ffine = (const ST*)F.f[F.cur];
+        a.fbox = F.box;
+    } else {
+        a.ffine = nullptr;
+        a.fbox = Box{};
+    }
+}
+
+template <class ST, class CT>
+void fill_wall_args(lbr_ctx* c, int l, WallArgs<ST, CT>& a) {
+    Level& L = c->lv[l];
+    const lbr_config& cfg = c->cfg;
+    a.nb = (int)L.nodes.size();
+    a.cell = L.bcell;
+    a.geo = L.bgeo;
+    a.st_cell = L.st_cell;
+    a.st_wr = L.st_wr;
+    a.st_wu = L.st_wu;
+    a.mac = (const CT*)L.mac[L.cur];
+    a.chi_next = (CT*)L.chi[1 - L.cur];
+    a.bw = (CT*)L.bw;
+    a.state = L.bstate;
+    a.plane = L.box.plane;
+    a.nu = L.nu;
+    a.d_wr = cfg.wall_model == LBR_WALL_NISHIMURA ? 1.75 : cfg.d_wr;
+    a.d_wv = cfg.d_wv;
+    a.uw_lo[0] = cfg.u_wall[0]; a.uw_lo[1] = cfg.u_wall[1];
+    a.uw_hi[0] = cfg.u_wall[2]; a.uw_hi[1] = cfg.u_wall[3];
+    a.model = cfg.wall_model;
+    a.write_chi = cfg.sa != LBR_SA_FROZEN;
+}
+
+enum { EV_STEP = 0, EV_STEP_FINE = 1, EV_WALL = 2, EV_XFER = 3 };
+
+hipEvent_t prof_begin(lbr_ctx* c) {
+    if (!c->prof) return nullptr;
+    while (c->ev.size() < c->ev_used + 2) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        c->ev.push_back(e);
+        c->ev_kind.push_back(0);
+    }
+    hipEvent_t e = c->ev[c->ev_used];
+    (void)hipEventRecord(e, c->stream);
+    return e;
+}
+
+void prof_end(lbr_ctx* c, hipEvent_t start, int kind) {
+    if (!c->prof || !start) return;
+    hipEvent_t e = c->ev[c->ev_used + 1];
+    (void)hipEventRecord(e, c->stream);
+    c->ev_kind[c->ev_used] = kind;
+    c->ev_used += 2;
+}
+
+int do_step(lbr_ctx* c, int l, int substep) {
+    Level& L = c->lv[l];
+    alignas(16) unsigned char buf[sizeof(StepArgs<double, double>)];
+    switch (c->prec) {
+        case P_F64: fill_step_args(c, l, substep, *reinterpret_cast<StepArgs<double, double>*>(buf)); break;
+        case P_F32: fill_step_args(c, l, substep, *reinterpret_cast<StepArgs<float, float>*>(buf)); break;
+        case P_F16: fill_step_args(c, l, substep, *reinterpret_cast<StepArgs<__half, float>*>(buf)); break;
+        default: fill_step_args(c, l, substep, *reinterpret_cast<StepArgs<__hip_bfloat16, float>*>(buf)); break;
+    }
+    hipEvent_t e = prof_begin(c);
+    HIPCHK(c, launch_step(c->prec, buf, c->stream));
+    prof_end(c, e, l + 1 == (int)c->lv.size() ? EV_STEP_FINE : EV_STEP);
+    L.cur ^= 1;
+    if (!L.nodes.empty()) {
+        alignas(16) unsigned char wb[sizeof(WallArgs<double, double>)];
+        switch (c->prec) {
+            case P_F64: fill_wall_args(c, l, *reinterpret_cast<WallArgs<double, double>*>(wb)); break;
+            case P_F32: fill_wall_args(c, l, *reinterpret_cast<WallArgs<float, float>*>(wb)); break;
+            case P_F16: fill_wall_args(c, l, *reinterpret_cast<WallArgs<__half, float>*>(wb)); break;
+            default: fill_wall_args(c, l, *reinterpret_cast<WallArgs<__hip_bfloat16, float>*>(wb)); break;
+        }
+        hipEvent_t e2 = prof_begin(c);
+        HIPCHK(c, launch_wall(c->prec, wb, c->stream));
+        prof_end(c, e2, EV_WALL);
+    }
+    return 0;
+}
+
+int do_transfers(lbr_ctx* c, int l) {
+    Level& C = c->lv[l];
+    Level& F = c->lv[l + 1];
+    hipEvent_t e = prof_begin(c);
+    RestrictArgs r{};
+    r.n = (int)C.covb.size();
+    r.list = C.covb_dev;
+    r.fbox = F.box;
+    r.cbox = C.box;
+    r.fmac = F.mac[F.cur];
+    r.fchi = F.chi[F.cur];
+    r.cmac = C.mac[C.cur];
+    r.cchi = C.chi[C.cur];
+    HIPCHK(c, launch_restrict(c->prec, r, c->stream));
+    FillArgs f{};
+    f.n = (int)F.ghosts.size();
+    f.list = F.ghosts_dev;
+    f.fbox = F.box;
+    f.cbox = C.box;
+    f.cmac = C.mac[C.cur];
+    f.cchi = C.chi[C.cur];
+    f.fmac0 = F.mac[0]; f.fmac1 = F.mac[1];
+    f.fchi0 = F.chi[0]; f.fchi1 = F.chi[1];
+    HIPCHK(c, launch_fill(c->prec, f, c->stream));
+    prof_end(c, e, EV_XFER);
+    return 0;
+}
+
+// Recursive cycle of Section 2.1: the finer level takes two sub-steps, then
+// this level streams (pulling the coalesced band of the finer level) and
+// collides.
+int cycle(lbr_ctx* c, int l, int substep) {
+    if (l + 1 < (int)c->lv.size()) {
+        if (int r = do_transfers(c, l)) return r;
+        if (int r = cycle(c, l + 1, 1)) return r;
+        if (int r = cycle(c, l + 1, 2)) return r;
+    }
+    return do_step(c, l, substep);
+}
+
+int init_level(lbr_ctx* c, int l, const double* rho, const double* ux, const double* uy,
+               const double* chi) {
+    Level& L = c->lv[l];
+    const size_t n = L.owned.size();
+    std::vector<double> v(4 * n);
+    for (size_t k = 0; k < n; ++k) {
+        const long cell = L.owned[k];
+        const int gx = (int)(cell % L.box.pitch) + L.box.gx0, gy = (int)(cell / L.box.pitch) + L.box.gy0;
+        const long io = (long)(gy - L.by0) * L.bnx + (gx - L.bx0);
+        v[k] = rho ? rho[io] : c->cfg.rho_ref;
+        v[n + k] = ux ? ux[io] : c->u_ref;
+        v[2 * n + k] = uy ? uy[io] : 0.0;
+        v[3 * n + k] = chi ? chi[io] : c->cfg.chi_init;
+    }
+    double* dv = static_cast<double*>(dalloc(c, std::max<size_t>(v.size(), 4) * sizeof(double)));
+    if (!dv) return set_err(c, LBR_ERR_OOM, "init staging allocation failed");
+    if (n) HIPCHK(c, hipMemcpyAsync(dv, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    InitArgs a{};
+    a.n = (int)n;
+    a.list = L.owned_dev;
+    a.rho = dv; a.ux = dv + n; a.uy = dv + 2 * n; a.chi = dv + 3 * n;
+    a.f = L.f[L.cur];
+    a.mac = L.mac[L.cur];
+    a.chi_a = L.chi[0];
+    a.chi_b = L.chi[1];
+    a.plane = L.box.plane;
+    a.nu = L.nu; a.fx = L.fx; a.fy = L.fy; a.omega_b = c->cfg.omega_b;
+    HIPCHK(c, launch_init(c->prec, a, c->stream));
+    HIPCHK(c, hipMemsetAsync(L.bstate, 0, std::max<size_t>(L.nodes.size(), 1) * 8 * sizeof(double), c->stream));
+    if (!L.nodes.empty()) {
+        alignas(16) unsigned char wb[sizeof(WallArgs<double, double>)];
+        switch (c->prec) {
+            case P_F64: fill_wall_args(c, l, *reinterpret_cast<WallArgs<double, double>*>(wb)); break;
+            case P_F32: fill_wall_args(c, l, *reinterpret_cast<WallArgs<float, float>*>(wb)); break;
+            case P_F16: fill_wall_args(c, l, *reinterpret_cast<WallArgs<__half, float>*>(wb)); break;
+            default: fill_wall_args(c, l, *reinterpret_cast<WallArgs<__hip_bfloat16, float>*>(wb)); break;
+        }
+        HIPCHK(c, launch_wall(c->prec, wb, c->stream));
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    dfree(c, dv);
+    return 0;
+}
+
+int build_surface(lbr_ctx* c, const std::vector<double>& seg) {
+    c->surf.assign(c->npts.size(), SurfaceBody());
+    c->wall_level = -1;
+    for (int l = (int)c->lv.size() - 1; l >= 0; --l)
+        if (!c->lv[l].nodes.empty()) { c->wall_level = l; break; }
+    if (c->wall_level < 0 || c->cfg.body_mode != LBR_BODY_SOLID) return 0;
+    const Level& L = c->lv[c->wall_level];
+    int maxseg = 0;
+    for (size_t b = 0; b < c->npts.size(); ++b) {
+        const int n = c->npts[b];
+        maxseg = std::max(maxseg, n);
+        std::vector<double> sg((size_t)n * 6);
+        std::vector<int32_t> near((size_t)n * 2, -1);
+        std::vector<double> wgt((size_t)n * 2, 0.0);
+        for (int k = 0; k < n; ++k) {
+            const double* s = &seg[5 * (c->off[b] + k)];
+            const double ax = s[0] * L.scale, ay = s[1] * L.scale, bx = s[2] * L.scale, by = s[3] * L.scale;
+            const double mx = 0.5 * (ax + bx), my = 0.5 * (ay + by);
+            double tx = bx - ax, ty = by - ay;
+            const double tl = std::sqrt(tx * tx + ty * ty);
+            tx /= tl; ty /= tl;
+            sg[6 * k + 0] = tx; sg[6 * k + 1] = ty;
+            sg[6 * k + 2] = ty; sg[6 * k + 3] = -tx;          // normal into the fluid
+            sg[6 * k + 4] = tl / L.scale * c->cfg.dx0 / c->cfg.ref_length;   // ds / c
+            int best[2] = {-1, -1};
+            double bd[2] = {1e300, 1e300};
+            for (size_t j = 0; j < L.nodes.size(); ++j) {
+                if (L.nodes[j].body != (int)b) continue;
+                const double dd = (L.nodes[j].iw[0] - mx) * (L.nodes[j].iw[0] - mx) +
+                                  (L.nodes[j].iw[1] - my) * (L.nodes[j].iw[1] - my);
+                if (dd < bd[0]) { bd[1] = bd[0]; best[1] = best[0]; bd[0] = dd; best[0] = (int)j; }
+                else if (dd < bd[1]) { bd[1] = dd; best[1] = (int)j; }
+            }
+            if (best[0] >= 0 && bd[0] < 1e-24) {
+                near[2 * k] = best[0];
+                wgt[2 * k] = 1.0;
+            } else {
+                for (int m = 0; m < 2; ++m)
+                    if (best[m] >= 0) { near[2 * k + m] = best[m]; wgt[2 * k + m] = 1.0 / bd[m]; }
+            }
+        }
+        SurfaceBody& sb = c->surf[b];
+        sb.nseg = n;
+        if (int r = upload(c, &sb.seg, sg, nullptr)) return r;
+        if (int r = upload(c, &sb.near, near, nullptr)) return r;
+        if (int r = upload(c, &sb.wgt, wgt, nullptr)) return r;
+    }
+    c->surf_cp = static_cast<double*>(dalloc(c, (size_t)maxseg * sizeof(double)));
+    c->surf_cf = static_cast<double*>(dalloc(c, (size_t)maxseg * sizeof(double)));
+    c->partial_n = std::max(1, (maxseg + 255) / 256);
+    size_t need = 0;
+    for (const Level& Lv : c->lv) need = std::max(need, (Lv.owned.size() + 255) / 256);
+    c->partial_n = std::max<int>(c->partial_n, (int)need);
+    c->partial = static_cast<double*>(dalloc(c, (size_t)c->partial_n * 4 * sizeof(double)));
+    if (!c->surf_cp || !c->surf_cf || !c->partial) return set_err(c, LBR_ERR_OOM, "surface buffers");
+    return 0;
+}
+
+int surface_eval(lbr_ctx* c, int body, double* cp, double* cf, double sums[4]) {
+    const SurfaceBody& sb = c->surf[body];
+    const Level& L = c->lv[c->wall_level];
+    SurfaceArgs a{};
+    a.nseg = sb.nseg;
+    a.seg = sb.seg;
+    a.near = sb.near;
+    a.wgt = sb.wgt;
+    a.bstate = L.bstate;
+    a.bw = L.bw;
+    a.u_ref = c->u_ref;
+    a.rho_ref = c->cfg.rho_ref;
+    a.cp = c->surf_cp;
+    a.cf = c->surf_cf;
+    a.partial = c->partial;
+    const int nb = (sb.nseg + 255) / 256;
+    HIPCHK(c, launch_surface(c->prec, a, nb, c->stream));
+    std::vector<double> part((size_t)nb * 4);
+    HIPCHK(c, hipMemcpyAsync(part.data(), c->partial, part.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    if (cp) HIPCHK(c, hipMemcpyAsync(cp, c->surf_cp, sb.nseg * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    if (cf) HIPCHK(c, hipMemcpyAsync(cf, c->surf_cf, sb.nseg * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int f = 0; f < 4; ++f) {
+        double s = 0.0;
+        for (int k = 0; k < nb; ++k) s += part[4 * k + f];
+        sums[f] = s;
+    }
+    return 0;
+}
+
+int capture_graph(lbr_ctx* c) {
+    if (c->graph) { (void)hipGraphExecDestroy(c->graph); c->graph = nullptr; }
+    // level 0 takes one step per coarse step, so two coarse steps bring every
+    // level back to the same buffer parity
+    c->graph_steps = 2;
+    const bool prof = c->prof;
+    c->prof = false;
+    hipGraph_t g;
+    HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    int r = 0;
+    for (int k = 0; k < c->graph_steps && !r; ++k) r = cycle(c, 0, 0);
+    hipError_t e = hipStreamEndCapture(c->stream, &g);
+    c->prof = prof;
+    if (r) return r;
+    if (e != hipSuccess) return set_err(c, LBR_ERR_HIP, "graph capture: %s", hipGetErrorString(e));
+    // capture advanced the buffer indices without running: undo
+    for (Level& L : c->lv) L.cur ^= (c->graph_steps << L.l) & 1;
+    e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return set_err(c, LBR_ERR_HIP, "graph instantiate: %s", hipGetErrorString(e));
+    return 0;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C entry points
+// ===========================================================================
+extern "C" {
+
+int lbr_create(const lbr_config* cfg, lbr_ctx** out) {
+    if (!out) return LBR_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!cfg || cfg->version != LBR_ABI_VERSION) return LBR_ERR_INVALID_ARG;
+    if (cfg->n_levels < 1 || cfg->n_levels > LBR_MAX_LEVELS || cfg->nx0 < 4 || cfg->ny0 < 4 ||
+        !(cfg->dx0 > 0) || cfg->storage < 0 || cfg->storage > 3)
+        return LBR_ERR_INVALID_ARG;
+    if ((cfg->bc[0] == LBR_BC_PERIODIC) != (cfg->bc[1] == LBR_BC_PERIODIC) ||
+        (cfg->bc[2] == LBR_BC_PERIODIC) != (cfg->bc[3] == LBR_BC_PERIODIC) ||
+        cfg->bc[0] == LBR_BC_WALL || cfg->bc[1] == LBR_BC_WALL)
+        return LBR_ERR_INVALID_ARG;
+    if ((long)cfg->nx0 << (cfg->n_levels - 1) > (1L << 28)) return LBR_ERR_INVALID_ARG;
+    lbr_ctx* c = new lbr_ctx();
+    c->cfg = *cfg;
+    c->stream = static_cast<hipStream_t>(cfg->stream);
+    c->prec = static_cast<Prec>(cfg->storage);
+    c->ssize = cfg->storage == LBR_STORE_F64 ? 8 : (cfg->storage == LBR_STORE_F32 ? 4 : 2);
+    c->csize = cfg->storage == LBR_STORE_F64 ? 8 : 4;
+    c->u_ref = cfg->u_ref > 0 ? cfg->u_ref : cfg->mach * std::sqrt(1.0 / 3.0);
+    c->nu0 = cfg->nu0 > 0 ? cfg->nu0 : c->u_ref * (cfg->ref_length / cfg->dx0) / cfg->reynolds;
+    if (!(c->nu0 > 0) || !std::isfinite(c->nu0)) {
+        delete c;
+        return LBR_ERR_INVALID_ARG;
+    }
+    c->wall_lat[0] = (cfg->wall_y[0] - cfg->origin[1]) / cfg->dx0;
+    c->wall_lat[1] = (cfg->wall_y[1] - cfg->origin[1]) / cfg->dx0;
+    *out = c;
+    return LBR_OK;
+}
+
+int lbr_set_geometry(lbr_ctx* c, int32_t n_bodies, const int32_t* n_pts, const double* xy) {
+    if (!c) return LBR_ERR_INVALID_ARG;
+    if (c->built) return set_err(c, LBR_ERR_STATE, "geometry must be set before lbr_build");
+    if (n_bodies < 0 || (n_bodies > 0 && (!n_pts || !xy)))
+        return set_err(c, LBR_ERR_INVALID_ARG, "invalid geometry arguments");
+    c->npts.clear();
+    c->off.assign(1, 0);
+    c->polyflat.clear();
+    const double* p = xy;
+    for (int b = 0; b < n_bodies; ++b) {
+        if (n_pts[b] < 3) return set_err(c, LBR_ERR_GEOMETRY, "body %d has fewer than 3 points", b);
+        for (int k = 0; k < n_pts[b]; ++k) {
+            const double x = (p[2 * k] - c->cfg.origin[0]) / c->cfg.dx0;
+            const double y = (p[2 * k + 1] - c->cfg.origin[1]) / c->cfg.dx0;
+            if (!std::isfinite(x) || !std::isfinite(y))
+                return set_err(c, LBR_ERR_GEOMETRY, "body %d has a non-finite point", b);
+            c->polyflat.push_back(x);
+            c->polyflat.push_back(y);
+        }
+        p += 2 * n_pts[b];
+        c->npts.push_back(n_pts[b]);
+        c->off.push_back(c->off.back() + n_pts[b]);
+    }
+    return LBR_OK;
+}
+
+int lbr_build(lbr_ctx* c) {
+    if (!c) return LBR_ERR_INVALID_ARG;
+    if (c->built) return set_err(c, LBR_ERR_STATE, "already built");
+    // segment table: ax, ay, bx, by, body (level-0 lattice units)
+    std::vector<double> seg;
+    for (size_t b = 0; b < c->npts.size(); ++b) {
+        const int n = c->npts[b], o = c->off[b];
+        for (int k = 0; k < n; ++k) {
+            const int k1 = (k + 1) % n;
+            seg.insert(seg.end(), {c->polyflat[2 * (o + k)], c->polyflat[2 * (o + k) + 1],
+                                   c->polyflat[2 * (o + k1)], c->polyflat[2 * (o + k1) + 1], (double)b});
+        }
+    }
+    double* poly_dev = nullptr;
+    int* off_dev = nullptr;
+    std::vector<double> pf = c->polyflat;
+    if (pf.empty()) pf.assign(2, 0.0);
+    std::vector<int> of = c->off;
+    if (int r = upload(c, &poly_dev, pf, nullptr)) return r;
+    if (int r = upload(c, &off_dev, of, nullptr)) return r;
+    if (int r = build_levels(c, poly_dev, off_dev)) return r;
+    if (int r = check_levels(c)) return r;
+    for (Level& L : c->lv) finish_level(c, L);
+    for (Level& L : c->lv)
+        if (int r = build_walls(c, L, seg)) return r;
+    for (Level& L : c->lv) {
+        make_tiles(L);
+        if (int r = alloc_level(c, L)) return r;
+        L.dbody.clear();
+        L.dbody.shrink_to_fit();
+        L.inside.clear();
+        L.inside.shrink_to_fit();
+    }
+    if (int r = build_surface(c, seg)) return r;
+    c->built = true;
+    for (int l = 0; l < (int)c->lv.size(); ++l)
+        if (int r = init_level(c, l, nullptr, nullptr, nullptr, nullptr)) return r;
+    return LBR_OK;
+}
+
+int lbr_level_info(lbr_ctx* c, int32_t level, lbr_level_desc* out) {
+    if (!c || !out) return LBR_ERR_INVALID_ARG;
+    if (!c->built || level < 0 || level >= (int)c->lv.size())
+        return set_err(c, LBR_ERR_INVALID_ARG, "bad level %d", level);
+    const Level& L = c->lv[level];
+    out->gx0 = L.bx0; out->gy0 = L.by0; out->nx = L.bnx; out->ny = L.bny;
+    out->n_fluid = L.n_fluid;
+    out->n_wall_nodes = (int64_t)L.nodes.size();
+    out->n_cut_links = L.n_cut;
+    out->n_ghost = L.n_ghost;
+    out->n_tiles = (int64_t)L.tiles.size();
+    out->bytes = (int64_t)L.bytes;
+    return LBR_OK;
+}
+
+int lbr_init_fields(lbr_ctx* c, int32_t level, const double* rho, const double* ux,
+                    const double* uy, const double* chi) {
+    if (!c) return LBR_ERR_INVALID_ARG;
+    if (!c->built || level < 0 || level >= (int)c->lv.size())
+        return set_err(c, LBR_ERR_INVALID_ARG, "bad level %d", level);
+    return init_level(c, level, rho, ux, uy, chi);
+}
+
+int lbr_advance(lbr_ctx* c, int64_t n) {
+    if (!c) return LBR_ERR_INVALID_ARG;
+    if (!c->built) return set_err(c, LBR_ERR_STATE, "lbr_build has not been called");
+    if (n < 0) return set_err(c, LBR_ERR_INVALID_ARG, "negative step count");
+    c->ev_used = 0;
+    int64_t k = 0;
+    if (c->use_graph && !c->prof) {
+        if (!c->graph)
+            if (int r = capture_graph(c)) return r;
+        for (; k + c->graph_steps <= n; k += c->graph_steps) {
+            HIPCHK(c, hipGraphLaunch(c->graph, c->stream));
+            for (Level& L : c->lv) L.cur ^= (c->graph_steps << L.l) & 1;
+        }
+    }
+    for (; k < n; ++k)
+        if (int r = cycle(c, 0, 0)) return r;
+    c->resid_steps += n;
+    if (c->prof && c->ev_used) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        double sum[4] = {0, 0, 0, 0};
+        int cnt[4] = {0, 0, 0, 0};
+        for (size_t i = 0; i + 1 < c->ev_used; i += 2) {
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]);
+            const int kind = c->ev_kind[i];
+            sum[kind] += ms;
+            cnt[kind]++;
+            if (kind == EV_STEP_FINE) { sum[EV_STEP] += ms; cnt[EV_STEP]++; }
+        }
+        for (int f = 0; f < 4; ++f) c->prof_out[f] = cnt[f] ? 1000.0 * sum[f] / cnt[f] : 0.0;
+    }
+    return LBR_OK;
+}
+
+int lbr_synchronize(lbr_ctx* c) {
+    if (!c) return LBR_ERR_INVALID_ARG;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LBR_OK;
+}
+
+int lbr_read_field(lbr_ctx* c, int32_t level, int32_t field, double* dst) {
+    if (!c || !dst) return LBR_ERR_INVALID_ARG;
+    if (!c->built || level < 0 || level >= (int)c->lv.size())
+        return set_err(c, LBR_ERR_INVALID_ARG, "bad level %d", level);
+    if (field < 0 || field > LBR_FIELD_DIST) return set_err(c, LBR_ERR_INVALID_ARG, "bad field %d", field);
+    Level& L = c->lv[level];
+    const long n = L.box.plane;
+    std::vector<double> v;
+    if (field == LBR_FIELD_RHO || field == LBR_FIELD_UX || field == LBR_FIELD_UY ||
+        field == LBR_FIELD_CHI || field == LBR_FIELD_NUT) {
+        const void* src = nullptr;
+        if (field == LBR_FIELD_CHI || field == LBR_FIELD_NUT) src = L.chi[L.cur];
+        else src = static_cast<const char*>(L.mac[L.cur]) + (size_t)field * n * c->csize;
+        double* tmp = static_cast<double*>(dalloc(c, n * sizeof(double)));
+        if (!tmp) return set_err(c, LBR_ERR_OOM, "readout scratch");
+        HIPCHK(c, launch_to_double(c->prec, src, tmp, n, c->stream));
+        v.resize(n);
+        HIPCHK(c, hipMemcpyAsync(v.data(), tmp, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        dfree(c, tmp);
+    } else {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    const double cv3 = 7.1 * 7.1 * 7.1;
+    for (int j = 0; j < L.bny; ++j)
+        for (int i = 0; i < L.bnx; ++i) {
+            const long k = L.idx(L.bx0 + i, L.by0 + j);
+            double& o = dst[(long)j * L.bnx + i];
+            const int t = L.flag[k] & F_TYPE;
+            if (field == LBR_FIELD_TYPE) { o = t; continue; }
+            if (t != T_FLUID) { o = NAN; continue; }
+            if (field == LBR_FIELD_DIST) { o = L.d[k]; continue; }
+            if (field == LBR_FIELD_NUT) {
+                const double x = v[k];
+                o = x > 0 ? L.nu * x * x * x * x / (x * x * x + cv3) : 0.0;
+                continue;
+            }
+            o = v[k];
+        }
+    return LBR_OK;
+}
+
+int lbr_wall_count(lbr_ctx* c, int32_t level) {
+    if (!c || !c->built || level < 0 || level >= (int)c->lv.size()) return LBR_ERR_INVALID_ARG;
+    return (int)c->lv[level].nodes.size();
+}
+
+int lbr_read_wall(lbr_ctx* c, int32_t level, double* dst) {
+    if (!c || !dst) return LBR_ERR_INVALID_ARG;
+    if (!c->built || level < 0 || level >= (int)c->lv.size())
+        return set_err(c, LBR_ERR_INVALID_ARG, "bad level %d", level);
+    Level& L = c->lv[level];
+    const int nb = (int)L.nodes.size();
+    if (nb == 0) return LBR_OK;
+    std::vector<double> st((size_t)nb * 8);
+    HIPCHK(c, hipMemcpyAsync(st.data(), L.bstate, st.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const double U = c->u_ref, rr = c->cfg.rho_ref;
+    for (int b = 0; b < nb; ++b) {
+        const Node& nd = L.nodes[b];
+        double* o = dst + (size_t)b * LBR_WALL_STRIDE;
+        int ncut = 0;
+        for (int i = 1; i < 9; ++i) ncut += nd.q[i] >= 0;
+        const double utau = st[8 * b], tx = st[8 * b + 1], ty = st[8 * b + 2], rhow = st[8 * b + 3];
+        const double uwx = st[8 * b + 4], uwy = st[8 * b + 5];
+        o[0] = nd.gi; o[1] = nd.gj; o[2] = nd.iw[0]; o[3] = nd.iw[1];
+        o[4] = nd.nrm[0]; o[5] = nd.nrm[1]; o[6] = nd.dwb; o[7] = ncut;
+        o[8] = utau; o[9] = uwx; o[10] = uwy; o[11] = rhow;
+        o[12] = std::sqrt(tx * tx + ty * ty);
+        o[13] = 2.0 / 3.0 * (rhow - rr) / (rr * U * U);
+        o[14] = 2.0 * (rhow / rr) * (utau / U) * (utau / U);
+        o[15] = nd.body;
+        o[16] = (c->cfg.wall_model == LBR_WALL_VN || c->cfg.wall_model == LBR_WALL_NISHIMURA)
+                    ? KAPPA_H * utau * nd.dwb / L.nu : 0.0;
+        o[17] = tx; o[18] = ty;
+        for (int i = 1; i < 9; ++i) o[18 + i] = nd.q[i];
+        o[27] = 0.0;
+    }
+    return LBR_OK;
+}
+
+int lbr_surface(lbr_ctx* c, int32_t body, double* cp, double* cf) {
+    if (!c || !c->built) return LBR_ERR_INVALID_ARG;
+    if (body < 0 || body >= (int)c->surf.size() || c->wall_level < 0)
+        return set_err(c, LBR_ERR_INVALID_ARG, "bad body %d", body);
+    double sums[4];
+    return surface_eval(c, body, cp, cf, sums);
+}
+
+int lbr_forces(lbr_ctx* c, int32_t body, double out[5]) {
+    if (!c || !c->built || !out) return LBR_ERR_INVALID_ARG;
+    if (body >= (int)c->surf.size() || c->wall_level < 0)
+        return set_err(c, LBR_ERR_INVALID_ARG, "bad body %d", body);
+    double acc[4] = {0, 0, 0, 0};
+    const int b0 = body < 0 ? 0 : body, b1 = body < 0 ? (int)c->surf.size() : body + 1;
+    for (int b = b0; b < b1; ++b) {
+        double s[4];
+        if (int r = surface_eval(c, b, nullptr, nullptr, s)) return r;
+        for (int f = 0; f < 4; ++f) acc[f] += s[f];
+    }
+    out[0] = acc[0];              // C_Df
+    out[1] = acc[2];              // C_Dp
+    out[2] = acc[0] + acc[2];     // C_D
+    out[3] = acc[3];              // C_L (pressure)
+    out[4] = acc[1];              // friction along y
+    return LBR_OK;
+}
+
+int lbr_residual(lbr_ctx* c, double* residual) {
+    if (!c || !c->built || !residual) return LBR_ERR_INVALID_ARG;
+    double du = 0.0, uu = 0.0;
+    for (Level& L : c->lv) {
+        const int n = (int)L.owned.size();
+        if (!n) continue;
+        const int nb = (n + 255) / 256;
+        const double area = 1.0 / (L.scale * L.scale);
+        HIPCHK(c, launch_residual(c->prec, L.mac[L.cur], L.snap, L.owned_dev, n, L.box.plane, area,
+                                  c->partial, nb, c->stream));
+        std::vector<double> part((size_t)nb * 2);
+        HIPCHK(c, hipMemcpyAsync(part.data(), c->partial, part.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        for (int k = 0; k < nb; ++k) { du += part[2 * k]; uu += part[2 * k + 1]; }
+    }
+    if (!c->resid_init || c->resid_steps == 0) {
+        *residual = 1.0;
+    } else {
+        *residual = std::sqrt(du / uu) / (double)c->resid_steps;
+    }
+    if (!std::isfinite(du) || !std::isfinite(uu))
+        return set_err(c, LBR_ERR_DIVERGED, "non-finite velocity field");
+    c->resid_init = true;
+    c->resid_steps = 0;
+    return LBR_OK;
+}
+
+int lbr_run_to_steady(lbr_ctx* c, double tol, int64_t max_steps, int64_t check_every,
+                      int64_t* steps_done, double* residual) {
+    if (!c || !c->built || check_every <= 0) return LBR_ERR_INVALID_ARG;
+    double r = 1.0;
+    if (int e = lbr_residual(c, &r)) return e;
+    int64_t done = 0;
+    while (done < max_steps) {
+        const int64_t k = std::min(check_every, max_steps - done);
+        if (int e = lbr_advance(c, k)) return e;
+        done += k;
+        if (int e = lbr_residual(c, &r)) {
+            if (steps_done) *steps_done = done;
+            if (residual) *residual = r;
+            return e;
+        }
+        if (r < tol) break;
+    }
+    if (steps_done) *steps_done = done;
+    if (residual) *residual = r;
+    return LBR_OK;
+}
+
+int64_t lbr_lups_per_coarse_step(lbr_ctx* c) {
+    if (!c || !c->built) return 0;
+    int64_t n = 0;
+    for (const Level& L : c->lv) n += L.n_fluid << L.l;
+    return n;
+}
+
+int lbr_use_graph(lbr_ctx* c, int32_t enable) {
+    if (!c) return LBR_ERR_INVALID_ARG;
+    c->use_graph = enable != 0;
+    if (!c->use_graph && c->graph) {
+        (void)hipGraphExecDestroy(c->graph);
+        c->graph = nullptr;
+    }
+    return LBR_OK;
+}
+
+int lbr_profile(lbr_ctx* c, int32_t enable, double out[4]) {
+    if (!c) return LBR_ERR_INVALID_ARG;
+    c->prof = enable != 0;
+    if (out)
+        for (int f = 0; f < 4; ++f) out[f] = c->prof_out[f];
+    return LBR_OK;
+}
+
+const char* lbr_last_error(const lbr_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+void lbr_destroy(lbr_ctx* c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    if (c->graph) (void)hipGraphExecDestroy(c->graph);
+    for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+    for (void* p : c->allocs) {
+        if (c->cfg.free_fn) c->cfg.free_fn(p, c->cfg.alloc_user);
+        else (void)hipFree(p);
+    }
+    delete c;
+}
+
+}  // extern "C"

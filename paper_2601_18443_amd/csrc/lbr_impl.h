@@ -1,0 +1,135 @@
+// Internal declarations of liblbr: device data layout, kernel argument blocks
+// and the launchers implemented in lbr_kernels.hip.
+#pragma once
+
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace lbr {
+
+// Cell flag byte: bits 0-2 hold the cell type, the others mark cells that
+// need more than the plain interior update.
+enum : uint8_t {
+    T_INACTIVE = 0, T_FLUID = 1, T_SOLID = 2, T_GHOST = 3, T_COVERED = 4,
+    F_TYPE = 7,
+    F_WALL = 8,         // boundary node B with cut links
+    F_IFACE = 16,       // coarse cell fed by coalescence of the finer level
+    F_NEARGHOST = 32,   // fine cell with a ghost neighbour
+    F_EDGE = 64,        // level-0 cell on the domain edge
+    F_COVB = 128,       // covered cell next to an owned cell (restriction target)
+};
+
+constexpr int TILE_X = 64;   // one wavefront per tile row
+constexpr int TILE_Y = 4;    // four wavefronts per 256-thread workgroup
+constexpr int MAX_STENCIL = 16;
+
+// Geometry of a level's storage box: global cell (gx, gy) of the level lives
+// at local (gx - gx0, gy - gy0), linear index ly * pitch + lx; every field is
+// a set of planes of `plane` elements.
+struct Box {
+    int gx0, gy0, pitch, ny;
+    long plane;
+};
+
+// Boundary-condition block of level 0 (all levels carry it; only level 0 has
+// F_EDGE cells).
+struct Domain {
+    int nxd, nyd;          // domain size in cells of this level
+    int bc[4];
+    int periodic_x;
+};
+
+template <class ST, class CT>
+struct StepArgs {
+    const ST* fsrc;  ST* fdst;       // 9 population planes (shifted by w_i)
+    const CT* msrc;  CT* mdst;       // 3 planes: rho, ux, uy
+    const CT* csrc;  CT* cdst;       // chi = nu~ / nu
+    const double* dist;              // wall distance (level lattice units)
+    const uint8_t* flag;
+    const int32_t* bidx;             // wall-node index of F_WALL cells
+    const CT* bq;                    // [nb][8] wall fraction q of links 1..8 (-1: not cut)
+    const CT* bw;                    // [nb][4] u_W (x, y), rho_W, unused
+    const uint32_t* tiles;           // active tiles, (tx | ty << 16)
+    int ntiles;
+    Box box;
+    Domain dom;
+    int gx_origin_unused;
+    CT nu, fx, fy, omega_b, u_in, chi_in;
+    int sa_mode, bb_halfway, frozen;
+    int substep;                     // 1 or 2 within the parent's step (0 on level 0)
+    const ST* fcoarse; Box cbox;     // parent level populations (ghost transfer)
+    const ST* ffine;   Box fbox;     // child level populations (coalescence)
+};
+
+template <class ST, class CT>
+struct WallArgs {
+    int nb;
+    const int32_t* cell;             // storage index of B
+    const double* geo;               // [nb][6] IW (x, y), n (x, y), d_WB, body
+    const int32_t* st_cell;          // [nb][MAX_STENCIL] storage index (-1 unused)
+    const double* st_wr;             // [nb][MAX_STENCIL] IDW weights for rho_R
+    const double* st_wu;             // [nb][MAX_STENCIL] LSQ weights for u_R
+    const CT* mac;                   // current macroscopic planes
+    CT* chi_next;                    // chi buffer the next step writes (Dirichlet at B)
+    CT* bw;                          // [nb][4]
+    double* state;                   // [nb][8] u_tau, u_Rt (x, y), rho_W, u_W (x, y), spare
+    long plane;
+    double nu, d_wr, d_wv, uw_lo[2], uw_hi[2];
+    int model, write_chi;
+};
+
+struct FillArgs {
+    int n; const int32_t* list;      // ghost cells of the fine level (storage index)
+    Box fbox, cbox;
+    const void* cmac; const void* cchi;  // coarse current
+    void* fmac0; void* fmac1; void* fchi0; void* fchi1;
+};
+
+struct RestrictArgs {
+    int n; const int32_t* list;      // F_COVB cells of the coarse level
+    Box fbox, cbox;
+    const void* fmac; const void* fchi;  // fine current
+    void* cmac; void* cchi;              // coarse current
+};
+
+struct InitArgs {
+    int n; const int32_t* list;      // owned fluid cells (storage index)
+    const double* rho; const double* ux; const double* uy; const double* chi;  // per listed cell
+    void* f; void* mac; void* chi_a; void* chi_b;
+    long plane;
+    double nu, fx, fy, omega_b;
+};
+
+struct SurfaceArgs {
+    int nseg;
+    const double* seg;               // [nseg][6]: t (x, y), n (x, y), ds, unused
+    const int32_t* near;             // [nseg][2] wall-node indices (-1 unused)
+    const double* wgt;               // [nseg][2] IDW weights
+    const double* bstate;            // wall-node state [nb][8]
+    const void* bw;                  // [nb][4] (CT)
+    double u_ref, rho_ref;
+    double* cp; double* cf;          // per segment
+    double* partial;                 // [nblocks][5]
+};
+
+// launchers (lbr_kernels.hip); `prec` selects the storage/compute pair
+enum Prec { P_F64 = 0, P_F32 = 1, P_F16 = 2, P_BF16 = 3 };
+
+hipError_t launch_geometry(int nx, int ny, int gx0, int gy0, double scale, int nbody,
+                           const int* npts_off, const double* poly, int solid,
+                           double* dist, uint8_t* inside, hipStream_t s);
+hipError_t launch_step(Prec p, const void* args, hipStream_t s);
+hipError_t launch_wall(Prec p, const void* args, hipStream_t s);
+hipError_t launch_fill(Prec p, const FillArgs& a, hipStream_t s);
+hipError_t launch_restrict(Prec p, const RestrictArgs& a, hipStream_t s);
+hipError_t launch_init(Prec p, const InitArgs& a, hipStream_t s);
+hipError_t launch_surface(Prec p, const SurfaceArgs& a, int nblocks, hipStream_t s);
+hipError_t launch_sum_partials(const double* partial, int nblocks, double* out, hipStream_t s);
+hipError_t launch_to_double(Prec p, const void* src, double* dst, long n, hipStream_t s);
+hipError_t launch_residual(Prec p, const void* mac, double* snap, const int32_t* list, int n,
+                           long plane, double area, double* partial, int nblocks, hipStream_t s);
+
+}  // namespace lbr

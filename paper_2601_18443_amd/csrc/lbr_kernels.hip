@@ -1,0 +1,812 @@
+// Device code of liblbr (gfx950).
+//
+// The hot kernel is k_step: one pass per (sub-)step of a level that, for each
+// owned fluid cell, advances the SA-neg variable, pulls the nine populations
+// (with bounce-back at cut links, domain rules, the coarse/fine transfer),
+// forms rho and u, and applies the central-moment collision.  Populations are
+// stored shifted by their lattice weight (s_i = f_i - w_i) in planes of a
+// level's storage box; one 64 x 4 tile per 256-thread workgroup, one
+// wavefront per tile row, so every population plane is read and written in
+// coalesced 64-wide rows.  The work is bandwidth-bound and uses no matrix
+// cores.
+#include "lbr_impl.h"
+
+#include <cmath>
+
+namespace lbr {
+namespace {
+
+constexpr int CX[9] = {0, 1, -1, 0, 0, 1, -1, 1, -1};
+constexpr int CY[9] = {0, 0, 0, 1, -1, 1, -1, -1, 1};
+constexpr int OPP[9] = {0, 2, 1, 4, 3, 6, 5, 8, 7};
+constexpr int MIRY[9] = {0, 1, 2, 4, 3, 7, 8, 5, 6};
+
+constexpr int BC_PERIODIC = 0, BC_INLET = 1, BC_OUTLET = 2, BC_SYMMETRY = 3;
+
+// SA-neg constants (Section 2.2)
+constexpr double KAPPA = 0.41, CB1 = 0.1355, CB2 = 0.622, SIGMA = 2.0 / 3.0, CW2 = 0.3,
+                 CW3 = 2.0, CV1 = 7.1, RLIM = 10.0, CV2 = 0.7, CV3 = 0.3, CT3 = 1.2, CN1 = 16.0;
+constexpr double CW1 = CB1 / (KAPPA * KAPPA) + (1.0 + CB2) / SIGMA;
+
+template <class T>
+__device__ __forceinline__ T wq(int i) {
+    return i == 0 ? T(4.0 / 9.0) : (i < 5 ? T(1.0 / 9.0) : T(1.0 / 36.0));
+}
+
+// storage <-> compute conversions
+template <class ST, class CT> struct Cv;
+template <> struct Cv<double, double> {
+    static __device__ __forceinline__ double ld(const double* p) { return *p; }
+    static __device__ __forceinline__ void st(double* p, double v) { *p = v; }
+};
+template <> struct Cv<float, float> {
+    static __device__ __forceinline__ float ld(const float* p) { return *p; }
+    static __device__ __forceinline__ void st(float* p, float v) { *p = v; }
+};
+template <> struct Cv<__half, float> {
+    static __device__ __forceinline__ float ld(const __half* p) { return __half2float(*p); }
+    static __device__ __forceinline__ void st(__half* p, float v) { *p = __float2half_rn(v); }
+};
+template <> struct Cv<__hip_bfloat16, float> {
+    static __device__ __forceinline__ float ld(const __hip_bfloat16* p) { return __bfloat162float(*p); }
+    static __device__ __forceinline__ void st(__hip_bfloat16* p, float v) { *p = __float2bfloat16(v); }
+};
+
+__device__ __forceinline__ double dmin(double a, double b) { return a < b ? a : b; }
+__device__ __forceinline__ float dmin(float a, float b) { return a < b ? a : b; }
+
+// ---------------------------------------------------------------------------
+// Central-moment collision (eqs (5)-(10)) in shifted variables.  The second
+// central moments are formed from the raw moments of s, the shear pair
+// (k4, k5) relaxes with omega, the trace k3 with omega_b, every other central
+// moment is set to its equilibrium value (K = 1), the force enters the first
+// central moments as F/2 after collision, and the post-collision raw moments
+// are mapped back to populations with the constant inverse of the D2Q9
+// raw-moment matrix.  All moments carry the lattice-weight part removed, so
+// the arithmetic never subtracts O(1) quantities.
+// ---------------------------------------------------------------------------
+template <class T>
+__device__ __forceinline__ void collide(T s[9], T drho, T ux, T uy, T omega, T omega_b, T fx,
+                                        T fy) {
+    const T rho = T(1) + drho;
+    const T sxx = s[1] + s[2] + s[5] + s[6] + s[7] + s[8];
+    const T syy = s[3] + s[4] + s[5] + s[6] + s[7] + s[8];
+    const T sxy = s[5] + s[6] - s[7] - s[8];
+    const T ux2 = ux * ux, uy2 = uy * uy, uxy = ux * uy;
+    const T k4 = (sxx - syy) - rho * (ux2 - uy2) + (ux * fx - uy * fy);
+    const T k5 = sxy - rho * uxy + T(0.5) * (ux * fy + uy * fx);
+    const T K3 = (sxx + syy) - T(2.0 / 3.0) * drho - rho * (ux2 + uy2) + (ux * fx + uy * fy);
+    const T k4s = (T(1) - omega) * k4;
+    const T k5s = (T(1) - omega) * k5;
+    const T K3s = (T(1) - omega_b) * K3;
+    const T c20 = T(0.5) * (K3s + k4s);        // kappa*_20 - rho/3
+    const T c02 = T(0.5) * (K3s - k4s);        // kappa*_02 - rho/3
+    const T c11 = k5s;
+    const T c10 = T(0.5) * fx, c01 = T(0.5) * fy;
+    const T k20 = rho * T(1.0 / 3.0) + c20, k02 = rho * T(1.0 / 3.0) + c02;
+    // post-collision raw moments minus those of the weights (1,0,0,1/3,1/3,0,0,0,1/9)
+    const T M00 = drho;
+    const T M10 = c10 + ux * rho;
+    const T M01 = c01 + uy * rho;
+    const T M20 = (drho * T(1.0 / 3.0) + c20) + T(2) * ux * c10 + ux2 * rho;
+    const T M02 = (drho * T(1.0 / 3.0) + c02) + T(2) * uy * c01 + uy2 * rho;
+    const T M11 = c11 + ux * c01 + uy * c10 + uxy * rho;
+    const T M21 = T(2) * ux * c11 + uy * k20 + ux2 * c01 + T(2) * uxy * c10 + ux2 * uy * rho;
+    const T M12 = T(2) * uy * c11 + ux * k02 + uy2 * c10 + T(2) * uxy * c01 + ux * uy2 * rho;
+    const T M22 = drho * T(1.0 / 9.0) + uy2 * k20 + ux2 * k02 + T(4) * uxy * c11 +
+                  T(2) * ux * uy2 * c10 + T(2) * ux2 * uy * c01 + ux2 * uy2 * rho;
+    s[0] = M00 - M20 - M02 + M22;
+    s[1] = T(0.5) * (M10 + M20 - M12 - M22);
+    s[2] = T(0.5) * (-M10 + M20 + M12 - M22);
+    s[3] = T(0.5) * (M01 + M02 - M21 - M22);
+    s[4] = T(0.5) * (-M01 + M02 + M21 - M22);
+    s[5] = T(0.25) * (M11 + M21 + M12 + M22);
+    s[6] = T(0.25) * (M11 - M21 - M12 + M22);
+    s[7] = T(0.25) * (-M11 - M21 + M12 + M22);
+    s[8] = T(0.25) * (-M11 + M21 - M12 + M22);
+}
+
+// Equilibrium of eq (4) (fourth-order coefficient 1/(4 c_s^8)), shifted by w_i.
+template <class T>
+__device__ __forceinline__ void equilibrium(T s[9], T drho, T ux, T uy) {
+    const T rho = T(1) + drho;
+    const T u2 = ux * ux + uy * uy;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const T cx = T(CX[i]), cy = T(CY[i]);
+        const T cu = cx * ux + cy * uy;
+        const T hx = cx * cx - T(1.0 / 3.0), hy = cy * cy - T(1.0 / 3.0);
+        const T e = T(3) * cu + T(4.5) * (cu * cu - u2 * T(1.0 / 3.0)) +
+                    T(13.5) * (hx * cy * ux * ux * uy + cx * hy * ux * uy * uy) +
+                    T(20.25) * hx * hy * ux * ux * uy * uy;
+        s[i] = wq<T>(i) * (drho + rho * e);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// SA-neg (Section 2.2): one explicit step at a fluid node from its 3 x 3
+// stencil (index (dy+1)*3 + dx+1).  Vorticity from the least-squares gradient
+// over the eight neighbours; Lax-Wendroff (or first-order upwind) convection;
+// centred diffusion with face-averaged nodal diffusivity.
+// ---------------------------------------------------------------------------
+template <class T>
+__device__ __forceinline__ T sa_mu(T nt, T nu) {
+    if (nt >= T(0)) return nu + nt;
+    const T c = nt / nu;
+    const T c3 = c * c * c;
+    return nu + nt * (T(CN1) + c3) / (T(CN1) - c3);
+}
+
+template <class T>
+__device__ T sa_update(const T nt[9], const T u[9], const T v[9], T nu, T d, int upwind) {
+    const T six = T(1.0 / 6.0);
+    const T dudy = ((u[7] - u[1]) + (u[8] - u[2]) + (u[6] - u[0])) * six;
+    const T dvdx = ((v[5] - v[3]) + (v[8] - v[6]) + (v[2] - v[0])) * six;
+    const T omega = fabs(dvdx - dudy);
+    const T C = nt[4];
+    const T chi = C / nu;
+    const T k2d2 = T(KAPPA * KAPPA) * d * d;
+    T P, D;
+    if (C >= T(0)) {
+        const T chi3 = chi * chi * chi;
+        const T fv1 = chi3 / (chi3 + T(CV1 * CV1 * CV1));
+        const T fv2 = T(1) - chi / (T(1) + chi * fv1);
+        const T sbar = C * fv2 / k2d2;
+        const T st = (sbar >= -T(CV2) * omega)
+                         ? omega + sbar
+                         : omega + omega * (T(CV2 * CV2) * omega + T(CV3) * sbar) /
+                                       (T(CV3 - 2.0 * CV2) * omega - sbar);
+        T r = (st > T(1e-30)) ? C / (st * k2d2) : T(RLIM);
+        r = dmin(r, T(RLIM));
+        const T r2 = r * r;
+        const T g = r + T(CW2) * (r2 * r2 * r2 - r);
+        const T g2 = g * g;
+        const T c6 = T(CW3 * CW3 * CW3 * CW3 * CW3 * CW3);
+        const T fw = g * pow((T(1) + c6) / (g2 * g2 * g2 + c6), T(1.0 / 6.0));
+        P = T(CB1) * st * C;
+        D = T(CW1) * fw * (C / d) * (C / d);
+    } else {
+        P = T(CB1 * (1.0 - CT3)) * omega * C;
+        D = -T(CW1) * (C / d) * (C / d);
+    }
+    const T E = nt[5], W = nt[3], N = nt[7], S = nt[1];
+    const T dX = T(0.5) * (E - W), dY = T(0.5) * (N - S);
+    const T uc = u[4], vc = v[4];
+    T conv;
+    if (upwind) {
+        conv = -(uc * (uc > T(0) ? C - W : E - C) + vc * (vc > T(0) ? C - S : N - C));
+    } else {
+        conv = -(uc * dX + vc * dY) +
+               T(0.5) * (uc * uc * (E - T(2) * C + W) +
+                         T(0.5) * uc * vc * (nt[8] - nt[6] - nt[2] + nt[0]) +
+                         vc * vc * (N - T(2) * C + S));
+    }
+    const T mC = sa_mu(C, nu);
+    const T diff = T(0.5) * (mC + sa_mu(E, nu)) * (E - C) - T(0.5) * (mC + sa_mu(W, nu)) * (C - W) +
+                   T(0.5) * (mC + sa_mu(N, nu)) * (N - C) - T(0.5) * (mC + sa_mu(S, nu)) * (C - S) +
+                   T(CB2) * (dX * dX + dY * dY);
+    return C + conv + (P - D) + diff * T(1.0 / SIGMA);
+}
+
+template <class T>
+__device__ __forceinline__ T eddy_viscosity(T chi, T nu) {
+    if (chi <= T(0)) return T(0);
+    const T c3 = chi * chi * chi;
+    return nu * chi * c3 / (c3 + T(CV1 * CV1 * CV1));
+}
+
+// ---------------------------------------------------------------------------
+// k_step
+// ---------------------------------------------------------------------------
+template <class ST, class CT>
+__device__ __forceinline__ CT coarse_val(const StepArgs<ST, CT>& a, int i, int gx, int gy) {
+    const long cc = (long)((gy >> 1) - a.cbox.gy0) * a.cbox.pitch + ((gx >> 1) - a.cbox.gx0);
+    return Cv<ST, CT>::ld(a.fcoarse + i * a.cbox.plane + cc);
+}
+
+// Yu's interpolated bounce-back (step 6 of the VN procedure), or eq (24).
+template <class ST, class CT>
+__device__ CT bounce(const StepArgs<ST, CT>& a, int b, int i, long c, int gx, int gy, CT q) {
+    const int o = OPP[i];
+    const long P = a.box.plane;
+    const CT uwx = a.bw[4 * b + 0], uwy = a.bw[4 * b + 1], rhow = a.bw[4 * b + 2];
+    const CT fo_b = Cv<ST, CT>::ld(a.fsrc + o * P + c);
+    const CT mom = CT(2) * wq<CT>(o) * rhow * (CT(CX[i]) * uwx + CT(CY[i]) * uwy) * CT(3);
+    if (!a.bb_halfway && a.bq[8 * b + i - 1] < CT(0)) {
+        int fx2 = gx + CX[i];
+        if (a.dom.periodic_x) fx2 = (fx2 + a.dom.nxd) % a.dom.nxd;
+        const long c2 = (long)(gy + CY[i] - a.box.gy0) * a.box.pitch + (fx2 - a.box.gx0);
+        if ((a.flag[c2] & F_TYPE) == T_FLUID) {
+            const CT fo_f2 = Cv<ST, CT>::ld(a.fsrc + o * P + c2);
+            const CT fi_b = Cv<ST, CT>::ld(a.fsrc + i * P + c);
+            const CT fw_o = q * fo_b + (CT(1) - q) * fo_f2;
+            const CT fw_i = fw_o + mom;
+            return fw_i + (q / (CT(1) + q)) * (fi_b - fw_i);
+        }
+    }
+    return fo_b + mom;
+}
+
+// Post-stream value of direction i at (gx, gy) for a cell next to the outlet
+// (interior or across a symmetry / periodic y edge).
+template <class ST, class CT>
+__device__ __forceinline__ CT poststream(const StepArgs<ST, CT>& a, int i, int gx, int gy) {
+    int sx = gx - CX[i], sy = gy - CY[i], di = i;
+    if (sy < 0 || sy >= a.dom.nyd) {
+        const int side = sy < 0 ? 2 : 3;
+        if (a.dom.bc[side] == BC_PERIODIC) sy = (sy + a.dom.nyd) % a.dom.nyd;
+        else { sy = gy; di = MIRY[i]; }
+    }
+    const long cs = (long)(sy - a.box.gy0) * a.box.pitch + (sx - a.box.gx0);
+    return Cv<ST, CT>::ld(a.fsrc + di * a.box.plane + cs);
+}
+
+template <class ST, class CT>
+__global__ __launch_bounds__(256) void k_step(const StepArgs<ST, CT> a) {
+    const int per = (a.ntiles + 7) >> 3;
+    const int t = (blockIdx.x & 7) * per + (blockIdx.x >> 3);   // tiles of one XCD are adjacent
+    if (t >= a.ntiles) return;
+    const uint32_t tile = a.tiles[t];
+    const int lx = (int)(tile & 0xffffu) * TILE_X + (threadIdx.x & 63);
+    const int ly = (int)(tile >> 16) * TILE_Y + (threadIdx.x >> 6);
+    const int pitch = a.box.pitch;
+    const long P = a.box.plane;
+    const long c = (long)ly * pitch + lx;
+    const uint8_t fl = a.flag[c];
+    const int type = fl & F_TYPE;
+    const int gx = lx + a.box.gx0, gy = ly + a.box.gy0;
+
+    if (type == T_GHOST) {
+        // fine band over a coarse interface cell: carries exploded coarse populations
+        // (first sub-step) and fine populations one cell per sub-step, no collision
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const long cs = c - CX[i] - (long)CY[i] * pitch;
+            const int st = a.flag[cs] & F_TYPE;
+            CT v;
+            if (st == T_FLUID || (st == T_GHOST && a.substep == 2))
+                v = Cv<ST, CT>::ld(a.fsrc + i * P + cs);
+            else if (a.substep == 1)
+                v = coarse_val(a, i, gx - CX[i], gy - CY[i]);
+            else
+                v = coarse_val(a, i, gx - 2 * CX[i], gy - 2 * CY[i]);
+            Cv<ST, CT>::st(a.fdst + i * P + c, v);
+        }
+        return;
+    }
+    if (type != T_FLUID) return;
+
+    // ---- SA-neg: chi at the new time level
+    CT chi_new;
+    const bool at_inlet = (fl & F_EDGE) && gx == 0 && a.dom.bc[0] == BC_INLET;
+    const bool at_outlet = (fl & F_EDGE) && gx == a.dom.nxd - 1 && a.dom.bc[1] == BC_OUTLET;
+    if (a.frozen) {
+        chi_new = a.csrc[c];
+    } else if (fl & F_WALL) {
+        chi_new = a.cdst[c];                 // Dirichlet value written by the wall model
+    } else if (at_inlet) {
+        chi_new = a.chi_in;
+    } else if (at_outlet) {
+        chi_new = a.csrc[c - 1];             // first-order extrapolation
+    } else {
+        CT nt[9], u[9], v[9];
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int k = (dy + 1) * 3 + dx + 1;
+                long cs = c + dx + (long)dy * pitch;
+                CT sgn = CT(1);
+                if (fl & F_EDGE) {
+                    int sx = gx + dx, sy = gy + dy;
+                    if (sx < 0 || sx >= a.dom.nxd) sx = (sx + a.dom.nxd) % a.dom.nxd;
+                    if (sy < 0 || sy >= a.dom.nyd) {
+                        const int side = sy < 0 ? 2 : 3;
+                        if (a.dom.bc[side] == BC_PERIODIC) sy = (sy + a.dom.nyd) % a.dom.nyd;
+                        else { sy = (sy < 0) ? -1 - sy : 2 * a.dom.nyd - 1 - sy; sgn = CT(-1); }
+                    }
+                    cs = (long)(sy - a.box.gy0) * pitch + (sx - a.box.gx0);
+                }
+                nt[k] = a.csrc[cs] * a.nu;
+                u[k] = a.msrc[P + cs];
+                v[k] = sgn * a.msrc[2 * P + cs];
+            }
+        CT d = CT(a.dist[c]);
+        chi_new = sa_update(nt, u, v, a.nu, d, a.sa_mode == 2) / a.nu;
+    }
+
+    // ---- streaming (pull)
+    CT s[9];
+    if (!(fl & (F_WALL | F_IFACE | F_NEARGHOST | F_EDGE))) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+            s[i] = Cv<ST, CT>::ld(a.fsrc + i * P + c - CX[i] - (long)CY[i] * pitch);
+    } else if (fl & F_IFACE) {
+        // coalescence: mean of the four children of the finer band
+        const long f0 = (long)(2 * gy - a.fbox.gy0) * a.fbox.pitch + (2 * gx - a.fbox.gx0);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const ST* p = a.ffine + i * a.fbox.plane + f0;
+            s[i] = CT(0.25) * ((Cv<ST, CT>::ld(p) + Cv<ST, CT>::ld(p + 1)) +
+                               (Cv<ST, CT>::ld(p + a.fbox.pitch) + Cv<ST, CT>::ld(p + a.fbox.pitch + 1)));
+        }
+    } else {
+        const int b = (fl & F_WALL) ? a.bidx[c] : -1;
+        for (int i = 0; i < 9; ++i) {
+            if (b >= 0 && i != 0) {
+                const CT q = a.bq[8 * b + OPP[i] - 1];
+                if (q >= CT(0)) { s[i] = bounce(a, b, i, c, gx, gy, q); continue; }
+            }
+            int sx = gx - CX[i], sy = gy - CY[i], di = i;
+            if (fl & F_EDGE) {
+                if (sx < 0 || sx >= a.dom.nxd) {
+                    if (!a.dom.periodic_x) { s[i] = CT(0); continue; }   // inlet / outlet unknown
+                    sx = (sx + a.dom.nxd) % a.dom.nxd;
+                }
+                if (sy < 0 || sy >= a.dom.nyd) {
+                    const int side = sy < 0 ? 2 : 3;
+                    if (a.dom.bc[side] == BC_PERIODIC) sy = (sy + a.dom.nyd) % a.dom.nyd;
+                    else if (a.dom.bc[side] == BC_SYMMETRY) { sy = gy; di = MIRY[i]; }
+                    else { s[i] = CT(0); continue; }
+                }
+            }
+            const long cs = (long)(sy - a.box.gy0) * pitch + (sx - a.box.gx0);
+            if ((fl & F_NEARGHOST) && a.substep == 1 && (a.flag[cs] & F_TYPE) == T_GHOST)
+                s[i] = coarse_val(a, di, sx, sy);
+            else
+                s[i] = Cv<ST, CT>::ld(a.fsrc + di * P + cs);
+        }
+        if (at_inlet) {
+            // Zou-He velocity inlet: unknowns have c_x = +1
+            const CT ui = a.u_in;
+            const CT rho = (CT(1) + s[0] + s[3] + s[4] + CT(2) * (s[2] + s[6] + s[8])) / (CT(1) - ui);
+            s[1] = s[2] + CT(2.0 / 3.0) * rho * ui;
+            s[5] = s[6] - CT(0.5) * (s[3] - s[4]) + rho * ui * CT(1.0 / 6.0);
+            s[7] = s[8] + CT(0.5) * (s[3] - s[4]) + rho * ui * CT(1.0 / 6.0);
+        }
+        if (at_outlet) {
+            // unknowns (c_x = -1) extrapolated from the two upstream cells
+            for (int i = 0; i < 9; ++i)
+                if (CX[i] == -1)
+                    s[i] = CT(2) * poststream(a, i, gx - 1, gy) - poststream(a, i, gx - 2, gy);
+        }
+    }
+
+    // ---- macroscopic values (eq (3) with the half-force shift)
+    CT drho = CT(0), jx = CT(0), jy = CT(0);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        drho += s[i];
+        jx += CT(CX[i]) * s[i];
+        jy += CT(CY[i]) * s[i];
+    }
+    const CT rho = CT(1) + drho;
+    const CT ux = (jx + CT(0.5) * a.fx) / rho;
+    const CT uy = (jy + CT(0.5) * a.fy) / rho;
+    a.mdst[c] = rho;
+    a.mdst[P + c] = ux;
+    a.mdst[2 * P + c] = uy;
+    a.cdst[c] = chi_new;
+
+    // ---- collision with nu_eff = nu + nu_t(chi) (eqs (9), (11))
+    const CT nu_eff = a.nu + eddy_viscosity(chi_new, a.nu);
+    const CT omega = CT(1) / (CT(3) * nu_eff + CT(0.5));
+    collide(s, drho, ux, uy, omega, a.omega_b, a.fx, a.fy);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Cv<ST, CT>::st(a.fdst + i * P + c, s[i]);
+}
+
+// ---------------------------------------------------------------------------
+// Wall model: steps 1-5 of the VN procedure (Section 2.3), FP64, one thread
+// per boundary node.
+// ---------------------------------------------------------------------------
+constexpr double WF_B = 5.033908790505579, WF_A1 = 8.148221580024245,
+                 WF_A2 = -6.9287093849022945, WF_B1 = 7.4600876082527945,
+                 WF_B2 = 7.468145790401841, WF_C1 = 2.5496773539754747,
+                 WF_C2 = 1.3301651588535228, WF_C3 = 3.599459109332379,
+                 WF_C4 = 3.639753186868684494;
+
+// eq (22), continuous branch of the arctangents
+__device__ double uplus(double y) {
+    const double p = y + WF_A1, m = y + WF_A2;
+    return WF_B + WF_C1 * log(p * p + WF_B1 * WF_B1) - WF_C2 * log(m * m + WF_B2 * WF_B2) -
+           WF_C3 * atan2(WF_B1, p) - WF_C4 * atan2(WF_B2, m);
+}
+
+// eq (21)
+__device__ double duplus(double y) {
+    const double ky = KAPPA * y, k3 = ky * ky * ky, c3 = CV1 * CV1 * CV1;
+    return (c3 + k3) / (c3 + k3 * (1.0 + ky));
+}
+
+__device__ double friction_velocity(double ut, double d, double nu, double guess) {
+    if (!(ut > 0.0)) return 0.0;
+    double u = guess > 0.0 ? guess : sqrt(nu * ut / d);
+    for (int it = 0; it < 100; ++it) {
+        const double yp = d * u / nu;
+        const double up = uplus(yp);
+        const double step = (u * up - ut) / (up + yp * duplus(yp));
+        double un = u - step;
+        if (!(un > 0.0)) un = 0.5 * u;
+        u = un;
+        if (fabs(step) <= 1e-14 * u) break;
+    }
+    if (!(u > 0.0) || !isfinite(u)) {
+        double lo = 0.0, hi = ut * 1e3;
+        for (int it = 0; it < 200; ++it) {
+            const double mid = 0.5 * (lo + hi);
+            if (mid * uplus(d * mid / nu) - ut > 0.0) hi = mid; else lo = mid;
+        }
+        u = 0.5 * (lo + hi);
+    }
+    return u;
+}
+
+template <class ST, class CT>
+__global__ __launch_bounds__(256) void k_wall(const WallArgs<ST, CT> a) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= a.nb) return;
+    const long P = a.plane;
+    const int cell = a.cell[b];
+    const double* g = a.geo + 6 * b;
+    double* st = a.state + 8 * b;
+    double uwx = 0.0, uwy = 0.0, rhow, utau = 0.0, tx = 0.0, ty = 0.0;
+    if (a.model == 2 || a.model == 3) {
+        rhow = (double)a.mac[cell];
+        if (a.model == 3) {
+            const double* uw = (g[5] == -2.0) ? a.uw_hi : a.uw_lo;
+            uwx = uw[0];
+            uwy = uw[1];
+        }
+    } else {
+        double rr = 0.0, ux = 0.0, uy = 0.0;
+        for (int j = 0; j < MAX_STENCIL; ++j) {
+            const int cj = a.st_cell[MAX_STENCIL * b + j];
+            if (cj < 0) break;
+            rr += a.st_wr[MAX_STENCIL * b + j] * (double)a.mac[cj];
+            const double wu = a.st_wu[MAX_STENCIL * b + j];
+            ux += wu * (double)a.mac[P + cj];
+            uy += wu * (double)a.mac[2 * P + cj];
+        }
+        const double un = ux * g[2] + uy * g[3];                 // step 2
+        tx = ux - un * g[2];
+        ty = uy - un * g[3];
+        const double ut = sqrt(tx * tx + ty * ty);
+        utau = friction_velocity(ut, a.d_wr, a.nu, st[0]);      // step 3
+        double uw;
+        if (a.model == 1) {                                      // eq (31)
+            const double yr = a.d_wr * utau / a.nu;
+            uw = ut - utau * utau * a.d_wr / (a.nu + a.nu * KAPPA * yr);
+        } else {                                                 // steps 4-5, eq (28)
+            const double yv = a.d_wv * utau / a.nu;
+            uw = utau * uplus(yv) - utau * utau * a.d_wv / (a.nu + a.nu * KAPPA * yv);
+        }
+        if (ut > 0.0) {
+            uwx = uw * tx / ut;
+            uwy = uw * ty / ut;
+        }
+        rhow = rr;                                               // step 6: rho_W = rho_R
+    }
+    a.bw[4 * b + 0] = (CT)uwx;
+    a.bw[4 * b + 1] = (CT)uwy;
+    a.bw[4 * b + 2] = (CT)rhow;
+    a.bw[4 * b + 3] = CT(0);
+    st[0] = utau;
+    st[1] = tx;
+    st[2] = ty;
+    st[3] = rhow;
+    st[4] = uwx;
+    st[5] = uwy;
+    if (a.write_chi) a.chi_next[cell] = (CT)(KAPPA * utau * g[4] / a.nu);
+}
+
+// ---------------------------------------------------------------------------
+// Level transfers of the macroscopic fields used by the SA stencils.
+// ---------------------------------------------------------------------------
+template <class CT>
+__global__ void k_fill(const FillArgs a) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.n) return;
+    const long g = a.list[k];
+    const int lx = (int)(g % a.fbox.pitch), ly = (int)(g / a.fbox.pitch);
+    const int gx = lx + a.fbox.gx0, gy = ly + a.fbox.gy0;
+    const int px = gx >> 1, py = gy >> 1;
+    const CT ox = (gx & 1) ? CT(0.25) : CT(-0.25), oy = (gy & 1) ? CT(0.25) : CT(-0.25);
+    const CT* cm = (const CT*)a.cmac;
+    const CT* cc = (const CT*)a.cchi;
+    CT sum[4] = {0, 0, 0, 0}, sx[4] = {0, 0, 0, 0}, sy[4] = {0, 0, 0, 0};
+    for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+            const long q = (long)(py + dy - a.cbox.gy0) * a.cbox.pitch + (px + dx - a.cbox.gx0);
+            const CT v[4] = {cm[q], cm[a.cbox.plane + q], cm[2 * a.cbox.plane + q], cc[q]};
+            for (int f = 0; f < 4; ++f) {
+                sum[f] += v[f];
+                sx[f] += CT(dx) * v[f];
+                sy[f] += CT(dy) * v[f];
+            }
+        }
+    // linear least-squares fit over the 3 x 3 coarse neighbourhood, at the child's centre
+    CT out[4];
+    for (int f = 0; f < 4; ++f)
+        out[f] = sum[f] * CT(1.0 / 9.0) + ox * sx[f] * CT(1.0 / 6.0) + oy * sy[f] * CT(1.0 / 6.0);
+    CT* m0 = (CT*)a.fmac0;
+    CT* m1 = (CT*)a.fmac1;
+    for (int f = 0; f < 3; ++f) {
+        m0[f * a.fbox.plane + g] = out[f];
+        m1[f * a.fbox.plane + g] = out[f];
+    }
+    ((CT*)a.fchi0)[g] = out[3];
+    ((CT*)a.fchi1)[g] = out[3];
+}
+
+template <class CT>
+__global__ void k_restrict(const RestrictArgs a) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.n) return;
+    const long g = a.list[k];
+    const int lx = (int)(g % a.cbox.pitch), ly = (int)(g / a.cbox.pitch);
+    const int gx = lx + a.cbox.gx0, gy = ly + a.cbox.gy0;
+    const long f0 = (long)(2 * gy - a.fbox.gy0) * a.fbox.pitch + (2 * gx - a.fbox.gx0);
+    const CT* fm = (const CT*)a.fmac;
+    const CT* fc = (const CT*)a.fchi;
+    CT* cm = (CT*)a.cmac;
+    for (int f = 0; f < 3; ++f) {
+        const CT* p = fm + f * a.fbox.plane + f0;
+        cm[f * a.cbox.plane + g] = CT(0.25) * ((p[0] + p[1]) + (p[a.fbox.pitch] + p[a.fbox.pitch + 1]));
+    }
+    const CT* p = fc + f0;
+    ((CT*)a.cchi)[g] = CT(0.25) * ((p[0] + p[1]) + (p[a.fbox.pitch] + p[a.fbox.pitch + 1]));
+}
+
+// Equilibrium initialisation followed by the first collision.
+template <class ST, class CT>
+__global__ void k_init(const InitArgs a) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.n) return;
+    const long c = a.list[k];
+    CT s[9];
+    equilibrium<CT>(s, CT(a.rho[k] - 1.0), CT(a.ux[k]), CT(a.uy[k]));
+    CT drho = 0, jx = 0, jy = 0;
+    for (int i = 0; i < 9; ++i) {
+        drho += s[i];
+        jx += CT(CX[i]) * s[i];
+        jy += CT(CY[i]) * s[i];
+    }
+    const CT rho = CT(1) + drho;
+    const CT ux = (jx + CT(0.5 * a.fx)) / rho, uy = (jy + CT(0.5 * a.fy)) / rho;
+    CT* mac = (CT*)a.mac;
+    mac[c] = rho;
+    mac[a.plane + c] = ux;
+    mac[2 * a.plane + c] = uy;
+    const CT chi = CT(a.chi[k]);
+    ((CT*)a.chi_a)[c] = chi;
+    ((CT*)a.chi_b)[c] = chi;
+    const CT nu = CT(a.nu);
+    const CT omega = CT(1) / (CT(3) * (nu + eddy_viscosity(chi, nu)) + CT(0.5));
+    collide(s, drho, ux, uy, omega, CT(a.omega_b), CT(a.fx), CT(a.fy));
+    ST* f = (ST*)a.f;
+    for (int i = 0; i < 9; ++i) Cv<ST, CT>::st(f + i * a.plane + c, s[i]);
+}
+
+// ---------------------------------------------------------------------------
+// Geometry: FP64 distance to the wall polylines and even-odd inside test, per
+// cell centre of a level's storage box.
+// ---------------------------------------------------------------------------
+__global__ void k_geometry(int nx, int ny, int gx0, int gy0, double scale, int nbody,
+                           const int* off, const double* poly, int solid, double* dist,
+                           uint8_t* inside) {
+    const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (long)nx * ny) return;
+    const double px = (double)(k % nx + gx0) + 0.5, py = (double)(k / nx + gy0) + 0.5;
+    double best2 = 1e300;
+    int in_any = 0;
+    for (int b = 0; b < nbody; ++b) {
+        const int s0 = off[b], n = off[b + 1] - off[b];
+        int in = 0;
+        for (int j = 0; j < n; ++j) {
+            const int j1 = (j + 1 == n) ? 0 : j + 1;
+            const double ax = poly[2 * (s0 + j)] * scale, ay = poly[2 * (s0 + j) + 1] * scale;
+            const double bx = poly[2 * (s0 + j1)] * scale, by = poly[2 * (s0 + j1) + 1] * scale;
+            const double ex = bx - ax, ey = by - ay;
+            const double l2 = ex * ex + ey * ey;
+            double t = l2 > 0.0 ? ((px - ax) * ex + (py - ay) * ey) / l2 : 0.0;
+            t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+            const double dx = px - (ax + t * ex), dy = py - (ay + t * ey);
+            const double d2 = dx * dx + dy * dy;
+            best2 = d2 < best2 ? d2 : best2;
+            if ((ay > py) != (by > py)) {
+                const double xc = ax + (py - ay) * (bx - ax) / (by - ay);
+                if (px < xc) in = !in;
+            }
+        }
+        in_any |= in;
+    }
+    dist[k] = nbody > 0 ? sqrt(best2) : 1e300;
+    inside[k] = (uint8_t)(solid && in_any);
+}
+
+// ---------------------------------------------------------------------------
+// Surface coefficients and force sums (eqs (29)-(30)), FP64.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <class CT>
+__global__ __launch_bounds__(256) void k_surface(const SurfaceArgs a) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    double acc[4] = {0, 0, 0, 0};
+    if (k < a.nseg) {
+        const double* sg = a.seg + 6 * k;
+        double sw = 0.0, scp = 0.0, scf = 0.0;
+        const double U2 = a.u_ref * a.u_ref;
+        for (int m = 0; m < 2; ++m) {
+            const int b = a.near[2 * k + m];
+            if (b < 0) continue;
+            const double w = a.wgt[2 * k + m];
+            const double* st = a.bstate + 8 * b;
+            const double rhow = st[3];
+            const double cpb = 2.0 * (1.0 / 3.0) * (rhow - a.rho_ref) / (a.rho_ref * U2);
+            const double cfb = 2.0 * (rhow / a.rho_ref) * st[0] * st[0] / U2;
+            const double sg_ = (st[1] * sg[0] + st[2] * sg[1] >= 0.0) ? 1.0 : -1.0;
+            sw += w;
+            scp += w * cpb;
+            scf += w * cfb * sg_;
+        }
+        const double cp = scp / sw, cf = scf / sw;
+        a.cp[k] = cp;
+        a.cf[k] = cf;
+        acc[0] = cf * sg[0] * sg[4];
+        acc[1] = cf * sg[1] * sg[4];
+        acc[2] = -cp * sg[2] * sg[4];
+        acc[3] = -cp * sg[3] * sg[4];
+    }
+    __shared__ double part[4][4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int f = 0; f < 4; ++f) {
+        const double v = wave_sum(acc[f]);
+        if (lane == 0) part[wv][f] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        const int f = threadIdx.x;
+        a.partial[4 * blockIdx.x + f] = (part[0][f] + part[1][f]) + (part[2][f] + part[3][f]);
+    }
+}
+
+template <class CT>
+__global__ __launch_bounds__(256) void k_residual(const CT* mac, double* snap, const int32_t* list,
+                                                 int n, long plane, double area, double* partial) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    double du = 0.0, uu = 0.0;
+    if (k < n) {
+        const long c = list[k];
+        const double ux = (double)mac[plane + c], uy = (double)mac[2 * plane + c];
+        const double dx = ux - snap[2 * k], dy = uy - snap[2 * k + 1];
+        du = area * (dx * dx + dy * dy);
+        uu = area * (ux * ux + uy * uy);
+        snap[2 * k] = ux;
+        snap[2 * k + 1] = uy;
+    }
+    __shared__ double part[4][2];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    du = wave_sum(du);
+    uu = wave_sum(uu);
+    if (lane == 0) { part[wv][0] = du; part[wv][1] = uu; }
+    __syncthreads();
+    if (threadIdx.x < 2)
+        partial[2 * blockIdx.x + threadIdx.x] =
+            (part[0][threadIdx.x] + part[1][threadIdx.x]) + (part[2][threadIdx.x] + part[3][threadIdx.x]);
+}
+
+template <class CT>
+__global__ void k_to_double(const CT* src, double* dst, long n) {
+    const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) dst[k] = (double)src[k];
+}
+
+inline unsigned nblocks(long n, int b) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+template <class ST, class CT>
+static hipError_t step_t(const void* args, hipStream_t s) {
+    const auto& a = *static_cast<const StepArgs<ST, CT>*>(args);
+    if (a.ntiles == 0) return hipSuccess;
+    const unsigned grid = 8u * (unsigned)((a.ntiles + 7) / 8);
+    hipLaunchKernelGGL((k_step<ST, CT>), dim3(grid), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_step(Prec p, const void* args, hipStream_t s) {
+    switch (p) {
+        case P_F64: return step_t<double, double>(args, s);
+        case P_F32: return step_t<float, float>(args, s);
+        case P_F16: return step_t<__half, float>(args, s);
+        default: return step_t<__hip_bfloat16, float>(args, s);
+    }
+}
+
+template <class ST, class CT>
+static hipError_t wall_t(const void* args, hipStream_t s) {
+    const auto& a = *static_cast<const WallArgs<ST, CT>*>(args);
+    if (a.nb == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_wall<ST, CT>), dim3(nblocks(a.nb, 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_wall(Prec p, const void* args, hipStream_t s) {
+    switch (p) {
+        case P_F64: return wall_t<double, double>(args, s);
+        case P_F32: return wall_t<float, float>(args, s);
+        case P_F16: return wall_t<__half, float>(args, s);
+        default: return wall_t<__hip_bfloat16, float>(args, s);
+    }
+}
+
+hipError_t launch_fill(Prec p, const FillArgs& a, hipStream_t s) {
+    if (a.n == 0) return hipSuccess;
+    if (p == P_F64) hipLaunchKernelGGL(k_fill<double>, dim3(nblocks(a.n, 256)), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_fill<float>, dim3(nblocks(a.n, 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_restrict(Prec p, const RestrictArgs& a, hipStream_t s) {
+    if (a.n == 0) return hipSuccess;
+    if (p == P_F64) hipLaunchKernelGGL(k_restrict<double>, dim3(nblocks(a.n, 256)), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_restrict<float>, dim3(nblocks(a.n, 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_init(Prec p, const InitArgs& a, hipStream_t s) {
+    if (a.n == 0) return hipSuccess;
+    const dim3 g(nblocks(a.n, 256)), b(256);
+    switch (p) {
+        case P_F64: hipLaunchKernelGGL((k_init<double, double>), g, b, 0, s, a); break;
+        case P_F32: hipLaunchKernelGGL((k_init<float, float>), g, b, 0, s, a); break;
+        case P_F16: hipLaunchKernelGGL((k_init<__half, float>), g, b, 0, s, a); break;
+        default: hipLaunchKernelGGL((k_init<__hip_bfloat16, float>), g, b, 0, s, a); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_geometry(int nx, int ny, int gx0, int gy0, double scale, int nbody,
+                           const int* off, const double* poly, int solid, double* dist,
+                           uint8_t* inside, hipStream_t s) {
+    hipLaunchKernelGGL(k_geometry, dim3(nblocks((long)nx * ny, 256)), dim3(256), 0, s, nx, ny,
+                       gx0, gy0, scale, nbody, off, poly, solid, dist, inside);
+    return hipGetLastError();
+}
+
+hipError_t launch_surface(Prec p, const SurfaceArgs& a, int nb, hipStream_t s) {
+    if (p == P_F64) hipLaunchKernelGGL(k_surface<double>, dim3(nb), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_surface<float>, dim3(nb), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual(Prec p, const void* mac, double* snap, const int32_t* list, int n,
+                           long plane, double area, double* partial, int nb, hipStream_t s) {
+    if (p == P_F64)
+        hipLaunchKernelGGL(k_residual<double>, dim3(nb), dim3(256), 0, s, (const double*)mac, snap,
+                           list, n, plane, area, partial);
+    else
+        hipLaunchKernelGGL(k_residual<float>, dim3(nb), dim3(256), 0, s, (const float*)mac, snap,
+                           list, n, plane, area, partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_double(Prec p, const void* src, double* dst, long n, hipStream_t s) {
+    if (p == P_F64)
+        hipLaunchKernelGGL(k_to_double<double>, dim3(nblocks(n, 256)), dim3(256), 0, s,
+                           (const double*)src, dst, n);
+    else
+        hipLaunchKernelGGL(k_to_double<float>, dim3(nblocks(n, 256)), dim3(256), 0, s,
+                           (const float*)src, dst, n);
+    return hipGetLastError();
+}
+
+}  // namespace lbr

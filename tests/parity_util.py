@@ -1,0 +1,103 @@
+"""Helpers that drive the oracle and the HIP library on identical seeded inputs."""
+import numpy as np
+
+import lbr_inputs as LI
+import oracle
+
+FIELDS = {"rho": (oracle.F_RHO, 0), "ux": (oracle.F_UX, 1), "uy": (oracle.F_UY, 2),
+          "chi": (oracle.F_CHI, 3)}
+
+
+def gpu_solver(case, storage):
+    import paper_2601_18443_amd as P
+    return P.Solver(case, storage=storage)
+
+
+def channel_init(case, sims):
+    ux, uy = LI.channel_initial_velocity(case)
+    rho = np.ones_like(ux)
+    chi = np.full_like(ux, case["chi_init"])
+    for s in sims:
+        s.init(0, rho=rho, ux=ux, uy=uy, chi=chi)
+
+
+def rel_l2(a, b):
+    m = np.isfinite(a) & np.isfinite(b)
+    assert np.array_equal(np.isfinite(a), np.isfinite(b)), "different fluid masks"
+    den = np.sqrt(np.sum(b[m] ** 2))
+    return np.sqrt(np.sum((a[m] - b[m]) ** 2)) / (den if den > 0 else 1.0)
+
+
+def field_errors(g, o, n_levels, names=("rho", "ux", "uy", "chi")):
+    out = {}
+    for l in range(n_levels):
+        for name in names:
+            fo, fg = FIELDS[name]
+            a = g.field(l, fg)
+            b = o.field(l, fo)
+            if name == "rho":
+                a, b = a - 1.0, b - 1.0          # compare the density deviation
+            out[(l, name)] = rel_l2(a, b)
+    return out
+
+
+def density_error(g, o, n_levels):
+    """Largest absolute density difference over all levels."""
+    worst = 0.0
+    for l in range(n_levels):
+        a, b = g.field(l, 0), o.field(l, oracle.F_RHO)
+        m = np.isfinite(b)
+        assert np.array_equal(np.isfinite(a), m), "different fluid masks"
+        worst = max(worst, float(np.max(np.abs(a[m] - b[m]))))
+    return worst
+
+
+def velocity_error(g, o, n_levels):
+    """Relative L2 error of the velocity vector over all levels (area weighted)."""
+    num = den = 0.0
+    for l in range(n_levels):
+        w = 4.0 ** -l
+        for fo, fg in ((oracle.F_UX, 1), (oracle.F_UY, 2)):
+            a, b = g.field(l, fg), o.field(l, fo)
+            m = np.isfinite(b)
+            num += w * np.sum((a[m] - b[m]) ** 2)
+            den += w * np.sum(b[m] ** 2)
+    return np.sqrt(num / den)
+
+
+def structure_mismatch(g, o, n_levels):
+    """Returns a list of differences in the grid and wall data built independently by both."""
+    bad = []
+    for l in range(n_levels):
+        gi, oi = g.level_info(l), o.level_info(l)
+        for k, gk in (("gx0", "gx0"), ("gy0", "gy0"), ("nx", "nx"), ("ny", "ny"),
+                      ("n_fluid", "n_fluid"), ("n_bnodes", "n_wall_nodes"),
+                      ("n_cut", "n_cut_links"), ("n_ghost", "n_ghost")):
+            if oi[k] != gi[gk]:
+                bad.append((l, k, oi[k], gi[gk]))
+        if bad:
+            continue
+        to = o.field(l, oracle.F_TYPE)
+        to = np.where(to == 5, 0, to)
+        tg = g.field(l, 5)
+        if not np.array_equal(to, tg):
+            bad.append((l, "type", int(np.sum(to != tg))))
+        do, dg = o.field(l, oracle.F_DIST), g.field(l, 6)
+        m = np.isfinite(do) & (do < 1e200)
+        if not np.allclose(do[m], dg[m], rtol=1e-12, atol=1e-12):
+            bad.append((l, "dist", float(np.max(np.abs(do[m] - dg[m])))))
+        wo, wg = o.wall(l), g.wall(l)
+        if len(wo) != len(wg):
+            bad.append((l, "wall count", len(wo), len(wg)))
+            continue
+        if len(wo):
+            if not np.array_equal(wo[:, :2], wg[:, :2]):
+                bad.append((l, "wall cells"))
+            for cols, name in (((2, 3), "IW"), ((4, 5), "normal"), ((6,), "d_WB")):
+                if not np.allclose(wo[:, cols], wg[:, cols], rtol=1e-11, atol=1e-11):
+                    bad.append((l, name, float(np.max(np.abs(wo[:, cols] - wg[:, cols])))))
+            if not np.array_equal(wo[:, 19:27] < 0, wg[:, 19:27] < 0):
+                bad.append((l, "cut links"))
+            elif not np.allclose(wo[:, 19:27], wg[:, 19:27], rtol=1e-11, atol=1e-11):
+                bad.append((l, "q", float(np.max(np.abs(wo[:, 19:27] - wg[:, 19:27])))))
+    return bad

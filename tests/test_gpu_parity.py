@@ -1,0 +1,115 @@
+"""HIP library vs. the FP64 oracle on the same seeded inputs (needs an MI355X).
+
+Tolerances:
+  * FP64 storage and arithmetic: relative L2 <= 1e-10 on the velocity vector
+    and on chi after the full channel run, friction velocity to 1e-10,
+    density to 1e-12 absolute (rounding-order differences only: the GPU uses
+    a closed-form central-moment collision in shifted variables, the oracle
+    solves with the transfer matrix of eq. (6)).
+  * FP32: relative L2 <= 1e-5 on velocity and chi over short windows.
+  * Grid, cut links and wall records are built independently by both sides
+    and must agree exactly (integers) or to 1e-11 (positions, q).
+"""
+import numpy as np
+import pytest
+
+import lbr_inputs as LI
+import oracle
+from tests import parity_util as U
+
+pytestmark = pytest.mark.gpu
+
+
+def _pair(case, storage):
+    o = oracle.Sim(case)
+    g = U.gpu_solver(case, storage)
+    return o, g
+
+
+def test_channel_structure():
+    case = LI.case_channel()
+    o, g = _pair(case, "f64")
+    assert U.structure_mismatch(g, o, 1) == []
+
+
+def test_airfoil_small_structure():
+    case = LI.case_airfoil_small()
+    o, g = _pair(case, "f64")
+    assert U.structure_mismatch(g, o, case["n_levels"]) == []
+
+
+@pytest.mark.parametrize("steps", [1, 10])
+def test_channel_fp64_short(steps):
+    case = LI.case_channel()
+    o, g = _pair(case, "f64")
+    U.channel_init(case, [o, g])
+    o.advance(steps)
+    g.advance(steps)
+    assert U.velocity_error(g, o, 1) < 1e-13
+    assert U.field_errors(g, o, 1, names=("chi",))[(0, "chi")] < 1e-13
+    assert U.density_error(g, o, 1) < 1e-14
+    wo, wg = o.wall(0), g.wall(0)
+    np.testing.assert_allclose(wg[:, 8], wo[:, 8], rtol=1e-12)          # u_tau
+    np.testing.assert_allclose(wg[:, 9:12], wo[:, 9:12], rtol=1e-11, atol=1e-16)
+
+
+def test_channel_fp64_full_run():
+    """2000 steps of the Re_tau = 2000 channel: u, chi, u_tau within 1e-10."""
+    case = LI.case_channel()
+    o, g = _pair(case, "f64")
+    U.channel_init(case, [o, g])
+    o.advance(case["steps"])
+    g.advance(case["steps"])
+    assert U.velocity_error(g, o, 1) < 1e-10
+    assert U.field_errors(g, o, 1, names=("chi",))[(0, "chi")] < 1e-10
+    assert U.density_error(g, o, 1) < 1e-12
+    np.testing.assert_allclose(g.wall(0)[:, 8], o.wall(0)[:, 8], rtol=1e-10)
+
+
+def test_airfoil_small_fp64():
+    case = LI.case_airfoil_small()
+    o, g = _pair(case, "f64")
+    for steps in (1, 4):
+        o.advance(steps)
+        g.advance(steps)
+        assert U.velocity_error(g, o, case["n_levels"]) < 1e-10
+        err = U.field_errors(g, o, case["n_levels"], names=("chi",))
+        assert max(err.values()) < 1e-10, err
+        assert U.density_error(g, o, case["n_levels"]) < 1e-12
+    lf = case["n_levels"] - 1
+    wo, wg = o.wall(lf), g.wall(lf)
+    np.testing.assert_allclose(wg[:, 8], wo[:, 8], rtol=1e-10)
+    np.testing.assert_allclose(g.forces(), o.forces(), rtol=1e-9, atol=1e-12)
+    cpo, cfo = o.surface(0)
+    cpg, cfg = g.surface(0)
+    np.testing.assert_allclose(cpg, cpo, rtol=1e-9, atol=1e-12)
+    np.testing.assert_allclose(cfg, cfo, rtol=1e-9, atol=1e-14)
+
+
+def test_airfoil_small_fp32_window():
+    case = LI.case_airfoil_small()
+    o, g = _pair(case, "f32")
+    o.advance(3)
+    g.advance(3)
+    assert U.velocity_error(g, o, case["n_levels"]) < 1e-5
+    err = U.field_errors(g, o, case["n_levels"], names=("chi",))
+    assert max(err.values()) < 1e-5, err
+
+
+def test_refined_box_conserves_mass_on_gpu():
+    case = LI.case_airfoil_small(alpha_deg=0.0)
+    case.update(bc=(LI.BC_PERIODIC,) * 4, body_mode=LI.BODY_REFINE, sa_mode=LI.SA_FROZEN,
+                chi_init=0.0, u_ref=0.05, nu0=0.002)
+    g = U.gpu_solver(case, "f64")
+    rng = np.random.default_rng(11)
+    for l in range(case["n_levels"]):
+        inf = g.level_info(l)
+        sh = (inf["ny"], inf["nx"])
+        g.init(l, rho=1 + 0.01 * rng.uniform(-1, 1, sh), ux=0.05 + 0.01 * rng.uniform(-1, 1, sh),
+               uy=0.01 * rng.uniform(-1, 1, sh), chi=np.zeros(sh))
+
+    def mass():
+        return sum(np.nansum(g.field(l, 0)) * 4.0**-l for l in range(case["n_levels"]))
+    m0 = mass()
+    g.advance(6)
+    assert abs(mass() - m0) / m0 < 1e-14
