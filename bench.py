@@ -1,0 +1,187 @@
+"""Throughput benchmark of the LBM-RANS step on one MI355X.
+
+Workload (default): single seeded airfoil-like body, FP32, Re_c = 6e6,
+Mach 0.15, 10 degrees incidence, 40-chord square domain, 8 levels from c/8 to
+c/1024 with distance-band refinement (about 2.0M fluid cells, 1.25e8 cell
+updates per coarse step).  A step is one coarse (level-0) step, i.e. the
+whole recursive multilevel cycle in which level l takes 2^l sub-steps.
+
+Prints one JSON line:  MLUPS = sum_l N_l 2^l per coarse step * steps / seconds.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS & % HBM peak, D2Q9 LBM-RANS step; FP16-store vs FP32 at equal Cf error"
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per cell update: populations read + write (18 x storage),
+# nu-tilde read + write (2 x 4), FP64 wall distance (8), one flag byte
+ALG_BYTES = {"f32": 18 * 4 + 8 + 8 + 1, "f16": 18 * 2 + 8 + 8 + 1, "bf16": 18 * 2 + 8 + 8 + 1,
+             "f64": 18 * 8 + 16 + 8 + 1}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_airfoil_2M_traffic.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_2601_18443_amd", "csrc", "lbr_kernels.hip")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    with open(KERNEL_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def measured_traffic(storage):
+    """HBM bytes per k_step launch from the committed rocprofv3 counter summary,
+    or None when the summary is missing or the kernel changed since."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256") != kernel_source_hash() or vals.get("storage") != storage:
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(case, seconds_hint=30.0):
+    """The FP64 oracle on the same workload: build the same grid, time one coarse step."""
+    import oracle
+    t0 = time.perf_counter()
+    sim = oracle.Sim(case)
+    tb = time.perf_counter() - t0
+    lups = sim.lups_per_coarse_step()
+    t0 = time.perf_counter()
+    sim.advance(1)
+    dt = time.perf_counter() - t0
+    log(f"oracle: build {tb:.1f} s, one coarse step {dt:.1f} s")
+    return {"value": lups / dt / 1e6, "unit": "MLUPS", "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"one coarse step ({lups} cell updates) of the same 8-level airfoil grid, "
+                      f"FP64, OpenMP, after building the grid ({tb:.0f} s, untimed)"}
+
+
+def copy_calibration(nbytes=1 << 30):
+    """A plain device copy of known size, for scaling the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    x = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    x.fill_(1.0)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "dispatches": 3}))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16", "f64"])
+    ap.add_argument("--graph", type=int, default=1, help="replay the coarse step from a HIP graph")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the multi-GPU path is not part of this build "
+              "(see DESIGN.md for how the step would shard)", file=sys.stderr)
+        sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
+
+    import torch
+    import lbr_inputs as LI
+    import paper_2601_18443_amd as P
+
+    case = LI.case_airfoil_cfg1()
+    log("building the 8-level airfoil grid on the GPU")
+    t0 = time.perf_counter()
+    sim = P.Solver(case, storage=args.storage)
+    sim.synchronize()
+    log(f"build {time.perf_counter() - t0:.1f} s")
+    lups = sim.lups_per_coarse_step()
+    finest = sim.level_info(case["n_levels"] - 1)
+    if args.graph:
+        sim.use_graph(True)
+    log(f"{lups} cell updates per coarse step; warmup {args.warmup}")
+    sim.advance(args.warmup)
+    sim.synchronize()
+
+    # timed region
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.advance(args.steps)
+    sim.synchronize()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    log(f"timed {args.steps} coarse steps in {dt:.3f} s")
+    # kernel durations: HIP events around every launch on the library's stream, over a
+    # window of the same length run with direct launches right after the timed region
+    sim.profile(True)
+    sim.advance(args.steps)
+    sim.synchronize()
+    kt = sim.profile(False)
+    log(f"event-timed kernels (us/launch): step all levels {kt[0]:.2f}, finest {kt[1]:.2f}, "
+        f"wall {kt[2]:.2f}, transfers {kt[3]:.2f}")
+    mlups = lups * args.steps / dt / 1e6
+    f = sim.forces()
+    if not np.all(np.isfinite(f)):
+        log("warning: non-finite force coefficients")
+
+    # roofline of the dominant kernel (k_step, all levels): algorithmic bytes per
+    # launch = ALG_BYTES x cell updates per launch; duration from the HIP events
+    n_levels = case["n_levels"]
+    launches_per_step = sum(2 ** l for l in range(n_levels))
+    bytes_per_launch = ALG_BYTES[args.storage] * lups / launches_per_step
+    roof = None
+    if kt[0] > 0:
+        achieved = bytes_per_launch / (kt[0] * 1e-6) / 1e9
+        traffic = measured_traffic(args.storage)
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None if traffic is None else round(traffic, 0),
+                "kernel": "k_step (all levels)", "avg_launch_us": round(kt[0], 3),
+                "finest_level_avg_launch_us": round(kt[1], 3),
+                "wall_kernel_avg_us": round(kt[2], 3), "transfer_avg_us": round(kt[3], 3),
+                "alg_bytes_per_launch": round(bytes_per_launch, 0)}
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on the same workload")
+        cpu = cpu_baseline(case)
+    out = {
+        "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1000 * dt / args.steps, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"f32": "f32", "f16": "f16-store/f32", "bf16": "bf16-store/f32", "f64": "f64"}[args.storage],
+        "data": "synthetic (seeded airfoil-like polyline)",
+        "config": {"workload": "single airfoil-like body, 8 levels c/8..c/1024, 40c domain, "
+                               "Re 6e6, M 0.15, AoA 10 deg",
+                   "cells": int(sum(sim.level_info(l)["n_fluid"] for l in range(n_levels))),
+                   "finest_cells": finest["n_fluid"], "lups_per_step": lups,
+                   "storage": args.storage, "graph": bool(args.graph)},
+        "roofline": roof, "cpu_baseline": cpu,
+        "forces": {"C_Df": f[0], "C_Dp": f[1], "C_D": f[2], "C_L": f[3]},
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

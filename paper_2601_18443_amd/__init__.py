@@ -155,7 +155,8 @@ class Solver:
             raise LbrError("liblbr needs a GPU (torch.cuda.is_available() is False)")
         self.device = torch.device(device)
         torch.cuda.set_device(self.device)
-        self.torch_stream = torch.cuda.current_stream(self.device)
+        # a stream of its own (default priority): the legacy default stream cannot be captured
+        self.torch_stream = torch.cuda.Stream(self.device)
         self.alloc = _TorchAllocator(self.device) if use_torch_memory else None
         self.case = case
         self.cfg = make_config(case, storage, C.c_void_p(self.torch_stream.cuda_stream), self.alloc)

@@ -9,12 +9,13 @@ LIB = os.path.join(HERE, "liblbr.so")
 SOURCES = ["csrc/lbr_kernels.hip", "csrc/lbr_host.cpp"]
 
 
-def build(verbose: bool = False, jobs: int = 2) -> str:
+def build(verbose: bool = False, jobs: int = 2, defines=(), out=None) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     flags = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-I" + os.path.join(ROOT, "include"), "-I" + os.path.join(HERE, "csrc"),
-             "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]
+             "-Wall", "-Wno-unused-function", "-Wno-unused-variable"] + ["-D" + d for d in defines]
+    lib = out or LIB
     objs = []
     procs = []
     for src in SOURCES:
@@ -27,14 +28,14 @@ def build(verbose: bool = False, jobs: int = 2) -> str:
     for p in procs:
         if p.wait() != 0:
             raise RuntimeError("hipcc failed")
-    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB + ".tmp"] + objs
+    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", lib + ".tmp"] + objs
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
+    os.replace(lib + ".tmp", lib)
     for o in objs:
         os.remove(o)
-    return LIB
+    return lib
 
 
 if __name__ == "__main__":

@@ -37,8 +37,8 @@ struct Level {
     std::vector<uint8_t> inside;
     std::vector<int32_t> bidx;
     std::vector<Node> nodes;
-    std::vector<uint32_t> tiles;
-    std::vector<int32_t> owned, ghosts, covb;
+    std::vector<uint32_t> rows;      // wave rows of k_step
+    std::vector<int32_t> owned, ghosts, covb, edge;
     int64_t n_fluid = 0, n_ghost = 0, n_cut = 0;
     // device
     void* f[2] = {nullptr, nullptr};
@@ -46,19 +46,20 @@ struct Level {
     void* chi[2] = {nullptr, nullptr};
     double* dist_dev = nullptr;
     uint8_t* flag_dev = nullptr;
-    int32_t* bidx_dev = nullptr;
-    uint32_t* tiles_dev = nullptr;
+    uint32_t* rows_dev = nullptr;
+    uint32_t* lmask_dev = nullptr;
     int32_t* ghosts_dev = nullptr;
     int32_t* covb_dev = nullptr;
     int32_t* owned_dev = nullptr;
-    void* bq = nullptr;
-    void* bw = nullptr;
+    int32_t* edge_dev = nullptr;
+    double* bq = nullptr;
     int32_t* bcell = nullptr;
     double* bgeo = nullptr;
     int32_t* st_cell = nullptr;
     double* st_wr = nullptr;
     double* st_wu = nullptr;
-    double* bstate = nullptr;
+    double* bstate = nullptr;   // friction velocity state carried between steps
+    double* bout = nullptr;     // wall model on the current state (output)
     double* snap = nullptr;
     int cur = 0;
     size_t bytes = 0;
@@ -87,6 +88,8 @@ struct lbr_ctx {
     lbr_config cfg{};
     std::string err = "";
     hipStream_t stream = nullptr;
+    hipStream_t side = nullptr;          // wall-node kernel runs here beside k_step
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     Prec prec = P_F32;
     size_t ssize = 4, csize = 4;
     double u_ref = 0, nu0 = 0;
@@ -145,6 +148,12 @@ void* dalloc(lbr_ctx* c, size_t bytes) {
     }
     if (p) c->allocs.push_back(p);
     return p;
+}
+
+// Allocation with `pad` spare elements on both ends; returns the shifted base.
+void* dalloc_padded(lbr_ctx* c, size_t elems, size_t esize, size_t pad) {
+    char* raw = static_cast<char*>(dalloc(c, (elems + 2 * pad) * esize));
+    return raw ? raw + pad * esize : nullptr;
 }
 
 void dfree(lbr_ctx* c, void* p) {
@@ -588,43 +597,71 @@ int stencils(lbr_ctx* c, Level& L, std::vector<int32_t>& sc, std::vector<double>
     return 0;
 }
 
-void make_tiles(Level& L) {
-    L.tiles.clear();
+// 64 x 4 tiles with work for k_step (owned fluid cells other than wall nodes
+// and domain-edge cells, or ghost cells).
+void make_rows(Level& L) {
+    L.rows.clear();
     const int ntx = L.box.pitch / TILE_X, nty = L.box.ny / TILE_Y;
     for (int ty = 0; ty < nty; ++ty)
         for (int tx = 0; tx < ntx; ++tx) {
             bool act = false;
             for (int y = 0; y < TILE_Y && !act; ++y)
                 for (int x = 0; x < TILE_X && !act; ++x) {
-                    const int t = L.flag[(long)(ty * TILE_Y + y) * L.box.pitch + tx * TILE_X + x] & F_TYPE;
-                    act = (t == T_FLUID || t == T_GHOST);
+                    const uint8_t f = L.flag[(long)(ty * TILE_Y + y) * L.box.pitch + tx * TILE_X + x];
+                    const int t = f & F_TYPE;
+                    act = (t == T_FLUID && !(f & (F_WALL | F_EDGE))) || t == T_GHOST;
                 }
-            if (act) L.tiles.push_back((uint32_t)tx | ((uint32_t)ty << 16));
+            if (act) L.rows.push_back((uint32_t)tx | ((uint32_t)ty << 16));
         }
 }
 
 int alloc_level(lbr_ctx* c, Level& L) {
     const size_t n = L.box.plane;
+    const size_t pad = (size_t)L.box.pitch + 1;    // k_step reads one row beyond both ends
     for (int b = 0; b < 2; ++b) {
-        L.f[b] = dalloc(c, 9 * n * c->ssize);
-        L.mac[b] = dalloc(c, 3 * n * c->csize);
-        L.chi[b] = dalloc(c, n * c->csize);
+        L.f[b] = dalloc_padded(c, 9 * n, c->ssize, pad);
+        L.mac[b] = dalloc_padded(c, 3 * n, c->csize, pad);
+        L.chi[b] = dalloc_padded(c, n, c->csize, pad);
         if (!L.f[b] || !L.mac[b] || !L.chi[b]) return set_err(c, LBR_ERR_OOM, "level %d: out of device memory", L.l);
-        HIPCHK(c, hipMemsetAsync(L.f[b], 0, 9 * n * c->ssize, c->stream));
-        HIPCHK(c, hipMemsetAsync(L.mac[b], 0, 3 * n * c->csize, c->stream));
-        HIPCHK(c, hipMemsetAsync(L.chi[b], 0, n * c->csize, c->stream));
+        HIPCHK(c, hipMemsetAsync(static_cast<char*>(L.f[b]) - pad * c->ssize, 0, (9 * n + 2 * pad) * c->ssize, c->stream));
+        HIPCHK(c, hipMemsetAsync(static_cast<char*>(L.mac[b]) - pad * c->csize, 0, (3 * n + 2 * pad) * c->csize, c->stream));
+        HIPCHK(c, hipMemsetAsync(static_cast<char*>(L.chi[b]) - pad * c->csize, 0, (n + 2 * pad) * c->csize, c->stream));
     }
-    L.bytes += 2 * n * (9 * c->ssize + 4 * c->csize);
+    L.bytes += 2 * (n + 2 * pad) * (9 * c->ssize + 4 * c->csize);
     std::vector<double> dclamp(L.d);
     if (c->prec != P_F64)
         for (double& v : dclamp) v = std::min(v, 1e18);
-    if (int r = upload(c, &L.dist_dev, dclamp, &L.bytes)) return r;
+    L.dist_dev = static_cast<double*>(dalloc_padded(c, n, sizeof(double), pad));
+    if (!L.dist_dev) return set_err(c, LBR_ERR_OOM, "level %d: out of device memory", L.l);
+    HIPCHK(c, hipMemsetAsync(L.dist_dev - pad, 0, (n + 2 * pad) * sizeof(double), c->stream));
+    HIPCHK(c, hipMemcpyAsync(L.dist_dev, dclamp.data(), n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    L.bytes += (n + 2 * pad) * sizeof(double);
     if (int r = upload(c, &L.flag_dev, L.flag, &L.bytes)) return r;
-    if (int r = upload(c, &L.bidx_dev, L.bidx, &L.bytes)) return r;
-    if (int r = upload(c, &L.tiles_dev, L.tiles, &L.bytes)) return r;
+    if (int r = upload(c, &L.rows_dev, L.rows, &L.bytes)) return r;
+    {
+        // static link mask: which pull sources are owned fluid cells / ghosts
+        std::vector<uint32_t> lm(n, 0u);
+        for (long k = 0; k < (long)n; ++k) {
+            const int t = L.flag[k] & F_TYPE;
+            if (t != T_GHOST && !(L.flag[k] & F_NEARGHOST)) continue;
+            const int gx = (int)(k % L.box.pitch) + L.box.gx0, gy = (int)(k / L.box.pitch) + L.box.gy0;
+            uint32_t m = 0;
+            for (int i = 0; i < 9; ++i) {
+                const int ts = L.type_at(gx - CXH[i], gy - CYH[i]);
+                if (ts == T_FLUID) m |= 1u << i;
+                if (ts == T_GHOST) m |= 1u << (16 + i);
+            }
+            lm[k] = m;
+        }
+        if (int r = upload(c, &L.lmask_dev, lm, &L.bytes)) return r;
+    }
     if (int r = upload(c, &L.ghosts_dev, L.ghosts, &L.bytes)) return r;
     if (int r = upload(c, &L.covb_dev, L.covb, &L.bytes)) return r;
     if (int r = upload(c, &L.owned_dev, L.owned, &L.bytes)) return r;
+    L.edge.clear();
+    for (int32_t k : L.owned)
+        if ((L.flag[k] & F_EDGE) && !(L.flag[k] & F_WALL)) L.edge.push_back(k);
+    if (int r = upload(c, &L.edge_dev, L.edge, &L.bytes)) return r;
     L.snap = static_cast<double*>(dalloc(c, std::max<size_t>(L.owned.size(), 1) * 2 * sizeof(double)));
     // wall records
     const int nb = (int)L.nodes.size();
@@ -640,21 +677,12 @@ int alloc_level(lbr_ctx* c, Level& L) {
     }
     if (int r = upload(c, &L.bcell, bcell, &L.bytes)) return r;
     if (int r = upload(c, &L.bgeo, geo, &L.bytes)) return r;
-    if (c->prec == P_F64) {
-        double* p;
-        if (int r = upload(c, &p, qd, &L.bytes)) return r;
-        L.bq = p;
-    } else {
-        std::vector<float> qf(qd.begin(), qd.end());
-        float* p;
-        if (int r = upload(c, &p, qf, &L.bytes)) return r;
-        L.bq = p;
-    }
-    L.bw = dalloc(c, std::max(nb, 1) * 4 * c->csize);
+    if (int r = upload(c, &L.bq, qd, &L.bytes)) return r;
     L.bstate = static_cast<double*>(dalloc(c, std::max(nb, 1) * 8 * sizeof(double)));
-    if (!L.bw || !L.bstate) return set_err(c, LBR_ERR_OOM, "wall state allocation failed");
-    HIPCHK(c, hipMemsetAsync(L.bw, 0, std::max(nb, 1) * 4 * c->csize, c->stream));
+    L.bout = static_cast<double*>(dalloc(c, std::max(nb, 1) * 8 * sizeof(double)));
+    if (!L.bstate || !L.bout) return set_err(c, LBR_ERR_OOM, "wall state allocation failed");
     HIPCHK(c, hipMemsetAsync(L.bstate, 0, std::max(nb, 1) * 8 * sizeof(double), c->stream));
+    HIPCHK(c, hipMemsetAsync(L.bout, 0, std::max(nb, 1) * 8 * sizeof(double), c->stream));
     std::vector<int32_t> sc;
     std::vector<double> wr, wu;
     if (int r = stencils(c, L, sc, wr, wu)) return r;
@@ -662,6 +690,24 @@ int alloc_level(lbr_ctx* c, Level& L) {
     if (int r = upload(c, &L.st_wr, wr, &L.bytes)) return r;
     if (int r = upload(c, &L.st_wu, wu, &L.bytes)) return r;
     return 0;
+}
+
+WallData wall_data(lbr_ctx* c, const Level& L) {
+    const lbr_config& cfg = c->cfg;
+    WallData w{};
+    w.nb = (int)L.nodes.size();
+    w.cell = L.bcell;
+    w.geo = L.bgeo;
+    w.st_cell = L.st_cell;
+    w.st_wr = L.st_wr;
+    w.st_wu = L.st_wu;
+    w.q = L.bq;
+    w.d_wr = cfg.wall_model == LBR_WALL_NISHIMURA ? 1.75 : cfg.d_wr;
+    w.d_wv = cfg.d_wv;
+    w.uw_lo[0] = cfg.u_wall[0]; w.uw_lo[1] = cfg.u_wall[1];
+    w.uw_hi[0] = cfg.u_wall[2]; w.uw_hi[1] = cfg.u_wall[3];
+    w.model = cfg.wall_model;
+    return w;
 }
 
 template <class ST, class CT>
@@ -676,11 +722,13 @@ void fill_step_args(lbr_ctx* c, int l, int substep, StepArgs<ST, CT>& a) {
     a.cdst = (CT*)L.chi[1 - L.cur];
     a.dist = L.dist_dev;
     a.flag = L.flag_dev;
-    a.bidx = L.bidx_dev;
-    a.bq = (const CT*)L.bq;
-    a.bw = (const CT*)L.bw;
-    a.tiles = L.tiles_dev;
-    a.ntiles = (int)L.tiles.size();
+    a.lmask = L.lmask_dev;
+    a.tiles = L.rows_dev;
+    a.ntiles = (int)L.rows.size();
+    a.edge = L.edge_dev;
+    a.nedge = (int)L.edge.size();
+    a.wall = wall_data(c, L);
+    a.wstate = L.bstate;
     a.box = L.box;
     a.dom.nxd = cfg.nx0 << l;
     a.dom.nyd = cfg.ny0 << l;
@@ -714,33 +762,35 @@ void fill_step_args(lbr_ctx* c, int l, int substep, StepArgs<ST, CT>& a) {
     }
 }
 
-template <class ST, class CT>
-void fill_wall_args(lbr_ctx* c, int l, WallArgs<ST, CT>& a) {
+// Wall model of one level on its current state, into L.bout (output only).
+int eval_wall(lbr_ctx* c, int l) {
     Level& L = c->lv[l];
-    const lbr_config& cfg = c->cfg;
-    a.nb = (int)L.nodes.size();
-    a.cell = L.bcell;
-    a.geo = L.bgeo;
-    a.st_cell = L.st_cell;
-    a.st_wr = L.st_wr;
-    a.st_wu = L.st_wu;
-    a.mac = (const CT*)L.mac[L.cur];
-    a.chi_next = (CT*)L.chi[1 - L.cur];
-    a.bw = (CT*)L.bw;
-    a.state = L.bstate;
-    a.plane = L.box.plane;
-    a.nu = L.nu;
-    a.d_wr = cfg.wall_model == LBR_WALL_NISHIMURA ? 1.75 : cfg.d_wr;
-    a.d_wv = cfg.d_wv;
-    a.uw_lo[0] = cfg.u_wall[0]; a.uw_lo[1] = cfg.u_wall[1];
-    a.uw_hi[0] = cfg.u_wall[2]; a.uw_hi[1] = cfg.u_wall[3];
-    a.model = cfg.wall_model;
-    a.write_chi = cfg.sa != LBR_SA_FROZEN;
+    if (L.nodes.empty()) return 0;
+    if (c->prec == P_F64) {
+        WallArgs<double> a{};
+        a.wall = wall_data(c, L);
+        a.mac = (const double*)L.mac[L.cur];
+        a.guess = L.bstate;
+        a.out = L.bout;
+        a.plane = L.box.plane;
+        a.nu = L.nu;
+        HIPCHK(c, launch_wall(c->prec, &a, c->stream));
+    } else {
+        WallArgs<float> a{};
+        a.wall = wall_data(c, L);
+        a.mac = (const float*)L.mac[L.cur];
+        a.guess = L.bstate;
+        a.out = L.bout;
+        a.plane = L.box.plane;
+        a.nu = L.nu;
+        HIPCHK(c, launch_wall(c->prec, &a, c->stream));
+    }
+    return 0;
 }
 
 enum { EV_STEP = 0, EV_STEP_FINE = 1, EV_WALL = 2, EV_XFER = 3 };
 
-hipEvent_t prof_begin(lbr_ctx* c) {
+hipEvent_t prof_begin(lbr_ctx* c, hipStream_t st) {
     if (!c->prof) return nullptr;
     while (c->ev.size() < c->ev_used + 2) {
         hipEvent_t e;
@@ -749,14 +799,14 @@ hipEvent_t prof_begin(lbr_ctx* c) {
         c->ev_kind.push_back(0);
     }
     hipEvent_t e = c->ev[c->ev_used];
-    (void)hipEventRecord(e, c->stream);
+    (void)hipEventRecord(e, st);
     return e;
 }
 
-void prof_end(lbr_ctx* c, hipEvent_t start, int kind) {
+void prof_end(lbr_ctx* c, hipEvent_t start, int kind, hipStream_t st) {
     if (!c->prof || !start) return;
     hipEvent_t e = c->ev[c->ev_used + 1];
-    (void)hipEventRecord(e, c->stream);
+    (void)hipEventRecord(e, st);
     c->ev_kind[c->ev_used] = kind;
     c->ev_used += 2;
 }
@@ -770,29 +820,30 @@ int do_step(lbr_ctx* c, int l, int substep) {
         case P_F16: fill_step_args(c, l, substep, *reinterpret_cast<StepArgs<__half, float>*>(buf)); break;
         default: fill_step_args(c, l, substep, *reinterpret_cast<StepArgs<__hip_bfloat16, float>*>(buf)); break;
     }
-    hipEvent_t e = prof_begin(c);
-    HIPCHK(c, launch_step(c->prec, buf, c->stream));
-    prof_end(c, e, l + 1 == (int)c->lv.size() ? EV_STEP_FINE : EV_STEP);
-    L.cur ^= 1;
-    if (!L.nodes.empty()) {
-        alignas(16) unsigned char wb[sizeof(WallArgs<double, double>)];
-        switch (c->prec) {
-            case P_F64: fill_wall_args(c, l, *reinterpret_cast<WallArgs<double, double>*>(wb)); break;
-            case P_F32: fill_wall_args(c, l, *reinterpret_cast<WallArgs<float, float>*>(wb)); break;
-            case P_F16: fill_wall_args(c, l, *reinterpret_cast<WallArgs<__half, float>*>(wb)); break;
-            default: fill_wall_args(c, l, *reinterpret_cast<WallArgs<__hip_bfloat16, float>*>(wb)); break;
-        }
-        hipEvent_t e2 = prof_begin(c);
-        HIPCHK(c, launch_wall(c->prec, wb, c->stream));
-        prof_end(c, e2, EV_WALL);
+    const bool walls = !L.nodes.empty() || !L.edge.empty();
+    if (walls) {
+        // wall nodes and domain-edge cells on the side stream, concurrently with
+        // the rest of the level (disjoint cells, same source state)
+        HIPCHK(c, hipEventRecord(c->ev_fork, c->stream));
+        HIPCHK(c, hipStreamWaitEvent(c->side, c->ev_fork, 0));
+        hipEvent_t e2 = prof_begin(c, c->side);
+        if (!L.nodes.empty()) HIPCHK(c, launch_boundary(c->prec, buf, c->side));
+        if (!L.edge.empty()) HIPCHK(c, launch_edge(c->prec, buf, c->side));
+        prof_end(c, e2, EV_WALL, c->side);
+        HIPCHK(c, hipEventRecord(c->ev_join, c->side));
     }
+    hipEvent_t e = prof_begin(c, c->stream);
+    HIPCHK(c, launch_step(c->prec, buf, c->stream));
+    prof_end(c, e, l + 1 == (int)c->lv.size() ? EV_STEP_FINE : EV_STEP, c->stream);
+    if (walls) HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
+    L.cur ^= 1;
     return 0;
 }
 
 int do_transfers(lbr_ctx* c, int l) {
     Level& C = c->lv[l];
     Level& F = c->lv[l + 1];
-    hipEvent_t e = prof_begin(c);
+    hipEvent_t e = prof_begin(c, c->stream);
     RestrictArgs r{};
     r.n = (int)C.covb.size();
     r.list = C.covb_dev;
@@ -813,7 +864,7 @@ int do_transfers(lbr_ctx* c, int l) {
     f.fmac0 = F.mac[0]; f.fmac1 = F.mac[1];
     f.fchi0 = F.chi[0]; f.fchi1 = F.chi[1];
     HIPCHK(c, launch_fill(c->prec, f, c->stream));
-    prof_end(c, e, EV_XFER);
+    prof_end(c, e, EV_XFER, c->stream);
     return 0;
 }
 
@@ -858,16 +909,6 @@ int init_level(lbr_ctx* c, int l, const double* rho, const double* ux, const dou
     a.nu = L.nu; a.fx = L.fx; a.fy = L.fy; a.omega_b = c->cfg.omega_b;
     HIPCHK(c, launch_init(c->prec, a, c->stream));
     HIPCHK(c, hipMemsetAsync(L.bstate, 0, std::max<size_t>(L.nodes.size(), 1) * 8 * sizeof(double), c->stream));
-    if (!L.nodes.empty()) {
-        alignas(16) unsigned char wb[sizeof(WallArgs<double, double>)];
-        switch (c->prec) {
-            case P_F64: fill_wall_args(c, l, *reinterpret_cast<WallArgs<double, double>*>(wb)); break;
-            case P_F32: fill_wall_args(c, l, *reinterpret_cast<WallArgs<float, float>*>(wb)); break;
-            case P_F16: fill_wall_args(c, l, *reinterpret_cast<WallArgs<__half, float>*>(wb)); break;
-            default: fill_wall_args(c, l, *reinterpret_cast<WallArgs<__hip_bfloat16, float>*>(wb)); break;
-        }
-        HIPCHK(c, launch_wall(c->prec, wb, c->stream));
-    }
     HIPCHK(c, hipStreamSynchronize(c->stream));
     dfree(c, dv);
     return 0;
@@ -933,14 +974,15 @@ int build_surface(lbr_ctx* c, const std::vector<double>& seg) {
 
 int surface_eval(lbr_ctx* c, int body, double* cp, double* cf, double sums[4]) {
     const SurfaceBody& sb = c->surf[body];
+    if (int r = eval_wall(c, c->wall_level)) return r;
     const Level& L = c->lv[c->wall_level];
     SurfaceArgs a{};
     a.nseg = sb.nseg;
     a.seg = sb.seg;
     a.near = sb.near;
     a.wgt = sb.wgt;
-    a.bstate = L.bstate;
-    a.bw = L.bw;
+    a.bstate = L.bout;
+    a.bw = nullptr;
     a.u_ref = c->u_ref;
     a.rho_ref = c->cfg.rho_ref;
     a.cp = c->surf_cp;
@@ -1050,6 +1092,11 @@ int lbr_set_geometry(lbr_ctx* c, int32_t n_bodies, const int32_t* n_pts, const d
 int lbr_build(lbr_ctx* c) {
     if (!c) return LBR_ERR_INVALID_ARG;
     if (c->built) return set_err(c, LBR_ERR_STATE, "already built");
+    if (!c->side) {
+        HIPCHK(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+        HIPCHK(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+        HIPCHK(c, hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+    }
     // segment table: ax, ay, bx, by, body (level-0 lattice units)
     std::vector<double> seg;
     for (size_t b = 0; b < c->npts.size(); ++b) {
@@ -1073,7 +1120,7 @@ int lbr_build(lbr_ctx* c) {
     for (Level& L : c->lv)
         if (int r = build_walls(c, L, seg)) return r;
     for (Level& L : c->lv) {
-        make_tiles(L);
+        make_rows(L);
         if (int r = alloc_level(c, L)) return r;
         L.dbody.clear();
         L.dbody.shrink_to_fit();
@@ -1097,7 +1144,7 @@ int lbr_level_info(lbr_ctx* c, int32_t level, lbr_level_desc* out) {
     out->n_wall_nodes = (int64_t)L.nodes.size();
     out->n_cut_links = L.n_cut;
     out->n_ghost = L.n_ghost;
-    out->n_tiles = (int64_t)L.tiles.size();
+    out->n_tiles = (int64_t)L.rows.size();
     out->bytes = (int64_t)L.bytes;
     return LBR_OK;
 }
@@ -1205,7 +1252,8 @@ int lbr_read_wall(lbr_ctx* c, int32_t level, double* dst) {
     const int nb = (int)L.nodes.size();
     if (nb == 0) return LBR_OK;
     std::vector<double> st((size_t)nb * 8);
-    HIPCHK(c, hipMemcpyAsync(st.data(), L.bstate, st.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    if (int r = eval_wall(c, level)) return r;
+    HIPCHK(c, hipMemcpyAsync(st.data(), L.bout, st.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     const double U = c->u_ref, rr = c->cfg.rho_ref;
     for (int b = 0; b < nb; ++b) {
@@ -1339,10 +1387,14 @@ void lbr_destroy(lbr_ctx* c) {
     (void)hipStreamSynchronize(c->stream);
     if (c->graph) (void)hipGraphExecDestroy(c->graph);
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+    if (c->side) (void)hipStreamSynchronize(c->side);
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     for (void* p : c->allocs) {
         if (c->cfg.free_fn) c->cfg.free_fn(p, c->cfg.alloc_user);
         else (void)hipFree(p);
     }
+    if (c->side) (void)hipStreamDestroy(c->side);
     delete c;
 }
 

@@ -25,6 +25,7 @@ enum : uint8_t {
 constexpr int TILE_X = 64;   // one wavefront per tile row
 constexpr int TILE_Y = 4;    // four wavefronts per 256-thread workgroup
 constexpr int MAX_STENCIL = 16;
+constexpr int ROWS_PER_GROUP = 4;   // wave rows per workgroup
 
 // Geometry of a level's storage box: global cell (gx, gy) of the level lives
 // at local (gx - gx0, gy - gy0), linear index ly * pitch + lx; every field is
@@ -42,6 +43,19 @@ struct Domain {
     int periodic_x;
 };
 
+// Link-wise wall data of one level (Sections 2.1 and 2.3).
+struct WallData {
+    int nb;
+    const int32_t* cell;             // storage index of each boundary node B
+    const double* geo;               // [nb][6] IW (x, y), n (x, y), d_WB, body
+    const int32_t* st_cell;          // [nb][MAX_STENCIL] storage index of R-stencil cells (-1 unused)
+    const double* st_wr;             // [nb][MAX_STENCIL] IDW weights for rho_R
+    const double* st_wu;             // [nb][MAX_STENCIL] LSQ weights for u_R
+    const double* q;                 // [nb][8] wall fraction of links 1..8 (-1: not cut)
+    double d_wr, d_wv, uw_lo[2], uw_hi[2];
+    int model;
+};
+
 template <class ST, class CT>
 struct StepArgs {
     const ST* fsrc;  ST* fdst;       // 9 population planes (shifted by w_i)
@@ -49,36 +63,33 @@ struct StepArgs {
     const CT* csrc;  CT* cdst;       // chi = nu~ / nu
     const double* dist;              // wall distance (level lattice units)
     const uint8_t* flag;
-    const int32_t* bidx;             // wall-node index of F_WALL cells
-    const CT* bq;                    // [nb][8] wall fraction q of links 1..8 (-1: not cut)
-    const CT* bw;                    // [nb][4] u_W (x, y), rho_W, unused
-    const uint32_t* tiles;           // active tiles, (tx | ty << 16)
+    const uint32_t* lmask;           // per cell: bit i, source c - c_i is owned fluid;
+                                     // bit 16 + i, source is a ghost
+    const uint32_t* tiles;           // active 64 x 4 tiles, (tx | ty << 16)
     int ntiles;
+    const int32_t* edge;             // level-0 domain-edge cells that are not wall nodes
+    int nedge;
     Box box;
     Domain dom;
-    int gx_origin_unused;
     CT nu, fx, fy, omega_b, u_in, chi_in;
     int sa_mode, bb_halfway, frozen;
     int substep;                     // 1 or 2 within the parent's step (0 on level 0)
     const ST* fcoarse; Box cbox;     // parent level populations (ghost transfer)
     const ST* ffine;   Box fbox;     // child level populations (coalescence)
+    WallData wall;                   // boundary nodes of this level (k_boundary)
+    double* wstate;                  // [nb][8] u_tau, u_Rt (x, y), rho_W, u_W (x, y), spare
 };
 
-template <class ST, class CT>
+// Wall model evaluated on the current state for output (does not touch the
+// friction velocities the next step starts its Newton iteration from).
+template <class CT>
 struct WallArgs {
-    int nb;
-    const int32_t* cell;             // storage index of B
-    const double* geo;               // [nb][6] IW (x, y), n (x, y), d_WB, body
-    const int32_t* st_cell;          // [nb][MAX_STENCIL] storage index (-1 unused)
-    const double* st_wr;             // [nb][MAX_STENCIL] IDW weights for rho_R
-    const double* st_wu;             // [nb][MAX_STENCIL] LSQ weights for u_R
-    const CT* mac;                   // current macroscopic planes
-    CT* chi_next;                    // chi buffer the next step writes (Dirichlet at B)
-    CT* bw;                          // [nb][4]
-    double* state;                   // [nb][8] u_tau, u_Rt (x, y), rho_W, u_W (x, y), spare
+    WallData wall;
+    const CT* mac;
+    const double* guess;             // [nb][8], u_tau in column 0
+    double* out;                     // [nb][8]
     long plane;
-    double nu, d_wr, d_wv, uw_lo[2], uw_hi[2];
-    int model, write_chi;
+    double nu;
 };
 
 struct FillArgs {
@@ -122,6 +133,8 @@ hipError_t launch_geometry(int nx, int ny, int gx0, int gy0, double scale, int n
                            const int* npts_off, const double* poly, int solid,
                            double* dist, uint8_t* inside, hipStream_t s);
 hipError_t launch_step(Prec p, const void* args, hipStream_t s);
+hipError_t launch_boundary(Prec p, const void* args, hipStream_t s);
+hipError_t launch_edge(Prec p, const void* args, hipStream_t s);
 hipError_t launch_wall(Prec p, const void* args, hipStream_t s);
 hipError_t launch_fill(Prec p, const FillArgs& a, hipStream_t s);
 hipError_t launch_restrict(Prec p, const RestrictArgs& a, hipStream_t s);

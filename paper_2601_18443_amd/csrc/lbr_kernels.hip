@@ -196,209 +196,8 @@ __device__ __forceinline__ T eddy_viscosity(T chi, T nu) {
 }
 
 // ---------------------------------------------------------------------------
-// k_step
-// ---------------------------------------------------------------------------
-template <class ST, class CT>
-__device__ __forceinline__ CT coarse_val(const StepArgs<ST, CT>& a, int i, int gx, int gy) {
-    const long cc = (long)((gy >> 1) - a.cbox.gy0) * a.cbox.pitch + ((gx >> 1) - a.cbox.gx0);
-    return Cv<ST, CT>::ld(a.fcoarse + i * a.cbox.plane + cc);
-}
-
-// Yu's interpolated bounce-back (step 6 of the VN procedure), or eq (24).
-template <class ST, class CT>
-__device__ CT bounce(const StepArgs<ST, CT>& a, int b, int i, long c, int gx, int gy, CT q) {
-    const int o = OPP[i];
-    const long P = a.box.plane;
-    const CT uwx = a.bw[4 * b + 0], uwy = a.bw[4 * b + 1], rhow = a.bw[4 * b + 2];
-    const CT fo_b = Cv<ST, CT>::ld(a.fsrc + o * P + c);
-    const CT mom = CT(2) * wq<CT>(o) * rhow * (CT(CX[i]) * uwx + CT(CY[i]) * uwy) * CT(3);
-    if (!a.bb_halfway && a.bq[8 * b + i - 1] < CT(0)) {
-        int fx2 = gx + CX[i];
-        if (a.dom.periodic_x) fx2 = (fx2 + a.dom.nxd) % a.dom.nxd;
-        const long c2 = (long)(gy + CY[i] - a.box.gy0) * a.box.pitch + (fx2 - a.box.gx0);
-        if ((a.flag[c2] & F_TYPE) == T_FLUID) {
-            const CT fo_f2 = Cv<ST, CT>::ld(a.fsrc + o * P + c2);
-            const CT fi_b = Cv<ST, CT>::ld(a.fsrc + i * P + c);
-            const CT fw_o = q * fo_b + (CT(1) - q) * fo_f2;
-            const CT fw_i = fw_o + mom;
-            return fw_i + (q / (CT(1) + q)) * (fi_b - fw_i);
-        }
-    }
-    return fo_b + mom;
-}
-
-// Post-stream value of direction i at (gx, gy) for a cell next to the outlet
-// (interior or across a symmetry / periodic y edge).
-template <class ST, class CT>
-__device__ __forceinline__ CT poststream(const StepArgs<ST, CT>& a, int i, int gx, int gy) {
-    int sx = gx - CX[i], sy = gy - CY[i], di = i;
-    if (sy < 0 || sy >= a.dom.nyd) {
-        const int side = sy < 0 ? 2 : 3;
-        if (a.dom.bc[side] == BC_PERIODIC) sy = (sy + a.dom.nyd) % a.dom.nyd;
-        else { sy = gy; di = MIRY[i]; }
-    }
-    const long cs = (long)(sy - a.box.gy0) * a.box.pitch + (sx - a.box.gx0);
-    return Cv<ST, CT>::ld(a.fsrc + di * a.box.plane + cs);
-}
-
-template <class ST, class CT>
-__global__ __launch_bounds__(256) void k_step(const StepArgs<ST, CT> a) {
-    const int per = (a.ntiles + 7) >> 3;
-    const int t = (blockIdx.x & 7) * per + (blockIdx.x >> 3);   // tiles of one XCD are adjacent
-    if (t >= a.ntiles) return;
-    const uint32_t tile = a.tiles[t];
-    const int lx = (int)(tile & 0xffffu) * TILE_X + (threadIdx.x & 63);
-    const int ly = (int)(tile >> 16) * TILE_Y + (threadIdx.x >> 6);
-    const int pitch = a.box.pitch;
-    const long P = a.box.plane;
-    const long c = (long)ly * pitch + lx;
-    const uint8_t fl = a.flag[c];
-    const int type = fl & F_TYPE;
-    const int gx = lx + a.box.gx0, gy = ly + a.box.gy0;
-
-    if (type == T_GHOST) {
-        // fine band over a coarse interface cell: carries exploded coarse populations
-        // (first sub-step) and fine populations one cell per sub-step, no collision
-#pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            const long cs = c - CX[i] - (long)CY[i] * pitch;
-            const int st = a.flag[cs] & F_TYPE;
-            CT v;
-            if (st == T_FLUID || (st == T_GHOST && a.substep == 2))
-                v = Cv<ST, CT>::ld(a.fsrc + i * P + cs);
-            else if (a.substep == 1)
-                v = coarse_val(a, i, gx - CX[i], gy - CY[i]);
-            else
-                v = coarse_val(a, i, gx - 2 * CX[i], gy - 2 * CY[i]);
-            Cv<ST, CT>::st(a.fdst + i * P + c, v);
-        }
-        return;
-    }
-    if (type != T_FLUID) return;
-
-    // ---- SA-neg: chi at the new time level
-    CT chi_new;
-    const bool at_inlet = (fl & F_EDGE) && gx == 0 && a.dom.bc[0] == BC_INLET;
-    const bool at_outlet = (fl & F_EDGE) && gx == a.dom.nxd - 1 && a.dom.bc[1] == BC_OUTLET;
-    if (a.frozen) {
-        chi_new = a.csrc[c];
-    } else if (fl & F_WALL) {
-        chi_new = a.cdst[c];                 // Dirichlet value written by the wall model
-    } else if (at_inlet) {
-        chi_new = a.chi_in;
-    } else if (at_outlet) {
-        chi_new = a.csrc[c - 1];             // first-order extrapolation
-    } else {
-        CT nt[9], u[9], v[9];
-#pragma unroll
-        for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll
-            for (int dx = -1; dx <= 1; ++dx) {
-                const int k = (dy + 1) * 3 + dx + 1;
-                long cs = c + dx + (long)dy * pitch;
-                CT sgn = CT(1);
-                if (fl & F_EDGE) {
-                    int sx = gx + dx, sy = gy + dy;
-                    if (sx < 0 || sx >= a.dom.nxd) sx = (sx + a.dom.nxd) % a.dom.nxd;
-                    if (sy < 0 || sy >= a.dom.nyd) {
-                        const int side = sy < 0 ? 2 : 3;
-                        if (a.dom.bc[side] == BC_PERIODIC) sy = (sy + a.dom.nyd) % a.dom.nyd;
-                        else { sy = (sy < 0) ? -1 - sy : 2 * a.dom.nyd - 1 - sy; sgn = CT(-1); }
-                    }
-                    cs = (long)(sy - a.box.gy0) * pitch + (sx - a.box.gx0);
-                }
-                nt[k] = a.csrc[cs] * a.nu;
-                u[k] = a.msrc[P + cs];
-                v[k] = sgn * a.msrc[2 * P + cs];
-            }
-        CT d = CT(a.dist[c]);
-        chi_new = sa_update(nt, u, v, a.nu, d, a.sa_mode == 2) / a.nu;
-    }
-
-    // ---- streaming (pull)
-    CT s[9];
-    if (!(fl & (F_WALL | F_IFACE | F_NEARGHOST | F_EDGE))) {
-#pragma unroll
-        for (int i = 0; i < 9; ++i)
-            s[i] = Cv<ST, CT>::ld(a.fsrc + i * P + c - CX[i] - (long)CY[i] * pitch);
-    } else if (fl & F_IFACE) {
-        // coalescence: mean of the four children of the finer band
-        const long f0 = (long)(2 * gy - a.fbox.gy0) * a.fbox.pitch + (2 * gx - a.fbox.gx0);
-#pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            const ST* p = a.ffine + i * a.fbox.plane + f0;
-            s[i] = CT(0.25) * ((Cv<ST, CT>::ld(p) + Cv<ST, CT>::ld(p + 1)) +
-                               (Cv<ST, CT>::ld(p + a.fbox.pitch) + Cv<ST, CT>::ld(p + a.fbox.pitch + 1)));
-        }
-    } else {
-        const int b = (fl & F_WALL) ? a.bidx[c] : -1;
-        for (int i = 0; i < 9; ++i) {
-            if (b >= 0 && i != 0) {
-                const CT q = a.bq[8 * b + OPP[i] - 1];
-                if (q >= CT(0)) { s[i] = bounce(a, b, i, c, gx, gy, q); continue; }
-            }
-            int sx = gx - CX[i], sy = gy - CY[i], di = i;
-            if (fl & F_EDGE) {
-                if (sx < 0 || sx >= a.dom.nxd) {
-                    if (!a.dom.periodic_x) { s[i] = CT(0); continue; }   // inlet / outlet unknown
-                    sx = (sx + a.dom.nxd) % a.dom.nxd;
-                }
-                if (sy < 0 || sy >= a.dom.nyd) {
-                    const int side = sy < 0 ? 2 : 3;
-                    if (a.dom.bc[side] == BC_PERIODIC) sy = (sy + a.dom.nyd) % a.dom.nyd;
-                    else if (a.dom.bc[side] == BC_SYMMETRY) { sy = gy; di = MIRY[i]; }
-                    else { s[i] = CT(0); continue; }
-                }
-            }
-            const long cs = (long)(sy - a.box.gy0) * pitch + (sx - a.box.gx0);
-            if ((fl & F_NEARGHOST) && a.substep == 1 && (a.flag[cs] & F_TYPE) == T_GHOST)
-                s[i] = coarse_val(a, di, sx, sy);
-            else
-                s[i] = Cv<ST, CT>::ld(a.fsrc + di * P + cs);
-        }
-        if (at_inlet) {
-            // Zou-He velocity inlet: unknowns have c_x = +1
-            const CT ui = a.u_in;
-            const CT rho = (CT(1) + s[0] + s[3] + s[4] + CT(2) * (s[2] + s[6] + s[8])) / (CT(1) - ui);
-            s[1] = s[2] + CT(2.0 / 3.0) * rho * ui;
-            s[5] = s[6] - CT(0.5) * (s[3] - s[4]) + rho * ui * CT(1.0 / 6.0);
-            s[7] = s[8] + CT(0.5) * (s[3] - s[4]) + rho * ui * CT(1.0 / 6.0);
-        }
-        if (at_outlet) {
-            // unknowns (c_x = -1) extrapolated from the two upstream cells
-            for (int i = 0; i < 9; ++i)
-                if (CX[i] == -1)
-                    s[i] = CT(2) * poststream(a, i, gx - 1, gy) - poststream(a, i, gx - 2, gy);
-        }
-    }
-
-    // ---- macroscopic values (eq (3) with the half-force shift)
-    CT drho = CT(0), jx = CT(0), jy = CT(0);
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        drho += s[i];
-        jx += CT(CX[i]) * s[i];
-        jy += CT(CY[i]) * s[i];
-    }
-    const CT rho = CT(1) + drho;
-    const CT ux = (jx + CT(0.5) * a.fx) / rho;
-    const CT uy = (jy + CT(0.5) * a.fy) / rho;
-    a.mdst[c] = rho;
-    a.mdst[P + c] = ux;
-    a.mdst[2 * P + c] = uy;
-    a.cdst[c] = chi_new;
-
-    // ---- collision with nu_eff = nu + nu_t(chi) (eqs (9), (11))
-    const CT nu_eff = a.nu + eddy_viscosity(chi_new, a.nu);
-    const CT omega = CT(1) / (CT(3) * nu_eff + CT(0.5));
-    collide(s, drho, ux, uy, omega, a.omega_b, a.fx, a.fy);
-#pragma unroll
-    for (int i = 0; i < 9; ++i) Cv<ST, CT>::st(a.fdst + i * P + c, s[i]);
-}
-
-// ---------------------------------------------------------------------------
-// Wall model: steps 1-5 of the VN procedure (Section 2.3), FP64, one thread
-// per boundary node.
+// Wall function and friction velocity (eqs (21)-(22) of Section 2.2; step 3
+// of the VN procedure), FP64.
 // ---------------------------------------------------------------------------
 constexpr double WF_B = 5.033908790505579, WF_A1 = 8.148221580024245,
                  WF_A2 = -6.9287093849022945, WF_B1 = 7.4600876082527945,
@@ -442,44 +241,44 @@ __device__ double friction_velocity(double ut, double d, double nu, double guess
     return u;
 }
 
-template <class ST, class CT>
-__global__ __launch_bounds__(256) void k_wall(const WallArgs<ST, CT> a) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= a.nb) return;
-    const long P = a.plane;
-    const int cell = a.cell[b];
-    const double* g = a.geo + 6 * b;
-    double* st = a.state + 8 * b;
+// Steps 1-5 of the VN procedure (Section 2.3) for wall node b, from the
+// macroscopic planes `mac`: rho_R and u_R with precomputed IDW / LSQ weights,
+// tangential part, u_tau by Newton, u_V and the slip velocity of eq (28)
+// (or eq (31)); rho_W = rho_R.  out: u_tau, u_Rt (x, y), rho_W, u_W (x, y).
+template <class CT>
+__device__ void wall_model(const WallData& w, int b, const CT* mac, long P, double nu,
+                           double guess, double out[6]) {
+    const double* g = w.geo + 6 * b;
     double uwx = 0.0, uwy = 0.0, rhow, utau = 0.0, tx = 0.0, ty = 0.0;
-    if (a.model == 2 || a.model == 3) {
-        rhow = (double)a.mac[cell];
-        if (a.model == 3) {
-            const double* uw = (g[5] == -2.0) ? a.uw_hi : a.uw_lo;
+    if (w.model == 2 || w.model == 3) {
+        rhow = (double)mac[w.cell[b]];
+        if (w.model == 3) {
+            const double* uw = (g[5] == -2.0) ? w.uw_hi : w.uw_lo;
             uwx = uw[0];
             uwy = uw[1];
         }
     } else {
         double rr = 0.0, ux = 0.0, uy = 0.0;
         for (int j = 0; j < MAX_STENCIL; ++j) {
-            const int cj = a.st_cell[MAX_STENCIL * b + j];
+            const int cj = w.st_cell[MAX_STENCIL * b + j];
             if (cj < 0) break;
-            rr += a.st_wr[MAX_STENCIL * b + j] * (double)a.mac[cj];
-            const double wu = a.st_wu[MAX_STENCIL * b + j];
-            ux += wu * (double)a.mac[P + cj];
-            uy += wu * (double)a.mac[2 * P + cj];
+            rr += w.st_wr[MAX_STENCIL * b + j] * (double)mac[cj];
+            const double wu = w.st_wu[MAX_STENCIL * b + j];
+            ux += wu * (double)mac[P + cj];
+            uy += wu * (double)mac[2 * P + cj];
         }
         const double un = ux * g[2] + uy * g[3];                 // step 2
         tx = ux - un * g[2];
         ty = uy - un * g[3];
         const double ut = sqrt(tx * tx + ty * ty);
-        utau = friction_velocity(ut, a.d_wr, a.nu, st[0]);      // step 3
+        utau = friction_velocity(ut, w.d_wr, nu, guess);         // step 3
         double uw;
-        if (a.model == 1) {                                      // eq (31)
-            const double yr = a.d_wr * utau / a.nu;
-            uw = ut - utau * utau * a.d_wr / (a.nu + a.nu * KAPPA * yr);
+        if (w.model == 1) {                                      // eq (31)
+            const double yr = w.d_wr * utau / nu;
+            uw = ut - utau * utau * w.d_wr / (nu + nu * KAPPA * yr);
         } else {                                                 // steps 4-5, eq (28)
-            const double yv = a.d_wv * utau / a.nu;
-            uw = utau * uplus(yv) - utau * utau * a.d_wv / (a.nu + a.nu * KAPPA * yv);
+            const double yv = w.d_wv * utau / nu;
+            uw = utau * uplus(yv) - utau * utau * w.d_wv / (nu + nu * KAPPA * yv);
         }
         if (ut > 0.0) {
             uwx = uw * tx / ut;
@@ -487,17 +286,338 @@ __global__ __launch_bounds__(256) void k_wall(const WallArgs<ST, CT> a) {
         }
         rhow = rr;                                               // step 6: rho_W = rho_R
     }
-    a.bw[4 * b + 0] = (CT)uwx;
-    a.bw[4 * b + 1] = (CT)uwy;
-    a.bw[4 * b + 2] = (CT)rhow;
-    a.bw[4 * b + 3] = CT(0);
-    st[0] = utau;
-    st[1] = tx;
-    st[2] = ty;
-    st[3] = rhow;
-    st[4] = uwx;
-    st[5] = uwy;
-    if (a.write_chi) a.chi_next[cell] = (CT)(KAPPA * utau * g[4] / a.nu);
+    out[0] = utau; out[1] = tx; out[2] = ty; out[3] = rhow; out[4] = uwx; out[5] = uwy;
+}
+
+// ---------------------------------------------------------------------------
+// Pieces of the per-cell update shared by k_step and k_boundary.
+// ---------------------------------------------------------------------------
+template <class ST, class CT>
+__device__ __forceinline__ CT coarse_val(const StepArgs<ST, CT>& a, int i, int gx, int gy) {
+    const long cc = (long)((gy >> 1) - a.cbox.gy0) * a.cbox.pitch + ((gx >> 1) - a.cbox.gx0);
+    return Cv<ST, CT>::ld(a.fcoarse + i * a.cbox.plane + cc);
+}
+
+// Pull of direction i into (gx, gy): domain rules of level 0 (periodic wrap,
+// specular reflection at symmetry edges) and the coarse band on the first
+// sub-step.  Returns false for an unknown population (inlet / outlet side).
+template <class ST, class CT>
+__device__ bool pull_general(const StepArgs<ST, CT>& a, uint8_t fl, int i, int gx, int gy, CT& out) {
+    int sx = gx - CX[i], sy = gy - CY[i], di = i;
+    if (fl & F_EDGE) {
+        if (sx < 0 || sx >= a.dom.nxd) {
+            if (!a.dom.periodic_x) return false;
+            sx = (sx + a.dom.nxd) % a.dom.nxd;
+        }
+        if (sy < 0 || sy >= a.dom.nyd) {
+            const int side = sy < 0 ? 2 : 3;
+            if (a.dom.bc[side] == BC_PERIODIC) sy = (sy + a.dom.nyd) % a.dom.nyd;
+            else if (a.dom.bc[side] == BC_SYMMETRY) { sy = gy; di = MIRY[i]; }
+            else return false;
+        }
+    }
+    const long cs = (long)(sy - a.box.gy0) * a.box.pitch + (sx - a.box.gx0);
+    if ((fl & F_NEARGHOST) && a.substep == 1 && (a.flag[cs] & F_TYPE) == T_GHOST)
+        out = coarse_val(a, di, sx, sy);
+    else
+        out = Cv<ST, CT>::ld(a.fsrc + di * a.box.plane + cs);
+    return true;
+}
+
+// SA stencil of an edge cell: periodic wrap, mirror at symmetry edges (u_y flips).
+template <class ST, class CT>
+__device__ void gather_edge(const StepArgs<ST, CT>& a, int gx, int gy, CT nt[9], CT u[9], CT v[9]) {
+    const long P = a.box.plane;
+    for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+            const int k = (dy + 1) * 3 + dx + 1;
+            int sx = gx + dx, sy = gy + dy;
+            CT sgn = CT(1);
+            if (sx < 0 || sx >= a.dom.nxd) sx = (sx + a.dom.nxd) % a.dom.nxd;
+            if (sy < 0 || sy >= a.dom.nyd) {
+                const int side = sy < 0 ? 2 : 3;
+                if (a.dom.bc[side] == BC_PERIODIC) sy = (sy + a.dom.nyd) % a.dom.nyd;
+                else { sy = (sy < 0) ? -1 - sy : 2 * a.dom.nyd - 1 - sy; sgn = CT(-1); }
+            }
+            const long cs = (long)(sy - a.box.gy0) * a.box.pitch + (sx - a.box.gx0);
+            nt[k] = a.csrc[cs];
+            u[k] = a.msrc[P + cs];
+            v[k] = sgn * a.msrc[2 * P + cs];
+        }
+}
+
+// Post-stream value of direction i at (gx, gy) for a cell next to the outlet
+// (interior or across a symmetry / periodic y edge).
+template <class ST, class CT>
+__device__ __forceinline__ CT poststream(const StepArgs<ST, CT>& a, int i, int gx, int gy) {
+    int sx = gx - CX[i], sy = gy - CY[i], di = i;
+    if (sy < 0 || sy >= a.dom.nyd) {
+        const int side = sy < 0 ? 2 : 3;
+        if (a.dom.bc[side] == BC_PERIODIC) sy = (sy + a.dom.nyd) % a.dom.nyd;
+        else { sy = gy; di = MIRY[i]; }
+    }
+    const long cs = (long)(sy - a.box.gy0) * a.box.pitch + (sx - a.box.gx0);
+    return Cv<ST, CT>::ld(a.fsrc + di * a.box.plane + cs);
+}
+
+// Moments (eq (3) with the half-force shift), collision with
+// nu_eff = nu + nu_t(chi) (eqs (9), (11)), stores.
+template <class ST, class CT>
+__device__ __forceinline__ void finish_cell(const StepArgs<ST, CT>& a, long c, CT s[9], CT chi_new) {
+    const long P = a.box.plane;
+    CT drho = CT(0), jx = CT(0), jy = CT(0);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        drho += s[i];
+        jx += CT(CX[i]) * s[i];
+        jy += CT(CY[i]) * s[i];
+    }
+    const CT rho = CT(1) + drho;
+    const CT ux = (jx + CT(0.5) * a.fx) / rho;
+    const CT uy = (jy + CT(0.5) * a.fy) / rho;
+    a.mdst[c] = rho;
+    a.mdst[P + c] = ux;
+    a.mdst[2 * P + c] = uy;
+    a.cdst[c] = chi_new;
+    const CT nu_eff = a.nu + eddy_viscosity(chi_new, a.nu);
+    const CT omega = CT(1) / (CT(3) * nu_eff + CT(0.5));
+    collide(s, drho, ux, uy, omega, a.omega_b, a.fx, a.fy);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Cv<ST, CT>::st(a.fdst + i * P + c, s[i]);
+}
+
+// ---------------------------------------------------------------------------
+// k_step: all owned fluid cells of a level except the wall nodes and the
+// domain edge (side-stream kernels), and the ghost band.  One workgroup per
+// active 64 x 4 tile, one wavefront per tile row: the nine pulled populations
+// are read straight from memory (coalesced rows), the 3 x 3 SA stencil of
+// chi, u_x and u_y is staged in LDS with a one-cell halo (allocations carry
+// one spare row at both ends, so every halo address is valid).
+// ---------------------------------------------------------------------------
+template <class ST, class CT>
+__global__ __launch_bounds__(256) void k_step(const StepArgs<ST, CT> a) {
+    // SA stencil of the 64 x 4 tile with a one-cell halo, staged in LDS
+    __shared__ CT sh_n[TILE_Y + 2][TILE_X + 2], sh_u[TILE_Y + 2][TILE_X + 2], sh_v[TILE_Y + 2][TILE_X + 2];
+    const int per = (a.ntiles + 7) >> 3;
+    const int t = (blockIdx.x & 7) * per + (blockIdx.x >> 3);   // neighbouring tiles share an XCD
+    if (t >= a.ntiles) return;                                   // whole workgroup
+    const uint32_t tile = a.tiles[t];
+    const int pitch = a.box.pitch;
+    const long P = a.box.plane;
+    const int lane = threadIdx.x & 63, wy = threadIdx.x >> 6;
+    const int tx0 = (int)(tile & 0xffffu) * TILE_X, ty0 = (int)(tile >> 16) * TILE_Y;
+    const int lx = tx0 + lane, ly = ty0 + wy;
+    const long c = (long)ly * pitch + lx;
+
+    sh_n[wy + 1][lane + 1] = a.csrc[c];
+    sh_u[wy + 1][lane + 1] = a.msrc[P + c];
+    sh_v[wy + 1][lane + 1] = a.msrc[2 * P + c];
+    if (threadIdx.x < 2 * TILE_X + 2 * (TILE_Y + 2)) {
+        const int h = threadIdx.x;
+        int hx, hy;
+        if (h < TILE_X) { hx = h; hy = -1; }
+        else if (h < 2 * TILE_X) { hx = h - TILE_X; hy = TILE_Y; }
+        else if (h < 2 * TILE_X + TILE_Y + 2) { hx = -1; hy = h - 2 * TILE_X - 1; }
+        else { hx = TILE_X; hy = h - 2 * TILE_X - (TILE_Y + 2) - 1; }
+        const long cs = (long)(ty0 + hy) * pitch + tx0 + hx;     // padded allocations: always valid
+        sh_n[hy + 1][hx + 1] = a.csrc[cs];
+        sh_u[hy + 1][hx + 1] = a.msrc[P + cs];
+        sh_v[hy + 1][hx + 1] = a.msrc[2 * P + cs];
+    }
+    const uint8_t fl = a.flag[c];
+    const uint32_t lm = a.lmask[c];
+    CT s[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+        s[i] = Cv<ST, CT>::ld(a.fsrc + i * P + c - CX[i] - (long)CY[i] * pitch);
+    const double dist = a.dist[c];
+    __syncthreads();
+
+    const int type = fl & F_TYPE;
+    const int gx = lx + a.box.gx0, gy = ly + a.box.gy0;
+    if (type == T_GHOST) {
+        // fine band over a coarse interface cell: carries exploded coarse populations
+        // (first sub-step) and fine populations one cell per sub-step, no collision
+        const int k = (a.substep == 1) ? 1 : 2;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const bool src_fluid = (lm >> i) & 1u, src_ghost = (lm >> (16 + i)) & 1u;
+            CT w = s[i];
+            if (!(src_fluid || (src_ghost && a.substep == 2)))
+                w = coarse_val(a, i, gx - k * CX[i], gy - k * CY[i]);
+            Cv<ST, CT>::st(a.fdst + i * P + c, w);
+        }
+        return;
+    }
+    if (type != T_FLUID || (fl & (F_WALL | F_EDGE))) return;     // side-stream kernels
+
+    if (fl & F_IFACE) {
+        // coalescence: mean of the four children of the finer band
+        const long f0 = (long)(2 * gy - a.fbox.gy0) * a.fbox.pitch + (2 * gx - a.fbox.gx0);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const ST* p = a.ffine + i * a.fbox.plane + f0;
+            s[i] = CT(0.25) * ((Cv<ST, CT>::ld(p) + Cv<ST, CT>::ld(p + 1)) +
+                               (Cv<ST, CT>::ld(p + a.fbox.pitch) + Cv<ST, CT>::ld(p + a.fbox.pitch + 1)));
+        }
+    } else if ((fl & F_NEARGHOST) && a.substep == 1) {
+        // next to the fine band on the first sub-step: exploded coarse populations
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+            if ((lm >> (16 + i)) & 1u) s[i] = coarse_val(a, i, gx - CX[i], gy - CY[i]);
+    }
+
+    // SA-neg: chi at the new time level
+    CT chi_new;
+    if (a.frozen) {
+        chi_new = sh_n[wy + 1][lane + 1];
+    } else {
+        CT nt[9], u[9], v[9];
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int k = (dy + 1) * 3 + dx + 1;
+                nt[k] = sh_n[wy + 1 + dy][lane + 1 + dx] * a.nu;
+                u[k] = sh_u[wy + 1 + dy][lane + 1 + dx];
+                v[k] = sh_v[wy + 1 + dy][lane + 1 + dx];
+            }
+        chi_new = sa_update(nt, u, v, a.nu, CT(dist), a.sa_mode == 2) / a.nu;
+    }
+    finish_cell(a, c, s, chi_new);
+}
+
+// ---------------------------------------------------------------------------
+// k_edge: level-0 cells on the domain edge (except wall nodes), one thread
+// each, beside k_step: periodic wrap, specular reflection at symmetry edges,
+// Zou-He velocity inlet, extrapolation outlet (Section 3.1.1), and the SA
+// boundary rules (inlet chi, outlet extrapolation, mirrored stencil).
+// ---------------------------------------------------------------------------
+template <class ST, class CT>
+__global__ __launch_bounds__(64) void k_edge(const StepArgs<ST, CT> a) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= a.nedge) return;
+    const int pitch = a.box.pitch;
+    const long P = a.box.plane;
+    const long c = a.edge[e];
+    const int gx = (int)(c % pitch) + a.box.gx0, gy = (int)(c / pitch) + a.box.gy0;
+    const double dist = a.dist[c];
+    CT s[9], nt[9], u[9], v[9];
+    const bool at_inlet = gx == 0 && a.dom.bc[0] == BC_INLET;
+    const bool at_outlet = gx == a.dom.nxd - 1 && a.dom.bc[1] == BC_OUTLET;
+    {
+        gather_edge(a, gx, gy, nt, u, v);
+        for (int i = 0; i < 9; ++i)
+            if (!pull_general(a, (uint8_t)F_EDGE, i, gx, gy, s[i])) s[i] = CT(0);
+        if (at_inlet) {
+            const CT ui = a.u_in;
+            const CT rho = (CT(1) + s[0] + s[3] + s[4] + CT(2) * (s[2] + s[6] + s[8])) / (CT(1) - ui);
+            s[1] = s[2] + CT(2.0 / 3.0) * rho * ui;
+            s[5] = s[6] - CT(0.5) * (s[3] - s[4]) + rho * ui * CT(1.0 / 6.0);
+            s[7] = s[8] + CT(0.5) * (s[3] - s[4]) + rho * ui * CT(1.0 / 6.0);
+        }
+        if (at_outlet)
+            for (int i = 0; i < 9; ++i)
+                if (CX[i] == -1) s[i] = CT(2) * poststream(a, i, gx - 1, gy) - poststream(a, i, gx - 2, gy);
+    }
+    CT chi_new;
+    if (a.frozen) {
+        chi_new = nt[4];
+    } else if (at_inlet) {
+        chi_new = a.chi_in;
+    } else if (at_outlet) {
+        chi_new = nt[3];                         // first-order extrapolation from upstream
+    } else {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) nt[k] *= a.nu;
+        chi_new = sa_update(nt, u, v, a.nu, CT(dist), a.sa_mode == 2) / a.nu;
+    }
+    finish_cell(a, c, s, chi_new);
+}
+
+// ---------------------------------------------------------------------------
+// k_boundary: the wall nodes B of a level, one thread each.  Runs beside
+// k_step (disjoint cells, same source state): steps 1-5 of the VN procedure
+// on the macroscopic state of the previous step, the Dirichlet value
+// nu~_B = kappa u_tau d_WB, Yu's interpolated bounce-back (step 6, eq (27)) or
+// eq (24) for the missing populations, and the collision.  All loads are
+// issued before the Newton iteration and the first store.
+// ---------------------------------------------------------------------------
+template <class ST, class CT>
+__global__ __launch_bounds__(64) void k_boundary(const StepArgs<ST, CT> a) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= a.wall.nb) return;
+    const long P = a.box.plane;
+    const int pitch = a.box.pitch;
+    const long c = a.wall.cell[b];
+    const double guess = a.wstate[8 * b];
+    const int gx = (int)(c % pitch) + a.box.gx0, gy = (int)(c / pitch) + a.box.gy0;
+    const uint8_t fl = a.flag[c];
+    // sources of the pull (periodic wrap in x on level 0) and next nodes F2
+    long src[9], f2[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        int sx = gx - CX[i], fx = gx + CX[i];
+        if (a.dom.periodic_x) {
+            sx = (sx + a.dom.nxd) % a.dom.nxd;
+            fx = (fx + a.dom.nxd) % a.dom.nxd;
+        }
+        src[i] = (long)(gy - CY[i] - a.box.gy0) * pitch + (sx - a.box.gx0);
+        f2[i] = (long)(gy + CY[i] - a.box.gy0) * pitch + (fx - a.box.gx0);
+    }
+    double q[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) q[k] = a.wall.q[8 * b + k];
+    CT pull[9], own[9], nxt[9];
+    uint8_t f2fl[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const bool cut = i > 0 && q[OPP[i] - 1] >= 0.0;
+        pull[i] = Cv<ST, CT>::ld(a.fsrc + i * P + (cut ? c : src[i]));
+        own[i] = Cv<ST, CT>::ld(a.fsrc + i * P + c);
+        nxt[i] = Cv<ST, CT>::ld(a.fsrc + OPP[i] * P + f2[i]);     // f*_o at F2 = B + c_i
+        f2fl[i] = a.flag[f2[i]];
+    }
+    double wm[6];
+    wall_model<CT>(a.wall, b, a.msrc, P, (double)a.nu, guess, wm);
+    const CT rhow = CT(wm[3]), uwx = CT(wm[4]), uwy = CT(wm[5]);
+    CT s[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const double qd = (i == 0) ? -1.0 : q[OPP[i] - 1];
+        if (qd < 0.0) { s[i] = pull[i]; continue; }
+        // i is the missing population; o = opp(i) is the link from B towards the wall
+        const int o = OPP[i];
+        const CT qo = CT(qd);
+        const CT fo_b = own[o];
+        const CT mom = CT(6) * wq<CT>(o) * rhow * (CT(CX[i]) * uwx + CT(CY[i]) * uwy);
+        CT val = fo_b + mom;                                      // eq (24)
+        if (!a.bb_halfway && q[i - 1] < 0.0 && (f2fl[i] & F_TYPE) == T_FLUID) {
+            // (A) outgoing value at the wall point, (B) reflection with the wall
+            // momentum, (C) interpolation between W and the next node F2
+            const CT fw_o = qo * fo_b + (CT(1) - qo) * nxt[i];
+            const CT fw_i = fw_o + mom;
+            val = fw_i + (qo / (CT(1) + qo)) * (own[i] - fw_i);
+        }
+        s[i] = val;
+    }
+    const CT chi_new = a.frozen ? a.csrc[c]
+                                : ((a.wall.model <= 1) ? CT(KAPPA * wm[0] * a.wall.geo[6 * b + 4] / (double)a.nu)
+                                                       : CT(0));
+    finish_cell(a, c, s, chi_new);
+    double* st = a.wstate + 8 * b;
+    for (int k = 0; k < 6; ++k) st[k] = wm[k];
+    (void)fl;
+}
+
+// Wall model on the current state, for output.
+template <class CT>
+__global__ __launch_bounds__(64) void k_wall(const WallArgs<CT> a) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= a.wall.nb) return;
+    double wm[6];
+    wall_model<CT>(a.wall, b, a.mac, a.plane, a.nu, a.guess[8 * b], wm);
+    for (int k = 0; k < 6; ++k) a.out[8 * b + k] = wm[k];
 }
 
 // ---------------------------------------------------------------------------
@@ -718,7 +838,7 @@ static hipError_t step_t(const void* args, hipStream_t s) {
     const auto& a = *static_cast<const StepArgs<ST, CT>*>(args);
     if (a.ntiles == 0) return hipSuccess;
     const unsigned grid = 8u * (unsigned)((a.ntiles + 7) / 8);
-    hipLaunchKernelGGL((k_step<ST, CT>), dim3(grid), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_step<ST, CT>), dim3(grid), dim3(TILE_X * TILE_Y), 0, s, a);
     return hipGetLastError();
 }
 
@@ -732,20 +852,50 @@ hipError_t launch_step(Prec p, const void* args, hipStream_t s) {
 }
 
 template <class ST, class CT>
-static hipError_t wall_t(const void* args, hipStream_t s) {
-    const auto& a = *static_cast<const WallArgs<ST, CT>*>(args);
-    if (a.nb == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_wall<ST, CT>), dim3(nblocks(a.nb, 256)), dim3(256), 0, s, a);
+static hipError_t boundary_t(const void* args, hipStream_t s) {
+    const auto& a = *static_cast<const StepArgs<ST, CT>*>(args);
+    if (a.wall.nb == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_boundary<ST, CT>), dim3(nblocks(a.wall.nb, 64)), dim3(64), 0, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_wall(Prec p, const void* args, hipStream_t s) {
+hipError_t launch_boundary(Prec p, const void* args, hipStream_t s) {
     switch (p) {
-        case P_F64: return wall_t<double, double>(args, s);
-        case P_F32: return wall_t<float, float>(args, s);
-        case P_F16: return wall_t<__half, float>(args, s);
-        default: return wall_t<__hip_bfloat16, float>(args, s);
+        case P_F64: return boundary_t<double, double>(args, s);
+        case P_F32: return boundary_t<float, float>(args, s);
+        case P_F16: return boundary_t<__half, float>(args, s);
+        default: return boundary_t<__hip_bfloat16, float>(args, s);
     }
+}
+
+template <class ST, class CT>
+static hipError_t edge_t(const void* args, hipStream_t s) {
+    const auto& a = *static_cast<const StepArgs<ST, CT>*>(args);
+    if (a.nedge == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_edge<ST, CT>), dim3(nblocks(a.nedge, 64)), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_edge(Prec p, const void* args, hipStream_t s) {
+    switch (p) {
+        case P_F64: return edge_t<double, double>(args, s);
+        case P_F32: return edge_t<float, float>(args, s);
+        case P_F16: return edge_t<__half, float>(args, s);
+        default: return edge_t<__hip_bfloat16, float>(args, s);
+    }
+}
+
+hipError_t launch_wall(Prec p, const void* args, hipStream_t s) {
+    if (p == P_F64) {
+        const auto& a = *static_cast<const WallArgs<double>*>(args);
+        if (a.wall.nb == 0) return hipSuccess;
+        hipLaunchKernelGGL(k_wall<double>, dim3(nblocks(a.wall.nb, 64)), dim3(64), 0, s, a);
+    } else {
+        const auto& a = *static_cast<const WallArgs<float>*>(args);
+        if (a.wall.nb == 0) return hipSuccess;
+        hipLaunchKernelGGL(k_wall<float>, dim3(nblocks(a.wall.nb, 64)), dim3(64), 0, s, a);
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_fill(Prec p, const FillArgs& a, hipStream_t s) {
