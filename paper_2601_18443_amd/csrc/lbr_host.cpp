@@ -615,6 +615,23 @@ void make_rows(Level& L) {
         }
 }
 
+// Marks the tiles that hold children of restriction targets of the parent level.
+void mark_restriction_tiles(lbr_ctx* c, Level& L) {
+    if (L.l == 0) return;
+    const Level& P = c->lv[L.l - 1];
+    for (uint32_t& tl : L.rows) {
+        const int tx = tl & 0x7fff, ty = (tl >> 16) & 0x7fff;
+        bool any = false;
+        for (int y = 0; y < TILE_Y && !any; y += 2)
+            for (int x = 0; x < TILE_X && !any; x += 2) {
+                const int gx = L.box.gx0 + tx * TILE_X + x, gy = L.box.gy0 + ty * TILE_Y + y;
+                const long pk = P.idx(gx >> 1, gy >> 1);
+                any = pk >= 0 && (P.flag[pk] & F_COVB) && (L.flag[(long)(ty * TILE_Y + y) * L.box.pitch + tx * TILE_X + x] & F_TYPE) == T_FLUID;
+            }
+        if (any) tl |= 1u << 31;
+    }
+}
+
 int alloc_level(lbr_ctx* c, Level& L) {
     const size_t n = L.box.plane;
     const size_t pad = (size_t)L.box.pitch + 1;    // k_step reads one row beyond both ends
@@ -636,16 +653,36 @@ int alloc_level(lbr_ctx* c, Level& L) {
     HIPCHK(c, hipMemsetAsync(L.dist_dev - pad, 0, (n + 2 * pad) * sizeof(double), c->stream));
     HIPCHK(c, hipMemcpyAsync(L.dist_dev, dclamp.data(), n * sizeof(double), hipMemcpyHostToDevice, c->stream));
     L.bytes += (n + 2 * pad) * sizeof(double);
-    if (int r = upload(c, &L.flag_dev, L.flag, &L.bytes)) return r;
+    // flags carry the same spare row at both ends (T_INACTIVE): the k_step halo reads them
+    L.flag_dev = static_cast<uint8_t*>(dalloc_padded(c, n, 1, pad));
+    if (!L.flag_dev) return set_err(c, LBR_ERR_OOM, "level %d: out of device memory", L.l);
+    HIPCHK(c, hipMemsetAsync(L.flag_dev - pad, T_INACTIVE, n + 2 * pad, c->stream));
+    HIPCHK(c, hipMemcpyAsync(L.flag_dev, L.flag.data(), n, hipMemcpyHostToDevice, c->stream));
+    L.bytes += n + 2 * pad;
     if (int r = upload(c, &L.rows_dev, L.rows, &L.bytes)) return r;
     {
         // static link mask: which pull sources are owned fluid cells / ghosts
         std::vector<uint32_t> lm(n, 0u);
+        const Level* Pp = L.l > 0 ? &c->lv[L.l - 1] : nullptr;
         for (long k = 0; k < (long)n; ++k) {
             const int t = L.flag[k] & F_TYPE;
-            if (t != T_GHOST && !(L.flag[k] & F_NEARGHOST)) continue;
             const int gx = (int)(k % L.box.pitch) + L.box.gx0, gy = (int)(k / L.box.pitch) + L.box.gy0;
-            uint32_t m = 0;
+            if (Pp && t == T_FLUID && !(gx & 1) && !(gy & 1)) {
+                const long pk = Pp->idx(gx >> 1, gy >> 1);
+                if (pk >= 0 && (Pp->flag[pk] & F_COVB)) {
+                    // the 2 x 2 block is averaged by the k_step workgroup that updates it
+                    for (int b = 0; b < 2; ++b)
+                        for (int a2 = 0; a2 < 2; ++a2) {
+                            const uint8_t fc = L.flag[k + (long)b * L.box.pitch + a2];
+                            if ((fc & F_TYPE) != T_FLUID || (fc & (F_WALL | F_EDGE)))
+                                return set_err(c, LBR_ERR_GEOMETRY, "level %d: restriction block at (%d, %d) "
+                                               "is not plain fluid", L.l, gx, gy);
+                        }
+                    lm[k] |= 1u << 31;
+                }
+            }
+            if (t != T_GHOST && !(L.flag[k] & F_NEARGHOST)) continue;
+            uint32_t m = lm[k];
             for (int i = 0; i < 9; ++i) {
                 const int ts = L.type_at(gx - CXH[i], gy - CYH[i]);
                 if (ts == T_FLUID) m |= 1u << i;
@@ -748,9 +785,15 @@ void fill_step_args(lbr_ctx* c, int l, int substep, StepArgs<ST, CT>& a) {
         Level& P = c->lv[l - 1];
         a.fcoarse = (const ST*)P.f[P.cur];
         a.cbox = P.box;
+        a.cmac = (const CT*)P.mac[P.cur];
+        a.cchi = (const CT*)P.chi[P.cur];
+        a.rmac = (CT*)P.mac[1 - P.cur];
+        a.rchi = (CT*)P.chi[1 - P.cur];
     } else {
         a.fcoarse = nullptr;
         a.cbox = Box{};
+        a.cmac = a.cchi = nullptr;
+        a.rmac = a.rchi = nullptr;
     }
     if (l + 1 < (int)c->lv.size()) {
         Level& F = c->lv[l + 1];
@@ -873,7 +916,6 @@ int do_transfers(lbr_ctx* c, int l) {
 // collides.
 int cycle(lbr_ctx* c, int l, int substep) {
     if (l + 1 < (int)c->lv.size()) {
-        if (int r = do_transfers(c, l)) return r;
         if (int r = cycle(c, l + 1, 1)) return r;
         if (int r = cycle(c, l + 1, 2)) return r;
     }
@@ -1121,6 +1163,7 @@ int lbr_build(lbr_ctx* c) {
         if (int r = build_walls(c, L, seg)) return r;
     for (Level& L : c->lv) {
         make_rows(L);
+        mark_restriction_tiles(c, L);
         if (int r = alloc_level(c, L)) return r;
         L.dbody.clear();
         L.dbody.shrink_to_fit();
@@ -1131,6 +1174,9 @@ int lbr_build(lbr_ctx* c) {
     c->built = true;
     for (int l = 0; l < (int)c->lv.size(); ++l)
         if (int r = init_level(c, l, nullptr, nullptr, nullptr, nullptr)) return r;
+    for (int l = 0; l + 1 < (int)c->lv.size(); ++l)
+        if (int r = do_transfers(c, l)) return r;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
     return LBR_OK;
 }
 
@@ -1154,7 +1200,15 @@ int lbr_init_fields(lbr_ctx* c, int32_t level, const double* rho, const double* 
     if (!c) return LBR_ERR_INVALID_ARG;
     if (!c->built || level < 0 || level >= (int)c->lv.size())
         return set_err(c, LBR_ERR_INVALID_ARG, "bad level %d", level);
-    return init_level(c, level, rho, ux, uy, chi);
+    if (int r = init_level(c, level, rho, ux, uy, chi)) return r;
+    // covered cells of the parent take the mean of the new children; the level's
+    // own covered cells the mean of its children
+    if (level > 0)
+        if (int r = do_transfers(c, level - 1)) return r;
+    if (level + 1 < (int)c->lv.size())
+        if (int r = do_transfers(c, level)) return r;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LBR_OK;
 }
 
 int lbr_advance(lbr_ctx* c, int64_t n) {

@@ -64,8 +64,9 @@ struct StepArgs {
     const double* dist;              // wall distance (level lattice units)
     const uint8_t* flag;
     const uint32_t* lmask;           // per cell: bit i, source c - c_i is owned fluid;
-                                     // bit 16 + i, source is a ghost
-    const uint32_t* tiles;           // active 64 x 4 tiles, (tx | ty << 16)
+                                     // bit 16 + i, source is a ghost; bit 31, lower-left
+                                     // child of a covered coarse cell next to coarse fluid
+    const uint32_t* tiles;           // active 64 x 4 tiles, (tx | ty << 16 | restriction << 31)
     int ntiles;
     const int32_t* edge;             // level-0 domain-edge cells that are not wall nodes
     int nedge;
@@ -75,6 +76,8 @@ struct StepArgs {
     int sa_mode, bb_halfway, frozen;
     int substep;                     // 1 or 2 within the parent's step (0 on level 0)
     const ST* fcoarse; Box cbox;     // parent level populations (ghost transfer)
+    const CT* cmac;  const CT* cchi; // parent level rho, u and chi of the current parent step
+    CT* rmac;        CT* rchi;       // parent level buffers of the next parent step (restriction)
     const ST* ffine;   Box fbox;     // child level populations (coalescence)
     WallData wall;                   // boundary nodes of this level (k_boundary)
     double* wstate;                  // [nb][8] u_tau, u_Rt (x, y), rho_W, u_W (x, y), spare

@@ -393,10 +393,39 @@ __device__ __forceinline__ void finish_cell(const StepArgs<ST, CT>& a, long c, C
 // are read straight from memory (coalesced rows), the 3 x 3 SA stencil of
 // chi, u_x and u_y is staged in LDS with a one-cell halo (allocations carry
 // one spare row at both ends, so every halo address is valid).
+//
+// Transfers between levels are folded in:
+//  * ghost cells of the stencil take chi and u from a linear least-squares fit
+//    over the 3 x 3 coarse neighbourhood of their parent (the coarse state of
+//    the current parent step, Section 2.2);
+//  * on the second sub-step, tiles holding children of covered coarse cells
+//    next to the coarse fluid write the mean of each 2 x 2 block of new values
+//    into the coarse buffer the next coarse step reads.
 // ---------------------------------------------------------------------------
+template <class CT>
+__device__ __forceinline__ void ghost_fill(const CT* cmac, const CT* cchi, const Box& cb, int gx,
+                                           int gy, CT& n, CT& u, CT& v) {
+    const int px = gx >> 1, py = gy >> 1;
+    const CT ox = (gx & 1) ? CT(0.25) : CT(-0.25), oy = (gy & 1) ? CT(0.25) : CT(-0.25);
+    CT sn = 0, su = 0, sv = 0, xn = 0, xu = 0, xv = 0, yn = 0, yu = 0, yv = 0;
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+            const long q = (long)(py + dy - cb.gy0) * cb.pitch + (px + dx - cb.gx0);
+            const CT a = cchi[q], b = cmac[cb.plane + q], c = cmac[2 * cb.plane + q];
+            sn += a; su += b; sv += c;
+            xn += CT(dx) * a; xu += CT(dx) * b; xv += CT(dx) * c;
+            yn += CT(dy) * a; yu += CT(dy) * b; yv += CT(dy) * c;
+        }
+    const CT k9 = CT(1.0 / 9.0), k6 = CT(1.0 / 6.0);
+    n = sn * k9 + (ox * xn + oy * yn) * k6;
+    u = su * k9 + (ox * xu + oy * yu) * k6;
+    v = sv * k9 + (ox * xv + oy * yv) * k6;
+}
+
 template <class ST, class CT>
 __global__ __launch_bounds__(256) void k_step(const StepArgs<ST, CT> a) {
-    // SA stencil of the 64 x 4 tile with a one-cell halo, staged in LDS
     __shared__ CT sh_n[TILE_Y + 2][TILE_X + 2], sh_u[TILE_Y + 2][TILE_X + 2], sh_v[TILE_Y + 2][TILE_X + 2];
     const int per = (a.ntiles + 7) >> 3;
     const int t = (blockIdx.x & 7) * per + (blockIdx.x >> 3);   // neighbouring tiles share an XCD
@@ -405,13 +434,23 @@ __global__ __launch_bounds__(256) void k_step(const StepArgs<ST, CT> a) {
     const int pitch = a.box.pitch;
     const long P = a.box.plane;
     const int lane = threadIdx.x & 63, wy = threadIdx.x >> 6;
-    const int tx0 = (int)(tile & 0xffffu) * TILE_X, ty0 = (int)(tile >> 16) * TILE_Y;
+    const int tx0 = (int)(tile & 0x7fffu) * TILE_X, ty0 = (int)((tile >> 16) & 0x7fffu) * TILE_Y;
+    const bool restrict_tile = (tile >> 31) && a.substep == 2;   // uniform over the workgroup
     const int lx = tx0 + lane, ly = ty0 + wy;
     const long c = (long)ly * pitch + lx;
 
-    sh_n[wy + 1][lane + 1] = a.csrc[c];
-    sh_u[wy + 1][lane + 1] = a.msrc[P + c];
-    sh_v[wy + 1][lane + 1] = a.msrc[2 * P + c];
+    const uint8_t fl = a.flag[c];
+    const uint32_t lm = a.lmask[c];
+    const int type = fl & F_TYPE;
+    const int gx = lx + a.box.gx0, gy = ly + a.box.gy0;
+    if (type == T_GHOST) {
+        ghost_fill(a.cmac, a.cchi, a.cbox, gx, gy, sh_n[wy + 1][lane + 1], sh_u[wy + 1][lane + 1],
+                   sh_v[wy + 1][lane + 1]);
+    } else {
+        sh_n[wy + 1][lane + 1] = a.csrc[c];
+        sh_u[wy + 1][lane + 1] = a.msrc[P + c];
+        sh_v[wy + 1][lane + 1] = a.msrc[2 * P + c];
+    }
     if (threadIdx.x < 2 * TILE_X + 2 * (TILE_Y + 2)) {
         const int h = threadIdx.x;
         int hx, hy;
@@ -420,12 +459,15 @@ __global__ __launch_bounds__(256) void k_step(const StepArgs<ST, CT> a) {
         else if (h < 2 * TILE_X + TILE_Y + 2) { hx = -1; hy = h - 2 * TILE_X - 1; }
         else { hx = TILE_X; hy = h - 2 * TILE_X - (TILE_Y + 2) - 1; }
         const long cs = (long)(ty0 + hy) * pitch + tx0 + hx;     // padded allocations: always valid
-        sh_n[hy + 1][hx + 1] = a.csrc[cs];
-        sh_u[hy + 1][hx + 1] = a.msrc[P + cs];
-        sh_v[hy + 1][hx + 1] = a.msrc[2 * P + cs];
+        if ((a.flag[cs] & F_TYPE) == T_GHOST) {
+            ghost_fill(a.cmac, a.cchi, a.cbox, a.box.gx0 + tx0 + hx, a.box.gy0 + ty0 + hy,
+                       sh_n[hy + 1][hx + 1], sh_u[hy + 1][hx + 1], sh_v[hy + 1][hx + 1]);
+        } else {
+            sh_n[hy + 1][hx + 1] = a.csrc[cs];
+            sh_u[hy + 1][hx + 1] = a.msrc[P + cs];
+            sh_v[hy + 1][hx + 1] = a.msrc[2 * P + cs];
+        }
     }
-    const uint8_t fl = a.flag[c];
-    const uint32_t lm = a.lmask[c];
     CT s[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i)
@@ -433,8 +475,7 @@ __global__ __launch_bounds__(256) void k_step(const StepArgs<ST, CT> a) {
     const double dist = a.dist[c];
     __syncthreads();
 
-    const int type = fl & F_TYPE;
-    const int gx = lx + a.box.gx0, gy = ly + a.box.gy0;
+    bool update = false;
     if (type == T_GHOST) {
         // fine band over a coarse interface cell: carries exploded coarse populations
         // (first sub-step) and fine populations one cell per sub-step, no collision
@@ -447,44 +488,66 @@ __global__ __launch_bounds__(256) void k_step(const StepArgs<ST, CT> a) {
                 w = coarse_val(a, i, gx - k * CX[i], gy - k * CY[i]);
             Cv<ST, CT>::st(a.fdst + i * P + c, w);
         }
-        return;
-    }
-    if (type != T_FLUID || (fl & (F_WALL | F_EDGE))) return;     // side-stream kernels
-
-    if (fl & F_IFACE) {
-        // coalescence: mean of the four children of the finer band
-        const long f0 = (long)(2 * gy - a.fbox.gy0) * a.fbox.pitch + (2 * gx - a.fbox.gx0);
+    } else if (type == T_FLUID && !(fl & (F_WALL | F_EDGE))) {   // others: side-stream kernels
+        update = true;
+        if (fl & F_IFACE) {
+            // coalescence: mean of the four children of the finer band
+            const long f0 = (long)(2 * gy - a.fbox.gy0) * a.fbox.pitch + (2 * gx - a.fbox.gx0);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            const ST* p = a.ffine + i * a.fbox.plane + f0;
-            s[i] = CT(0.25) * ((Cv<ST, CT>::ld(p) + Cv<ST, CT>::ld(p + 1)) +
-                               (Cv<ST, CT>::ld(p + a.fbox.pitch) + Cv<ST, CT>::ld(p + a.fbox.pitch + 1)));
-        }
-    } else if ((fl & F_NEARGHOST) && a.substep == 1) {
-        // next to the fine band on the first sub-step: exploded coarse populations
-#pragma unroll
-        for (int i = 0; i < 9; ++i)
-            if ((lm >> (16 + i)) & 1u) s[i] = coarse_val(a, i, gx - CX[i], gy - CY[i]);
-    }
-
-    // SA-neg: chi at the new time level
-    CT chi_new;
-    if (a.frozen) {
-        chi_new = sh_n[wy + 1][lane + 1];
-    } else {
-        CT nt[9], u[9], v[9];
-#pragma unroll
-        for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll
-            for (int dx = -1; dx <= 1; ++dx) {
-                const int k = (dy + 1) * 3 + dx + 1;
-                nt[k] = sh_n[wy + 1 + dy][lane + 1 + dx] * a.nu;
-                u[k] = sh_u[wy + 1 + dy][lane + 1 + dx];
-                v[k] = sh_v[wy + 1 + dy][lane + 1 + dx];
+            for (int i = 0; i < 9; ++i) {
+                const ST* p = a.ffine + i * a.fbox.plane + f0;
+                s[i] = CT(0.25) * ((Cv<ST, CT>::ld(p) + Cv<ST, CT>::ld(p + 1)) +
+                                   (Cv<ST, CT>::ld(p + a.fbox.pitch) + Cv<ST, CT>::ld(p + a.fbox.pitch + 1)));
             }
-        chi_new = sa_update(nt, u, v, a.nu, CT(dist), a.sa_mode == 2) / a.nu;
+        } else if ((fl & F_NEARGHOST) && a.substep == 1) {
+            // next to the fine band on the first sub-step: exploded coarse populations
+#pragma unroll
+            for (int i = 0; i < 9; ++i)
+                if ((lm >> (16 + i)) & 1u) s[i] = coarse_val(a, i, gx - CX[i], gy - CY[i]);
+        }
+        // SA-neg: chi at the new time level
+        CT chi_new;
+        if (a.frozen) {
+            chi_new = sh_n[wy + 1][lane + 1];
+        } else {
+            CT nt[9], u[9], v[9];
+#pragma unroll
+            for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const int k = (dy + 1) * 3 + dx + 1;
+                    nt[k] = sh_n[wy + 1 + dy][lane + 1 + dx] * a.nu;
+                    u[k] = sh_u[wy + 1 + dy][lane + 1 + dx];
+                    v[k] = sh_v[wy + 1 + dy][lane + 1 + dx];
+                }
+            chi_new = sa_update(nt, u, v, a.nu, CT(dist), a.sa_mode == 2) / a.nu;
+        }
+        finish_cell(a, c, s, chi_new);
     }
-    finish_cell(a, c, s, chi_new);
+    if (!restrict_tile) return;
+    // restriction for the next parent step: the new rho, u and chi of each 2 x 2
+    // block under a covered coarse cell, averaged by the block's lower-left cell
+    __shared__ CT sh_r[4][TILE_Y][TILE_X];
+    __syncthreads();
+    if (update) {
+        sh_r[0][wy][lane] = a.mdst[c];
+        sh_r[1][wy][lane] = a.mdst[P + c];
+        sh_r[2][wy][lane] = a.mdst[2 * P + c];
+        sh_r[3][wy][lane] = a.cdst[c];
+    }
+    __syncthreads();
+    if (lm >> 31) {
+        const long q = (long)((gy >> 1) - a.cbox.gy0) * a.cbox.pitch + ((gx >> 1) - a.cbox.gx0);
+        CT m[4];
+#pragma unroll
+        for (int f = 0; f < 4; ++f)
+            m[f] = CT(0.25) * ((sh_r[f][wy][lane] + sh_r[f][wy][lane + 1]) +
+                               (sh_r[f][wy + 1][lane] + sh_r[f][wy + 1][lane + 1]));
+        a.rmac[q] = m[0];
+        a.rmac[a.cbox.plane + q] = m[1];
+        a.rmac[2 * a.cbox.plane + q] = m[2];
+        a.rchi[q] = m[3];
+    }
 }
 
 // ---------------------------------------------------------------------------
