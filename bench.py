@@ -91,7 +91,7 @@ def copy_calibration(nbytes=1 << 30):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16", "f64"])
     ap.add_argument("--graph", type=int, default=1, help="replay the coarse step from a HIP graph")
@@ -133,14 +133,15 @@ def main():
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     log(f"timed {args.steps} coarse steps in {dt:.3f} s")
-    # kernel durations: HIP events around every launch on the library's stream, over a
-    # window of the same length run with direct launches right after the timed region
+    # kernel durations: start / stop HIP events attached to every dispatch on the
+    # library's streams (hipExtLaunchKernelGGL), over a window of the same length run
+    # with direct launches right after the timed region
     sim.profile(True)
     sim.advance(args.steps)
     sim.synchronize()
     kt = sim.profile(False)
-    log(f"event-timed kernels (us/launch): step all levels {kt[0]:.2f}, finest {kt[1]:.2f}, "
-        f"wall {kt[2]:.2f}, transfers {kt[3]:.2f}")
+    log(f"event-timed kernels (us/launch): k_step all levels {kt[0]:.2f}, finest {kt[1]:.2f}, "
+        f"k_boundary {kt[2]:.2f}, k_edge {kt[3]:.2f}")
     mlups = lups * args.steps / dt / 1e6
     f = sim.forces()
     if not np.all(np.isfinite(f)):
@@ -160,7 +161,7 @@ def main():
                 "traffic": None if traffic is None else round(traffic, 0),
                 "kernel": "k_step (all levels)", "avg_launch_us": round(kt[0], 3),
                 "finest_level_avg_launch_us": round(kt[1], 3),
-                "wall_kernel_avg_us": round(kt[2], 3), "transfer_avg_us": round(kt[3], 3),
+                "k_boundary_avg_us": round(kt[2], 3), "k_edge_avg_us": round(kt[3], 3),
                 "alg_bytes_per_launch": round(bytes_per_launch, 0)}
     cpu = None
     if not args.no_cpu_baseline:

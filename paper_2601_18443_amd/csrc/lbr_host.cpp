@@ -831,27 +831,23 @@ int eval_wall(lbr_ctx* c, int l) {
     return 0;
 }
 
-enum { EV_STEP = 0, EV_STEP_FINE = 1, EV_WALL = 2, EV_XFER = 3 };
+enum { EV_STEP = 0, EV_STEP_FINE = 1, EV_WALL = 2, EV_EDGE = 3 };
 
-hipEvent_t prof_begin(lbr_ctx* c, hipStream_t st) {
-    if (!c->prof) return nullptr;
+// Start / stop events for one dispatch of the given kind (profiling mode only).
+Timing prof_events(lbr_ctx* c, int kind) {
+    Timing tm;
+    if (!c->prof) return tm;
     while (c->ev.size() < c->ev_used + 2) {
         hipEvent_t e;
-        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return tm;
         c->ev.push_back(e);
         c->ev_kind.push_back(0);
     }
-    hipEvent_t e = c->ev[c->ev_used];
-    (void)hipEventRecord(e, st);
-    return e;
-}
-
-void prof_end(lbr_ctx* c, hipEvent_t start, int kind, hipStream_t st) {
-    if (!c->prof || !start) return;
-    hipEvent_t e = c->ev[c->ev_used + 1];
-    (void)hipEventRecord(e, st);
+    tm.start = c->ev[c->ev_used];
+    tm.stop = c->ev[c->ev_used + 1];
     c->ev_kind[c->ev_used] = kind;
     c->ev_used += 2;
+    return tm;
 }
 
 int do_step(lbr_ctx* c, int l, int substep) {
@@ -869,15 +865,12 @@ int do_step(lbr_ctx* c, int l, int substep) {
         // the rest of the level (disjoint cells, same source state)
         HIPCHK(c, hipEventRecord(c->ev_fork, c->stream));
         HIPCHK(c, hipStreamWaitEvent(c->side, c->ev_fork, 0));
-        hipEvent_t e2 = prof_begin(c, c->side);
-        if (!L.nodes.empty()) HIPCHK(c, launch_boundary(c->prec, buf, c->side));
-        if (!L.edge.empty()) HIPCHK(c, launch_edge(c->prec, buf, c->side));
-        prof_end(c, e2, EV_WALL, c->side);
+        if (!L.nodes.empty()) HIPCHK(c, launch_boundary(c->prec, buf, c->side, prof_events(c, EV_WALL)));
+        if (!L.edge.empty()) HIPCHK(c, launch_edge(c->prec, buf, c->side, prof_events(c, EV_EDGE)));
         HIPCHK(c, hipEventRecord(c->ev_join, c->side));
     }
-    hipEvent_t e = prof_begin(c, c->stream);
-    HIPCHK(c, launch_step(c->prec, buf, c->stream));
-    prof_end(c, e, l + 1 == (int)c->lv.size() ? EV_STEP_FINE : EV_STEP, c->stream);
+    HIPCHK(c, launch_step(c->prec, buf, c->stream,
+                          prof_events(c, l + 1 == (int)c->lv.size() ? EV_STEP_FINE : EV_STEP)));
     if (walls) HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
     L.cur ^= 1;
     return 0;
@@ -886,7 +879,6 @@ int do_step(lbr_ctx* c, int l, int substep) {
 int do_transfers(lbr_ctx* c, int l) {
     Level& C = c->lv[l];
     Level& F = c->lv[l + 1];
-    hipEvent_t e = prof_begin(c, c->stream);
     RestrictArgs r{};
     r.n = (int)C.covb.size();
     r.list = C.covb_dev;
@@ -907,7 +899,6 @@ int do_transfers(lbr_ctx* c, int l) {
     f.fmac0 = F.mac[0]; f.fmac1 = F.mac[1];
     f.fchi0 = F.chi[0]; f.fchi1 = F.chi[1];
     HIPCHK(c, launch_fill(c->prec, f, c->stream));
-    prof_end(c, e, EV_XFER, c->stream);
     return 0;
 }
 
@@ -1230,6 +1221,7 @@ int lbr_advance(lbr_ctx* c, int64_t n) {
     c->resid_steps += n;
     if (c->prof && c->ev_used) {
         HIPCHK(c, hipStreamSynchronize(c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->side));
         double sum[4] = {0, 0, 0, 0};
         int cnt[4] = {0, 0, 0, 0};
         for (size_t i = 0; i + 1 < c->ev_used; i += 2) {

@@ -135,9 +135,13 @@ enum Prec { P_F64 = 0, P_F32 = 1, P_F16 = 2, P_BF16 = 3 };
 hipError_t launch_geometry(int nx, int ny, int gx0, int gy0, double scale, int nbody,
                            const int* npts_off, const double* poly, int solid,
                            double* dist, uint8_t* inside, hipStream_t s);
-hipError_t launch_step(Prec p, const void* args, hipStream_t s);
-hipError_t launch_boundary(Prec p, const void* args, hipStream_t s);
-hipError_t launch_edge(Prec p, const void* args, hipStream_t s);
+// Optional events recorded by the dispatch itself at kernel start and end.
+struct Timing {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+hipError_t launch_step(Prec p, const void* args, hipStream_t s, const Timing& tm = Timing{});
+hipError_t launch_boundary(Prec p, const void* args, hipStream_t s, const Timing& tm = Timing{});
+hipError_t launch_edge(Prec p, const void* args, hipStream_t s, const Timing& tm = Timing{});
 hipError_t launch_wall(Prec p, const void* args, hipStream_t s);
 hipError_t launch_fill(Prec p, const FillArgs& a, hipStream_t s);
 hipError_t launch_restrict(Prec p, const RestrictArgs& a, hipStream_t s);

@@ -10,6 +10,7 @@
 // coalesced 64-wide rows.  The work is bandwidth-bound and uses no matrix
 // cores.
 #include "lbr_impl.h"
+#include <hip/hip_ext.h>
 
 #include <cmath>
 
@@ -891,60 +892,68 @@ __global__ void k_to_double(const CT* src, double* dst, long n) {
 
 inline unsigned nblocks(long n, int b) { return (unsigned)((n + b - 1) / b); }
 
+// Plain launch, or with start / stop events attached to the dispatch itself
+// (kernel execution time without the cost of separate event records).
+template <class K, class A>
+inline void launch_timed(K kernel, dim3 g, dim3 b, hipStream_t s, const Timing& tm, const A& a) {
+    if (tm.start) hipExtLaunchKernelGGL(kernel, g, b, 0, s, tm.start, tm.stop, 0, a);
+    else hipLaunchKernelGGL(kernel, g, b, 0, s, a);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 template <class ST, class CT>
-static hipError_t step_t(const void* args, hipStream_t s) {
+static hipError_t step_t(const void* args, hipStream_t s, const Timing& tm) {
     const auto& a = *static_cast<const StepArgs<ST, CT>*>(args);
     if (a.ntiles == 0) return hipSuccess;
     const unsigned grid = 8u * (unsigned)((a.ntiles + 7) / 8);
-    hipLaunchKernelGGL((k_step<ST, CT>), dim3(grid), dim3(TILE_X * TILE_Y), 0, s, a);
+    launch_timed(k_step<ST, CT>, dim3(grid), dim3(TILE_X * TILE_Y), s, tm, a);
     return hipGetLastError();
 }
 
-hipError_t launch_step(Prec p, const void* args, hipStream_t s) {
+hipError_t launch_step(Prec p, const void* args, hipStream_t s, const Timing& tm) {
     switch (p) {
-        case P_F64: return step_t<double, double>(args, s);
-        case P_F32: return step_t<float, float>(args, s);
-        case P_F16: return step_t<__half, float>(args, s);
-        default: return step_t<__hip_bfloat16, float>(args, s);
+        case P_F64: return step_t<double, double>(args, s, tm);
+        case P_F32: return step_t<float, float>(args, s, tm);
+        case P_F16: return step_t<__half, float>(args, s, tm);
+        default: return step_t<__hip_bfloat16, float>(args, s, tm);
     }
 }
 
 template <class ST, class CT>
-static hipError_t boundary_t(const void* args, hipStream_t s) {
+static hipError_t boundary_t(const void* args, hipStream_t s, const Timing& tm) {
     const auto& a = *static_cast<const StepArgs<ST, CT>*>(args);
     if (a.wall.nb == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_boundary<ST, CT>), dim3(nblocks(a.wall.nb, 64)), dim3(64), 0, s, a);
+    launch_timed(k_boundary<ST, CT>, dim3(nblocks(a.wall.nb, 64)), dim3(64), s, tm, a);
     return hipGetLastError();
 }
 
-hipError_t launch_boundary(Prec p, const void* args, hipStream_t s) {
+hipError_t launch_boundary(Prec p, const void* args, hipStream_t s, const Timing& tm) {
     switch (p) {
-        case P_F64: return boundary_t<double, double>(args, s);
-        case P_F32: return boundary_t<float, float>(args, s);
-        case P_F16: return boundary_t<__half, float>(args, s);
-        default: return boundary_t<__hip_bfloat16, float>(args, s);
+        case P_F64: return boundary_t<double, double>(args, s, tm);
+        case P_F32: return boundary_t<float, float>(args, s, tm);
+        case P_F16: return boundary_t<__half, float>(args, s, tm);
+        default: return boundary_t<__hip_bfloat16, float>(args, s, tm);
     }
 }
 
 template <class ST, class CT>
-static hipError_t edge_t(const void* args, hipStream_t s) {
+static hipError_t edge_t(const void* args, hipStream_t s, const Timing& tm) {
     const auto& a = *static_cast<const StepArgs<ST, CT>*>(args);
     if (a.nedge == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_edge<ST, CT>), dim3(nblocks(a.nedge, 64)), dim3(64), 0, s, a);
+    launch_timed(k_edge<ST, CT>, dim3(nblocks(a.nedge, 64)), dim3(64), s, tm, a);
     return hipGetLastError();
 }
 
-hipError_t launch_edge(Prec p, const void* args, hipStream_t s) {
+hipError_t launch_edge(Prec p, const void* args, hipStream_t s, const Timing& tm) {
     switch (p) {
-        case P_F64: return edge_t<double, double>(args, s);
-        case P_F32: return edge_t<float, float>(args, s);
-        case P_F16: return edge_t<__half, float>(args, s);
-        default: return edge_t<__hip_bfloat16, float>(args, s);
+        case P_F64: return edge_t<double, double>(args, s, tm);
+        case P_F32: return edge_t<float, float>(args, s, tm);
+        case P_F16: return edge_t<__half, float>(args, s, tm);
+        default: return edge_t<__hip_bfloat16, float>(args, s, tm);
     }
 }
 
