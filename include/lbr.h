@@ -73,6 +73,13 @@ enum lbr_bb { LBR_BB_AUTO = 0, LBR_BB_YU = 1, LBR_BB_HALFWAY = 2 };
 
 /* SA-neg convection: frozen (no SA update), Lax-Wendroff, first-order upwind. */
 enum lbr_sa { LBR_SA_FROZEN = 0, LBR_SA_LW = 1, LBR_SA_UPWIND1 = 2 };
+/* Outlet (Section 3.1.1).  EXTRAP2 / EXTRAP1: the populations entering from
+   outside are extrapolated from the upstream cells, to second order
+   (2 f(N-1) - f(N-2), the extrapolation the paper cites) or to first order
+   (f(N-1)).  PRESSURE: Zou-He's rule (the inlet's, Section 3.1.1) with the
+   density held at rho_ref and the tangential velocity of the upstream cell;
+   it fixes the pressure level that the two extrapolations leave free. */
+enum lbr_outlet { LBR_OUTLET_EXTRAP2 = 0, LBR_OUTLET_EXTRAP1 = 1, LBR_OUTLET_PRESSURE = 2 };
 
 enum lbr_body { LBR_BODY_SOLID = 0, LBR_BODY_REFINE_ONLY = 1 };
 
@@ -97,7 +104,8 @@ typedef struct lbr_config {
     int32_t bb;                    /* enum lbr_bb */
     int32_t sa;                    /* enum lbr_sa */
     int32_t body_mode;             /* enum lbr_body */
-    int32_t reserved0;
+    int32_t outlet;                /* enum lbr_outlet: rule for the unknown populations at an
+                                      OUTLET edge */
     double origin[2];              /* physical position of the level-0 box corner */
     double dx0;                    /* physical size of a level-0 cell */
     double band[LBR_MAX_LEVELS];   /* band[l] (l >= 1): level l-1 cells closer than this

@@ -34,6 +34,9 @@ BB_HALFWAY = 2   # half-way rule eq (24) at every cut link
 
 BODY_SOLID = 0   # bodies are walls
 BODY_REFINE = 1  # bodies only mark where the grid is refined
+OUTLET_EXTRAP2 = 0   # outlet populations extrapolated to second order (two upstream cells)
+OUTLET_EXTRAP1 = 1   # outlet populations copied from the next upstream cell
+OUTLET_PRESSURE = 2  # Zou-He outlet at the reference density
 
 SA_FROZEN = 0
 SA_LW = 1

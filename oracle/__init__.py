@@ -25,7 +25,7 @@ class Config(C.Structure):
         ("nx0", C.c_int32), ("ny0", C.c_int32), ("n_levels", C.c_int32),
         ("bc", C.c_int32 * 4),
         ("wall_model", C.c_int32), ("bb_mode", C.c_int32), ("sa_mode", C.c_int32),
-        ("body_mode", C.c_int32),
+        ("body_mode", C.c_int32), ("outlet", C.c_int32),
         ("origin", C.c_double * 2), ("dx0", C.c_double),
         ("band", C.c_double * MAX_LEVELS), ("wall_y", C.c_double * 2),
         ("mach", C.c_double), ("reynolds", C.c_double), ("ref_length", C.c_double),
@@ -165,6 +165,7 @@ def make_config(case) -> Config:
         c.bc[k] = case["bc"][k]
     c.wall_model, c.bb_mode, c.sa_mode = case["wall_model"], case["bb_mode"], case["sa_mode"]
     c.body_mode = case.get("body_mode", 0)
+    c.outlet = case.get("outlet", 0)
     c.origin[0], c.origin[1] = case["origin"]
     c.dx0 = case["dx0"]
     for l, b in enumerate(case.get("bands", ())):

@@ -90,7 +90,7 @@ static const double WF_C3 = 3.599459109332379, WF_C4 = 3.639753186868684494;
 #define SA_CV1 7.1
 #define SA_RLIM 10.0
 #define SA_CV2 0.7
-#define SA_CV3 0.3
+#define SA_CV3 0.9   /* printed as 0.3, which makes eq (14) singular; SA-neg's value */
 #define SA_CT3 1.2
 #define SA_CN1 16.0
 
@@ -819,7 +819,7 @@ int lbro_create(const lbro_config* cfg, int32_t n_bodies, const int32_t* n_pts, 
                 lbro_sim** out) {
     *out = NULL;
     if (!cfg || cfg->n_levels < 1 || cfg->n_levels > LBRO_MAX_LEVELS || cfg->nx0 < 4 ||
-        cfg->ny0 < 4 || !(cfg->dx0 > 0.0))
+        cfg->ny0 < 4 || !(cfg->dx0 > 0.0) || cfg->outlet < 0 || cfg->outlet > 2)
         return fail("invalid configuration");
     if ((cfg->bc[0] == LBRO_BC_PERIODIC) != (cfg->bc[1] == LBRO_BC_PERIODIC) ||
         (cfg->bc[2] == LBRO_BC_PERIODIC) != (cfg->bc[3] == LBRO_BC_PERIODIC))
@@ -1283,14 +1283,29 @@ static int stream_level(lbro_sim* s, int l) {
         }
     }
     if (err) return fail("stream on level %d reached a cell without data", l);
-    /* outlet: unknowns (c_x = -1) extrapolated from the two upstream cells */
+    /* outlet: unknowns (c_x = -1) extrapolated from the upstream cells, to second
+       order (two cells) or, when selected, to first order (a copy of the next
+       cell); or Zou-He's rule with the density held at rho_ref and the
+       tangential velocity of the upstream cell at time n */
     if (l == 0 && s->cfg.bc[1] == LBRO_BC_OUTLET) {
         for (int gj = 0; gj < dom_ny(s, 0); ++gj) {
             int c = idx(L, nxd - 1, gj);
             if (L->type[c] != T_FLUID) continue;
             int c1 = idx(L, nxd - 2, gj), c2 = idx(L, nxd - 3, gj);
-            for (int i = 0; i < 9; ++i)
-                if (CX[i] == -1) L->fn[9 * c + i] = 2.0 * L->fn[9 * c1 + i] - L->fn[9 * c2 + i];
+            double* fo = &L->fn[9 * c];
+            if (s->cfg.outlet == 2) {
+                double rho = s->cfg.rho_ref, uy = L->uy[c1];
+                double ux = (fo[0] + fo[3] + fo[4] + 2.0 * (fo[1] + fo[5] + fo[7])) / rho - 1.0;
+                fo[2] = fo[1] - (2.0 / 3.0) * rho * ux;
+                fo[6] = fo[5] + 0.5 * (fo[3] - fo[4]) - rho * ux / 6.0 - 0.5 * rho * uy;
+                fo[8] = fo[7] - 0.5 * (fo[3] - fo[4]) - rho * ux / 6.0 + 0.5 * rho * uy;
+                continue;
+            }
+            for (int i = 0; i < 9; ++i) {
+                if (CX[i] != -1) continue;
+                if (s->cfg.outlet == 1) fo[i] = L->fn[9 * c1 + i];
+                else fo[i] = 2.0 * L->fn[9 * c1 + i] - L->fn[9 * c2 + i];
+            }
         }
     }
     double* t;

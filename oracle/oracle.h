@@ -44,6 +44,8 @@ typedef struct {
     int32_t bc[4];                /* x-lo, x-hi, y-lo, y-hi */
     int32_t wall_model, bb_mode, sa_mode;
     int32_t body_mode;            /* 0: bodies are solid walls, 1: they only mark refinement */
+    int32_t outlet;               /* 0: second-order, 1: first-order outlet extrapolation,
+                                     2: Zou-He pressure outlet at rho_ref */
     double origin[2];             /* physical corner of the level-0 box */
     double dx0;                   /* physical level-0 cell size */
     double band[LBRO_MAX_LEVELS]; /* band[l], l >= 1: physical refinement distance */

@@ -31,7 +31,7 @@ class lbr_config(C.Structure):
     _fields_ = [
         ("version", C.c_int32), ("storage", C.c_int32), ("nx0", C.c_int32), ("ny0", C.c_int32),
         ("n_levels", C.c_int32), ("bc", C.c_int32 * 4), ("wall_model", C.c_int32),
-        ("bb", C.c_int32), ("sa", C.c_int32), ("body_mode", C.c_int32), ("reserved0", C.c_int32),
+        ("bb", C.c_int32), ("sa", C.c_int32), ("body_mode", C.c_int32), ("outlet", C.c_int32),
         ("origin", C.c_double * 2), ("dx0", C.c_double), ("band", C.c_double * MAX_LEVELS),
         ("wall_y", C.c_double * 2), ("mach", C.c_double), ("reynolds", C.c_double),
         ("ref_length", C.c_double), ("u_ref", C.c_double), ("nu0", C.c_double),
@@ -126,6 +126,7 @@ def make_config(case, storage="f32", stream=None, allocator=None) -> lbr_config:
         c.bc[k] = case["bc"][k]
     c.wall_model, c.bb, c.sa = case["wall_model"], case["bb_mode"], case["sa_mode"]
     c.body_mode = case.get("body_mode", 0)
+    c.outlet = case.get("outlet", 0)
     c.origin[0], c.origin[1] = case["origin"]
     c.dx0 = case["dx0"]
     for l, b in enumerate(case.get("bands", ())):

@@ -111,6 +111,7 @@ struct lbr_ctx {
     bool use_graph = false;
     hipGraphExec_t graph = nullptr;
     int graph_steps = 0;
+    int graph_parity = 0;          // buffer index of level 0 the graph was captured with
     // profiling
     bool prof = false;
     std::vector<hipEvent_t> ev;
@@ -771,12 +772,14 @@ void fill_step_args(lbr_ctx* c, int l, int substep, StepArgs<ST, CT>& a) {
     a.dom.nyd = cfg.ny0 << l;
     for (int k = 0; k < 4; ++k) a.dom.bc[k] = cfg.bc[k];
     a.dom.periodic_x = cfg.bc[0] == LBR_BC_PERIODIC;
+    a.dom.outlet = cfg.outlet;
     a.nu = (CT)L.nu;
     a.fx = (CT)L.fx;
     a.fy = (CT)L.fy;
     a.omega_b = (CT)cfg.omega_b;
     a.u_in = (CT)c->u_ref;
     a.chi_in = (CT)cfg.chi_inlet;
+    a.rho_out = (CT)cfg.rho_ref;
     a.sa_mode = cfg.sa;
     a.frozen = cfg.sa == LBR_SA_FROZEN;
     a.bb_halfway = cfg.bb == LBR_BB_HALFWAY;
@@ -1053,6 +1056,9 @@ int capture_graph(lbr_ctx* c) {
     if (e != hipSuccess) return set_err(c, LBR_ERR_HIP, "graph capture: %s", hipGetErrorString(e));
     // capture advanced the buffer indices without running: undo
     for (Level& L : c->lv) L.cur ^= (c->graph_steps << L.l) & 1;
+    // the graph holds the buffer addresses of this parity; finer levels take an
+    // even number of sub-steps per coarse step, so level 0 alone decides it
+    c->graph_parity = c->lv[0].cur;
     e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return set_err(c, LBR_ERR_HIP, "graph instantiate: %s", hipGetErrorString(e));
@@ -1071,7 +1077,7 @@ int lbr_create(const lbr_config* cfg, lbr_ctx** out) {
     *out = nullptr;
     if (!cfg || cfg->version != LBR_ABI_VERSION) return LBR_ERR_INVALID_ARG;
     if (cfg->n_levels < 1 || cfg->n_levels > LBR_MAX_LEVELS || cfg->nx0 < 4 || cfg->ny0 < 4 ||
-        !(cfg->dx0 > 0) || cfg->storage < 0 || cfg->storage > 3)
+        !(cfg->dx0 > 0) || cfg->storage < 0 || cfg->storage > 3 || cfg->outlet < 0 || cfg->outlet > 2)
         return LBR_ERR_INVALID_ARG;
     if ((cfg->bc[0] == LBR_BC_PERIODIC) != (cfg->bc[1] == LBR_BC_PERIODIC) ||
         (cfg->bc[2] == LBR_BC_PERIODIC) != (cfg->bc[3] == LBR_BC_PERIODIC) ||
@@ -1211,7 +1217,12 @@ int lbr_advance(lbr_ctx* c, int64_t n) {
     if (c->use_graph && !c->prof) {
         if (!c->graph)
             if (int r = capture_graph(c)) return r;
-        for (; k + c->graph_steps <= n; k += c->graph_steps) {
+        // after an odd number of direct coarse steps, one more restores the parity
+        if (c->lv[0].cur != c->graph_parity && n - k > c->graph_steps) {
+            if (int r = cycle(c, 0, 0)) return r;
+            ++k;
+        }
+        for (; k + c->graph_steps <= n && c->lv[0].cur == c->graph_parity; k += c->graph_steps) {
             HIPCHK(c, hipGraphLaunch(c->graph, c->stream));
             for (Level& L : c->lv) L.cur ^= (c->graph_steps << L.l) & 1;
         }

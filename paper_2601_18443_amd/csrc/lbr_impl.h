@@ -41,6 +41,7 @@ struct Domain {
     int nxd, nyd;          // domain size in cells of this level
     int bc[4];
     int periodic_x;
+    int outlet;            // LBR_OUTLET_*: rule for the unknown outlet populations
 };
 
 // Link-wise wall data of one level (Sections 2.1 and 2.3).
@@ -72,7 +73,7 @@ struct StepArgs {
     int nedge;
     Box box;
     Domain dom;
-    CT nu, fx, fy, omega_b, u_in, chi_in;
+    CT nu, fx, fy, omega_b, u_in, chi_in, rho_out;
     int sa_mode, bb_halfway, frozen;
     int substep;                     // 1 or 2 within the parent's step (0 on level 0)
     const ST* fcoarse; Box cbox;     // parent level populations (ghost transfer)

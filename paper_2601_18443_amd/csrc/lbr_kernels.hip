@@ -26,7 +26,7 @@ constexpr int BC_PERIODIC = 0, BC_INLET = 1, BC_OUTLET = 2, BC_SYMMETRY = 3;
 
 // SA-neg constants (Section 2.2)
 constexpr double KAPPA = 0.41, CB1 = 0.1355, CB2 = 0.622, SIGMA = 2.0 / 3.0, CW2 = 0.3,
-                 CW3 = 2.0, CV1 = 7.1, RLIM = 10.0, CV2 = 0.7, CV3 = 0.3, CT3 = 1.2, CN1 = 16.0;
+                 CW3 = 2.0, CV1 = 7.1, RLIM = 10.0, CV2 = 0.7, CV3 = 0.9, CT3 = 1.2, CN1 = 16.0;
 constexpr double CW1 = CB1 / (KAPPA * KAPPA) + (1.0 + CB2) / SIGMA;
 
 template <class T>
@@ -554,7 +554,8 @@ __global__ __launch_bounds__(256) void k_step(const StepArgs<ST, CT> a) {
 // ---------------------------------------------------------------------------
 // k_edge: level-0 cells on the domain edge (except wall nodes), one thread
 // each, beside k_step: periodic wrap, specular reflection at symmetry edges,
-// Zou-He velocity inlet, extrapolation outlet (Section 3.1.1), and the SA
+// Zou-He velocity inlet, extrapolation or Zou-He pressure outlet (Section
+// 3.1.1), and the SA
 // boundary rules (inlet chi, outlet extrapolation, mirrored stencil).
 // ---------------------------------------------------------------------------
 template <class ST, class CT>
@@ -580,9 +581,20 @@ __global__ __launch_bounds__(64) void k_edge(const StepArgs<ST, CT> a) {
             s[5] = s[6] - CT(0.5) * (s[3] - s[4]) + rho * ui * CT(1.0 / 6.0);
             s[7] = s[8] + CT(0.5) * (s[3] - s[4]) + rho * ui * CT(1.0 / 6.0);
         }
-        if (at_outlet)
+        if (at_outlet && a.dom.outlet == 2) {
+            // Zou-He with rho = rho_ref and u_y of the upstream cell (unknowns: c_x = -1)
+            const CT rho = a.rho_out, uy = v[3];
+            const CT ux = (CT(1) + s[0] + s[3] + s[4] + CT(2) * (s[1] + s[5] + s[7])) / rho - CT(1);
+            s[2] = s[1] - CT(2.0 / 3.0) * rho * ux;
+            s[6] = s[5] + CT(0.5) * (s[3] - s[4]) - rho * ux * CT(1.0 / 6.0) - CT(0.5) * rho * uy;
+            s[8] = s[7] - CT(0.5) * (s[3] - s[4]) - rho * ux * CT(1.0 / 6.0) + CT(0.5) * rho * uy;
+        } else if (at_outlet) {
             for (int i = 0; i < 9; ++i)
-                if (CX[i] == -1) s[i] = CT(2) * poststream(a, i, gx - 1, gy) - poststream(a, i, gx - 2, gy);
+                if (CX[i] == -1)
+                    s[i] = (a.dom.outlet == 1)
+                               ? poststream(a, i, gx - 1, gy)
+                               : CT(2) * poststream(a, i, gx - 1, gy) - poststream(a, i, gx - 2, gy);
+        }
     }
     CT chi_new;
     if (a.frozen) {

@@ -267,3 +267,46 @@ def test_wall_distance_field_by_brute_force():
         t = np.clip(((x - A[:, 0]) * e[:, 0] + (y - A[:, 1]) * e[:, 1]) / (e**2).sum(1), 0, 1)
         dist = np.hypot(A[:, 0] + t * e[:, 0] - x, A[:, 1] + t * e[:, 1] - y).min()
         assert d[js[k], is_[k]] == pytest.approx(dist, rel=1e-12)
+
+
+def _open_channel(outlet, nx=32, ny=16, seed=5):
+    c = box_case(nx, ny, bc=(LI.BC_INLET, LI.BC_OUTLET, LI.BC_SYMMETRY, LI.BC_SYMMETRY),
+                 outlet=outlet, u_ref=0.05, nu0=0.01)
+    s = oracle.Sim(c)
+    rng = np.random.default_rng(seed)
+    sh = (ny, nx)
+    rho = 1.0 + 0.01 * rng.uniform(-1, 1, sh)
+    ux = 0.05 + 0.01 * rng.uniform(-1, 1, sh)
+    uy = 0.01 * rng.uniform(-1, 1, sh)
+    s.init(0, rho=rho, ux=ux, uy=uy, chi=np.zeros(sh))
+    return s, rho, ux, uy
+
+
+def test_pressure_outlet_holds_reference_density_and_upstream_tangential_velocity():
+    """Zou-He outlet (Section 3.1.1, the inlet's rule applied with a prescribed
+    density): after one step every outlet cell carries exactly rho_ref, and the
+    tangential velocity of its upstream neighbour at the previous time."""
+    s, rho, ux, uy = _open_channel(LI.OUTLET_PRESSURE)
+    s.advance(1)
+    r1, v1 = s.field(0, oracle.F_RHO), s.field(0, oracle.F_UY)
+    np.testing.assert_allclose(r1[:, -1], 1.0, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(v1[:, -1], uy[:, -2], rtol=0, atol=1e-14)
+
+
+def test_velocity_inlet_holds_prescribed_velocity():
+    """Zou-He inlet: after one step the inlet column carries u = (U, 0) exactly."""
+    s, rho, ux, uy = _open_channel(LI.OUTLET_EXTRAP2)
+    s.advance(1)
+    np.testing.assert_allclose(s.field(0, oracle.F_UX)[:, 0], 0.05, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(s.field(0, oracle.F_UY)[:, 0], 0.0, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("outlet", [LI.OUTLET_EXTRAP2, LI.OUTLET_EXTRAP1, LI.OUTLET_PRESSURE])
+def test_open_channel_preserves_uniform_flow(outlet):
+    c = box_case(32, 16, bc=(LI.BC_INLET, LI.BC_OUTLET, LI.BC_SYMMETRY, LI.BC_SYMMETRY),
+                 outlet=outlet, u_ref=0.05, nu0=0.01)
+    s = oracle.Sim(c)
+    s.advance(20)
+    np.testing.assert_allclose(s.field(0, oracle.F_UX), 0.05, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(s.field(0, oracle.F_UY), 0.0, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(s.field(0, oracle.F_RHO), 1.0, rtol=0, atol=1e-14)

@@ -51,6 +51,27 @@ def test_modified_vorticity_is_continuous_at_branch_switch():
         assert st == pytest.approx((1 - SA["c_v2"]) * omega, rel=1e-6)
 
 
+def test_modified_vorticity_stays_bounded_on_the_second_branch():
+    """Below S-bar = -c_v2 Omega, eq. (14) must keep S-tilde between
+    (1 - c_v3) Omega (S-bar -> -inf) and (1 - c_v2) Omega (the switch), with no
+    pole: sweep S-bar over five decades through the branch."""
+    nu, omega = 1e-5, 2e-3
+    chi = 10.0                                    # f_v2 < 0: S-bar < 0
+    nt = chi * nu
+    fv2 = 1 - chi / (1 + chi * fv1(chi))
+    assert fv2 < 0
+    lo, hi = (1 - SA["c_v3"]) * omega, (1 - SA["c_v2"]) * omega
+    prev = None
+    for ratio in np.logspace(np.log10(0.71), 4, 400):          # |S-bar| / Omega
+        d = np.sqrt(nt * fv2 / (-ratio * omega * K**2))
+        st = oracle.sa_source(nt, nu, omega, d)["S_tilde"]
+        assert lo <= st <= hi * (1 + 1e-12), (ratio, st)
+        if prev is not None:
+            assert st <= prev * (1 + 1e-12)                    # decreasing in |S-bar|
+        prev = st
+    assert prev == pytest.approx(lo, rel=1e-3)
+
+
 @pytest.mark.parametrize("chi", [-0.5, -2.0, -10.0])
 def test_negative_branch(chi):
     nu, omega, d = 1e-5, 2e-3, 0.01
