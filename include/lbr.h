@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define LBR_ABI_VERSION 1
+#define LBR_ABI_VERSION 2
 #define LBR_MAX_LEVELS 12
 
 enum lbr_status {
@@ -80,6 +80,13 @@ enum lbr_sa { LBR_SA_FROZEN = 0, LBR_SA_LW = 1, LBR_SA_UPWIND1 = 2 };
    density held at rho_ref and the tangential velocity of the upstream cell;
    it fixes the pressure level that the two extrapolations leave free. */
 enum lbr_outlet { LBR_OUTLET_EXTRAP2 = 0, LBR_OUTLET_EXTRAP1 = 1, LBR_OUTLET_PRESSURE = 2 };
+/* Absorbing layer (not part of the paper's method; off unless sponge_width > 0).
+   Level 0 is nearly inviscid under acoustic scaling, so pressure waves of the
+   whole domain reflect between its far-field sides for thousands of steps.
+   Within sponge_width cells of an INLET, OUTLET or SYMMETRY side, each level-0
+   step relaxes the post-collision populations towards the free-stream
+   equilibrium, f <- f - sigma (f - f_eq(rho_ref, u_ref, 0)), with
+   sigma = sponge_strength ((W - d) / W)^2 at distance d (cell centre to side). */
 
 enum lbr_body { LBR_BODY_SOLID = 0, LBR_BODY_REFINE_ONLY = 1 };
 
@@ -122,6 +129,9 @@ typedef struct lbr_config {
     double omega_b;                /* bulk relaxation frequency (paper: 1) */
     double d_wr, d_wv;             /* reference / virtual node distances in cells (2, 1) */
     double u_wall[4];              /* LBR_WALL_PRESCRIBED: (ux, uy) lower, (ux, uy) upper */
+    double sponge_width;           /* absorbing layer along the INLET, OUTLET and SYMMETRY
+                                      sides of level 0, in level-0 cells (0 = none) */
+    double sponge_strength;        /* its largest relaxation rate per level-0 step */
     lbr_alloc_fn alloc_fn;         /* optional device allocator */
     lbr_free_fn free_fn;
     void* alloc_user;

@@ -158,12 +158,14 @@ def case_channel(nx: int = 256, ny: int = 64, steps: int = 2000):
 def case_airfoil(seed: int = 0, finest_cells_per_chord: int = 1024, n_levels: int = 8,
                  domain_chords: float = 40.0, band_finest: float = 0.25,
                  mach: float = 0.15, reynolds: float = 6e6, alpha_deg: float = 10.0,
-                 n_side: int = 2048, thickness: float = 0.12):
+                 n_side: int = 2048, thickness: float = 0.12, outlet: int = OUTLET_EXTRAP2,
+                 sponge_fraction: float = 0.075, sponge_strength: float = 0.1):
     """Single airfoil-like body in a square domain with distance-band refinement.
 
     Level l (l = 0 coarsest) has cell size dx0 / 2^l; cells of level l-1 whose
     centre lies within bands[l] of the body are refined, with bands doubling
-    towards the coarse levels (band_finest at the finest level).
+    towards the coarse levels (band_finest at the finest level).  An absorbing
+    layer of sponge_fraction of the level-0 width lines the four far-field sides.
     """
     dx_f = 1.0 / finest_cells_per_chord
     dx0 = dx_f * 2 ** (n_levels - 1)
@@ -177,7 +179,8 @@ def case_airfoil(seed: int = 0, finest_cells_per_chord: int = 1024, n_levels: in
         wall_y=(0.0, 0.0), bands=bands, u_ref=0.0, nu0=0.0, force=(0.0, 0.0),
         mach=mach, reynolds=reynolds, ref_length=1.0, chi_init=3.0, chi_inlet=3.0,
         omega_b=1.0, d_wr=2.0, d_wv=1.0, wall_model=WALL_VN, bb_mode=BB_AUTO,
-        sa_mode=SA_LW, alpha_deg=alpha_deg, bodies=[xy],
+        sa_mode=SA_LW, alpha_deg=alpha_deg, bodies=[xy], outlet=outlet,
+        sponge_width=float(round(sponge_fraction * n0)), sponge_strength=sponge_strength,
     )
 
 

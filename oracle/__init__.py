@@ -33,6 +33,7 @@ class Config(C.Structure):
         ("rho_ref", C.c_double), ("chi_inlet", C.c_double), ("chi_init", C.c_double),
         ("force", C.c_double * 2), ("omega_b", C.c_double),
         ("d_wr", C.c_double), ("d_wv", C.c_double), ("u_wall", C.c_double * 4),
+        ("sponge_width", C.c_double), ("sponge_strength", C.c_double),
     ]
 
 
@@ -81,6 +82,8 @@ def lib():
         L.lbro_lsq_point.restype = d
         L.lbro_idw_point.argtypes = [i32, dp, dp, dp, d, d]
         L.lbro_idw_point.restype = d
+        L.lbro_sponge_cell.argtypes = [dp, d, d, d, d, dp]
+        L.lbro_sponge_cell.restype = None
         _lib = L
     return _lib
 
@@ -114,6 +117,13 @@ def slip(utau, dwv, nu):
 def feq(rho, ux, uy):
     out = np.zeros(9)
     lib().lbro_feq(rho, ux, uy, _dp(out))
+    return out
+
+
+def sponge_cell(f, sigma, rho, ux, uy):
+    f = _arr(f)
+    out = np.zeros(9)
+    lib().lbro_sponge_cell(_dp(f), sigma, rho, ux, uy, _dp(out))
     return out
 
 
@@ -180,6 +190,8 @@ def make_config(case) -> Config:
     uw = case.get("u_wall", (0.0, 0.0, 0.0, 0.0))
     for k in range(4):
         c.u_wall[k] = uw[k]
+    c.sponge_width = case.get("sponge_width", 0.0)
+    c.sponge_strength = case.get("sponge_strength", 0.0)
     return c
 
 

@@ -819,7 +819,8 @@ int lbro_create(const lbro_config* cfg, int32_t n_bodies, const int32_t* n_pts, 
                 lbro_sim** out) {
     *out = NULL;
     if (!cfg || cfg->n_levels < 1 || cfg->n_levels > LBRO_MAX_LEVELS || cfg->nx0 < 4 ||
-        cfg->ny0 < 4 || !(cfg->dx0 > 0.0) || cfg->outlet < 0 || cfg->outlet > 2)
+        cfg->ny0 < 4 || !(cfg->dx0 > 0.0) || cfg->outlet < 0 || cfg->outlet > 2 ||
+        cfg->sponge_width < 0.0 || cfg->sponge_strength < 0.0 || cfg->sponge_strength > 1.0)
         return fail("invalid configuration");
     if ((cfg->bc[0] == LBRO_BC_PERIODIC) != (cfg->bc[1] == LBRO_BC_PERIODIC) ||
         (cfg->bc[2] == LBRO_BC_PERIODIC) != (cfg->bc[3] == LBRO_BC_PERIODIC))
@@ -1044,6 +1045,40 @@ static void collide_level(const lbro_sim* s, olevel* L) {
         if (L->type[c] != T_FLUID) continue;
         double nut = sa_nut(L->chi[c] * L->nu, L->nu);
         lbro_collide(&L->f[9 * c], L->nu + nut, s->cfg.omega_b, F, &L->fs[9 * c]);
+    }
+}
+
+/* Absorbing layer (an addition to the paper's method, used only when
+   sponge_width > 0): level-0 post-collision populations within sponge_width
+   cells of an inlet, outlet or symmetry side are relaxed towards the
+   free-stream equilibrium, sigma = strength ((W - d) / W)^2. */
+void lbro_sponge_cell(const double f[9], double sigma, double rho, double ux, double uy, double out[9]) {
+    double t[9];
+    lbro_feq(rho, ux, uy, t);
+    for (int i = 0; i < 9; ++i) out[i] = f[i] - sigma * (f[i] - t[i]);
+}
+
+static void sponge_level0(const lbro_sim* s, olevel* L) {
+    const lbro_config* cfg = &s->cfg;
+    double W = cfg->sponge_width;
+    if (L->level != 0 || !(W > 0.0) || !(cfg->sponge_strength > 0.0)) return;
+    int far[4];
+    for (int k = 0; k < 4; ++k)
+        far[k] = cfg->bc[k] == LBRO_BC_INLET || cfg->bc[k] == LBRO_BC_OUTLET ||
+                 cfg->bc[k] == LBRO_BC_SYMMETRY;
+    int n = L->nx * L->ny;
+    for (int c = 0; c < n; ++c) {
+        if (L->type[c] != T_FLUID) continue;
+        int gi = c % L->nx + L->gx0, gj = c / L->nx + L->gy0;
+        double d = 1e300;
+        if (far[0] && gi + 0.5 < d) d = gi + 0.5;
+        if (far[1] && cfg->nx0 - gi - 0.5 < d) d = cfg->nx0 - gi - 0.5;
+        if (far[2] && gj + 0.5 < d) d = gj + 0.5;
+        if (far[3] && cfg->ny0 - gj - 0.5 < d) d = cfg->ny0 - gj - 0.5;
+        if (d >= W) continue;
+        double x = (W - d) / W;
+        double sigma = cfg->sponge_strength * x * x;
+        lbro_sponge_cell(&L->fs[9 * c], sigma, cfg->rho_ref, s->u_ref, 0.0, &L->fs[9 * c]);
     }
 }
 
@@ -1325,6 +1360,7 @@ static int cycle(lbro_sim* s, int l) {
     macros(L);
     wall_model_level(s, L);
     collide_level(s, L);
+    sponge_level0(s, L);
     if (l + 1 < s->nl) {
         olevel* F = &s->lv[l + 1];
         macros(F);

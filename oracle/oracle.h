@@ -57,6 +57,8 @@ typedef struct {
     double omega_b;
     double d_wr, d_wv;            /* reference / virtual node distances, in cells */
     double u_wall[4];             /* PRESCRIBED slip velocity: lower (x,y), upper (x,y) */
+    double sponge_width;          /* absorbing layer of level 0, in level-0 cells (0: none) */
+    double sponge_strength;       /* its largest relaxation rate per step */
 } lbro_config;
 
 typedef struct lbro_sim lbro_sim;
@@ -66,6 +68,9 @@ typedef struct lbro_sim lbro_sim;
    u_tau, u_W (x, y), rho_W, |u_Rt|, Cp, Cf, body, chi_B, u_Rt (x, y),
    q[1..8] (-1 where the link is not cut), spare. */
 #define LBRO_WALL_STRIDE 28
+
+/* Absorbing-layer rule for one cell (test access): out = f - sigma (f - f_eq(rho, ux, uy)). */
+void lbro_sponge_cell(const double f[9], double sigma, double rho, double ux, double uy, double out[9]);
 
 const char* lbro_error(void);
 

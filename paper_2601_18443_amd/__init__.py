@@ -15,7 +15,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbr.so")
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 MAX_LEVELS = 12
 WALL_STRIDE = 28
 
@@ -38,6 +38,7 @@ class lbr_config(C.Structure):
         ("rho_ref", C.c_double), ("chi_inlet", C.c_double), ("chi_init", C.c_double),
         ("force", C.c_double * 2), ("omega_b", C.c_double), ("d_wr", C.c_double),
         ("d_wv", C.c_double), ("u_wall", C.c_double * 4),
+        ("sponge_width", C.c_double), ("sponge_strength", C.c_double),
         ("alloc_fn", ALLOC_FN), ("free_fn", FREE_FN), ("alloc_user", C.c_void_p),
         ("stream", C.c_void_p),
     ]
@@ -140,6 +141,8 @@ def make_config(case, storage="f32", stream=None, allocator=None) -> lbr_config:
     c.omega_b, c.d_wr, c.d_wv = case["omega_b"], case["d_wr"], case["d_wv"]
     for k, v in enumerate(case.get("u_wall", (0.0, 0.0, 0.0, 0.0))):
         c.u_wall[k] = v
+    c.sponge_width = case.get("sponge_width", 0.0)
+    c.sponge_strength = case.get("sponge_strength", 0.0)
     if allocator is not None:
         c.alloc_fn, c.free_fn = allocator.alloc_cb, allocator.free_cb
     c.stream = stream

@@ -52,6 +52,9 @@ struct Level {
     int32_t* covb_dev = nullptr;
     int32_t* owned_dev = nullptr;
     int32_t* edge_dev = nullptr;
+    int32_t* sponge_dev = nullptr;
+    double* sponge_sigma = nullptr;
+    int n_sponge = 0;
     double* bq = nullptr;
     int32_t* bcell = nullptr;
     double* bgeo = nullptr;
@@ -700,6 +703,34 @@ int alloc_level(lbr_ctx* c, Level& L) {
     for (int32_t k : L.owned)
         if ((L.flag[k] & F_EDGE) && !(L.flag[k] & F_WALL)) L.edge.push_back(k);
     if (int r = upload(c, &L.edge_dev, L.edge, &L.bytes)) return r;
+    {
+        // absorbing layer of level 0 along the far-field sides
+        const lbr_config& cfg = c->cfg;
+        std::vector<int32_t> sl;
+        std::vector<double> sg;
+        const double W = cfg.sponge_width;
+        if (L.l == 0 && W > 0.0 && cfg.sponge_strength > 0.0) {
+            auto far = [&](int side) {
+                return cfg.bc[side] == LBR_BC_INLET || cfg.bc[side] == LBR_BC_OUTLET ||
+                       cfg.bc[side] == LBR_BC_SYMMETRY;
+            };
+            for (int32_t k : L.owned) {
+                const int gx = (int)(k % L.box.pitch) + L.box.gx0, gy = (int)(k / L.box.pitch) + L.box.gy0;
+                double d = 1e300;
+                if (far(0)) d = std::min(d, gx + 0.5);
+                if (far(1)) d = std::min(d, cfg.nx0 - gx - 0.5);
+                if (far(2)) d = std::min(d, gy + 0.5);
+                if (far(3)) d = std::min(d, cfg.ny0 - gy - 0.5);
+                if (d >= W) continue;
+                const double x = (W - d) / W;
+                sl.push_back(k);
+                sg.push_back(cfg.sponge_strength * x * x);
+            }
+        }
+        L.n_sponge = (int)sl.size();
+        if (int r = upload(c, &L.sponge_dev, sl, &L.bytes)) return r;
+        if (int r = upload(c, &L.sponge_sigma, sg, &L.bytes)) return r;
+    }
     L.snap = static_cast<double*>(dalloc(c, std::max<size_t>(L.owned.size(), 1) * 2 * sizeof(double)));
     // wall records
     const int nb = (int)L.nodes.size();
@@ -875,6 +906,17 @@ int do_step(lbr_ctx* c, int l, int substep) {
     HIPCHK(c, launch_step(c->prec, buf, c->stream,
                           prof_events(c, l + 1 == (int)c->lv.size() ? EV_STEP_FINE : EV_STEP)));
     if (walls) HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
+    if (L.n_sponge) {
+        SpongeArgs sp{};
+        sp.n = L.n_sponge;
+        sp.list = L.sponge_dev;
+        sp.sigma = L.sponge_sigma;
+        sp.f = L.f[1 - L.cur];
+        sp.plane = L.box.plane;
+        sp.drho = c->cfg.rho_ref - 1.0;
+        sp.ux = c->u_ref;
+        HIPCHK(c, launch_sponge(c->prec, sp, c->stream));
+    }
     L.cur ^= 1;
     return 0;
 }
@@ -1077,7 +1119,8 @@ int lbr_create(const lbr_config* cfg, lbr_ctx** out) {
     *out = nullptr;
     if (!cfg || cfg->version != LBR_ABI_VERSION) return LBR_ERR_INVALID_ARG;
     if (cfg->n_levels < 1 || cfg->n_levels > LBR_MAX_LEVELS || cfg->nx0 < 4 || cfg->ny0 < 4 ||
-        !(cfg->dx0 > 0) || cfg->storage < 0 || cfg->storage > 3 || cfg->outlet < 0 || cfg->outlet > 2)
+        !(cfg->dx0 > 0) || cfg->storage < 0 || cfg->storage > 3 || cfg->outlet < 0 || cfg->outlet > 2 ||
+        cfg->sponge_width < 0 || cfg->sponge_strength < 0 || cfg->sponge_strength > 1)
         return LBR_ERR_INVALID_ARG;
     if ((cfg->bc[0] == LBR_BC_PERIODIC) != (cfg->bc[1] == LBR_BC_PERIODIC) ||
         (cfg->bc[2] == LBR_BC_PERIODIC) != (cfg->bc[3] == LBR_BC_PERIODIC) ||

@@ -118,6 +118,13 @@ struct InitArgs {
     double nu, fx, fy, omega_b;
 };
 
+// Absorbing layer of level 0: listed cells and their relaxation rates.
+struct SpongeArgs {
+    int n; const int32_t* list; const double* sigma;
+    void* f; long plane;
+    double drho, ux;                 // target: rho_ref - 1, u_ref (u_y = 0)
+};
+
 struct SurfaceArgs {
     int nseg;
     const double* seg;               // [nseg][6]: t (x, y), n (x, y), ds, unused
@@ -147,6 +154,7 @@ hipError_t launch_wall(Prec p, const void* args, hipStream_t s);
 hipError_t launch_fill(Prec p, const FillArgs& a, hipStream_t s);
 hipError_t launch_restrict(Prec p, const RestrictArgs& a, hipStream_t s);
 hipError_t launch_init(Prec p, const InitArgs& a, hipStream_t s);
+hipError_t launch_sponge(Prec p, const SpongeArgs& a, hipStream_t s);
 hipError_t launch_surface(Prec p, const SurfaceArgs& a, int nblocks, hipStream_t s);
 hipError_t launch_sum_partials(const double* partial, int nblocks, double* out, hipStream_t s);
 hipError_t launch_to_double(Prec p, const void* src, double* dst, long n, hipStream_t s);

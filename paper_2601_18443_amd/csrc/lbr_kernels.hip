@@ -784,6 +784,24 @@ __global__ void k_init(const InitArgs a) {
     for (int i = 0; i < 9; ++i) Cv<ST, CT>::st(f + i * a.plane + c, s[i]);
 }
 
+// Absorbing layer of level 0: post-collision populations relaxed towards the
+// free-stream equilibrium (shifted form, so the target is w_i-free).
+template <class ST, class CT>
+__global__ __launch_bounds__(256) void k_sponge(const SpongeArgs a) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.n) return;
+    const long c = a.list[k];
+    const CT sg = CT(a.sigma[k]);
+    CT t[9];
+    equilibrium<CT>(t, CT(a.drho), CT(a.ux), CT(0));
+    ST* f = (ST*)a.f;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const CT v = Cv<ST, CT>::ld(f + i * a.plane + c);
+        Cv<ST, CT>::st(f + i * a.plane + c, v - sg * (v - t[i]));
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Geometry: FP64 distance to the wall polylines and even-odd inside test, per
 // cell centre of a level's storage box.
@@ -1004,6 +1022,18 @@ hipError_t launch_init(Prec p, const InitArgs& a, hipStream_t s) {
         case P_F32: hipLaunchKernelGGL((k_init<float, float>), g, b, 0, s, a); break;
         case P_F16: hipLaunchKernelGGL((k_init<__half, float>), g, b, 0, s, a); break;
         default: hipLaunchKernelGGL((k_init<__hip_bfloat16, float>), g, b, 0, s, a); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_sponge(Prec p, const SpongeArgs& a, hipStream_t s) {
+    if (a.n == 0) return hipSuccess;
+    const dim3 g(nblocks(a.n, 256)), b(256);
+    switch (p) {
+        case P_F64: hipLaunchKernelGGL((k_sponge<double, double>), g, b, 0, s, a); break;
+        case P_F32: hipLaunchKernelGGL((k_sponge<float, float>), g, b, 0, s, a); break;
+        case P_F16: hipLaunchKernelGGL((k_sponge<__half, float>), g, b, 0, s, a); break;
+        default: hipLaunchKernelGGL((k_sponge<__hip_bfloat16, float>), g, b, 0, s, a); break;
     }
     return hipGetLastError();
 }

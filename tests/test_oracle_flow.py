@@ -310,3 +310,38 @@ def test_open_channel_preserves_uniform_flow(outlet):
     np.testing.assert_allclose(s.field(0, oracle.F_UX), 0.05, rtol=0, atol=1e-14)
     np.testing.assert_allclose(s.field(0, oracle.F_UY), 0.0, rtol=0, atol=1e-14)
     np.testing.assert_allclose(s.field(0, oracle.F_RHO), 1.0, rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_absorbing_layer_rule_blends_mass_and_momentum(seed):
+    """f - sigma (f - f_eq(rho_t, u_t)): mass and momentum become the sigma-weighted
+    blend of the cell's and the target's (moments of eq. (4) are rho and rho u)."""
+    rng = np.random.default_rng(seed)
+    f = LI.random_populations(seed, 1, amplitude=0.05)[0]
+    sigma = rng.uniform(0.01, 0.5)
+    rt, ut, vt = 1.0 + 0.01 * rng.uniform(-1, 1), 0.08, 0.01 * rng.uniform(-1, 1)
+    out = oracle.sponge_cell(f, sigma, rt, ut, vt)
+    cx = np.array([0, 1, -1, 0, 0, 1, -1, 1, -1])
+    cy = np.array([0, 0, 0, 1, -1, 1, -1, -1, 1])
+    assert out.sum() == pytest.approx((1 - sigma) * f.sum() + sigma * rt, abs=1e-15)
+    assert (cx * out).sum() == pytest.approx((1 - sigma) * (cx * f).sum() + sigma * rt * ut, abs=1e-15)
+    assert (cy * out).sum() == pytest.approx((1 - sigma) * (cy * f).sum() + sigma * rt * vt, abs=1e-15)
+
+
+def test_absorbing_layer_keeps_the_free_stream_and_damps_a_pressure_pulse():
+    base = dict(bc=(LI.BC_INLET, LI.BC_OUTLET, LI.BC_SYMMETRY, LI.BC_SYMMETRY),
+                outlet=LI.OUTLET_EXTRAP1, u_ref=0.05, nu0=1e-4)
+    c = box_case(64, 32, sponge_width=12.0, sponge_strength=0.2, **base)
+    s = oracle.Sim(c)
+    s.advance(30)
+    np.testing.assert_allclose(s.field(0, oracle.F_UX), 0.05, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(s.field(0, oracle.F_RHO), 1.0, rtol=0, atol=1e-14)
+
+    def pulse_energy(width):
+        s = oracle.Sim(box_case(64, 32, sponge_width=width, sponge_strength=0.2, **base))
+        y, x = np.mgrid[0:32, 0:64] + 0.5
+        rho = 1.0 + 1e-3 * np.exp(-((x - 32) ** 2 + (y - 16) ** 2) / 8.0)
+        s.init(0, rho=rho, ux=np.full((32, 64), 0.05), uy=np.zeros((32, 64)), chi=np.zeros((32, 64)))
+        s.advance(400)
+        return float(np.sum((s.field(0, oracle.F_RHO) - 1.0) ** 2))
+    assert pulse_energy(12.0) < 1e-2 * pulse_energy(0.0)
