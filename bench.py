@@ -100,6 +100,8 @@ def main():
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16", "f64"])
     ap.add_argument("--graph", type=int, default=1, help="replay the coarse step from a HIP graph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the FP16 / BF16 storage runs reported beside the main line")
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
 
@@ -148,6 +150,7 @@ def main():
         f"k_boundary {kt[2]:.2f}, k_edge {kt[3]:.2f}")
     mlups = lups * args.steps / dt / 1e6
     f = sim.forces()
+    n_cells = int(sum(sim.level_info(l)["n_fluid"] for l in range(case["n_levels"])))
     if not np.all(np.isfinite(f)):
         log("warning: non-finite force coefficients")
 
@@ -167,6 +170,37 @@ def main():
                 "finest_level_avg_launch_us": round(kt[1], 3),
                 "k_boundary_avg_us": round(kt[2], 3), "k_edge_avg_us": round(kt[3], 3),
                 "alg_bytes_per_launch": round(bytes_per_launch, 0)}
+    # the same workload with 16-bit population storage (FP32 arithmetic), same timing
+    variants = {}
+    if not args.no_variants and args.storage == "f32":
+        sim.close()
+        del sim
+        for st in ("f16", "bf16"):
+            v = P.Solver(case, storage=st)
+            if args.graph:
+                v.use_graph(True)
+            v.advance(args.warmup)
+            v.synchronize()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            v.advance(args.steps)
+            v.synchronize()
+            torch.cuda.synchronize()
+            dtv = time.perf_counter() - t0
+            v.profile(True)
+            v.advance(args.steps)
+            v.synchronize()
+            ktv = v.profile(False)
+            ach = ALG_BYTES[st] * lups / launches_per_step / (ktv[0] * 1e-6) / 1e9 if ktv[0] > 0 else None
+            variants[st] = {"value": round(lups * args.steps / dtv / 1e6, 1), "unit": "MLUPS",
+                            "ms_per_step": round(1000 * dtv / args.steps, 4),
+                            "k_step_avg_launch_us": round(ktv[0], 3),
+                            "achieved_GBps": None if ach is None else round(ach, 1),
+                            "frac": None if ach is None else round(ach / HBM_PEAK_GBS, 4),
+                            "alg_bytes_per_lup": ALG_BYTES[st]}
+            log(f"{st} storage: {variants[st]['value']} MLUPS, k_step {ktv[0]:.2f} us")
+            v.close()
+            del v
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on the same workload")
@@ -179,10 +213,11 @@ def main():
         "data": "synthetic (seeded airfoil-like polyline)",
         "config": {"workload": "single airfoil-like body, 8 levels c/8..c/1024, 40c domain, "
                                "Re 6e6, M 0.15, AoA 10 deg",
-                   "cells": int(sum(sim.level_info(l)["n_fluid"] for l in range(n_levels))),
+                   "cells": n_cells,
                    "finest_cells": finest["n_fluid"], "lups_per_step": lups,
                    "storage": args.storage, "graph": bool(args.graph)},
         "roofline": roof, "cpu_baseline": cpu,
+        "storage_variants": variants or None,
         "forces": {"C_Df": f[0], "C_Dp": f[1], "C_D": f[2], "C_L": f[3]},
     }
     print(json.dumps(out), flush=True)

@@ -1,0 +1,61 @@
+"""Storage precision against the FP64 oracle at a converged state (needs an MI355X).
+
+The 3-level airfoil (finest c/64, Re 6e6, M 0.15, 10 degrees) is run for 4000
+coarse steps, by which the oracle's force coefficients are steady to six
+digits, with populations stored in FP64, FP32, FP16 and BF16 (shifted,
+f_i - w_i; arithmetic in FP32 for the 16-bit formats, FP64 Newton and force
+sums). Each storage is checked against the oracle's surface Cp, Cf and forces:
+
+  * FP64: rounding-order differences only (1e-9 relative);
+  * FP32: Cp max-abs 1e-4, Cf max-abs 1e-4 max|Cf|, C_D and C_L 1e-5 relative
+    (measured 6e-6, 1.4e-6, 6e-7, 3e-7);
+  * FP16: Cp 3e-2, Cf 1e-2 max|Cf| (the FP32 Cf bound of the study, which FP16
+    meets here), C_D and C_L 6e-3 relative (measured 1.1e-2, 2.9e-3, 2.1e-3,
+    2.3e-3);
+  * BF16: Cp 0.2, Cf 5e-2 max|Cf|, C_D and C_L 8e-2 (measured 7.7e-2, 2.2e-2,
+    1.7e-2, 3.1e-2).
+
+The 16-bit bounds are the measured errors with a margin of about 2.5: they
+record how much accuracy each format gives up, so that a regression shows.
+"""
+import numpy as np
+import pytest
+
+import lbr_inputs as LI
+import oracle
+from tests import parity_util as U
+
+pytestmark = pytest.mark.gpu
+
+STEPS = 4000
+BOUNDS = {  # storage: (Cp max-abs, Cf max-abs / max|Cf|, C_D and C_L relative)
+    "f64": (1e-9, 1e-9, 1e-9),
+    "f32": (1e-4, 1e-4, 1e-5),
+    "f16": (3e-2, 1e-2, 6e-3),
+    "bf16": (0.2, 5e-2, 8e-2),
+}
+
+
+@pytest.fixture(scope="module")
+def converged_oracle():
+    case = LI.case_airfoil_small()
+    o = oracle.Sim(case)
+    o.advance(STEPS)
+    cp, cf = o.surface(0)
+    return case, cp, cf, o.forces()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16"])
+def test_converged_surface_data_per_storage(converged_oracle, storage):
+    case, cpo, cfo, fo = converged_oracle
+    g = U.gpu_solver(case, storage)
+    g.use_graph(True)
+    g.advance(STEPS)
+    cp, cf = g.surface(0)
+    f = g.forces()
+    bcp, bcf, bforce = BOUNDS[storage]
+    assert np.all(np.isfinite(cp)) and np.all(np.isfinite(cf))
+    assert np.max(np.abs(cp - cpo)) <= bcp
+    assert np.max(np.abs(cf - cfo)) <= bcf * np.max(np.abs(cfo))
+    for k in (2, 3):                                   # C_D, C_L
+        assert abs(f[k] - fo[k]) <= bforce * abs(fo[k]), (k, f[k], fo[k])
