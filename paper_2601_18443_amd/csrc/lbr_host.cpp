@@ -639,6 +639,10 @@ void mark_restriction_tiles(lbr_ctx* c, Level& L) {
 int alloc_level(lbr_ctx* c, Level& L) {
     const size_t n = L.box.plane;
     const size_t pad = (size_t)L.box.pitch + 1;    // k_step reads one row beyond both ends
+    // k_step addresses each array through a buffer resource with 32-bit byte offsets
+    if ((9 * n + 2 * pad) * std::max<size_t>(c->ssize, 8) >= (size_t)1 << 31)
+        return set_err(c, LBR_ERR_INVALID_ARG, "level %d: storage box of %zu cells exceeds the "
+                       "2 GiB per-array limit", L.l, n);
     for (int b = 0; b < 2; ++b) {
         L.f[b] = dalloc_padded(c, 9 * n, c->ssize, pad);
         L.mac[b] = dalloc_padded(c, 3 * n, c->csize, pad);
@@ -804,6 +808,7 @@ void fill_step_args(lbr_ctx* c, int l, int substep, StepArgs<ST, CT>& a) {
     for (int k = 0; k < 4; ++k) a.dom.bc[k] = cfg.bc[k];
     a.dom.periodic_x = cfg.bc[0] == LBR_BC_PERIODIC;
     a.dom.outlet = cfg.outlet;
+    a.pad = L.box.pitch + 1;
     a.nu = (CT)L.nu;
     a.fx = (CT)L.fx;
     a.fy = (CT)L.fy;

@@ -76,6 +76,8 @@ struct StepArgs {
     CT nu, fx, fy, omega_b, u_in, chi_in, rho_out;
     int sa_mode, bb_halfway, frozen;
     int substep;                     // 1 or 2 within the parent's step (0 on level 0)
+    int pad;                         // spare elements before and after every field array
+                                     // of the level (one row plus one cell)
     const ST* fcoarse; Box cbox;     // parent level populations (ghost transfer)
     const CT* cmac;  const CT* cchi; // parent level rho, u and chi of the current parent step
     CT* rmac;        CT* rchi;       // parent level buffers of the next parent step (restriction)

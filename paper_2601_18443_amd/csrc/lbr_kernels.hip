@@ -39,22 +39,102 @@ template <class ST, class CT> struct Cv;
 template <> struct Cv<double, double> {
     static __device__ __forceinline__ double ld(const double* p) { return *p; }
     static __device__ __forceinline__ void st(double* p, double v) { *p = v; }
+    static __device__ __forceinline__ double ld_val(double v) { return v; }
+    static __device__ __forceinline__ double st_val(double v) { return v; }
 };
 template <> struct Cv<float, float> {
     static __device__ __forceinline__ float ld(const float* p) { return *p; }
     static __device__ __forceinline__ void st(float* p, float v) { *p = v; }
+    static __device__ __forceinline__ float ld_val(float v) { return v; }
+    static __device__ __forceinline__ float st_val(float v) { return v; }
 };
 template <> struct Cv<__half, float> {
     static __device__ __forceinline__ float ld(const __half* p) { return __half2float(*p); }
     static __device__ __forceinline__ void st(__half* p, float v) { *p = __float2half_rn(v); }
+    static __device__ __forceinline__ float ld_val(__half v) { return __half2float(v); }
+    static __device__ __forceinline__ __half st_val(float v) { return __float2half_rn(v); }
 };
 template <> struct Cv<__hip_bfloat16, float> {
     static __device__ __forceinline__ float ld(const __hip_bfloat16* p) { return __bfloat162float(*p); }
     static __device__ __forceinline__ void st(__hip_bfloat16* p, float v) { *p = __float2bfloat16(v); }
+    static __device__ __forceinline__ float ld_val(__hip_bfloat16 v) { return __bfloat162float(v); }
+    static __device__ __forceinline__ __hip_bfloat16 st_val(float v) { return __float2bfloat16(v); }
 };
 
 __device__ __forceinline__ double dmin(double a, double b) { return a < b ? a : b; }
 __device__ __forceinline__ float dmin(float a, float b) { return a < b ? a : b; }
+
+// Reciprocal and x^(1/6): IEEE in FP64; in FP32 the hardware reciprocal and
+// base-2 exp / log (about one ulp), which the FP32 tolerance absorbs.
+__device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double fdiv(double a, double b) { return a / b; }
+__device__ __forceinline__ float fdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ double sixth_root(double x) { return pow(x, 1.0 / 6.0); }
+__device__ __forceinline__ float sixth_root(float x) {
+    return __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(x) * (1.0f / 6.0f));
+}
+
+// ---------------------------------------------------------------------------
+// Raw buffer access for the hot kernel: one buffer resource per array (base at
+// the start of the padded allocation, size in bytes), a per-thread 32-bit byte
+// offset shared by all planes, and a wave-uniform byte offset per plane in a
+// scalar register -- no 64-bit address arithmetic per access.  Offsets beyond
+// the resource size read 0 and drop stores instead of faulting.
+// ---------------------------------------------------------------------------
+using Rsrc = __amdgpu_buffer_rsrc_t;
+constexpr int RSRC_WORD3 = 0x00020000;   // raw (untyped) access on gfx9-family parts
+
+template <class T>
+__device__ __forceinline__ Rsrc make_rsrc(const T* alloc_begin, long elems) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(alloc_begin), (short)0,
+                                             (int)(elems * (long)sizeof(T)), RSRC_WORD3);
+}
+
+template <class T> struct Bf;
+template <> struct Bf<double> {
+    static __device__ __forceinline__ double ld(Rsrc r, uint32_t vo, uint32_t so) {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
+    }
+    static __device__ __forceinline__ void st(Rsrc r, uint32_t vo, uint32_t so, double v) {
+        typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, vo, so, 0);
+    }
+};
+template <> struct Bf<float> {
+    static __device__ __forceinline__ float ld(Rsrc r, uint32_t vo, uint32_t so) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
+    }
+    static __device__ __forceinline__ void st(Rsrc r, uint32_t vo, uint32_t so, float v) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, vo, so, 0);
+    }
+};
+template <> struct Bf<__half> {
+    static __device__ __forceinline__ __half ld(Rsrc r, uint32_t vo, uint32_t so) {
+        return __builtin_bit_cast(__half, __builtin_amdgcn_raw_buffer_load_b16(r, vo, so, 0));
+    }
+    static __device__ __forceinline__ void st(Rsrc r, uint32_t vo, uint32_t so, __half v) {
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, vo, so, 0);
+    }
+};
+template <> struct Bf<__hip_bfloat16> {
+    static __device__ __forceinline__ __hip_bfloat16 ld(Rsrc r, uint32_t vo, uint32_t so) {
+        return __builtin_bit_cast(__hip_bfloat16, __builtin_amdgcn_raw_buffer_load_b16(r, vo, so, 0));
+    }
+    static __device__ __forceinline__ void st(Rsrc r, uint32_t vo, uint32_t so, __hip_bfloat16 v) {
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, vo, so, 0);
+    }
+};
+
+// storage <-> compute conversion on top of a buffer access
+template <class ST, class CT>
+__device__ __forceinline__ CT bld(Rsrc r, uint32_t vo, uint32_t so) {
+    return Cv<ST, CT>::ld_val(Bf<ST>::ld(r, vo, so));
+}
+template <class ST, class CT>
+__device__ __forceinline__ void bst(Rsrc r, uint32_t vo, uint32_t so, CT v) {
+    Bf<ST>::st(r, vo, so, Cv<ST, CT>::st_val(v));
+}
 
 // ---------------------------------------------------------------------------
 // Central-moment collision (eqs (5)-(10)) in shifted variables.  The second
@@ -133,9 +213,9 @@ __device__ __forceinline__ void equilibrium(T s[9], T drho, T ux, T uy) {
 template <class T>
 __device__ __forceinline__ T sa_mu(T nt, T nu) {
     if (nt >= T(0)) return nu + nt;
-    const T c = nt / nu;
+    const T c = fdiv(nt, nu);
     const T c3 = c * c * c;
-    return nu + nt * (T(CN1) + c3) / (T(CN1) - c3);
+    return nu + fdiv(nt * (T(CN1) + c3), T(CN1) - c3);
 }
 
 template <class T>
@@ -145,30 +225,31 @@ __device__ T sa_update(const T nt[9], const T u[9], const T v[9], T nu, T d, int
     const T dvdx = ((v[5] - v[3]) + (v[8] - v[6]) + (v[2] - v[0])) * six;
     const T omega = fabs(dvdx - dudy);
     const T C = nt[4];
-    const T chi = C / nu;
+    const T chi = fdiv(C, nu);
     const T k2d2 = T(KAPPA * KAPPA) * d * d;
+    const T Cd = fdiv(C, d);
     T P, D;
     if (C >= T(0)) {
         const T chi3 = chi * chi * chi;
-        const T fv1 = chi3 / (chi3 + T(CV1 * CV1 * CV1));
-        const T fv2 = T(1) - chi / (T(1) + chi * fv1);
-        const T sbar = C * fv2 / k2d2;
+        const T fv1 = fdiv(chi3, chi3 + T(CV1 * CV1 * CV1));
+        const T fv2 = T(1) - fdiv(chi, T(1) + chi * fv1);
+        const T sbar = fdiv(C * fv2, k2d2);
         const T st = (sbar >= -T(CV2) * omega)
                          ? omega + sbar
-                         : omega + omega * (T(CV2 * CV2) * omega + T(CV3) * sbar) /
-                                       (T(CV3 - 2.0 * CV2) * omega - sbar);
-        T r = (st > T(1e-30)) ? C / (st * k2d2) : T(RLIM);
+                         : omega + fdiv(omega * (T(CV2 * CV2) * omega + T(CV3) * sbar),
+                                        T(CV3 - 2.0 * CV2) * omega - sbar);
+        T r = (st > T(1e-30)) ? fdiv(C, st * k2d2) : T(RLIM);
         r = dmin(r, T(RLIM));
         const T r2 = r * r;
         const T g = r + T(CW2) * (r2 * r2 * r2 - r);
         const T g2 = g * g;
         const T c6 = T(CW3 * CW3 * CW3 * CW3 * CW3 * CW3);
-        const T fw = g * pow((T(1) + c6) / (g2 * g2 * g2 + c6), T(1.0 / 6.0));
+        const T fw = g * sixth_root(fdiv(T(1) + c6, g2 * g2 * g2 + c6));
         P = T(CB1) * st * C;
-        D = T(CW1) * fw * (C / d) * (C / d);
+        D = T(CW1) * fw * Cd * Cd;
     } else {
         P = T(CB1 * (1.0 - CT3)) * omega * C;
-        D = -T(CW1) * (C / d) * (C / d);
+        D = -T(CW1) * Cd * Cd;
     }
     const T E = nt[5], W = nt[3], N = nt[7], S = nt[1];
     const T dX = T(0.5) * (E - W), dY = T(0.5) * (N - S);
@@ -193,7 +274,7 @@ template <class T>
 __device__ __forceinline__ T eddy_viscosity(T chi, T nu) {
     if (chi <= T(0)) return T(0);
     const T c3 = chi * chi * chi;
-    return nu * chi * c3 / (c3 + T(CV1 * CV1 * CV1));
+    return fdiv(nu * chi * c3, c3 + T(CV1 * CV1 * CV1));
 }
 
 // ---------------------------------------------------------------------------
@@ -361,11 +442,11 @@ __device__ __forceinline__ CT poststream(const StepArgs<ST, CT>& a, int i, int g
     return Cv<ST, CT>::ld(a.fsrc + di * a.box.plane + cs);
 }
 
-// Moments (eq (3) with the half-force shift), collision with
-// nu_eff = nu + nu_t(chi) (eqs (9), (11)), stores.
+// Moments (eq (3) with the half-force shift) and the collision with
+// nu_eff = nu + nu_t(chi) (eqs (9), (11)), in place on s.
 template <class ST, class CT>
-__device__ __forceinline__ void finish_cell(const StepArgs<ST, CT>& a, long c, CT s[9], CT chi_new) {
-    const long P = a.box.plane;
+__device__ __forceinline__ void relax_cell(const StepArgs<ST, CT>& a, CT s[9], CT chi_new, CT& rho,
+                                           CT& ux, CT& uy) {
     CT drho = CT(0), jx = CT(0), jy = CT(0);
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
@@ -373,16 +454,27 @@ __device__ __forceinline__ void finish_cell(const StepArgs<ST, CT>& a, long c, C
         jx += CT(CX[i]) * s[i];
         jy += CT(CY[i]) * s[i];
     }
-    const CT rho = CT(1) + drho;
-    const CT ux = (jx + CT(0.5) * a.fx) / rho;
-    const CT uy = (jy + CT(0.5) * a.fy) / rho;
+    rho = CT(1) + drho;
+    // correctly rounded: the collision conserves momentum only for u = j / rho
+    ux = (jx + CT(0.5) * a.fx) / rho;
+    uy = (jy + CT(0.5) * a.fy) / rho;
+    const CT nu_eff = a.nu + eddy_viscosity(chi_new, a.nu);
+    // correctly rounded: near tau = 1/2 the viscosity amplifies an error of omega
+    // by about 1 / (tau - 1/2)
+    const CT omega = CT(1) / (CT(3) * nu_eff + CT(0.5));
+    collide(s, drho, ux, uy, omega, a.omega_b, a.fx, a.fy);
+}
+
+// relax_cell plus plain stores of the new state (side-stream kernels).
+template <class ST, class CT>
+__device__ __forceinline__ void finish_cell(const StepArgs<ST, CT>& a, long c, CT s[9], CT chi_new) {
+    const long P = a.box.plane;
+    CT rho, ux, uy;
+    relax_cell(a, s, chi_new, rho, ux, uy);
     a.mdst[c] = rho;
     a.mdst[P + c] = ux;
     a.mdst[2 * P + c] = uy;
     a.cdst[c] = chi_new;
-    const CT nu_eff = a.nu + eddy_viscosity(chi_new, a.nu);
-    const CT omega = CT(1) / (CT(3) * nu_eff + CT(0.5));
-    collide(s, drho, ux, uy, omega, a.omega_b, a.fx, a.fy);
 #pragma unroll
     for (int i = 0; i < 9; ++i) Cv<ST, CT>::st(a.fdst + i * P + c, s[i]);
 }
@@ -439,44 +531,63 @@ __global__ __launch_bounds__(256) void k_step(const StepArgs<ST, CT> a) {
     const bool restrict_tile = (tile >> 31) && a.substep == 2;   // uniform over the workgroup
     const int lx = tx0 + lane, ly = ty0 + wy;
     const long c = (long)ly * pitch + lx;
-
-    const uint8_t fl = a.flag[c];
-    const uint32_t lm = a.lmask[c];
-    const int type = fl & F_TYPE;
     const int gx = lx + a.box.gx0, gy = ly + a.box.gy0;
-    if (type == T_GHOST) {
-        ghost_fill(a.cmac, a.cchi, a.cbox, gx, gy, sh_n[wy + 1][lane + 1], sh_u[wy + 1][lane + 1],
-                   sh_v[wy + 1][lane + 1]);
-    } else {
-        sh_n[wy + 1][lane + 1] = a.csrc[c];
-        sh_u[wy + 1][lane + 1] = a.msrc[P + c];
-        sh_v[wy + 1][lane + 1] = a.msrc[2 * P + c];
-    }
-    if (threadIdx.x < 2 * TILE_X + 2 * (TILE_Y + 2)) {
-        const int h = threadIdx.x;
-        int hx, hy;
-        if (h < TILE_X) { hx = h; hy = -1; }
-        else if (h < 2 * TILE_X) { hx = h - TILE_X; hy = TILE_Y; }
-        else if (h < 2 * TILE_X + TILE_Y + 2) { hx = -1; hy = h - 2 * TILE_X - 1; }
-        else { hx = TILE_X; hy = h - 2 * TILE_X - (TILE_Y + 2) - 1; }
-        const long cs = (long)(ty0 + hy) * pitch + tx0 + hx;     // padded allocations: always valid
-        if ((a.flag[cs] & F_TYPE) == T_GHOST) {
-            ghost_fill(a.cmac, a.cchi, a.cbox, a.box.gx0 + tx0 + hx, a.box.gy0 + ty0 + hy,
-                       sh_n[hy + 1][hx + 1], sh_u[hy + 1][hx + 1], sh_v[hy + 1][hx + 1]);
-        } else {
-            sh_n[hy + 1][hx + 1] = a.csrc[cs];
-            sh_u[hy + 1][hx + 1] = a.msrc[P + cs];
-            sh_v[hy + 1][hx + 1] = a.msrc[2 * P + cs];
-        }
-    }
+
+    // buffer resources over the padded allocations; element offset of the cell
+    const int pad = a.pad;
+    const Rsrc rf = make_rsrc(a.fsrc - pad, 9 * P + 2 * pad);
+    const Rsrc rm = make_rsrc(a.msrc - pad, 3 * P + 2 * pad);
+    const Rsrc rc = make_rsrc(a.csrc - pad, P + 2 * pad);
+    const Rsrc rd = make_rsrc(a.dist - pad, P + 2 * pad);
+    const Rsrc rg = make_rsrc(a.flag - pad, P + 2 * pad);
+    const uint32_t e = (uint32_t)(c + pad);
+    constexpr uint32_t SS = sizeof(ST), CS = sizeof(CT);
+
+    // Every load whose address is known from the tile alone is issued first, in
+    // one round: the nine pulls, the wall distance, flags, and the stencil values
+    // of the cell and of its halo share (all addresses valid thanks to the spare
+    // rows; ghost-band values are replaced below).
     CT s[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i)
-        s[i] = Cv<ST, CT>::ld(a.fsrc + i * P + c - CX[i] - (long)CY[i] * pitch);
-    const double dist = a.dist[c];
+        s[i] = bld<ST, CT>(rf, e * SS, (uint32_t)(i * P - CX[i] - CY[i] * pitch) * SS);
+    const double dist = Bf<double>::ld(rd, e * 8u, 0);
+    const uint8_t fl = __builtin_amdgcn_raw_buffer_load_b8(rg, e, 0, 0);
+    const uint32_t lm = a.lmask[c];
+    CT own_n = bld<CT, CT>(rc, e * CS, 0), own_u = bld<CT, CT>(rm, e * CS, (uint32_t)P * CS),
+       own_v = bld<CT, CT>(rm, e * CS, 2u * (uint32_t)P * CS);
+    const bool halo = threadIdx.x < 2 * TILE_X + 2 * (TILE_Y + 2);
+    int hx = 0, hy = 0;
+    if (threadIdx.x < TILE_X) { hx = threadIdx.x; hy = -1; }
+    else if (threadIdx.x < 2 * TILE_X) { hx = threadIdx.x - TILE_X; hy = TILE_Y; }
+    else if (threadIdx.x < 2 * TILE_X + TILE_Y + 2) { hx = -1; hy = threadIdx.x - 2 * TILE_X - 1; }
+    else { hx = TILE_X; hy = threadIdx.x - 2 * TILE_X - (TILE_Y + 2) - 1; }
+    const uint32_t he = (uint32_t)((ty0 + hy) * pitch + tx0 + hx + pad);
+    uint8_t hfl = 0;
+    CT hn = CT(0), hu = CT(0), hv = CT(0);
+    if (halo) {
+        hfl = __builtin_amdgcn_raw_buffer_load_b8(rg, he, 0, 0);
+        hn = bld<CT, CT>(rc, he * CS, 0);
+        hu = bld<CT, CT>(rm, he * CS, (uint32_t)P * CS);
+        hv = bld<CT, CT>(rm, he * CS, 2u * (uint32_t)P * CS);
+    }
+    const int type = fl & F_TYPE;
+    if (type == T_GHOST) ghost_fill(a.cmac, a.cchi, a.cbox, gx, gy, own_n, own_u, own_v);
+    sh_n[wy + 1][lane + 1] = own_n;
+    sh_u[wy + 1][lane + 1] = own_u;
+    sh_v[wy + 1][lane + 1] = own_v;
+    if (halo) {
+        if ((hfl & F_TYPE) == T_GHOST)
+            ghost_fill(a.cmac, a.cchi, a.cbox, a.box.gx0 + tx0 + hx, a.box.gy0 + ty0 + hy, hn, hu, hv);
+        sh_n[hy + 1][hx + 1] = hn;
+        sh_u[hy + 1][hx + 1] = hu;
+        sh_v[hy + 1][hx + 1] = hv;
+    }
     __syncthreads();
 
+    const Rsrc rfo = make_rsrc(a.fdst - pad, 9 * P + 2 * pad);
     bool update = false;
+    CT m_rho = CT(0), m_ux = CT(0), m_uy = CT(0), m_chi = CT(0);
     if (type == T_GHOST) {
         // fine band over a coarse interface cell: carries exploded coarse populations
         // (first sub-step) and fine populations one cell per sub-step, no collision
@@ -487,7 +598,7 @@ __global__ __launch_bounds__(256) void k_step(const StepArgs<ST, CT> a) {
             CT w = s[i];
             if (!(src_fluid || (src_ghost && a.substep == 2)))
                 w = coarse_val(a, i, gx - k * CX[i], gy - k * CY[i]);
-            Cv<ST, CT>::st(a.fdst + i * P + c, w);
+            bst<ST, CT>(rfo, e * SS, (uint32_t)(i * P) * SS, w);
         }
     } else if (type == T_FLUID && !(fl & (F_WALL | F_EDGE))) {   // others: side-stream kernels
         update = true;
@@ -521,9 +632,18 @@ __global__ __launch_bounds__(256) void k_step(const StepArgs<ST, CT> a) {
                     u[k] = sh_u[wy + 1 + dy][lane + 1 + dx];
                     v[k] = sh_v[wy + 1 + dy][lane + 1 + dx];
                 }
-            chi_new = sa_update(nt, u, v, a.nu, CT(dist), a.sa_mode == 2) / a.nu;
+            chi_new = fdiv(sa_update(nt, u, v, a.nu, CT(dist), a.sa_mode == 2), a.nu);
         }
-        finish_cell(a, c, s, chi_new);
+        relax_cell(a, s, chi_new, m_rho, m_ux, m_uy);
+        m_chi = chi_new;
+        const Rsrc rmo = make_rsrc(a.mdst - pad, 3 * P + 2 * pad);
+        const Rsrc rco = make_rsrc(a.cdst - pad, P + 2 * pad);
+        bst<CT, CT>(rmo, e * CS, 0, m_rho);
+        bst<CT, CT>(rmo, e * CS, (uint32_t)P * CS, m_ux);
+        bst<CT, CT>(rmo, e * CS, 2u * (uint32_t)P * CS, m_uy);
+        bst<CT, CT>(rco, e * CS, 0, chi_new);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) bst<ST, CT>(rfo, e * SS, (uint32_t)(i * P) * SS, s[i]);
     }
     if (!restrict_tile) return;
     // restriction for the next parent step: the new rho, u and chi of each 2 x 2
@@ -531,10 +651,10 @@ __global__ __launch_bounds__(256) void k_step(const StepArgs<ST, CT> a) {
     __shared__ CT sh_r[4][TILE_Y][TILE_X];
     __syncthreads();
     if (update) {
-        sh_r[0][wy][lane] = a.mdst[c];
-        sh_r[1][wy][lane] = a.mdst[P + c];
-        sh_r[2][wy][lane] = a.mdst[2 * P + c];
-        sh_r[3][wy][lane] = a.cdst[c];
+        sh_r[0][wy][lane] = m_rho;
+        sh_r[1][wy][lane] = m_ux;
+        sh_r[2][wy][lane] = m_uy;
+        sh_r[3][wy][lane] = m_chi;
     }
     __syncthreads();
     if (lm >> 31) {
@@ -606,7 +726,7 @@ __global__ __launch_bounds__(64) void k_edge(const StepArgs<ST, CT> a) {
     } else {
 #pragma unroll
         for (int k = 0; k < 9; ++k) nt[k] *= a.nu;
-        chi_new = sa_update(nt, u, v, a.nu, CT(dist), a.sa_mode == 2) / a.nu;
+        chi_new = fdiv(sa_update(nt, u, v, a.nu, CT(dist), a.sa_mode == 2), a.nu);
     }
     finish_cell(a, c, s, chi_new);
 }
