@@ -52,9 +52,6 @@ struct Level {
     int32_t* covb_dev = nullptr;
     int32_t* owned_dev = nullptr;
     int32_t* edge_dev = nullptr;
-    int32_t* sponge_dev = nullptr;
-    double* sponge_sigma = nullptr;
-    int n_sponge = 0;
     double* bq = nullptr;
     int32_t* bcell = nullptr;
     double* bgeo = nullptr;
@@ -91,8 +88,6 @@ struct lbr_ctx {
     lbr_config cfg{};
     std::string err = "";
     hipStream_t stream = nullptr;
-    hipStream_t side = nullptr;          // wall-node kernel runs here beside k_step
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     Prec prec = P_F32;
     size_t ssize = 4, csize = 4;
     double u_ref = 0, nu0 = 0;
@@ -707,34 +702,6 @@ int alloc_level(lbr_ctx* c, Level& L) {
     for (int32_t k : L.owned)
         if ((L.flag[k] & F_EDGE) && !(L.flag[k] & F_WALL)) L.edge.push_back(k);
     if (int r = upload(c, &L.edge_dev, L.edge, &L.bytes)) return r;
-    {
-        // absorbing layer of level 0 along the far-field sides
-        const lbr_config& cfg = c->cfg;
-        std::vector<int32_t> sl;
-        std::vector<double> sg;
-        const double W = cfg.sponge_width;
-        if (L.l == 0 && W > 0.0 && cfg.sponge_strength > 0.0) {
-            auto far = [&](int side) {
-                return cfg.bc[side] == LBR_BC_INLET || cfg.bc[side] == LBR_BC_OUTLET ||
-                       cfg.bc[side] == LBR_BC_SYMMETRY;
-            };
-            for (int32_t k : L.owned) {
-                const int gx = (int)(k % L.box.pitch) + L.box.gx0, gy = (int)(k / L.box.pitch) + L.box.gy0;
-                double d = 1e300;
-                if (far(0)) d = std::min(d, gx + 0.5);
-                if (far(1)) d = std::min(d, cfg.nx0 - gx - 0.5);
-                if (far(2)) d = std::min(d, gy + 0.5);
-                if (far(3)) d = std::min(d, cfg.ny0 - gy - 0.5);
-                if (d >= W) continue;
-                const double x = (W - d) / W;
-                sl.push_back(k);
-                sg.push_back(cfg.sponge_strength * x * x);
-            }
-        }
-        L.n_sponge = (int)sl.size();
-        if (int r = upload(c, &L.sponge_dev, sl, &L.bytes)) return r;
-        if (int r = upload(c, &L.sponge_sigma, sg, &L.bytes)) return r;
-    }
     L.snap = static_cast<double*>(dalloc(c, std::max<size_t>(L.owned.size(), 1) * 2 * sizeof(double)));
     // wall records
     const int nb = (int)L.nodes.size();
@@ -809,6 +776,20 @@ void fill_step_args(lbr_ctx* c, int l, int substep, StepArgs<ST, CT>& a) {
     a.dom.periodic_x = cfg.bc[0] == LBR_BC_PERIODIC;
     a.dom.outlet = cfg.outlet;
     a.pad = L.box.pitch + 1;
+    a.wall_blocks = 8 * (((int)L.nodes.size() + 8 * TILE_X * TILE_Y - 1) / (8 * TILE_X * TILE_Y));
+    a.tile_blocks = 8 * (((int)L.rows.size() + 7) / 8);
+    a.sp_width = 0.0;
+    a.sp_strength = 0.0;
+    a.sp_sides = 0;
+    a.sp_drho = cfg.rho_ref - 1.0;
+    a.sp_ux = c->u_ref;
+    if (l == 0 && cfg.sponge_width > 0.0 && cfg.sponge_strength > 0.0) {
+        a.sp_width = cfg.sponge_width;
+        a.sp_strength = cfg.sponge_strength;
+        for (int k = 0; k < 4; ++k)
+            if (cfg.bc[k] == LBR_BC_INLET || cfg.bc[k] == LBR_BC_OUTLET || cfg.bc[k] == LBR_BC_SYMMETRY)
+                a.sp_sides |= 1 << k;
+    }
     a.nu = (CT)L.nu;
     a.fx = (CT)L.fx;
     a.fy = (CT)L.fy;
@@ -870,7 +851,7 @@ int eval_wall(lbr_ctx* c, int l) {
     return 0;
 }
 
-enum { EV_STEP = 0, EV_STEP_FINE = 1, EV_WALL = 2, EV_EDGE = 3 };
+enum { EV_STEP = 0, EV_STEP_FINE = 1, EV_STEP_L0 = 2 };
 
 // Start / stop events for one dispatch of the given kind (profiling mode only).
 Timing prof_events(lbr_ctx* c, int kind) {
@@ -898,30 +879,10 @@ int do_step(lbr_ctx* c, int l, int substep) {
         case P_F16: fill_step_args(c, l, substep, *reinterpret_cast<StepArgs<__half, float>*>(buf)); break;
         default: fill_step_args(c, l, substep, *reinterpret_cast<StepArgs<__hip_bfloat16, float>*>(buf)); break;
     }
-    const bool walls = !L.nodes.empty() || !L.edge.empty();
-    if (walls) {
-        // wall nodes and domain-edge cells on the side stream, concurrently with
-        // the rest of the level (disjoint cells, same source state)
-        HIPCHK(c, hipEventRecord(c->ev_fork, c->stream));
-        HIPCHK(c, hipStreamWaitEvent(c->side, c->ev_fork, 0));
-        if (!L.nodes.empty()) HIPCHK(c, launch_boundary(c->prec, buf, c->side, prof_events(c, EV_WALL)));
-        if (!L.edge.empty()) HIPCHK(c, launch_edge(c->prec, buf, c->side, prof_events(c, EV_EDGE)));
-        HIPCHK(c, hipEventRecord(c->ev_join, c->side));
-    }
-    HIPCHK(c, launch_step(c->prec, buf, c->stream,
-                          prof_events(c, l + 1 == (int)c->lv.size() ? EV_STEP_FINE : EV_STEP)));
-    if (walls) HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
-    if (L.n_sponge) {
-        SpongeArgs sp{};
-        sp.n = L.n_sponge;
-        sp.list = L.sponge_dev;
-        sp.sigma = L.sponge_sigma;
-        sp.f = L.f[1 - L.cur];
-        sp.plane = L.box.plane;
-        sp.drho = c->cfg.rho_ref - 1.0;
-        sp.ux = c->u_ref;
-        HIPCHK(c, launch_sponge(c->prec, sp, c->stream));
-    }
+    // one launch per level sub-step: tiles, wall nodes and domain-edge cells are
+    // workgroups of the same grid (disjoint cells, same source state)
+    const int kind = l + 1 == (int)c->lv.size() ? EV_STEP_FINE : (l == 0 ? EV_STEP_L0 : EV_STEP);
+    HIPCHK(c, launch_step(c->prec, buf, c->stream, prof_events(c, kind)));
     L.cur ^= 1;
     return 0;
 }
@@ -1179,11 +1140,6 @@ int lbr_set_geometry(lbr_ctx* c, int32_t n_bodies, const int32_t* n_pts, const d
 int lbr_build(lbr_ctx* c) {
     if (!c) return LBR_ERR_INVALID_ARG;
     if (c->built) return set_err(c, LBR_ERR_STATE, "already built");
-    if (!c->side) {
-        HIPCHK(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
-        HIPCHK(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
-        HIPCHK(c, hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
-    }
     // segment table: ax, ay, bx, by, body (level-0 lattice units)
     std::vector<double> seg;
     for (size_t b = 0; b < c->npts.size(); ++b) {
@@ -1280,7 +1236,6 @@ int lbr_advance(lbr_ctx* c, int64_t n) {
     c->resid_steps += n;
     if (c->prof && c->ev_used) {
         HIPCHK(c, hipStreamSynchronize(c->stream));
-        HIPCHK(c, hipStreamSynchronize(c->side));
         double sum[4] = {0, 0, 0, 0};
         int cnt[4] = {0, 0, 0, 0};
         for (size_t i = 0; i + 1 < c->ev_used; i += 2) {
@@ -1289,7 +1244,7 @@ int lbr_advance(lbr_ctx* c, int64_t n) {
             const int kind = c->ev_kind[i];
             sum[kind] += ms;
             cnt[kind]++;
-            if (kind == EV_STEP_FINE) { sum[EV_STEP] += ms; cnt[EV_STEP]++; }
+            if (kind != EV_STEP) { sum[EV_STEP] += ms; cnt[EV_STEP]++; }
         }
         for (int f = 0; f < 4; ++f) c->prof_out[f] = cnt[f] ? 1000.0 * sum[f] / cnt[f] : 0.0;
     }
@@ -1492,14 +1447,10 @@ void lbr_destroy(lbr_ctx* c) {
     (void)hipStreamSynchronize(c->stream);
     if (c->graph) (void)hipGraphExecDestroy(c->graph);
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
-    if (c->side) (void)hipStreamSynchronize(c->side);
-    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
-    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     for (void* p : c->allocs) {
         if (c->cfg.free_fn) c->cfg.free_fn(p, c->cfg.alloc_user);
         else (void)hipFree(p);
     }
-    if (c->side) (void)hipStreamDestroy(c->side);
     delete c;
 }
 

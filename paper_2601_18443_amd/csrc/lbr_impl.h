@@ -78,6 +78,12 @@ struct StepArgs {
     int substep;                     // 1 or 2 within the parent's step (0 on level 0)
     int pad;                         // spare elements before and after every field array
                                      // of the level (one row plus one cell)
+    int wall_blocks, tile_blocks;    // k_step grid: wall-node blocks (a multiple of 8),
+                                     // tile blocks (a multiple of 8), then edge-cell blocks
+    // absorbing layer of level 0 (sp_width = 0 elsewhere): sides bit k = bc[k] is a far field
+    double sp_width, sp_strength;
+    int sp_sides;
+    double sp_drho, sp_ux;           // target state: rho_ref - 1, u_ref
     const ST* fcoarse; Box cbox;     // parent level populations (ghost transfer)
     const CT* cmac;  const CT* cchi; // parent level rho, u and chi of the current parent step
     CT* rmac;        CT* rchi;       // parent level buffers of the next parent step (restriction)
@@ -120,13 +126,6 @@ struct InitArgs {
     double nu, fx, fy, omega_b;
 };
 
-// Absorbing layer of level 0: listed cells and their relaxation rates.
-struct SpongeArgs {
-    int n; const int32_t* list; const double* sigma;
-    void* f; long plane;
-    double drho, ux;                 // target: rho_ref - 1, u_ref (u_y = 0)
-};
-
 struct SurfaceArgs {
     int nseg;
     const double* seg;               // [nseg][6]: t (x, y), n (x, y), ds, unused
@@ -150,13 +149,10 @@ struct Timing {
     hipEvent_t start = nullptr, stop = nullptr;
 };
 hipError_t launch_step(Prec p, const void* args, hipStream_t s, const Timing& tm = Timing{});
-hipError_t launch_boundary(Prec p, const void* args, hipStream_t s, const Timing& tm = Timing{});
-hipError_t launch_edge(Prec p, const void* args, hipStream_t s, const Timing& tm = Timing{});
 hipError_t launch_wall(Prec p, const void* args, hipStream_t s);
 hipError_t launch_fill(Prec p, const FillArgs& a, hipStream_t s);
 hipError_t launch_restrict(Prec p, const RestrictArgs& a, hipStream_t s);
 hipError_t launch_init(Prec p, const InitArgs& a, hipStream_t s);
-hipError_t launch_sponge(Prec p, const SpongeArgs& a, hipStream_t s);
 hipError_t launch_surface(Prec p, const SurfaceArgs& a, int nblocks, hipStream_t s);
 hipError_t launch_sum_partials(const double* partial, int nblocks, double* out, hipStream_t s);
 hipError_t launch_to_double(Prec p, const void* src, double* dst, long n, hipStream_t s);

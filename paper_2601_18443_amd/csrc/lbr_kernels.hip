@@ -340,14 +340,24 @@ __device__ void wall_model(const WallData& w, int b, const CT* mac, long P, doub
             uwy = uw[1];
         }
     } else {
+        // gathered four slots at a time (the enclosing 2 x 2 block is the usual
+        // stencil), the loads of a group issued together; unused slots of a group
+        // read the node's own cell with weight 0, an exact no-op
         double rr = 0.0, ux = 0.0, uy = 0.0;
-        for (int j = 0; j < MAX_STENCIL; ++j) {
-            const int cj = w.st_cell[MAX_STENCIL * b + j];
-            if (cj < 0) break;
-            rr += w.st_wr[MAX_STENCIL * b + j] * (double)mac[cj];
-            const double wu = w.st_wu[MAX_STENCIL * b + j];
-            ux += wu * (double)mac[P + cj];
-            uy += wu * (double)mac[2 * P + cj];
+        const int own = w.cell[b];
+        for (int j0 = 0; j0 < MAX_STENCIL; j0 += 4) {
+            if (w.st_cell[MAX_STENCIL * b + j0] < 0) break;
+#pragma unroll
+            for (int j = j0; j < j0 + 4; ++j) {
+                const int cj = w.st_cell[MAX_STENCIL * b + j];
+                const bool use = cj >= 0;
+                const int cc = use ? cj : own;
+                const double wr = use ? w.st_wr[MAX_STENCIL * b + j] : 0.0;
+                const double wu = use ? w.st_wu[MAX_STENCIL * b + j] : 0.0;
+                rr += wr * (double)mac[cc];
+                ux += wu * (double)mac[P + cc];
+                uy += wu * (double)mac[2 * P + cc];
+            }
         }
         const double un = ux * g[2] + uy * g[3];                 // step 2
         tx = ux - un * g[2];
@@ -465,12 +475,36 @@ __device__ __forceinline__ void relax_cell(const StepArgs<ST, CT>& a, CT s[9], C
     collide(s, drho, ux, uy, omega, a.omega_b, a.fx, a.fy);
 }
 
-// relax_cell plus plain stores of the new state (side-stream kernels).
+// Absorbing layer of level 0 (an addition to the method; sp_width = 0 turns it
+// off): within sp_width cells of a far-field side the post-collision
+// populations relax towards the free-stream equilibrium with
+// sigma = sp_strength ((W - d) / W)^2, d the distance of the cell centre.
 template <class ST, class CT>
-__device__ __forceinline__ void finish_cell(const StepArgs<ST, CT>& a, long c, CT s[9], CT chi_new) {
+__device__ __forceinline__ void absorb(const StepArgs<ST, CT>& a, int gx, int gy, CT s[9]) {
+    if (!(a.sp_width > 0.0)) return;
+    double d = 1e300;
+    if (a.sp_sides & 1) d = fmin(d, gx + 0.5);
+    if (a.sp_sides & 2) d = fmin(d, a.dom.nxd - gx - 0.5);
+    if (a.sp_sides & 4) d = fmin(d, gy + 0.5);
+    if (a.sp_sides & 8) d = fmin(d, a.dom.nyd - gy - 0.5);
+    if (!(d < a.sp_width)) return;
+    const double x = (a.sp_width - d) / a.sp_width;
+    const CT sg = CT(a.sp_strength * x * x);
+    CT t[9];
+    equilibrium<CT>(t, CT(a.sp_drho), CT(a.sp_ux), CT(0));
+#pragma unroll
+    for (int i = 0; i < 9; ++i) s[i] = s[i] - sg * (s[i] - t[i]);
+}
+
+// relax_cell, the absorbing layer and plain stores of the new state (wall
+// nodes and domain-edge cells).
+template <class ST, class CT>
+__device__ __forceinline__ void finish_cell(const StepArgs<ST, CT>& a, long c, CT s[9], CT chi_new,
+                                            int gx, int gy) {
     const long P = a.box.plane;
     CT rho, ux, uy;
     relax_cell(a, s, chi_new, rho, ux, uy);
+    absorb(a, gx, gy, s);
     a.mdst[c] = rho;
     a.mdst[P + c] = ux;
     a.mdst[2 * P + c] = uy;
@@ -517,11 +551,161 @@ __device__ __forceinline__ void ghost_fill(const CT* cmac, const CT* cchi, const
     v = sv * k9 + (ox * xv + oy * yv) * k6;
 }
 
+// ---------------------------------------------------------------------------
+// k_edge: level-0 cells on the domain edge (except wall nodes), one thread
+// each, beside k_step: periodic wrap, specular reflection at symmetry edges,
+// Zou-He velocity inlet, extrapolation or Zou-He pressure outlet (Section
+// 3.1.1), and the SA
+// boundary rules (inlet chi, outlet extrapolation, mirrored stencil).
+// ---------------------------------------------------------------------------
 template <class ST, class CT>
-__global__ __launch_bounds__(256) void k_step(const StepArgs<ST, CT> a) {
+__device__ __forceinline__ void edge_cell(const StepArgs<ST, CT>& a, int e) {
+    const int pitch = a.box.pitch;
+    const long P = a.box.plane;
+    const long c = a.edge[e];
+    const int gx = (int)(c % pitch) + a.box.gx0, gy = (int)(c / pitch) + a.box.gy0;
+    const double dist = a.dist[c];
+    CT s[9], nt[9], u[9], v[9];
+    const bool at_inlet = gx == 0 && a.dom.bc[0] == BC_INLET;
+    const bool at_outlet = gx == a.dom.nxd - 1 && a.dom.bc[1] == BC_OUTLET;
+    {
+        gather_edge(a, gx, gy, nt, u, v);
+        for (int i = 0; i < 9; ++i)
+            if (!pull_general(a, (uint8_t)F_EDGE, i, gx, gy, s[i])) s[i] = CT(0);
+        if (at_inlet) {
+            const CT ui = a.u_in;
+            const CT rho = (CT(1) + s[0] + s[3] + s[4] + CT(2) * (s[2] + s[6] + s[8])) / (CT(1) - ui);
+            s[1] = s[2] + CT(2.0 / 3.0) * rho * ui;
+            s[5] = s[6] - CT(0.5) * (s[3] - s[4]) + rho * ui * CT(1.0 / 6.0);
+            s[7] = s[8] + CT(0.5) * (s[3] - s[4]) + rho * ui * CT(1.0 / 6.0);
+        }
+        if (at_outlet && a.dom.outlet == 2) {
+            // Zou-He with rho = rho_ref and u_y of the upstream cell (unknowns: c_x = -1)
+            const CT rho = a.rho_out, uy = v[3];
+            const CT ux = (CT(1) + s[0] + s[3] + s[4] + CT(2) * (s[1] + s[5] + s[7])) / rho - CT(1);
+            s[2] = s[1] - CT(2.0 / 3.0) * rho * ux;
+            s[6] = s[5] + CT(0.5) * (s[3] - s[4]) - rho * ux * CT(1.0 / 6.0) - CT(0.5) * rho * uy;
+            s[8] = s[7] - CT(0.5) * (s[3] - s[4]) - rho * ux * CT(1.0 / 6.0) + CT(0.5) * rho * uy;
+        } else if (at_outlet) {
+            for (int i = 0; i < 9; ++i)
+                if (CX[i] == -1)
+                    s[i] = (a.dom.outlet == 1)
+                               ? poststream(a, i, gx - 1, gy)
+                               : CT(2) * poststream(a, i, gx - 1, gy) - poststream(a, i, gx - 2, gy);
+        }
+    }
+    CT chi_new;
+    if (a.frozen) {
+        chi_new = nt[4];
+    } else if (at_inlet) {
+        chi_new = a.chi_in;
+    } else if (at_outlet) {
+        chi_new = nt[3];                         // first-order extrapolation from upstream
+    } else {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) nt[k] *= a.nu;
+        chi_new = fdiv(sa_update(nt, u, v, a.nu, CT(dist), a.sa_mode == 2), a.nu);
+    }
+    finish_cell(a, c, s, chi_new, gx, gy);
+}
+
+// ---------------------------------------------------------------------------
+// Wall nodes B of a level, one thread each (workgroups of k_step).  Runs beside
+// k_step (disjoint cells, same source state): steps 1-5 of the VN procedure
+// on the macroscopic state of the previous step, the Dirichlet value
+// nu~_B = kappa u_tau d_WB, Yu's interpolated bounce-back (step 6, eq (27)) or
+// eq (24) for the missing populations, and the collision.  All loads are
+// issued before the Newton iteration and the first store.
+// ---------------------------------------------------------------------------
+template <class ST, class CT>
+__device__ __forceinline__ void boundary_node(const StepArgs<ST, CT>& a, int b) {
+    const long P = a.box.plane;
+    const int pitch = a.box.pitch;
+    const int c = a.wall.cell[b];
+    const int gx = c % pitch + a.box.gx0, gy = c / pitch + a.box.gy0;
+    // steps 1-5 of the VN procedure on the macroscopic state of the previous step;
+    // the populations are loaded afterwards so that they are not held in
+    // registers through the FP64 Newton iteration
+    double wm[6];
+    wall_model<CT>(a.wall, b, a.msrc, P, (double)a.nu, a.wstate[8 * b], wm);
+    const int pad = a.pad;
+    const Rsrc rf = make_rsrc(a.fsrc - pad, 9 * P + 2 * pad);
+    const Rsrc rg = make_rsrc(a.flag - pad, P + 2 * pad);
+    constexpr uint32_t SS = sizeof(ST);
+    const uint32_t e = (uint32_t)(c + pad);
+    // one round of loads once the Newton iteration is done: link fractions,
+    // pulled, own and next-node populations, next-node flags
+    double q[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) q[k] = a.wall.q[8 * b + k];
+    CT pull[9], own[9], nxt[9];
+    uint8_t f2fl[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        // pull source (periodic wrap in x on level 0) and next node F2 = B + c_i
+        int sx = gx - CX[i], fx = gx + CX[i];
+        if (a.dom.periodic_x) {
+            sx = (sx + a.dom.nxd) % a.dom.nxd;
+            fx = (fx + a.dom.nxd) % a.dom.nxd;
+        }
+        const uint32_t src = (uint32_t)((gy - CY[i] - a.box.gy0) * pitch + (sx - a.box.gx0) + pad);
+        const uint32_t f2 = (uint32_t)((gy + CY[i] - a.box.gy0) * pitch + (fx - a.box.gx0) + pad);
+        pull[i] = bld<ST, CT>(rf, src * SS, (uint32_t)(i * P) * SS);
+        own[i] = bld<ST, CT>(rf, e * SS, (uint32_t)(i * P) * SS);
+        nxt[i] = bld<ST, CT>(rf, f2 * SS, (uint32_t)(OPP[i] * P) * SS);   // f*_o at F2
+        f2fl[i] = __builtin_amdgcn_raw_buffer_load_b8(rg, f2, 0, 0);
+    }
+    const CT rhow = CT(wm[3]), uwx = CT(wm[4]), uwy = CT(wm[5]);
+    CT s[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const double qd = (i == 0) ? -1.0 : q[OPP[i] - 1];
+        if (qd < 0.0) { s[i] = pull[i]; continue; }
+        // i is the missing population; o = opp(i) is the link from B towards the wall
+        const int o = OPP[i];
+        const CT qo = CT(qd);
+        const CT fo_b = own[o];
+        const CT mom = CT(6) * wq<CT>(o) * rhow * (CT(CX[i]) * uwx + CT(CY[i]) * uwy);
+        CT val = fo_b + mom;                                      // eq (24)
+        if (!a.bb_halfway && q[i - 1] < 0.0 && (f2fl[i] & F_TYPE) == T_FLUID) {
+            // (A) outgoing value at the wall point, (B) reflection with the wall
+            // momentum, (C) interpolation between W and the next node F2
+            const CT fw_o = qo * fo_b + (CT(1) - qo) * nxt[i];
+            const CT fw_i = fw_o + mom;
+            val = fw_i + (qo / (CT(1) + qo)) * (own[i] - fw_i);
+        }
+        s[i] = val;
+    }
+    const CT chi_new = a.frozen ? a.csrc[c]
+                                : ((a.wall.model <= 1) ? CT(KAPPA * wm[0] * a.wall.geo[6 * b + 4] / (double)a.nu)
+                                                       : CT(0));
+    finish_cell(a, c, s, chi_new, gx, gy);
+    double* st = a.wstate + 8 * b;
+    for (int k = 0; k < 6; ++k) st[k] = wm[k];
+}
+
+template <class ST, class CT>
+__global__ __launch_bounds__(256, 8) void k_step(const StepArgs<ST, CT> a) {
     __shared__ CT sh_n[TILE_Y + 2][TILE_X + 2], sh_u[TILE_Y + 2][TILE_X + 2], sh_v[TILE_Y + 2][TILE_X + 2];
+    // grid: wall-node blocks first (their FP64 Newton iteration is the longest
+    // chain), then the tiles, then the level-0 domain-edge cells; each branch is
+    // uniform over a workgroup
+    if ((int)blockIdx.x < a.wall_blocks) {
+        // the wall-node waves carry the longest dependency chain of the launch
+        // (FP64 Newton): they get issue priority over the tile waves of their SIMD
+        __builtin_amdgcn_s_setprio(3);
+        const int b = blockIdx.x * TILE_X * TILE_Y + threadIdx.x;
+        if (b < a.wall.nb) boundary_node(a, b);
+        return;
+    }
+    const int bid = (int)blockIdx.x - a.wall_blocks;             // a multiple of 8 shifts no XCD
+    if (bid >= a.tile_blocks) {
+        const int e = (bid - a.tile_blocks) * TILE_X * TILE_Y + threadIdx.x;
+        if (e < a.nedge) edge_cell(a, e);
+        return;
+    }
     const int per = (a.ntiles + 7) >> 3;
-    const int t = (blockIdx.x & 7) * per + (blockIdx.x >> 3);   // neighbouring tiles share an XCD
+    const int t = (bid & 7) * per + (bid >> 3);                  // neighbouring tiles share an XCD
     if (t >= a.ntiles) return;                                   // whole workgroup
     const uint32_t tile = a.tiles[t];
     const int pitch = a.box.pitch;
@@ -635,6 +819,7 @@ __global__ __launch_bounds__(256) void k_step(const StepArgs<ST, CT> a) {
             chi_new = fdiv(sa_update(nt, u, v, a.nu, CT(dist), a.sa_mode == 2), a.nu);
         }
         relax_cell(a, s, chi_new, m_rho, m_ux, m_uy);
+        absorb(a, gx, gy, s);
         m_chi = chi_new;
         const Rsrc rmo = make_rsrc(a.mdst - pad, 3 * P + 2 * pad);
         const Rsrc rco = make_rsrc(a.cdst - pad, P + 2 * pad);
@@ -671,140 +856,6 @@ __global__ __launch_bounds__(256) void k_step(const StepArgs<ST, CT> a) {
     }
 }
 
-// ---------------------------------------------------------------------------
-// k_edge: level-0 cells on the domain edge (except wall nodes), one thread
-// each, beside k_step: periodic wrap, specular reflection at symmetry edges,
-// Zou-He velocity inlet, extrapolation or Zou-He pressure outlet (Section
-// 3.1.1), and the SA
-// boundary rules (inlet chi, outlet extrapolation, mirrored stencil).
-// ---------------------------------------------------------------------------
-template <class ST, class CT>
-__global__ __launch_bounds__(64) void k_edge(const StepArgs<ST, CT> a) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= a.nedge) return;
-    const int pitch = a.box.pitch;
-    const long P = a.box.plane;
-    const long c = a.edge[e];
-    const int gx = (int)(c % pitch) + a.box.gx0, gy = (int)(c / pitch) + a.box.gy0;
-    const double dist = a.dist[c];
-    CT s[9], nt[9], u[9], v[9];
-    const bool at_inlet = gx == 0 && a.dom.bc[0] == BC_INLET;
-    const bool at_outlet = gx == a.dom.nxd - 1 && a.dom.bc[1] == BC_OUTLET;
-    {
-        gather_edge(a, gx, gy, nt, u, v);
-        for (int i = 0; i < 9; ++i)
-            if (!pull_general(a, (uint8_t)F_EDGE, i, gx, gy, s[i])) s[i] = CT(0);
-        if (at_inlet) {
-            const CT ui = a.u_in;
-            const CT rho = (CT(1) + s[0] + s[3] + s[4] + CT(2) * (s[2] + s[6] + s[8])) / (CT(1) - ui);
-            s[1] = s[2] + CT(2.0 / 3.0) * rho * ui;
-            s[5] = s[6] - CT(0.5) * (s[3] - s[4]) + rho * ui * CT(1.0 / 6.0);
-            s[7] = s[8] + CT(0.5) * (s[3] - s[4]) + rho * ui * CT(1.0 / 6.0);
-        }
-        if (at_outlet && a.dom.outlet == 2) {
-            // Zou-He with rho = rho_ref and u_y of the upstream cell (unknowns: c_x = -1)
-            const CT rho = a.rho_out, uy = v[3];
-            const CT ux = (CT(1) + s[0] + s[3] + s[4] + CT(2) * (s[1] + s[5] + s[7])) / rho - CT(1);
-            s[2] = s[1] - CT(2.0 / 3.0) * rho * ux;
-            s[6] = s[5] + CT(0.5) * (s[3] - s[4]) - rho * ux * CT(1.0 / 6.0) - CT(0.5) * rho * uy;
-            s[8] = s[7] - CT(0.5) * (s[3] - s[4]) - rho * ux * CT(1.0 / 6.0) + CT(0.5) * rho * uy;
-        } else if (at_outlet) {
-            for (int i = 0; i < 9; ++i)
-                if (CX[i] == -1)
-                    s[i] = (a.dom.outlet == 1)
-                               ? poststream(a, i, gx - 1, gy)
-                               : CT(2) * poststream(a, i, gx - 1, gy) - poststream(a, i, gx - 2, gy);
-        }
-    }
-    CT chi_new;
-    if (a.frozen) {
-        chi_new = nt[4];
-    } else if (at_inlet) {
-        chi_new = a.chi_in;
-    } else if (at_outlet) {
-        chi_new = nt[3];                         // first-order extrapolation from upstream
-    } else {
-#pragma unroll
-        for (int k = 0; k < 9; ++k) nt[k] *= a.nu;
-        chi_new = fdiv(sa_update(nt, u, v, a.nu, CT(dist), a.sa_mode == 2), a.nu);
-    }
-    finish_cell(a, c, s, chi_new);
-}
-
-// ---------------------------------------------------------------------------
-// k_boundary: the wall nodes B of a level, one thread each.  Runs beside
-// k_step (disjoint cells, same source state): steps 1-5 of the VN procedure
-// on the macroscopic state of the previous step, the Dirichlet value
-// nu~_B = kappa u_tau d_WB, Yu's interpolated bounce-back (step 6, eq (27)) or
-// eq (24) for the missing populations, and the collision.  All loads are
-// issued before the Newton iteration and the first store.
-// ---------------------------------------------------------------------------
-template <class ST, class CT>
-__global__ __launch_bounds__(64) void k_boundary(const StepArgs<ST, CT> a) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= a.wall.nb) return;
-    const long P = a.box.plane;
-    const int pitch = a.box.pitch;
-    const long c = a.wall.cell[b];
-    const double guess = a.wstate[8 * b];
-    const int gx = (int)(c % pitch) + a.box.gx0, gy = (int)(c / pitch) + a.box.gy0;
-    const uint8_t fl = a.flag[c];
-    // sources of the pull (periodic wrap in x on level 0) and next nodes F2
-    long src[9], f2[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        int sx = gx - CX[i], fx = gx + CX[i];
-        if (a.dom.periodic_x) {
-            sx = (sx + a.dom.nxd) % a.dom.nxd;
-            fx = (fx + a.dom.nxd) % a.dom.nxd;
-        }
-        src[i] = (long)(gy - CY[i] - a.box.gy0) * pitch + (sx - a.box.gx0);
-        f2[i] = (long)(gy + CY[i] - a.box.gy0) * pitch + (fx - a.box.gx0);
-    }
-    double q[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) q[k] = a.wall.q[8 * b + k];
-    CT pull[9], own[9], nxt[9];
-    uint8_t f2fl[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        const bool cut = i > 0 && q[OPP[i] - 1] >= 0.0;
-        pull[i] = Cv<ST, CT>::ld(a.fsrc + i * P + (cut ? c : src[i]));
-        own[i] = Cv<ST, CT>::ld(a.fsrc + i * P + c);
-        nxt[i] = Cv<ST, CT>::ld(a.fsrc + OPP[i] * P + f2[i]);     // f*_o at F2 = B + c_i
-        f2fl[i] = a.flag[f2[i]];
-    }
-    double wm[6];
-    wall_model<CT>(a.wall, b, a.msrc, P, (double)a.nu, guess, wm);
-    const CT rhow = CT(wm[3]), uwx = CT(wm[4]), uwy = CT(wm[5]);
-    CT s[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        const double qd = (i == 0) ? -1.0 : q[OPP[i] - 1];
-        if (qd < 0.0) { s[i] = pull[i]; continue; }
-        // i is the missing population; o = opp(i) is the link from B towards the wall
-        const int o = OPP[i];
-        const CT qo = CT(qd);
-        const CT fo_b = own[o];
-        const CT mom = CT(6) * wq<CT>(o) * rhow * (CT(CX[i]) * uwx + CT(CY[i]) * uwy);
-        CT val = fo_b + mom;                                      // eq (24)
-        if (!a.bb_halfway && q[i - 1] < 0.0 && (f2fl[i] & F_TYPE) == T_FLUID) {
-            // (A) outgoing value at the wall point, (B) reflection with the wall
-            // momentum, (C) interpolation between W and the next node F2
-            const CT fw_o = qo * fo_b + (CT(1) - qo) * nxt[i];
-            const CT fw_i = fw_o + mom;
-            val = fw_i + (qo / (CT(1) + qo)) * (own[i] - fw_i);
-        }
-        s[i] = val;
-    }
-    const CT chi_new = a.frozen ? a.csrc[c]
-                                : ((a.wall.model <= 1) ? CT(KAPPA * wm[0] * a.wall.geo[6 * b + 4] / (double)a.nu)
-                                                       : CT(0));
-    finish_cell(a, c, s, chi_new);
-    double* st = a.wstate + 8 * b;
-    for (int k = 0; k < 6; ++k) st[k] = wm[k];
-    (void)fl;
-}
 
 // Wall model on the current state, for output.
 template <class CT>
@@ -902,24 +953,6 @@ __global__ void k_init(const InitArgs a) {
     collide(s, drho, ux, uy, omega, CT(a.omega_b), CT(a.fx), CT(a.fy));
     ST* f = (ST*)a.f;
     for (int i = 0; i < 9; ++i) Cv<ST, CT>::st(f + i * a.plane + c, s[i]);
-}
-
-// Absorbing layer of level 0: post-collision populations relaxed towards the
-// free-stream equilibrium (shifted form, so the target is w_i-free).
-template <class ST, class CT>
-__global__ __launch_bounds__(256) void k_sponge(const SpongeArgs a) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= a.n) return;
-    const long c = a.list[k];
-    const CT sg = CT(a.sigma[k]);
-    CT t[9];
-    equilibrium<CT>(t, CT(a.drho), CT(a.ux), CT(0));
-    ST* f = (ST*)a.f;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        const CT v = Cv<ST, CT>::ld(f + i * a.plane + c);
-        Cv<ST, CT>::st(f + i * a.plane + c, v - sg * (v - t[i]));
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1058,8 +1091,8 @@ inline void launch_timed(K kernel, dim3 g, dim3 b, hipStream_t s, const Timing& 
 template <class ST, class CT>
 static hipError_t step_t(const void* args, hipStream_t s, const Timing& tm) {
     const auto& a = *static_cast<const StepArgs<ST, CT>*>(args);
-    if (a.ntiles == 0) return hipSuccess;
-    const unsigned grid = 8u * (unsigned)((a.ntiles + 7) / 8);
+    const unsigned grid = (unsigned)(a.wall_blocks + a.tile_blocks) + nblocks(a.nedge, TILE_X * TILE_Y);
+    if (grid == 0) return hipSuccess;
     launch_timed(k_step<ST, CT>, dim3(grid), dim3(TILE_X * TILE_Y), s, tm, a);
     return hipGetLastError();
 }
@@ -1070,40 +1103,6 @@ hipError_t launch_step(Prec p, const void* args, hipStream_t s, const Timing& tm
         case P_F32: return step_t<float, float>(args, s, tm);
         case P_F16: return step_t<__half, float>(args, s, tm);
         default: return step_t<__hip_bfloat16, float>(args, s, tm);
-    }
-}
-
-template <class ST, class CT>
-static hipError_t boundary_t(const void* args, hipStream_t s, const Timing& tm) {
-    const auto& a = *static_cast<const StepArgs<ST, CT>*>(args);
-    if (a.wall.nb == 0) return hipSuccess;
-    launch_timed(k_boundary<ST, CT>, dim3(nblocks(a.wall.nb, 64)), dim3(64), s, tm, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_boundary(Prec p, const void* args, hipStream_t s, const Timing& tm) {
-    switch (p) {
-        case P_F64: return boundary_t<double, double>(args, s, tm);
-        case P_F32: return boundary_t<float, float>(args, s, tm);
-        case P_F16: return boundary_t<__half, float>(args, s, tm);
-        default: return boundary_t<__hip_bfloat16, float>(args, s, tm);
-    }
-}
-
-template <class ST, class CT>
-static hipError_t edge_t(const void* args, hipStream_t s, const Timing& tm) {
-    const auto& a = *static_cast<const StepArgs<ST, CT>*>(args);
-    if (a.nedge == 0) return hipSuccess;
-    launch_timed(k_edge<ST, CT>, dim3(nblocks(a.nedge, 64)), dim3(64), s, tm, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_edge(Prec p, const void* args, hipStream_t s, const Timing& tm) {
-    switch (p) {
-        case P_F64: return edge_t<double, double>(args, s, tm);
-        case P_F32: return edge_t<float, float>(args, s, tm);
-        case P_F16: return edge_t<__half, float>(args, s, tm);
-        default: return edge_t<__hip_bfloat16, float>(args, s, tm);
     }
 }
 
@@ -1142,18 +1141,6 @@ hipError_t launch_init(Prec p, const InitArgs& a, hipStream_t s) {
         case P_F32: hipLaunchKernelGGL((k_init<float, float>), g, b, 0, s, a); break;
         case P_F16: hipLaunchKernelGGL((k_init<__half, float>), g, b, 0, s, a); break;
         default: hipLaunchKernelGGL((k_init<__hip_bfloat16, float>), g, b, 0, s, a); break;
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_sponge(Prec p, const SpongeArgs& a, hipStream_t s) {
-    if (a.n == 0) return hipSuccess;
-    const dim3 g(nblocks(a.n, 256)), b(256);
-    switch (p) {
-        case P_F64: hipLaunchKernelGGL((k_sponge<double, double>), g, b, 0, s, a); break;
-        case P_F32: hipLaunchKernelGGL((k_sponge<float, float>), g, b, 0, s, a); break;
-        case P_F16: hipLaunchKernelGGL((k_sponge<__half, float>), g, b, 0, s, a); break;
-        default: hipLaunchKernelGGL((k_sponge<__hip_bfloat16, float>), g, b, 0, s, a); break;
     }
     return hipGetLastError();
 }
