@@ -235,14 +235,14 @@ int64_t lbr_lups_per_coarse_step(lbr_ctx* ctx);
    (enable != 0), or returns to direct launches (enable == 0). */
 int lbr_use_graph(lbr_ctx* ctx, int32_t enable);
 
-/* Average device time per launch of each kernel over the last lbr_advance,
-   in microseconds, from start / stop events attached to each dispatch
-   (hipExtLaunchKernelGGL): out[0] main step kernel k_step (all levels),
-   out[1] k_step on the finest level, out[2] wall-node kernel k_boundary,
-   out[3] domain-edge kernel k_edge.  enable != 0 turns the timing on for the
-   following lbr_advance calls (direct launches: the graph is not replayed
-   while timing); enable == 0 turns it off.  out may be NULL; it receives the
-   figures of the last timed lbr_advance. */
+/* Average device time per launch of the step kernel k_step over the last
+   lbr_advance, in microseconds, from start / stop events attached to each
+   dispatch (hipExtLaunchKernelGGL): out[0] all levels, out[1] the finest
+   level, out[2] level 0, out[3] unused (0).  One k_step launch covers a whole
+   level sub-step: tiles, wall nodes and domain-edge cells.  enable != 0 turns
+   the timing on for the following lbr_advance calls (direct launches: the
+   graph is not replayed while timing); enable == 0 turns it off.  out may be
+   NULL; it receives the figures of the last timed lbr_advance. */
 int lbr_profile(lbr_ctx* ctx, int32_t enable, double out[4]);
 
 /* Last error message of the context (never NULL). */

@@ -776,7 +776,7 @@ void fill_step_args(lbr_ctx* c, int l, int substep, StepArgs<ST, CT>& a) {
     a.dom.periodic_x = cfg.bc[0] == LBR_BC_PERIODIC;
     a.dom.outlet = cfg.outlet;
     a.pad = L.box.pitch + 1;
-    a.wall_blocks = 8 * (((int)L.nodes.size() + 8 * TILE_X * TILE_Y - 1) / (8 * TILE_X * TILE_Y));
+    a.wall_blocks = 8 * (((int)L.nodes.size() + 8 * WALL_PER_BLOCK - 1) / (8 * WALL_PER_BLOCK));
     a.tile_blocks = 8 * (((int)L.rows.size() + 7) / 8);
     a.sp_width = 0.0;
     a.sp_strength = 0.0;

@@ -22,6 +22,7 @@ enum : uint8_t {
     F_COVB = 128,       // covered cell next to an owned cell (restriction target)
 };
 
+constexpr int WALL_PER_BLOCK = 16;   // wall nodes per k_step workgroup
 constexpr int TILE_X = 64;   // one wavefront per tile row
 constexpr int TILE_Y = 4;    // four wavefronts per 256-thread workgroup
 constexpr int MAX_STENCIL = 16;
@@ -78,7 +79,8 @@ struct StepArgs {
     int substep;                     // 1 or 2 within the parent's step (0 on level 0)
     int pad;                         // spare elements before and after every field array
                                      // of the level (one row plus one cell)
-    int wall_blocks, tile_blocks;    // k_step grid: wall-node blocks (a multiple of 8),
+    int wall_blocks, tile_blocks;    // k_step grid: wall-node blocks of WALL_PER_BLOCK nodes
+                                     // (a multiple of 8 blocks),
                                      // tile blocks (a multiple of 8), then edge-cell blocks
     // absorbing layer of level 0 (sp_width = 0 elsewhere): sides bit k = bc[k] is a far field
     double sp_width, sp_strength;

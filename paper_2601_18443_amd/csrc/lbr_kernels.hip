@@ -288,10 +288,12 @@ constexpr double WF_B = 5.033908790505579, WF_A1 = 8.148221580024245,
                  WF_C4 = 3.639753186868684494;
 
 // eq (22), continuous branch of the arctangents
+// (b > 0, so atan2(b, x) = pi/2 - atan(x / b): no division, no quadrant logic)
 __device__ double uplus(double y) {
     const double p = y + WF_A1, m = y + WF_A2;
+    constexpr double HALF_PI = 1.5707963267948966, IB1 = 1.0 / WF_B1, IB2 = 1.0 / WF_B2;
     return WF_B + WF_C1 * log(p * p + WF_B1 * WF_B1) - WF_C2 * log(m * m + WF_B2 * WF_B2) -
-           WF_C3 * atan2(WF_B1, p) - WF_C4 * atan2(WF_B2, m);
+           WF_C3 * (HALF_PI - atan(p * IB1)) - WF_C4 * (HALF_PI - atan(m * IB2));
 }
 
 // eq (21)
@@ -691,10 +693,11 @@ __global__ __launch_bounds__(256, 8) void k_step(const StepArgs<ST, CT> a) {
     // chain), then the tiles, then the level-0 domain-edge cells; each branch is
     // uniform over a workgroup
     if ((int)blockIdx.x < a.wall_blocks) {
-        // the wall-node waves carry the longest dependency chain of the launch
-        // (FP64 Newton): they get issue priority over the tile waves of their SIMD
-        __builtin_amdgcn_s_setprio(3);
-        const int b = blockIdx.x * TILE_X * TILE_Y + threadIdx.x;
+        // the wall nodes carry the longest dependency chain of the launch (FP64
+        // Newton iteration): a few per block spreads them over many compute units
+        // instead of crowding the SIMDs of a few
+        if ((int)threadIdx.x >= WALL_PER_BLOCK) return;
+        const int b = blockIdx.x * WALL_PER_BLOCK + threadIdx.x;
         if (b < a.wall.nb) boundary_node(a, b);
         return;
     }
