@@ -94,7 +94,7 @@ def stats(directory, cmd):
                     d = float(_col(r, "End_Timestamp")) - float(_col(r, "Start_Timestamp"))
                     per[(n, g)].append(d)
         out += ["", "k_step by launch size (one grid size per level)",
-                f"{'kernel':34s} {'threads':>9s} {'tiles':>7s} {'calls':>7s} {'avg us':>9s} {'median us':>10s}"]
+                f"{'kernel':34s} {'threads':>9s} {'blocks':>7s} {'calls':>7s} {'avg us':>9s} {'median us':>10s}"]
         for (n, g), v in sorted(per.items(), key=lambda kv: -kv[0][1]):
             v.sort()
             out.append(f"{n:34s} {g:9d} {g // 256:7d} {len(v):7d} {sum(v) / len(v) / 1e3:9.2f} "
