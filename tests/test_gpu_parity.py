@@ -134,3 +134,26 @@ def test_graph_replay_matches_direct_launches(storage):
             assert np.array_equal(np.isnan(x), np.isnan(y))
             m = ~np.isnan(x)
             assert np.array_equal(x[m], y[m]), (l, f)
+
+
+@pytest.mark.parametrize("variant", [
+    dict(sa_mode=LI.SA_UPWIND1),                 # first-order upwind SA convection (Section 3.3)
+    dict(wall_model=LI.WALL_NISHIMURA),          # eq (31) with d_WR = 1.75 (Section 3.1.5)
+    dict(bb_mode=LI.BB_HALFWAY),                 # eq (24) at every cut link
+    dict(outlet=LI.OUTLET_EXTRAP1),
+    dict(outlet=LI.OUTLET_PRESSURE),
+    dict(sponge_width=0.0),
+])
+def test_airfoil_small_variants_fp64(variant):
+    case = LI.case_airfoil_small()
+    case.update(variant)
+    o, g = _pair(case, "f64")
+    o.advance(4)
+    g.advance(4)
+    assert U.velocity_error(g, o, case["n_levels"]) < 1e-10
+    err = U.field_errors(g, o, case["n_levels"], names=("chi",))
+    assert max(err.values()) < 1e-10, err
+    assert U.density_error(g, o, case["n_levels"]) < 1e-12
+    lf = case["n_levels"] - 1
+    np.testing.assert_allclose(g.wall(lf)[:, 8], o.wall(lf)[:, 8], rtol=1e-10)
+    np.testing.assert_allclose(g.forces(), o.forces(), rtol=1e-9, atol=1e-12)
