@@ -157,3 +157,21 @@ def test_airfoil_small_variants_fp64(variant):
     lf = case["n_levels"] - 1
     np.testing.assert_allclose(g.wall(lf)[:, 8], o.wall(lf)[:, 8], rtol=1e-10)
     np.testing.assert_allclose(g.forces(), o.forces(), rtol=1e-9, atol=1e-12)
+
+
+def test_full_size_airfoil_fp32_against_oracle():
+    """The benchmark workload itself (8 levels, ~2.0M cells, FP32, graph replay as
+    timed by bench.py) against the FP64 oracle after two coarse steps (510 k_step
+    launches, 2.5e8 cell updates): velocity and chi within 1e-5 relative on every
+    level, density within 1e-6, forces within 1e-4."""
+    case = LI.case_airfoil_cfg1()
+    o, g = _pair(case, "f32")
+    assert U.structure_mismatch(g, o, case["n_levels"]) == []
+    g.use_graph(True)
+    o.advance(2)
+    g.advance(2)
+    assert U.velocity_error(g, o, case["n_levels"]) < 1e-5
+    err = U.field_errors(g, o, case["n_levels"], names=("chi",))
+    assert max(err.values()) < 1e-5, err
+    assert U.density_error(g, o, case["n_levels"]) < 1e-6
+    np.testing.assert_allclose(g.forces()[:4], o.forces()[:4], rtol=1e-4)
