@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define LBR_ABI_VERSION 2
+#define LBR_ABI_VERSION 3
 #define LBR_MAX_LEVELS 12
 
 enum lbr_status {
@@ -132,6 +132,13 @@ typedef struct lbr_config {
     double sponge_width;           /* absorbing layer along the INLET, OUTLET and SYMMETRY
                                       sides of level 0, in level-0 cells (0 = none) */
     double sponge_strength;        /* its largest relaxation rate per level-0 step */
+    double ramp_steps;             /* start-up ramp (not part of the paper's method): coarse
+                                      steps N over which the inlet velocity and the
+                                      absorbing-layer target rise from ramp_start u_ref to
+                                      u_ref as r0 + (1 - r0) (1 - cos(pi n / N)) / 2; the
+                                      default initial state moves at ramp_start u_ref
+                                      (N = 0: impulsive start at u_ref) */
+    double ramp_start;             /* r0, in [0, 1] */
     lbr_alloc_fn alloc_fn;         /* optional device allocator */
     lbr_free_fn free_fn;
     void* alloc_user;

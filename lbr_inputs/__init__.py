@@ -190,6 +190,70 @@ def case_airfoil_small(seed: int = 0, alpha_deg: float = 10.0, n_side: int = 256
                         band_finest=0.25, alpha_deg=alpha_deg, n_side=n_side)
 
 
+def _min_distance(a: np.ndarray, b: np.ndarray) -> float:
+    """Smallest point-to-point distance between two polylines (dense sampling)."""
+    d = np.inf
+    for k in range(0, len(a), 256):
+        blk = a[k:k + 256]
+        d = min(d, float(np.sqrt(((blk[:, None, :] - b[None, :, :]) ** 2).sum(-1)).min()))
+    return d
+
+
+def three_element_polylines(seed: int = 0, n_side: int = 1024, alpha_deg: float = 8.0,
+                            deflection_deg: float = 30.0, gap: float = 0.02):
+    """Seeded slat, main element and flap (stand-in for the MD-30P30N of Section 3.2).
+
+    Main element: chord 0.8, 12 % thick, seeded camber in [0.02, 0.05].  Slat
+    chord 0.15 and flap chord 0.30 (each +-10 %, seeded), 10 % and 12 % thick,
+    both deflected by ``deflection_deg`` (slat nose down about its trailing
+    edge, flap trailing edge down about its leading edge) and placed with
+    ``gap`` clearance; the assembly is rotated by -alpha about (0.25, 0).  Each
+    element is a closed CCW polyline of 2 * n_side points.  The smallest
+    distance between elements is at least half the gap.
+    """
+    rng = np.random.default_rng(1000 + seed)
+    camber = rng.uniform(0.02, 0.05)
+    cs = 0.15 * rng.uniform(0.9, 1.1)
+    cf = 0.30 * rng.uniform(0.9, 1.1)
+    main = 0.8 * airfoil_polyline(seed, n_side=n_side, thickness=0.12, camber=camber)
+    slat = cs * airfoil_polyline(seed + 1, n_side=n_side, thickness=0.10, camber=0.03)
+    flap = cf * airfoil_polyline(seed + 2, n_side=n_side, thickness=0.12, camber=0.03)
+    # slat: nose down about its trailing edge (cs, 0); flap: trailing edge down about (0, 0)
+    slat = rotate(slat, -deflection_deg, pivot=(cs, 0.0))
+    flap = rotate(flap, deflection_deg, pivot=(0.0, 0.0))
+    # place the slat trailing edge ahead of and above the main leading edge, the flap
+    # leading edge below the main trailing edge, then open the gaps until clear
+    le_main = main[np.argmin(main[:, 0])]
+    te_main = main[0]
+    s_off = np.array([le_main[0] - cs + 0.01, le_main[1] + 0.02])
+    f_off = np.array([te_main[0] - 0.03, te_main[1] - 0.03])
+    for _ in range(200):
+        if _min_distance(slat + s_off, main) >= gap:
+            break
+        s_off += np.array([-0.002, 0.002])
+    for _ in range(200):
+        if _min_distance(flap + f_off, main) >= gap:
+            break
+        f_off += np.array([0.002, -0.002])
+    bodies = [slat + s_off, main, flap + f_off]
+    return [np.ascontiguousarray(rotate(b, alpha_deg)) for b in bodies]
+
+
+def case_three_element(seed: int = 0, finest_cells_per_chord: int = 4096, n_levels: int = 8,
+                       domain_chords: float = 40.0, band_finest: float = 0.165,
+                       mach: float = 0.2, reynolds: float = 9e6, alpha_deg: float = 8.0,
+                       n_side: int = 1024):
+    """Three-element high-lift-like configuration: Re 9e6, Mach 0.2, 8 degrees,
+    finest c/4096 in a 40-chord domain, 8 levels from c/32 (the distance bands of
+    more levels would leave the domain)."""
+    case = case_airfoil(seed=seed, finest_cells_per_chord=finest_cells_per_chord,
+                        n_levels=n_levels, domain_chords=domain_chords, band_finest=band_finest,
+                        mach=mach, reynolds=reynolds, alpha_deg=alpha_deg, n_side=16)
+    case.update(name="three_element", ramp_steps=1000.0, ramp_start=0.25,
+                bodies=three_element_polylines(seed, n_side=n_side, alpha_deg=alpha_deg))
+    return case
+
+
 def case_airfoil_cfg1(seed: int = 0):
     """Single body, FP32: Re 6e6, Mach 0.15, 10 deg, finest c/1024, 40-chord domain."""
     return case_airfoil(seed=seed)

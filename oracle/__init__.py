@@ -34,6 +34,7 @@ class Config(C.Structure):
         ("force", C.c_double * 2), ("omega_b", C.c_double),
         ("d_wr", C.c_double), ("d_wv", C.c_double), ("u_wall", C.c_double * 4),
         ("sponge_width", C.c_double), ("sponge_strength", C.c_double),
+        ("ramp_steps", C.c_double), ("ramp_start", C.c_double),
     ]
 
 
@@ -192,6 +193,8 @@ def make_config(case) -> Config:
         c.u_wall[k] = uw[k]
     c.sponge_width = case.get("sponge_width", 0.0)
     c.sponge_strength = case.get("sponge_strength", 0.0)
+    c.ramp_steps = case.get("ramp_steps", 0.0)
+    c.ramp_start = case.get("ramp_start", 0.0)
     return c
 
 

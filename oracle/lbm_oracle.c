@@ -364,9 +364,14 @@ double lbro_sa_cell(const double nt[9], const double ux[9], const double uy[9], 
         double dXY = 0.25 * (nt[8] - nt[6] - nt[2] + nt[0]);
         conv = -(u * dX + v * dY) + 0.5 * (u * u * dXX + 2.0 * u * v * dXY + v * v * dYY);
     }
+    /* Face diffusivity capped at 0.2 sigma (lattice units): the explicit update is
+       stable only while (1/sigma) sum_faces mu <= 1, which a large eddy viscosity on
+       a fine level exceeds (the paper does not discuss the bound); below the cap
+       the scheme is unchanged. */
+    const double mu_max = 0.2 * SA_SIGMA;
     double muC = sa_mu(C, nu);
-    double me = 0.5 * (muC + sa_mu(E, nu)), mw = 0.5 * (muC + sa_mu(W, nu));
-    double mn = 0.5 * (muC + sa_mu(N, nu)), ms = 0.5 * (muC + sa_mu(S, nu));
+    double me = fmin(0.5 * (muC + sa_mu(E, nu)), mu_max), mw = fmin(0.5 * (muC + sa_mu(W, nu)), mu_max);
+    double mn = fmin(0.5 * (muC + sa_mu(N, nu)), mu_max), ms = fmin(0.5 * (muC + sa_mu(S, nu)), mu_max);
     double diff = me * (E - C) - mw * (C - W) + mn * (N - C) - ms * (C - S) +
                   SA_CB2 * (dX * dX + dY * dY);
     return C + conv + (src[0] - src[1]) + diff / SA_SIGMA;
@@ -441,12 +446,23 @@ struct lbro_sim {
     lbro_config cfg;
     int nl;
     double u_ref, nu0;
+    int64_t step;           /* coarse steps completed */
     int nbody;
     int* npts;
     double** poly;          /* level-0 lattice coordinates, 2*npts doubles each */
     double wall_lat[2];     /* channel wall y in level-0 lattice units */
     olevel lv[LBRO_MAX_LEVELS];
 };
+
+/* Start-up ramp (not part of the paper's method; ramp_steps = 0 starts the flow
+   impulsively at u_ref): the initial state moves uniformly at r0 u_ref and during
+   coarse step n the inlet velocity and the target of the absorbing layer are
+   u_ref (r0 + (1 - r0) (1 - cos(pi min(1, n / N))) / 2). */
+static double ramp(const lbro_sim* s, int64_t n) {
+    double N = s->cfg.ramp_steps, r0 = s->cfg.ramp_start;
+    if (!(N > 0.0) || (double)n >= N) return 1.0;
+    return r0 + (1.0 - r0) * (0.5 - 0.5 * cos(3.14159265358979323846 * (double)n / N));
+}
 
 static int idx(const olevel* L, int gi, int gj) {
     int i = gi - L->gx0, j = gj - L->gy0;
@@ -820,7 +836,8 @@ int lbro_create(const lbro_config* cfg, int32_t n_bodies, const int32_t* n_pts, 
     *out = NULL;
     if (!cfg || cfg->n_levels < 1 || cfg->n_levels > LBRO_MAX_LEVELS || cfg->nx0 < 4 ||
         cfg->ny0 < 4 || !(cfg->dx0 > 0.0) || cfg->outlet < 0 || cfg->outlet > 2 ||
-        cfg->sponge_width < 0.0 || cfg->sponge_strength < 0.0 || cfg->sponge_strength > 1.0)
+        cfg->sponge_width < 0.0 || cfg->sponge_strength < 0.0 || cfg->sponge_strength > 1.0 ||
+        cfg->ramp_steps < 0.0 || cfg->ramp_start < 0.0 || cfg->ramp_start > 1.0)
         return fail("invalid configuration");
     if ((cfg->bc[0] == LBRO_BC_PERIODIC) != (cfg->bc[1] == LBRO_BC_PERIODIC) ||
         (cfg->bc[2] == LBRO_BC_PERIODIC) != (cfg->bc[3] == LBRO_BC_PERIODIC))
@@ -897,7 +914,7 @@ int lbro_create(const lbro_config* cfg, int32_t n_bodies, const int32_t* n_pts, 
                 }
         }
     }
-    /* default initial state: uniform reference flow */
+    /* default initial state: uniform reference flow (at rest under a start-up ramp) */
     for (int l = 0; l < s->nl; ++l) lbro_init(s, l, NULL, NULL, NULL, NULL);
     *out = s;
     return 0;
@@ -926,7 +943,7 @@ int lbro_init(lbro_sim* s, int32_t level, const double* rho, const double* ux, c
             int c = idx(L, L->bx0 + i, L->by0 + j);
             int k = j * L->bnx + i;
             double r = rho ? rho[k] : s->cfg.rho_ref;
-            double u = ux ? ux[k] : s->u_ref;
+            double u = ux ? ux[k] : s->u_ref * ramp(s, 0);
             double v = uy ? uy[k] : 0.0;
             double x = chi ? chi[k] : s->cfg.chi_init;
             lbro_feq(r, u, v, &L->f[9 * c]);
@@ -1078,7 +1095,8 @@ static void sponge_level0(const lbro_sim* s, olevel* L) {
         if (d >= W) continue;
         double x = (W - d) / W;
         double sigma = cfg->sponge_strength * x * x;
-        lbro_sponge_cell(&L->fs[9 * c], sigma, cfg->rho_ref, s->u_ref, 0.0, &L->fs[9 * c]);
+        lbro_sponge_cell(&L->fs[9 * c], sigma, cfg->rho_ref, s->u_ref * ramp(s, s->step), 0.0,
+                         &L->fs[9 * c]);
     }
 }
 
@@ -1310,7 +1328,7 @@ static int stream_level(lbro_sim* s, int l) {
         }
         /* Zou-He velocity inlet (unknowns have c_x = +1) */
         if (l == 0 && gi == 0 && s->cfg.bc[0] == LBRO_BC_INLET) {
-            double ux = s->u_ref, uy = 0.0;
+            double ux = s->u_ref * ramp(s, s->step), uy = 0.0;
             double rho = (fo[0] + fo[3] + fo[4] + 2.0 * (fo[2] + fo[6] + fo[8])) / (1.0 - ux);
             fo[1] = fo[2] + (2.0 / 3.0) * rho * ux;
             fo[5] = fo[6] - 0.5 * (fo[3] - fo[4]) + rho * ux / 6.0 + 0.5 * rho * uy;
@@ -1376,8 +1394,10 @@ static int cycle(lbro_sim* s, int l) {
 
 int lbro_advance(lbro_sim* s, int64_t n) {
     if (!s) return fail("null simulation");
-    for (int64_t k = 0; k < n; ++k)
+    for (int64_t k = 0; k < n; ++k) {
         if (cycle(s, 0)) return -1;
+        s->step++;
+    }
     return 0;
 }
 

@@ -59,6 +59,10 @@ typedef struct {
     double u_wall[4];             /* PRESCRIBED slip velocity: lower (x,y), upper (x,y) */
     double sponge_width;          /* absorbing layer of level 0, in level-0 cells (0: none) */
     double sponge_strength;       /* its largest relaxation rate per step */
+    double ramp_steps;            /* start-up: coarse steps over which the inlet velocity and
+                                     the absorbing-layer target rise from ramp_start u_ref to
+                                     u_ref (0: none) */
+    double ramp_start;            /* initial fraction of u_ref under a start-up ramp */
 } lbro_config;
 
 typedef struct lbro_sim lbro_sim;

@@ -15,7 +15,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbr.so")
 
-ABI_VERSION = 2
+ABI_VERSION = 3
 MAX_LEVELS = 12
 WALL_STRIDE = 28
 
@@ -39,6 +39,7 @@ class lbr_config(C.Structure):
         ("force", C.c_double * 2), ("omega_b", C.c_double), ("d_wr", C.c_double),
         ("d_wv", C.c_double), ("u_wall", C.c_double * 4),
         ("sponge_width", C.c_double), ("sponge_strength", C.c_double),
+        ("ramp_steps", C.c_double), ("ramp_start", C.c_double),
         ("alloc_fn", ALLOC_FN), ("free_fn", FREE_FN), ("alloc_user", C.c_void_p),
         ("stream", C.c_void_p),
     ]
@@ -143,6 +144,8 @@ def make_config(case, storage="f32", stream=None, allocator=None) -> lbr_config:
         c.u_wall[k] = v
     c.sponge_width = case.get("sponge_width", 0.0)
     c.sponge_strength = case.get("sponge_strength", 0.0)
+    c.ramp_steps = case.get("ramp_steps", 0.0)
+    c.ramp_start = case.get("ramp_start", 0.0)
     if allocator is not None:
         c.alloc_fn, c.free_fn = allocator.alloc_cb, allocator.free_cb
     c.stream = stream

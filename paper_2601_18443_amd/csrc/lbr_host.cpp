@@ -110,6 +110,7 @@ struct lbr_ctx {
     hipGraphExec_t graph = nullptr;
     int graph_steps = 0;
     int graph_parity = 0;          // buffer index of level 0 the graph was captured with
+    int64_t step_count = 0;        // coarse steps completed (start-up ramp)
     // profiling
     bool prof = false;
     std::vector<hipEvent_t> ev;
@@ -750,6 +751,32 @@ WallData wall_data(lbr_ctx* c, const Level& L) {
     return w;
 }
 
+// Start-up ramp (not part of the paper's method; ramp_steps = 0 starts the flow
+// impulsively at u_ref): the initial state moves uniformly at r0 u_ref and during
+// coarse step n the inlet velocity and the target of the absorbing layer are
+// u_ref (r0 + (1 - r0) (1 - cos(pi min(1, n / N))) / 2).
+double ramp(const lbr_ctx* c, int64_t n) {
+    const double N = c->cfg.ramp_steps, r0 = c->cfg.ramp_start;
+    if (!(N > 0.0) || (double)n >= N) return 1.0;
+    return r0 + (1.0 - r0) * (0.5 - 0.5 * std::cos(3.14159265358979323846 * (double)n / N));
+}
+
+// Absorbing layer of level l (none above level 0) with the free stream scaled by r.
+Absorber absorber(const lbr_ctx* c, int l, double r) {
+    const lbr_config& cfg = c->cfg;
+    Absorber sp{};
+    sp.drho = cfg.rho_ref - 1.0;
+    sp.ux = c->u_ref * r;
+    if (l == 0 && cfg.sponge_width > 0.0 && cfg.sponge_strength > 0.0) {
+        sp.width = cfg.sponge_width;
+        sp.strength = cfg.sponge_strength;
+        for (int k = 0; k < 4; ++k)
+            if (cfg.bc[k] == LBR_BC_INLET || cfg.bc[k] == LBR_BC_OUTLET || cfg.bc[k] == LBR_BC_SYMMETRY)
+                sp.sides |= 1 << k;
+    }
+    return sp;
+}
+
 template <class ST, class CT>
 void fill_step_args(lbr_ctx* c, int l, int substep, StepArgs<ST, CT>& a) {
     Level& L = c->lv[l];
@@ -778,23 +805,13 @@ void fill_step_args(lbr_ctx* c, int l, int substep, StepArgs<ST, CT>& a) {
     a.pad = L.box.pitch + 1;
     a.wall_blocks = 8 * (((int)L.nodes.size() + 8 * WALL_PER_BLOCK - 1) / (8 * WALL_PER_BLOCK));
     a.tile_blocks = 8 * (((int)L.rows.size() + 7) / 8);
-    a.sp_width = 0.0;
-    a.sp_strength = 0.0;
-    a.sp_sides = 0;
-    a.sp_drho = cfg.rho_ref - 1.0;
-    a.sp_ux = c->u_ref;
-    if (l == 0 && cfg.sponge_width > 0.0 && cfg.sponge_strength > 0.0) {
-        a.sp_width = cfg.sponge_width;
-        a.sp_strength = cfg.sponge_strength;
-        for (int k = 0; k < 4; ++k)
-            if (cfg.bc[k] == LBR_BC_INLET || cfg.bc[k] == LBR_BC_OUTLET || cfg.bc[k] == LBR_BC_SYMMETRY)
-                a.sp_sides |= 1 << k;
-    }
+    // this launch streams coarse step n = step_count and collides step n + 1
+    a.sp = absorber(c, l, ramp(c, c->step_count + 1));
     a.nu = (CT)L.nu;
     a.fx = (CT)L.fx;
     a.fy = (CT)L.fy;
     a.omega_b = (CT)cfg.omega_b;
-    a.u_in = (CT)c->u_ref;
+    a.u_in = (CT)(c->u_ref * ramp(c, c->step_count));
     a.chi_in = (CT)cfg.chi_inlet;
     a.rho_out = (CT)cfg.rho_ref;
     a.sa_mode = cfg.sa;
@@ -934,7 +951,7 @@ int init_level(lbr_ctx* c, int l, const double* rho, const double* ux, const dou
         const int gx = (int)(cell % L.box.pitch) + L.box.gx0, gy = (int)(cell / L.box.pitch) + L.box.gy0;
         const long io = (long)(gy - L.by0) * L.bnx + (gx - L.bx0);
         v[k] = rho ? rho[io] : c->cfg.rho_ref;
-        v[n + k] = ux ? ux[io] : c->u_ref;
+        v[n + k] = ux ? ux[io] : c->u_ref * ramp(c, c->step_count);
         v[2 * n + k] = uy ? uy[io] : 0.0;
         v[3 * n + k] = chi ? chi[io] : c->cfg.chi_init;
     }
@@ -951,6 +968,9 @@ int init_level(lbr_ctx* c, int l, const double* rho, const double* ux, const dou
     a.chi_b = L.chi[1];
     a.plane = L.box.plane;
     a.nu = L.nu; a.fx = L.fx; a.fy = L.fy; a.omega_b = c->cfg.omega_b;
+    a.pitch = L.box.pitch; a.gx0 = L.box.gx0; a.gy0 = L.box.gy0;
+    a.nxd = c->cfg.nx0 << l; a.nyd = c->cfg.ny0 << l;
+    a.sp = absorber(c, l, ramp(c, c->step_count));
     HIPCHK(c, launch_init(c->prec, a, c->stream));
     HIPCHK(c, hipMemsetAsync(L.bstate, 0, std::max<size_t>(L.nodes.size(), 1) * 8 * sizeof(double), c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -1086,7 +1106,8 @@ int lbr_create(const lbr_config* cfg, lbr_ctx** out) {
     if (!cfg || cfg->version != LBR_ABI_VERSION) return LBR_ERR_INVALID_ARG;
     if (cfg->n_levels < 1 || cfg->n_levels > LBR_MAX_LEVELS || cfg->nx0 < 4 || cfg->ny0 < 4 ||
         !(cfg->dx0 > 0) || cfg->storage < 0 || cfg->storage > 3 || cfg->outlet < 0 || cfg->outlet > 2 ||
-        cfg->sponge_width < 0 || cfg->sponge_strength < 0 || cfg->sponge_strength > 1)
+        cfg->sponge_width < 0 || cfg->sponge_strength < 0 || cfg->sponge_strength > 1 ||
+        cfg->ramp_steps < 0 || cfg->ramp_start < 0 || cfg->ramp_start > 1)
         return LBR_ERR_INVALID_ARG;
     if ((cfg->bc[0] == LBR_BC_PERIODIC) != (cfg->bc[1] == LBR_BC_PERIODIC) ||
         (cfg->bc[2] == LBR_BC_PERIODIC) != (cfg->bc[3] == LBR_BC_PERIODIC) ||
@@ -1218,21 +1239,30 @@ int lbr_advance(lbr_ctx* c, int64_t n) {
     if (n < 0) return set_err(c, LBR_ERR_INVALID_ARG, "negative step count");
     c->ev_used = 0;
     int64_t k = 0;
-    if (c->use_graph && !c->prof) {
+    // during the start-up ramp the launch arguments change every step: direct launches
+    for (; k < n && (double)c->step_count < c->cfg.ramp_steps; ++k) {
+        if (int r = cycle(c, 0, 0)) return r;
+        c->step_count++;
+    }
+    if (c->use_graph && !c->prof && k < n) {
         if (!c->graph)
             if (int r = capture_graph(c)) return r;
         // after an odd number of direct coarse steps, one more restores the parity
         if (c->lv[0].cur != c->graph_parity && n - k > c->graph_steps) {
             if (int r = cycle(c, 0, 0)) return r;
+            c->step_count++;
             ++k;
         }
         for (; k + c->graph_steps <= n && c->lv[0].cur == c->graph_parity; k += c->graph_steps) {
             HIPCHK(c, hipGraphLaunch(c->graph, c->stream));
             for (Level& L : c->lv) L.cur ^= (c->graph_steps << L.l) & 1;
+            c->step_count += c->graph_steps;
         }
     }
-    for (; k < n; ++k)
+    for (; k < n; ++k) {
         if (int r = cycle(c, 0, 0)) return r;
+        c->step_count++;
+    }
     c->resid_steps += n;
     if (c->prof && c->ev_used) {
         HIPCHK(c, hipStreamSynchronize(c->stream));

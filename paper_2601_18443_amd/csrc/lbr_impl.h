@@ -38,6 +38,13 @@ struct Box {
 
 // Boundary-condition block of level 0 (all levels carry it; only level 0 has
 // F_EDGE cells).
+// Absorbing layer along the far-field sides of level 0 (width 0: none).
+struct Absorber {
+    double width, strength;          // in level-0 cells; largest relaxation rate
+    int sides;                       // bit k: side k (x-lo, x-hi, y-lo, y-hi) is a far field
+    double drho, ux;                 // target state: rho_ref - 1 and the free-stream velocity
+};
+
 struct Domain {
     int nxd, nyd;          // domain size in cells of this level
     int bc[4];
@@ -82,10 +89,7 @@ struct StepArgs {
     int wall_blocks, tile_blocks;    // k_step grid: wall-node blocks of WALL_PER_BLOCK nodes
                                      // (a multiple of 8 blocks),
                                      // tile blocks (a multiple of 8), then edge-cell blocks
-    // absorbing layer of level 0 (sp_width = 0 elsewhere): sides bit k = bc[k] is a far field
-    double sp_width, sp_strength;
-    int sp_sides;
-    double sp_drho, sp_ux;           // target state: rho_ref - 1, u_ref
+    Absorber sp;                     // absorbing layer (level 0 only; width 0 elsewhere)
     const ST* fcoarse; Box cbox;     // parent level populations (ghost transfer)
     const CT* cmac;  const CT* cchi; // parent level rho, u and chi of the current parent step
     CT* rmac;        CT* rchi;       // parent level buffers of the next parent step (restriction)
@@ -126,6 +130,8 @@ struct InitArgs {
     void* f; void* mac; void* chi_a; void* chi_b;
     long plane;
     double nu, fx, fy, omega_b;
+    int pitch, gx0, gy0, nxd, nyd;   // storage box origin and domain size (absorbing layer)
+    Absorber sp;
 };
 
 struct SurfaceArgs {

@@ -263,9 +263,14 @@ __device__ T sa_update(const T nt[9], const T u[9], const T v[9], T nu, T d, int
                          T(0.5) * uc * vc * (nt[8] - nt[6] - nt[2] + nt[0]) +
                          vc * vc * (N - T(2) * C + S));
     }
-    const T mC = sa_mu(C, nu);
-    const T diff = T(0.5) * (mC + sa_mu(E, nu)) * (E - C) - T(0.5) * (mC + sa_mu(W, nu)) * (C - W) +
-                   T(0.5) * (mC + sa_mu(N, nu)) * (N - C) - T(0.5) * (mC + sa_mu(S, nu)) * (C - S) +
+    // face diffusivity capped at 0.2 sigma: the explicit update is stable only while
+    // (1/sigma) sum_faces mu <= 1, which a large eddy viscosity on a fine level
+    // exceeds; below the cap the scheme is unchanged
+    const T mC = sa_mu(C, nu), cap = T(0.2 * SIGMA);
+    const T diff = dmin(T(0.5) * (mC + sa_mu(E, nu)), cap) * (E - C) -
+                   dmin(T(0.5) * (mC + sa_mu(W, nu)), cap) * (C - W) +
+                   dmin(T(0.5) * (mC + sa_mu(N, nu)), cap) * (N - C) -
+                   dmin(T(0.5) * (mC + sa_mu(S, nu)), cap) * (C - S) +
                    T(CB2) * (dX * dX + dY * dY);
     return C + conv + (P - D) + diff * T(1.0 / SIGMA);
 }
@@ -481,21 +486,25 @@ __device__ __forceinline__ void relax_cell(const StepArgs<ST, CT>& a, CT s[9], C
 // off): within sp_width cells of a far-field side the post-collision
 // populations relax towards the free-stream equilibrium with
 // sigma = sp_strength ((W - d) / W)^2, d the distance of the cell centre.
-template <class ST, class CT>
-__device__ __forceinline__ void absorb(const StepArgs<ST, CT>& a, int gx, int gy, CT s[9]) {
-    if (!(a.sp_width > 0.0)) return;
+template <class CT>
+__device__ __forceinline__ void absorb(const Absorber& sp, int nxd, int nyd, int gx, int gy, CT s[9]) {
+    if (!(sp.width > 0.0)) return;
     double d = 1e300;
-    if (a.sp_sides & 1) d = fmin(d, gx + 0.5);
-    if (a.sp_sides & 2) d = fmin(d, a.dom.nxd - gx - 0.5);
-    if (a.sp_sides & 4) d = fmin(d, gy + 0.5);
-    if (a.sp_sides & 8) d = fmin(d, a.dom.nyd - gy - 0.5);
-    if (!(d < a.sp_width)) return;
-    const double x = (a.sp_width - d) / a.sp_width;
-    const CT sg = CT(a.sp_strength * x * x);
+    if (sp.sides & 1) d = fmin(d, gx + 0.5);
+    if (sp.sides & 2) d = fmin(d, nxd - gx - 0.5);
+    if (sp.sides & 4) d = fmin(d, gy + 0.5);
+    if (sp.sides & 8) d = fmin(d, nyd - gy - 0.5);
+    if (!(d < sp.width)) return;
+    const double x = (sp.width - d) / sp.width;
+    const CT sg = CT(sp.strength * x * x);
     CT t[9];
-    equilibrium<CT>(t, CT(a.sp_drho), CT(a.sp_ux), CT(0));
+    equilibrium<CT>(t, CT(sp.drho), CT(sp.ux), CT(0));
 #pragma unroll
     for (int i = 0; i < 9; ++i) s[i] = s[i] - sg * (s[i] - t[i]);
+}
+template <class ST, class CT>
+__device__ __forceinline__ void absorb(const StepArgs<ST, CT>& a, int gx, int gy, CT s[9]) {
+    absorb<CT>(a.sp, a.dom.nxd, a.dom.nyd, gx, gy, s);
 }
 
 // relax_cell, the absorbing layer and plain stores of the new state (wall
@@ -954,6 +963,7 @@ __global__ void k_init(const InitArgs a) {
     const CT nu = CT(a.nu);
     const CT omega = CT(1) / (CT(3) * (nu + eddy_viscosity(chi, nu)) + CT(0.5));
     collide(s, drho, ux, uy, omega, CT(a.omega_b), CT(a.fx), CT(a.fy));
+    absorb<CT>(a.sp, a.nxd, a.nyd, (int)(c % a.pitch) + a.gx0, (int)(c / a.pitch) + a.gy0, s);
     ST* f = (ST*)a.f;
     for (int i = 0; i < 9; ++i) Cv<ST, CT>::st(f + i * a.plane + c, s[i]);
 }

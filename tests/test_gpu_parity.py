@@ -143,16 +143,23 @@ def test_graph_replay_matches_direct_launches(storage):
     dict(outlet=LI.OUTLET_EXTRAP1),
     dict(outlet=LI.OUTLET_PRESSURE),
     dict(sponge_width=0.0),
+    dict(ramp_steps=3.0),                        # start-up ramp over the first 3 steps
 ])
 def test_airfoil_small_variants_fp64(variant):
     case = LI.case_airfoil_small()
     case.update(variant)
     o, g = _pair(case, "f64")
-    o.advance(4)
-    g.advance(4)
+    # from rest (start-up ramp) the flow needs ~100 coarse steps to reach the body;
+    # until then u at R is round-off noise, u_tau about its square root and
+    # chi_B = kappa u_tau d_WB / nu noise-sized, so the comparison waits for the flow
+    # and allows chi the size of that early noise
+    ramped = "ramp_steps" in variant
+    steps = 150 if ramped else 4
+    o.advance(steps)
+    g.advance(steps)
     assert U.velocity_error(g, o, case["n_levels"]) < 1e-10
     err = U.field_errors(g, o, case["n_levels"], names=("chi",))
-    assert max(err.values()) < 1e-10, err
+    assert max(err.values()) < (1e-7 if ramped else 1e-10), err
     assert U.density_error(g, o, case["n_levels"]) < 1e-12
     lf = case["n_levels"] - 1
     np.testing.assert_allclose(g.wall(lf)[:, 8], o.wall(lf)[:, 8], rtol=1e-10)

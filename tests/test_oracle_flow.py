@@ -345,3 +345,16 @@ def test_absorbing_layer_keeps_the_free_stream_and_damps_a_pressure_pulse():
         s.advance(400)
         return float(np.sum((s.field(0, oracle.F_RHO) - 1.0) ** 2))
     assert pulse_energy(12.0) < 1e-2 * pulse_energy(0.0)
+
+
+def test_start_up_ramp_of_the_inlet_velocity():
+    """Start-up ramp: the flow starts at rest and coarse step n imposes
+    U (1 - cos(pi n / N)) / 2 at the inlet (n counted from 0), U from step N on."""
+    c = box_case(32, 16, bc=(LI.BC_INLET, LI.BC_OUTLET, LI.BC_SYMMETRY, LI.BC_SYMMETRY),
+                 outlet=LI.OUTLET_EXTRAP1, u_ref=0.05, nu0=0.01, ramp_steps=4.0)
+    s = oracle.Sim(c)
+    assert np.all(s.field(0, oracle.F_UX) == 0.0)
+    for n in range(6):
+        s.advance(1)
+        expect = 0.05 * (0.5 - 0.5 * math.cos(math.pi * min(n, 4) / 4.0))
+        np.testing.assert_allclose(s.field(0, oracle.F_UX)[:, 0], expect, rtol=0, atol=1e-15)

@@ -153,3 +153,16 @@ def test_idw_exact_for_constants_and_at_nodes():
     assert oracle.idw_point(px, py, v, px[2], py[2]) == v[2]
     got = oracle.idw_point(px, py, v, 0.1, 0.2)
     assert v.min() <= got <= v.max()
+
+
+@pytest.mark.parametrize("chi", [10.0, 1e3, 1e5, 1e7])
+def test_explicit_diffusion_stays_within_the_stencil_at_any_eddy_viscosity(chi):
+    """Pure diffusion (no velocity, wall far away) of a centre value below its four
+    face neighbours: the update must not overshoot them, whatever the diffusivity,
+    so the face diffusivity is bounded (0.2 sigma per face)."""
+    nu, d = 1e-4, 1e12
+    hi = chi * nu
+    nt = np.full(9, hi)
+    nt[4] = 0.5 * hi
+    new = oracle.sa_cell(nt, np.zeros(9), np.zeros(9), nu, d, 1)
+    assert 0.5 * hi < new <= hi
