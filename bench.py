@@ -103,6 +103,9 @@ def main():
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the FP16 / BF16 storage runs reported beside the main line")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--workload", default="airfoil", choices=["airfoil", "three_element"],
+                    help="airfoil: the benchmark line (8 levels, 2.0M cells); three_element: the "
+                         "19.4M-cell high-lift case (cycle time per step, run past its start-up ramp)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -117,8 +120,13 @@ def main():
     import lbr_inputs as LI
     import paper_2601_18443_amd as P
 
-    case = LI.case_airfoil_cfg1()
-    log("building the 8-level airfoil grid on the GPU")
+    if args.workload == "three_element":
+        case = LI.case_three_element()
+        args.warmup = max(args.warmup, int(case["ramp_steps"]) + 10)
+        args.no_cpu_baseline = True
+    else:
+        case = LI.case_airfoil_cfg1()
+    log(f"building the {case['n_levels']}-level {args.workload} grid on the GPU")
     t0 = time.perf_counter()
     sim = P.Solver(case, storage=args.storage)
     sim.synchronize()
@@ -210,9 +218,12 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1000 * dt / args.steps, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": {"f32": "f32", "f16": "f16-store/f32", "bf16": "bf16-store/f32", "f64": "f64"}[args.storage],
-        "data": "synthetic (seeded airfoil-like polyline)",
-        "config": {"workload": "single airfoil-like body, 8 levels c/8..c/1024, 40c domain, "
-                               "Re 6e6, M 0.15, AoA 10 deg",
+        "data": "synthetic (seeded airfoil-like polylines)",
+        "config": {"workload": ("single airfoil-like body, 8 levels c/8..c/1024, 40c domain, "
+                                "Re 6e6, M 0.15, AoA 10 deg") if args.workload == "airfoil" else
+                               ("three-element high-lift-like configuration (slat, main, flap; "
+                                "30 deg deflections), 8 levels c/32..c/4096, 40c domain, Re 9e6, "
+                                "M 0.2, AoA 8 deg, after the start-up ramp"),
                    "cells": n_cells,
                    "finest_cells": finest["n_fluid"], "lups_per_step": lups,
                    "storage": args.storage, "graph": bool(args.graph)},

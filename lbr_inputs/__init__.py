@@ -200,12 +200,14 @@ def _min_distance(a: np.ndarray, b: np.ndarray) -> float:
 
 
 def three_element_polylines(seed: int = 0, n_side: int = 1024, alpha_deg: float = 8.0,
-                            deflection_deg: float = 30.0, gap: float = 0.02):
+                            deflection_deg: float = 30.0, gap: float = 0.02,
+                            thickness=(0.16, 0.15, 0.15)):
     """Seeded slat, main element and flap (stand-in for the MD-30P30N of Section 3.2).
 
-    Main element: chord 0.8, 12 % thick, seeded camber in [0.02, 0.05].  Slat
-    chord 0.15 and flap chord 0.30 (each +-10 %, seeded), 10 % and 12 % thick,
-    both deflected by ``deflection_deg`` (slat nose down about its trailing
+    Main element: chord 0.8, seeded camber in [0.02, 0.05].  Slat chord 0.15 and
+    flap chord 0.30 (each +-10 %, seeded); thicknesses (slat, main, flap) 16, 15
+    and 15 % (blunt leading edges keep the suction peaks within the lattice Mach
+    range of D2Q9); both deflected by ``deflection_deg`` (slat nose down about its trailing
     edge, flap trailing edge down about its leading edge) and placed with
     ``gap`` clearance; the assembly is rotated by -alpha about (0.25, 0).  Each
     element is a closed CCW polyline of 2 * n_side points.  The smallest
@@ -215,9 +217,10 @@ def three_element_polylines(seed: int = 0, n_side: int = 1024, alpha_deg: float 
     camber = rng.uniform(0.02, 0.05)
     cs = 0.15 * rng.uniform(0.9, 1.1)
     cf = 0.30 * rng.uniform(0.9, 1.1)
-    main = 0.8 * airfoil_polyline(seed, n_side=n_side, thickness=0.12, camber=camber)
-    slat = cs * airfoil_polyline(seed + 1, n_side=n_side, thickness=0.10, camber=0.03)
-    flap = cf * airfoil_polyline(seed + 2, n_side=n_side, thickness=0.12, camber=0.03)
+    ts, tm, tf = thickness
+    main = 0.8 * airfoil_polyline(seed, n_side=n_side, thickness=tm, camber=camber)
+    slat = cs * airfoil_polyline(seed + 1, n_side=n_side, thickness=ts, camber=0.03)
+    flap = cf * airfoil_polyline(seed + 2, n_side=n_side, thickness=tf, camber=0.03)
     # slat: nose down about its trailing edge (cs, 0); flap: trailing edge down about (0, 0)
     slat = rotate(slat, -deflection_deg, pivot=(cs, 0.0))
     flap = rotate(flap, deflection_deg, pivot=(0.0, 0.0))
@@ -242,7 +245,7 @@ def three_element_polylines(seed: int = 0, n_side: int = 1024, alpha_deg: float 
 def case_three_element(seed: int = 0, finest_cells_per_chord: int = 4096, n_levels: int = 8,
                        domain_chords: float = 40.0, band_finest: float = 0.165,
                        mach: float = 0.2, reynolds: float = 9e6, alpha_deg: float = 8.0,
-                       n_side: int = 1024):
+                       n_side: int = 1024, thickness=(0.16, 0.15, 0.15)):
     """Three-element high-lift-like configuration: Re 9e6, Mach 0.2, 8 degrees,
     finest c/4096 in a 40-chord domain, 8 levels from c/32 (the distance bands of
     more levels would leave the domain)."""
@@ -250,7 +253,8 @@ def case_three_element(seed: int = 0, finest_cells_per_chord: int = 4096, n_leve
                         n_levels=n_levels, domain_chords=domain_chords, band_finest=band_finest,
                         mach=mach, reynolds=reynolds, alpha_deg=alpha_deg, n_side=16)
     case.update(name="three_element", ramp_steps=1000.0, ramp_start=0.25,
-                bodies=three_element_polylines(seed, n_side=n_side, alpha_deg=alpha_deg))
+                bodies=three_element_polylines(seed, n_side=n_side, alpha_deg=alpha_deg,
+                                               thickness=thickness))
     return case
 
 

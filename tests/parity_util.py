@@ -65,10 +65,18 @@ def velocity_error(g, o, n_levels):
     return np.sqrt(num / den)
 
 
-def structure_mismatch(g, o, n_levels):
-    """Returns a list of differences in the grid and wall data built independently by both."""
+def structure_mismatch(g, o, n_levels, nx0=None):
+    """Returns a list of differences in the grid and wall data built independently by both.
+
+    Integers must agree exactly.  Positions, distances and link fractions are FP64
+    values computed from lattice coordinates of up to the level's domain size L
+    cells, so both codes round them at about L * 2^-52; they must agree within
+    16 of those units (and 1e-11 at least).
+    """
     bad = []
     for l in range(n_levels):
+        size = (nx0 or 0) << l
+        tol = max(1e-11, 16 * size * 2.0**-52)
         gi, oi = g.level_info(l), o.level_info(l)
         for k, gk in (("gx0", "gx0"), ("gy0", "gy0"), ("nx", "nx"), ("ny", "ny"),
                       ("n_fluid", "n_fluid"), ("n_bnodes", "n_wall_nodes"),
@@ -84,7 +92,7 @@ def structure_mismatch(g, o, n_levels):
             bad.append((l, "type", int(np.sum(to != tg))))
         do, dg = o.field(l, oracle.F_DIST), g.field(l, 6)
         m = np.isfinite(do) & (do < 1e200)
-        if not np.allclose(do[m], dg[m], rtol=1e-12, atol=1e-12):
+        if not np.allclose(do[m], dg[m], rtol=1e-12, atol=tol):
             bad.append((l, "dist", float(np.max(np.abs(do[m] - dg[m])))))
         wo, wg = o.wall(l), g.wall(l)
         if len(wo) != len(wg):
@@ -94,10 +102,10 @@ def structure_mismatch(g, o, n_levels):
             if not np.array_equal(wo[:, :2], wg[:, :2]):
                 bad.append((l, "wall cells"))
             for cols, name in (((2, 3), "IW"), ((4, 5), "normal"), ((6,), "d_WB")):
-                if not np.allclose(wo[:, cols], wg[:, cols], rtol=1e-11, atol=1e-11):
+                if not np.allclose(wo[:, cols], wg[:, cols], rtol=1e-11, atol=tol):
                     bad.append((l, name, float(np.max(np.abs(wo[:, cols] - wg[:, cols])))))
             if not np.array_equal(wo[:, 19:27] < 0, wg[:, 19:27] < 0):
                 bad.append((l, "cut links"))
-            elif not np.allclose(wo[:, 19:27], wg[:, 19:27], rtol=1e-11, atol=1e-11):
+            elif not np.allclose(wo[:, 19:27], wg[:, 19:27], rtol=1e-11, atol=tol):
                 bad.append((l, "q", float(np.max(np.abs(wo[:, 19:27] - wg[:, 19:27])))))
     return bad
