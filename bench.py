@@ -92,6 +92,90 @@ def copy_calibration(nbytes=1 << 30):
     print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "dispatches": 3}))
 
 
+def run_sweep(args):
+    """Batched angle-of-attack sweep: 16 seeded cases (alpha -4..16 deg, 3-5 levels,
+    finest c/512, 0.5M-3.4M cells each, 27M in all) advanced by shared launches, one
+    super step taking case k through 2^(5 - L_k) coarse steps; against the same cases
+    advanced one after another with the same number of steps each."""
+    import torch
+    import lbr_inputs as LI
+    import paper_2601_18443_amd as P
+
+    cases = [LI.case_sweep(k) for k in range(16)]
+    log("building the 16 sweep grids on the GPU")
+    t0 = time.perf_counter()
+    sims = [P.Solver(c, storage=args.storage) for c in cases]
+    for s in sims:
+        s.synchronize()
+    log(f"build {time.perf_counter() - t0:.1f} s")
+    n_cells = int(sum(s.level_info(l)["n_fluid"] for s, c in zip(sims, cases) for l in range(c["n_levels"])))
+    batch = P.Batch(sims)
+    per = [batch.steps_per_super_step(k) for k in range(len(cases))]
+    lups = batch.lups_per_super_step()
+    lmax = max(c["n_levels"] for c in cases)
+    launches = 2 ** lmax - 1
+    if args.graph:
+        batch.use_graph(True)
+    log(f"{n_cells} cells, {lups} cell updates per super step ({launches} launches); warmup {args.warmup}")
+    batch.advance(args.warmup)
+    batch.synchronize()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch.advance(args.steps)
+    batch.synchronize()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    batch.profile(True)
+    batch.advance(args.steps)
+    batch.synchronize()
+    kt = batch.profile(False)
+    batch.close()
+    log(f"batched: {args.steps} super steps in {dt:.3f} s; k_step_batch {kt[0]:.2f} us/launch, "
+        f"finest {kt[1]:.2f}, level 0 {kt[2]:.2f}")
+    # the same cases one after another, each with its own graph
+    seq = 0.0
+    for s, p in zip(sims, per):
+        if args.graph:
+            s.use_graph(True)
+        s.advance(2 * p)
+        s.synchronize()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.advance(args.steps * p)
+        s.synchronize()
+        torch.cuda.synchronize()
+        seq += time.perf_counter() - t0
+    log(f"one after another: {seq:.3f} s")
+    finite = all(np.all(np.isfinite(s.forces())) for s in sims)
+    mlups = lups * args.steps / dt / 1e6
+    bytes_per_launch = ALG_BYTES[args.storage] * lups / launches
+    roof = None
+    if kt[0] > 0:
+        achieved = bytes_per_launch / (kt[0] * 1e-6) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_step_batch (all virtual levels)", "avg_launch_us": round(kt[0], 3),
+                "finest_level_avg_launch_us": round(kt[1], 3), "level0_avg_launch_us": round(kt[2], 3),
+                "alg_bytes_per_launch": round(bytes_per_launch, 0)}
+    out = {
+        "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1000 * dt / args.steps, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"f32": "f32", "f16": "f16-store/f32", "bf16": "bf16-store/f32", "f64": "f64"}[args.storage],
+        "data": "synthetic (seeded airfoil-like polylines)",
+        "config": {"workload": "batched sweep: 16 airfoil-like cases, AoA -4..16 deg, 3-5 levels to c/512, "
+                               "Re 6e6, M 0.15; a step is one super step (2^(5 - L_k) coarse steps of case k)",
+                   "cells": n_cells, "lups_per_step": lups, "coarse_steps_per_super_step": per,
+                   "storage": args.storage, "graph": bool(args.graph)},
+        "roofline": roof, "cpu_baseline": None,
+        "one_after_another": {"value": round(lups * args.steps / seq / 1e6, 1), "unit": "MLUPS",
+                              "ms_per_step": round(1000 * seq / args.steps, 4)},
+        "batched_over_one_after_another": round(seq / dt, 3),
+        "finite": bool(finite),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,9 +187,10 @@ def main():
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the FP16 / BF16 storage runs reported beside the main line")
     ap.add_argument("--copy-calibration", action="store_true")
-    ap.add_argument("--workload", default="airfoil", choices=["airfoil", "three_element"],
+    ap.add_argument("--workload", default="airfoil", choices=["airfoil", "three_element", "sweep"],
                     help="airfoil: the benchmark line (8 levels, 2.0M cells); three_element: the "
-                         "19.4M-cell high-lift case (cycle time per step, run past its start-up ramp)")
+                         "19.4M-cell high-lift case (cycle time per step, run past its start-up ramp); "
+                         "sweep: 16 cases in shared launches against the same cases one after another")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -114,6 +199,9 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.workload == "sweep":
+        run_sweep(args)
         return
 
     import torch

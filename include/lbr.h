@@ -258,6 +258,70 @@ const char* lbr_last_error(const lbr_ctx* ctx);
 /* Frees every device and host resource of the context (NULL is allowed). */
 void lbr_destroy(lbr_ctx* ctx);
 
+/* ---------------------------------------------------------------------------
+   Batched sweep: several cases of one study advanced by shared launches.  The
+   studies of Section 3 run one configuration at several angles of attack
+   (Sections 3.1.1 and 3.2) and on several grids with different numbers of
+   refinement levels (Section 3.1.3, Table 1); each case on its own fills
+   only a fraction of the GPU at its coarse levels.  The cases are aligned on their finest level:
+   virtual level v of the batch is level v - (lmax - L_k) of case k, so one
+   super step advances case k by 2^(lmax - L_k) of its coarse steps and each
+   launch of k_step covers the same virtual level of every case (one grid split
+   into per-case parts).  The numbers each case computes are identical to
+   advancing it alone.
+   --------------------------------------------------------------------------- */
+typedef struct lbr_batch lbr_batch;
+
+/* Groups n distinct built contexts of the same storage precision on one device
+   (a context listed twice, a NULL one or mixed precisions: LBR_ERR_INVALID_ARG).
+   The batch launches on the first context's stream; the contexts' pending work
+   is synchronised here.  Cases still inside a start-up ramp are refused
+   (LBR_ERR_STATE).  The batch borrows the contexts (destroy the batch first)
+   and allocates its launch tables through the first context's allocator.
+   Returns 0 or a negative code; on failure *out may still hold a batch that
+   carries the message (lbr_batch_last_error) and must be destroyed. */
+int lbr_batch_create(int32_t n, lbr_ctx* const* cases, lbr_batch** out);
+
+/* Enqueues n super steps on the batch stream (asynchronous).  Work already
+   queued on the contexts' own streams runs first, and work queued there later
+   waits for the super steps.  A case may also be advanced on its own between
+   batch calls by an even number of coarse steps; after an odd number the
+   batch refuses to run (LBR_ERR_STATE) because its launch tables address the
+   other level-0 buffer. */
+int lbr_batch_advance(lbr_batch* batch, int64_t n_super_steps);
+
+/* Super steps until the residual of every case (lbr_residual, evaluated every
+   check_every super steps) drops below tol, or max_super_steps.  A case whose
+   residual is below tol leaves the launches, so the others run on without its
+   cell updates; at return the batch covers every case again.  steps_done[k]
+   receives the coarse steps case k took and residual[k] its last residual
+   (arrays of n entries, either may be NULL).  Returns LBR_ERR_DIVERGED if a
+   case's state becomes non-finite. */
+int lbr_batch_run_to_steady(lbr_batch* batch, double tol, int64_t max_super_steps, int64_t check_every,
+                            int64_t* steps_done, double* residual);
+
+/* Replays two super steps from one HIP graph (enable != 0) or launches
+   directly (enable == 0). */
+int lbr_batch_use_graph(lbr_batch* batch, int32_t enable);
+
+/* As lbr_profile, for the batched launches: out[0] all launches, out[1] the
+   launches of the finest virtual level, out[2] virtual level 0, out[3] 0. */
+int lbr_batch_profile(lbr_batch* batch, int32_t enable, double out[4]);
+
+/* Waits for the batch stream; afterwards every per-context call (fields,
+   forces, residual) sees the advanced state. */
+int lbr_batch_synchronize(lbr_batch* batch);
+
+/* Coarse steps case k takes per super step (2^(lmax - L_k), with lmax the
+   most levels of any case). */
+int64_t lbr_batch_steps_per_super_step(const lbr_batch* batch, int32_t k);
+
+/* Cell updates of all cases per super step. */
+int64_t lbr_batch_lups_per_super_step(lbr_batch* batch);
+
+const char* lbr_batch_last_error(const lbr_batch* batch);
+void lbr_batch_destroy(lbr_batch* batch);
+
 #ifdef __cplusplus
 }
 #endif

@@ -258,6 +258,50 @@ def case_three_element(seed: int = 0, finest_cells_per_chord: int = 4096, n_leve
     return case
 
 
+def _estimate_cells(S: float, D0: float, L: int, finest: int) -> float:
+    """Rough fluid-cell count of a single 12 %-thick body in an S x S domain with
+    distance bands D0 2^(L-1-l) (Steiner area of each band region)."""
+    perim, area = 2.05, 0.08
+
+    def region(D):
+        return area + perim * D + np.pi * D * D
+    total = 0.0
+    for l in range(L):
+        dx = 2.0 ** (L - 1 - l) / finest
+        outer = S * S if l == 0 else region(D0 * 2 ** (L - 1 - l))
+        inner = region(D0 * 2 ** (L - 2 - l)) if l + 1 < L else area
+        total += max(outer - inner, 0.0) / (dx * dx)
+    return total
+
+
+def case_sweep(k: int, seed: int = 0, finest_cells_per_chord: int = 512):
+    """Case k (0..15) of the batched angle-of-attack sweep: its own seeded body,
+    alpha = -4 + 4k/3 degrees, 3 + (k mod 3) levels, finest c/512, and a domain
+    width S in [8c, 20c] and finest band D0 in [0.25c, 1c] chosen so that the
+    estimated cell count is closest to a seeded target drawn log-uniformly in
+    [0.5M, 4M] (the level-1 band must stay clear of the absorbing layer)."""
+    rng = np.random.default_rng(5000 + seed)
+    targets = np.exp(rng.uniform(np.log(0.5e6), np.log(4e6), size=16))
+    L = 3 + (k % 3)
+    alpha = -4.0 + 4.0 * k / 3.0
+    best = None
+    for S in np.linspace(8.0, 20.0, 49):
+        dx0 = 2.0 ** (L - 1) / finest_cells_per_chord
+        for D0 in np.linspace(0.25, 1.0, 31):
+            band1 = D0 * 2 ** (L - 2)
+            if band1 + 0.5 > 0.425 * S - 4 * dx0 * 2:
+                continue
+            err = abs(np.log(_estimate_cells(S, D0, L, finest_cells_per_chord) / targets[k]))
+            if best is None or err < best[0]:
+                best = (err, S, D0)
+    _, S, D0 = best
+    case = case_airfoil(seed=100 + seed * 16 + k, finest_cells_per_chord=finest_cells_per_chord,
+                        n_levels=L, domain_chords=float(S), band_finest=float(D0),
+                        alpha_deg=alpha, n_side=512)
+    case.update(name=f"sweep{k}", target_cells=float(targets[k]))
+    return case
+
+
 def case_airfoil_cfg1(seed: int = 0):
     """Single body, FP32: Re 6e6, Mach 0.15, 10 deg, finest c/1024, 40-chord domain."""
     return case_airfoil(seed=seed)

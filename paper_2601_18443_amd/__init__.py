@@ -83,6 +83,21 @@ def lib():
         L.lbr_last_error.restype = C.c_char_p
         L.lbr_destroy.argtypes = [p]
         L.lbr_destroy.restype = None
+        L.lbr_batch_create.argtypes = [i32, C.POINTER(p), C.POINTER(p)]
+        L.lbr_batch_advance.argtypes = [p, i64]
+        L.lbr_batch_use_graph.argtypes = [p, i32]
+        L.lbr_batch_run_to_steady.argtypes = [p, C.c_double, i64, i64, C.POINTER(i64),
+                                              C.POINTER(C.c_double)]
+        L.lbr_batch_profile.argtypes = [p, i32, C.POINTER(C.c_double)]
+        L.lbr_batch_synchronize.argtypes = [p]
+        L.lbr_batch_steps_per_super_step.argtypes = [p, i32]
+        L.lbr_batch_steps_per_super_step.restype = i64
+        L.lbr_batch_lups_per_super_step.argtypes = [p]
+        L.lbr_batch_lups_per_super_step.restype = i64
+        L.lbr_batch_last_error.argtypes = [p]
+        L.lbr_batch_last_error.restype = C.c_char_p
+        L.lbr_batch_destroy.argtypes = [p]
+        L.lbr_batch_destroy.restype = None
         _lib = L
     return _lib
 
@@ -258,3 +273,68 @@ class Solver:
         cur = 1 if enable else 0
         self._check(lib().lbr_profile(self.h, cur, _dp(out)))
         return out
+
+
+class Batch:
+    """lbr_batch over several Solver objects of the same storage precision.
+
+    Super steps run on the first solver's stream; reads through any solver are
+    ordered after them.  A solver may be advanced on its own between batch
+    calls by an even number of coarse steps.  Close the batch before the
+    solvers.
+    """
+
+    def __init__(self, solvers):
+        L = lib()
+        self.solvers = list(solvers)
+        arr = (C.c_void_p * len(self.solvers))(*[s.h.value for s in self.solvers])
+        h = C.c_void_p()
+        rc = L.lbr_batch_create(len(self.solvers), arr, C.byref(h))
+        self.h = h if h.value else None
+        if rc != 0:
+            msg = L.lbr_batch_last_error(self.h).decode() if self.h else ""
+            self.close()
+            raise LbrError(f"lbr_batch_create failed ({rc}) {msg}")
+
+    def _check(self, rc):
+        if rc != 0:
+            raise LbrError(f"liblbr batch error {rc}: {lib().lbr_batch_last_error(self.h).decode()}")
+
+    def advance(self, n_super_steps):
+        self._check(lib().lbr_batch_advance(self.h, int(n_super_steps)))
+
+    def use_graph(self, enable=True):
+        self._check(lib().lbr_batch_use_graph(self.h, 1 if enable else 0))
+
+    def run_to_steady(self, tol, max_super_steps, check_every=100):
+        """Returns (coarse steps taken per case, last residual per case)."""
+        n = len(self.solvers)
+        steps, res = (C.c_int64 * n)(), (C.c_double * n)()
+        self._check(lib().lbr_batch_run_to_steady(self.h, float(tol), int(max_super_steps),
+                                                  int(check_every), steps, res))
+        return [int(v) for v in steps], [float(v) for v in res]
+
+    def profile(self, enable=True):
+        out = (C.c_double * 4)()
+        self._check(lib().lbr_batch_profile(self.h, 1 if enable else 0, out))
+        return [float(v) for v in out]
+
+    def synchronize(self):
+        self._check(lib().lbr_batch_synchronize(self.h))
+
+    def steps_per_super_step(self, k):
+        return int(lib().lbr_batch_steps_per_super_step(self.h, k))
+
+    def lups_per_super_step(self):
+        return int(lib().lbr_batch_lups_per_super_step(self.h))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().lbr_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -4,6 +4,7 @@
 #include "lbr_impl.h"
 
 #include <algorithm>
+#include <new>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -1416,7 +1417,9 @@ int lbr_residual(lbr_ctx* c, double* residual) {
     } else {
         *residual = std::sqrt(du / uu) / (double)c->resid_steps;
     }
-    if (!std::isfinite(du) || !std::isfinite(uu))
+    // the first call compares against a snapshot that does not exist yet (the
+    // buffer holds whatever the allocator returned): only the state counts
+    if (!std::isfinite(uu) || (c->resid_init && !std::isfinite(du)))
         return set_err(c, LBR_ERR_DIVERGED, "non-finite velocity field");
     c->resid_init = true;
     c->resid_steps = 0;
@@ -1482,6 +1485,395 @@ void lbr_destroy(lbr_ctx* c) {
         else (void)hipFree(p);
     }
     delete c;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Batched sweep: several cases advanced by shared launches
+// ===========================================================================
+struct lbr_batch {
+    std::vector<lbr_ctx*> all;         // the cases, in the caller's order
+    std::vector<lbr_ctx*> cases;       // the cases the launch tables cover
+    int lmax = 0;
+    Prec prec = P_F32;
+    hipStream_t stream = nullptr;
+    size_t args_size = 0;
+    struct Launch { int part0, nparts, nblocks, v; };
+    std::vector<Launch> launches;      // the launches of two super steps, in order
+    int per_super = 0;                 // launches per super step
+    void* parts_dev = nullptr;         // StepArgs of every part of every launch
+    int* start_dev = nullptr;          // first block of each part, relative to its launch
+    int parity = 0;                    // super steps advanced since the tables were built, modulo 2
+    std::vector<int> cur0;             // level-0 buffer index of each covered case at parity 0
+    std::vector<hipEvent_t> ev;        // ordering between the case streams and the batch stream
+    bool use_graph = false;
+    bool ready = false;                // launch tables built and uploaded
+    hipGraphExec_t graph = nullptr;
+    bool prof = false;                 // start / stop events on every launch
+    std::vector<hipEvent_t> pev;
+    std::vector<int> pev_v;            // virtual level of each event pair
+    size_t pev_used = 0;
+    double prof_out[4] = {0, 0, 0, 0};
+    std::string err;
+};
+
+namespace {
+
+int bset_err(lbr_batch* b, int code, const char* msg) {
+    b->err = msg;
+    return code;
+}
+
+// Virtual level v of the batch is level v - (lmax - L_k) of case k: every case's
+// finest level is stepped by the same launches, and a case with fewer levels
+// takes 2^(lmax - L_k) of its coarse steps per super step.
+void batch_schedule(lbr_batch* b, int v, int substep, std::vector<std::pair<int, int>>& seq) {
+    if (v + 1 < b->lmax) {
+        batch_schedule(b, v + 1, 1, seq);
+        batch_schedule(b, v + 1, 2, seq);
+    }
+    seq.push_back({v, substep});
+}
+
+// Launch tables of two super steps for the covered cases, from their current
+// state: the host replays the buffer flips each launch makes, and two super
+// steps bring every buffer index back.
+int batch_build(lbr_batch* b) {
+    std::vector<std::pair<int, int>> seq;
+    batch_schedule(b, 0, 0, seq);
+    b->per_super = (int)seq.size();
+    std::vector<unsigned char> parts;
+    std::vector<int> starts;
+    b->launches.clear();
+    alignas(16) unsigned char buf[sizeof(StepArgs<double, double>)];
+    for (int rep = 0; rep < 2; ++rep)
+        for (const auto& vs : seq) {
+            lbr_batch::Launch ln{(int)starts.size(), 0, 0, vs.first};
+            for (lbr_ctx* c : b->cases) {
+                const int l = vs.first - (b->lmax - (int)c->lv.size());
+                if (l < 0) continue;
+                Level& L = c->lv[l];
+                const int sub = l == 0 ? 0 : vs.second;       // a case's level 0 has no parent
+                int wb = 0, tb = 0;
+                switch (c->prec) {
+                    case P_F64: { auto& a = *reinterpret_cast<StepArgs<double, double>*>(buf);
+                        fill_step_args(c, l, sub, a); wb = a.wall_blocks; tb = a.tile_blocks; break; }
+                    case P_F32: { auto& a = *reinterpret_cast<StepArgs<float, float>*>(buf);
+                        fill_step_args(c, l, sub, a); wb = a.wall_blocks; tb = a.tile_blocks; break; }
+                    case P_F16: { auto& a = *reinterpret_cast<StepArgs<__half, float>*>(buf);
+                        fill_step_args(c, l, sub, a); wb = a.wall_blocks; tb = a.tile_blocks; break; }
+                    default: { auto& a = *reinterpret_cast<StepArgs<__hip_bfloat16, float>*>(buf);
+                        fill_step_args(c, l, sub, a); wb = a.wall_blocks; tb = a.tile_blocks; break; }
+                }
+                // parts start on multiples of 8 blocks, so that each part's own
+                // block-to-XCD mapping holds inside the shared grid
+                const int eb = 8 * (((int)L.edge.size() + 8 * TILE_X * TILE_Y - 1) / (8 * TILE_X * TILE_Y));
+                parts.insert(parts.end(), buf, buf + b->args_size);
+                starts.push_back(ln.nblocks);
+                ln.nblocks += wb + tb + eb;
+                ln.nparts++;
+                L.cur ^= 1;                                   // as the launch will
+                if (l == 0) c->step_count++;
+            }
+            b->launches.push_back(ln);
+        }
+    for (lbr_ctx* c : b->cases) c->step_count -= 2 * (int64_t(1) << (b->lmax - (int)c->lv.size()));
+    lbr_ctx* c0 = b->all[0];
+    b->parts_dev = dalloc(c0, std::max<size_t>(parts.size(), 16));
+    b->start_dev = static_cast<int*>(dalloc(c0, std::max<size_t>(starts.size(), 1) * sizeof(int)));
+    if (!b->parts_dev || !b->start_dev) return bset_err(b, LBR_ERR_OOM, "batch tables: out of device memory");
+    if (hipMemcpy(b->parts_dev, parts.data(), parts.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->start_dev, starts.data(), starts.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+        return bset_err(b, LBR_ERR_HIP, "batch tables: copy failed");
+    b->ready = true;
+    return 0;
+}
+
+// Points the launch tables at a new set of cases (after the queued super steps
+// have finished with the old tables).
+int batch_cover(lbr_batch* b, const std::vector<lbr_ctx*>& cases) {
+    if (hipStreamSynchronize(b->stream) != hipSuccess) return bset_err(b, LBR_ERR_HIP, "synchronize failed");
+    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    b->graph = nullptr;
+    dfree(b->all[0], b->parts_dev);
+    dfree(b->all[0], b->start_dev);
+    b->parts_dev = nullptr;
+    b->start_dev = nullptr;
+    b->ready = false;
+    b->cases = cases;
+    b->lmax = 0;
+    b->cur0.clear();
+    for (lbr_ctx* c : cases) {
+        b->lmax = std::max(b->lmax, (int)c->lv.size());
+        b->cur0.push_back(c->lv[0].cur);
+    }
+    b->parity = 0;
+    return batch_build(b);
+}
+
+hipEvent_t* batch_prof_events(lbr_batch* b, int v) {
+    while (b->pev.size() < b->pev_used + 2) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        b->pev.push_back(e);
+        b->pev_v.push_back(0);
+    }
+    b->pev_v[b->pev_used] = v;
+    hipEvent_t* e = &b->pev[b->pev_used];
+    b->pev_used += 2;
+    return e;
+}
+
+int batch_super_step(lbr_batch* b) {
+    const int first = b->parity * b->per_super;
+    for (int k = 0; k < b->per_super; ++k) {
+        const lbr_batch::Launch& ln = b->launches[first + k];
+        const void* parts = static_cast<const unsigned char*>(b->parts_dev) + (size_t)ln.part0 * b->args_size;
+        Timing tm;
+        if (b->prof)
+            if (hipEvent_t* e = batch_prof_events(b, ln.v)) { tm.start = e[0]; tm.stop = e[1]; }
+        if (launch_step_batch(b->prec, parts, b->start_dev + ln.part0, ln.nparts, ln.nblocks, b->stream, tm) !=
+            hipSuccess)
+            return bset_err(b, LBR_ERR_HIP, "batched k_step launch failed");
+    }
+    return 0;
+}
+
+// Host bookkeeping after one super step: level 0 of a case with lmax levels
+// changes buffers; every case advanced 2^(lmax - L_k) coarse steps.
+void batch_account(lbr_batch* b) {
+    for (lbr_ctx* c : b->cases) {
+        const int off = b->lmax - (int)c->lv.size();
+        if (off == 0) c->lv[0].cur ^= 1;
+        c->step_count += int64_t(1) << off;
+        c->resid_steps += int64_t(1) << off;
+    }
+    b->parity ^= 1;
+}
+
+// Every case's level 0 must sit in the buffer the launch tables were built for:
+// a case advanced by an odd number of steps outside the batch would not.
+int batch_check(lbr_batch* b) {
+    for (size_t k = 0; k < b->cases.size(); ++k) {
+        const lbr_ctx* c = b->cases[k];
+        const int off = b->lmax - (int)c->lv.size();
+        if (c->lv[0].cur != (b->cur0[k] ^ (off == 0 ? b->parity : 0)))
+            return bset_err(b, LBR_ERR_STATE, "a case was advanced outside the batch by an odd number of steps");
+    }
+    return 0;
+}
+
+// The batch runs on the stream of its first case; work queued on the other
+// cases' streams before a batch call completes before it, and work queued on
+// them after it waits for it.
+int batch_wait_cases(lbr_batch* b) {
+    for (size_t k = 1; k < b->all.size(); ++k)
+        if (hipEventRecord(b->ev[k], b->all[k]->stream) != hipSuccess ||
+            hipStreamWaitEvent(b->stream, b->ev[k], 0) != hipSuccess)
+            return bset_err(b, LBR_ERR_HIP, "stream ordering failed");
+    return 0;
+}
+
+int batch_release_cases(lbr_batch* b) {
+    if (hipEventRecord(b->ev[0], b->stream) != hipSuccess) return bset_err(b, LBR_ERR_HIP, "stream ordering failed");
+    for (size_t k = 1; k < b->all.size(); ++k)
+        if (hipStreamWaitEvent(b->all[k]->stream, b->ev[0], 0) != hipSuccess)
+            return bset_err(b, LBR_ERR_HIP, "stream ordering failed");
+    return 0;
+}
+
+int batch_run(lbr_batch* b, int64_t n) {
+    int64_t k = 0;
+    if (b->use_graph && !b->prof && n >= 2) {
+        if (!b->graph) {
+            hipGraph_t g;
+            if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+                return bset_err(b, LBR_ERR_HIP, "batch graph capture failed");
+            const int p = b->parity;
+            int r = 0;
+            b->parity = 0;                                    // the graph starts at parity 0
+            for (int s = 0; s < 2 && !r; ++s) {
+                r = batch_super_step(b);
+                b->parity ^= 1;
+            }
+            b->parity = p;
+            if (hipStreamEndCapture(b->stream, &g) != hipSuccess || r)
+                return bset_err(b, LBR_ERR_HIP, "batch graph capture failed");
+            const hipError_t e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) return bset_err(b, LBR_ERR_HIP, "batch graph instantiate failed");
+        }
+        if (b->parity != 0) {
+            if (int r = batch_super_step(b)) return r;
+            batch_account(b);
+            ++k;
+        }
+        for (; k + 2 <= n; k += 2) {
+            if (hipGraphLaunch(b->graph, b->stream) != hipSuccess)
+                return bset_err(b, LBR_ERR_HIP, "batch graph launch failed");
+            batch_account(b);
+            batch_account(b);
+        }
+    }
+    for (; k < n; ++k) {
+        if (int r = batch_super_step(b)) return r;
+        batch_account(b);
+    }
+    return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbr_batch_create(int32_t n, lbr_ctx* const* cases, lbr_batch** out) {
+    if (!out) return LBR_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (n < 1 || !cases) return LBR_ERR_INVALID_ARG;
+    for (int k = 0; k < n; ++k) {
+        if (!cases[k] || !cases[k]->built || cases[k]->prec != cases[0]->prec) return LBR_ERR_INVALID_ARG;
+        for (int j = 0; j < k; ++j)
+            if (cases[j] == cases[k]) return LBR_ERR_INVALID_ARG;   // one case, two slots: a race
+    }
+    for (int k = 0; k < n; ++k)
+        if ((double)cases[k]->step_count < cases[k]->cfg.ramp_steps)
+            return LBR_ERR_STATE;                                   // start-up ramps run case by case
+    auto* b = new (std::nothrow) lbr_batch();
+    if (!b) return LBR_ERR_OOM;
+    *out = b;
+    b->all.assign(cases, cases + n);
+    b->prec = cases[0]->prec;
+    b->stream = cases[0]->stream;
+    switch (b->prec) {
+        case P_F64: b->args_size = sizeof(StepArgs<double, double>); break;
+        case P_F32: b->args_size = sizeof(StepArgs<float, float>); break;
+        case P_F16: b->args_size = sizeof(StepArgs<__half, float>); break;
+        default: b->args_size = sizeof(StepArgs<__hip_bfloat16, float>); break;
+    }
+    for (lbr_ctx* c : b->all)
+        if (hipStreamSynchronize(c->stream) != hipSuccess) return bset_err(b, LBR_ERR_HIP, "synchronize failed");
+    b->ev.assign(b->all.size(), nullptr);
+    for (hipEvent_t& e : b->ev)
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+            return bset_err(b, LBR_ERR_HIP, "event creation failed");
+    return batch_cover(b, b->all);
+}
+
+int lbr_batch_advance(lbr_batch* b, int64_t n) {
+    if (!b) return LBR_ERR_INVALID_ARG;
+    if (n < 0) return bset_err(b, LBR_ERR_INVALID_ARG, "negative step count");
+    if (!b->ready) return bset_err(b, LBR_ERR_STATE, "batch launch tables missing");
+    if (int r = batch_check(b)) return r;
+    if (int r = batch_wait_cases(b)) return r;
+    b->pev_used = 0;
+    if (int r = batch_run(b, n)) return r;
+    if (b->prof && b->pev_used) {
+        if (hipStreamSynchronize(b->stream) != hipSuccess) return bset_err(b, LBR_ERR_HIP, "synchronize failed");
+        double sum[3] = {0, 0, 0};
+        int cnt[3] = {0, 0, 0};
+        for (size_t i = 0; i + 1 < b->pev_used; i += 2) {
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, b->pev[i], b->pev[i + 1]);
+            const int v = b->pev_v[i];
+            sum[0] += ms;
+            cnt[0]++;
+            if (v == b->lmax - 1) { sum[1] += ms; cnt[1]++; }
+            if (v == 0) { sum[2] += ms; cnt[2]++; }
+        }
+        for (int f = 0; f < 3; ++f) b->prof_out[f] = cnt[f] ? 1000.0 * sum[f] / cnt[f] : 0.0;
+        b->prof_out[3] = 0.0;
+    }
+    return batch_release_cases(b);
+}
+
+int lbr_batch_run_to_steady(lbr_batch* b, double tol, int64_t max_super_steps, int64_t check_every,
+                            int64_t* steps_done, double* residual) {
+    if (!b || check_every <= 0 || max_super_steps < 0) return LBR_ERR_INVALID_ARG;
+    if (!b->ready) return bset_err(b, LBR_ERR_STATE, "batch launch tables missing");
+    const size_t n = b->all.size();
+    std::vector<int64_t> start(n);
+    std::vector<double> r(n, 1.0);
+    int rc = 0;
+    for (size_t k = 0; k < n && !rc; ++k) {
+        start[k] = b->all[k]->step_count;
+        if ((rc = lbr_residual(b->all[k], &r[k]))) b->err = b->all[k]->err;   // records the reference state
+    }
+    std::vector<lbr_ctx*> active = b->cases;
+    int64_t done = 0;
+    while (!rc && done < max_super_steps && !active.empty()) {
+        const int64_t k = std::min(check_every, max_super_steps - done);
+        if ((rc = lbr_batch_advance(b, k))) break;
+        done += k;
+        std::vector<lbr_ctx*> keep;
+        for (size_t j = 0; j < n && !rc; ++j) {
+            lbr_ctx* c = b->all[j];
+            if (std::find(active.begin(), active.end(), c) == active.end()) continue;
+            if ((rc = lbr_residual(c, &r[j]))) { b->err = c->err; break; }
+            if (!(r[j] < tol)) keep.push_back(c);
+        }
+        // converged cases leave the launches; the others go on without them
+        if (!rc && !keep.empty() && keep.size() != active.size()) rc = batch_cover(b, keep);
+        active.swap(keep);
+    }
+    if (b->cases.size() != n) {                               // the batch covers every case again
+        const int r2 = batch_cover(b, b->all);
+        if (!rc) rc = r2;
+    }
+    for (size_t k = 0; k < n; ++k) {
+        if (steps_done) steps_done[k] = b->all[k]->step_count - start[k];
+        if (residual) residual[k] = r[k];
+    }
+    return rc;
+}
+
+int lbr_batch_use_graph(lbr_batch* b, int32_t enable) {
+    if (!b) return LBR_ERR_INVALID_ARG;
+    b->use_graph = enable != 0;
+    return LBR_OK;
+}
+
+int lbr_batch_profile(lbr_batch* b, int32_t enable, double out[4]) {
+    if (!b) return LBR_ERR_INVALID_ARG;
+    b->prof = enable != 0;
+    if (out)
+        for (int f = 0; f < 4; ++f) out[f] = b->prof_out[f];
+    return LBR_OK;
+}
+
+int lbr_batch_synchronize(lbr_batch* b) {
+    if (!b) return LBR_ERR_INVALID_ARG;
+    return hipStreamSynchronize(b->stream) == hipSuccess ? LBR_OK : bset_err(b, LBR_ERR_HIP, "synchronize failed");
+}
+
+int64_t lbr_batch_steps_per_super_step(const lbr_batch* b, int32_t k) {
+    if (!b || k < 0 || k >= (int)b->all.size()) return LBR_ERR_INVALID_ARG;
+    if (std::find(b->cases.begin(), b->cases.end(), b->all[k]) == b->cases.end()) return 0;
+    return int64_t(1) << (b->lmax - (int)b->all[k]->lv.size());
+}
+
+int64_t lbr_batch_lups_per_super_step(lbr_batch* b) {
+    if (!b) return LBR_ERR_INVALID_ARG;
+    int64_t s = 0;
+    for (lbr_ctx* c : b->cases)
+        s += lbr_lups_per_coarse_step(c) * (int64_t(1) << (b->lmax - (int)c->lv.size()));
+    return s;
+}
+
+const char* lbr_batch_last_error(const lbr_batch* b) { return b ? b->err.c_str() : "null batch"; }
+
+void lbr_batch_destroy(lbr_batch* b) {
+    if (!b) return;
+    (void)hipStreamSynchronize(b->stream);
+    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    for (hipEvent_t e : b->ev)
+        if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : b->pev) (void)hipEventDestroy(e);
+    if (!b->all.empty()) {
+        dfree(b->all[0], b->parts_dev);
+        dfree(b->all[0], b->start_dev);
+    }
+    delete b;
 }
 
 }  // extern "C"

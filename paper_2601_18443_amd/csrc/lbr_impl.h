@@ -157,6 +157,10 @@ struct Timing {
     hipEvent_t start = nullptr, stop = nullptr;
 };
 hipError_t launch_step(Prec p, const void* args, hipStream_t s, const Timing& tm = Timing{});
+// parts: device array of nparts StepArgs<ST, CT> of the precision p; start: device
+// array of the first block of each part (multiples of 8); nblocks_total: grid size
+hipError_t launch_step_batch(Prec p, const void* parts, const int* start, int nparts, int nblocks_total,
+                             hipStream_t s, const Timing& tm = Timing{});
 hipError_t launch_wall(Prec p, const void* args, hipStream_t s);
 hipError_t launch_fill(Prec p, const FillArgs& a, hipStream_t s);
 hipError_t launch_restrict(Prec p, const RestrictArgs& a, hipStream_t s);

@@ -695,22 +695,24 @@ __device__ __forceinline__ void boundary_node(const StepArgs<ST, CT>& a, int b) 
     for (int k = 0; k < 6; ++k) st[k] = wm[k];
 }
 
+// One workgroup of a level sub-step; blk is the block index within the level's
+// part of the grid.
 template <class ST, class CT>
-__global__ __launch_bounds__(256, 8) void k_step(const StepArgs<ST, CT> a) {
+__device__ __forceinline__ void step_block(const StepArgs<ST, CT>& a, const int blk) {
     __shared__ CT sh_n[TILE_Y + 2][TILE_X + 2], sh_u[TILE_Y + 2][TILE_X + 2], sh_v[TILE_Y + 2][TILE_X + 2];
     // grid: wall-node blocks first (their FP64 Newton iteration is the longest
     // chain), then the tiles, then the level-0 domain-edge cells; each branch is
     // uniform over a workgroup
-    if ((int)blockIdx.x < a.wall_blocks) {
+    if (blk < a.wall_blocks) {
         // the wall nodes carry the longest dependency chain of the launch (FP64
         // Newton iteration): a few per block spreads them over many compute units
         // instead of crowding the SIMDs of a few
         if ((int)threadIdx.x >= WALL_PER_BLOCK) return;
-        const int b = blockIdx.x * WALL_PER_BLOCK + threadIdx.x;
+        const int b = blk * WALL_PER_BLOCK + threadIdx.x;
         if (b < a.wall.nb) boundary_node(a, b);
         return;
     }
-    const int bid = (int)blockIdx.x - a.wall_blocks;             // a multiple of 8 shifts no XCD
+    const int bid = blk - a.wall_blocks;                         // a multiple of 8 shifts no XCD
     if (bid >= a.tile_blocks) {
         const int e = (bid - a.tile_blocks) * TILE_X * TILE_Y + threadIdx.x;
         if (e < a.nedge) edge_cell(a, e);
@@ -868,6 +870,23 @@ __global__ __launch_bounds__(256, 8) void k_step(const StepArgs<ST, CT> a) {
     }
 }
 
+
+// One level sub-step of one case.
+template <class ST, class CT>
+__global__ __launch_bounds__(256, 8) void k_step(const StepArgs<ST, CT> a) {
+    step_block(a, (int)blockIdx.x);
+}
+
+// One launch for the same virtual level of several cases (batched sweep): the
+// grid is split into parts, part p starting at block start[p] (a multiple of 8,
+// so the XCD mapping of each part is kept) with its arguments in parts[p].
+template <class ST, class CT>
+__global__ __launch_bounds__(256, 8) void k_step_batch(const StepArgs<ST, CT>* __restrict__ parts,
+                                                     const int* __restrict__ start, int nparts) {
+    int p = 0;
+    while (p + 1 < nparts && (int)blockIdx.x >= start[p + 1]) ++p;
+    step_block(parts[p], (int)blockIdx.x - start[p]);
+}
 
 // Wall model on the current state, for output.
 template <class CT>
@@ -1108,6 +1127,30 @@ static hipError_t step_t(const void* args, hipStream_t s, const Timing& tm) {
     if (grid == 0) return hipSuccess;
     launch_timed(k_step<ST, CT>, dim3(grid), dim3(TILE_X * TILE_Y), s, tm, a);
     return hipGetLastError();
+}
+
+template <class ST, class CT>
+static hipError_t batch_t(const void* parts, const int* start, int nparts, int nblocks_total, hipStream_t s,
+                          const Timing& tm) {
+    if (nblocks_total == 0) return hipSuccess;
+    const auto* pa = static_cast<const StepArgs<ST, CT>*>(parts);
+    if (tm.start)
+        hipExtLaunchKernelGGL((k_step_batch<ST, CT>), dim3(nblocks_total), dim3(TILE_X * TILE_Y), 0, s,
+                              tm.start, tm.stop, 0, pa, start, nparts);
+    else
+        hipLaunchKernelGGL((k_step_batch<ST, CT>), dim3(nblocks_total), dim3(TILE_X * TILE_Y), 0, s,
+                           pa, start, nparts);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_batch(Prec p, const void* parts, const int* start, int nparts, int nblocks_total,
+                             hipStream_t s, const Timing& tm) {
+    switch (p) {
+        case P_F64: return batch_t<double, double>(parts, start, nparts, nblocks_total, s, tm);
+        case P_F32: return batch_t<float, float>(parts, start, nparts, nblocks_total, s, tm);
+        case P_F16: return batch_t<__half, float>(parts, start, nparts, nblocks_total, s, tm);
+        default: return batch_t<__hip_bfloat16, float>(parts, start, nparts, nblocks_total, s, tm);
+    }
 }
 
 hipError_t launch_step(Prec p, const void* args, hipStream_t s, const Timing& tm) {
