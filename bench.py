@@ -28,6 +28,24 @@ HBM_PEAK_GBS = 8000.0
 # nu-tilde read + write (2 x 4), FP64 wall distance (8), one flag byte
 ALG_BYTES = {"f32": 18 * 4 + 8 + 8 + 1, "f16": 18 * 2 + 8 + 8 + 1, "bf16": 18 * 2 + 8 + 8 + 1,
              "f64": 18 * 8 + 16 + 8 + 1}
+DTYPE = {"f32": "f32", "f16": "f16-store/f32", "bf16": "bf16-store/f32", "f64": "f64",
+         "mixed": "f32-store on the two finest levels, f16-store below/f32"}
+
+
+def lup_bytes(storage, level, n_levels):
+    """Algorithmic bytes of one cell update on a level (mixed storage: FP32 on the
+    two finest levels, FP16 below)."""
+    if storage == "mixed":
+        return ALG_BYTES["f32"] if level >= n_levels - 2 else ALG_BYTES["f16"]
+    return ALG_BYTES[storage]
+
+
+def step_bytes(storage, sim, n_levels, repeat=1):
+    """Algorithmic bytes of one coarse step of a solver (times repeat)."""
+    return repeat * sum(lup_bytes(storage, l, n_levels) * sim.level_info(l)["n_fluid"] * 2 ** l
+                        for l in range(n_levels))
+
+
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_airfoil_2M_traffic.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_2601_18443_amd", "csrc", "lbr_kernels.hip")
 
@@ -148,7 +166,8 @@ def run_sweep(args):
     log(f"one after another: {seq:.3f} s")
     finite = all(np.all(np.isfinite(s.forces())) for s in sims)
     mlups = lups * args.steps / dt / 1e6
-    bytes_per_launch = ALG_BYTES[args.storage] * lups / launches
+    bytes_per_launch = sum(step_bytes(args.storage, s, c["n_levels"], p)
+                           for s, c, p in zip(sims, cases, per)) / launches
     roof = None
     if kt[0] > 0:
         achieved = bytes_per_launch / (kt[0] * 1e-6) / 1e9
@@ -161,7 +180,7 @@ def run_sweep(args):
         "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1000 * dt / args.steps, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": {"f32": "f32", "f16": "f16-store/f32", "bf16": "bf16-store/f32", "f64": "f64"}[args.storage],
+        "dtype": DTYPE[args.storage],
         "data": "synthetic (seeded airfoil-like polylines)",
         "config": {"workload": "batched sweep: 16 airfoil-like cases, AoA -4..16 deg, 3-5 levels to c/512, "
                                "Re 6e6, M 0.15; a step is one super step (2^(5 - L_k) coarse steps of case k)",
@@ -181,7 +200,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16", "f64"])
+    ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16", "f64", "mixed"])
     ap.add_argument("--graph", type=int, default=1, help="replay the coarse step from a HIP graph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true",
@@ -254,7 +273,7 @@ def main():
     # launch = ALG_BYTES x cell updates per launch; duration from the HIP events
     n_levels = case["n_levels"]
     launches_per_step = sum(2 ** l for l in range(n_levels))
-    bytes_per_launch = ALG_BYTES[args.storage] * lups / launches_per_step
+    bytes_per_launch = step_bytes(args.storage, sim, n_levels) / launches_per_step
     roof = None
     if kt[0] > 0:
         achieved = bytes_per_launch / (kt[0] * 1e-6) / 1e9
@@ -271,7 +290,7 @@ def main():
     if not args.no_variants and args.storage == "f32":
         sim.close()
         del sim
-        for st in ("f16", "bf16"):
+        for st in ("f16", "bf16", "mixed"):
             v = P.Solver(case, storage=st)
             if args.graph:
                 v.use_graph(True)
@@ -287,13 +306,14 @@ def main():
             v.advance(args.steps)
             v.synchronize()
             ktv = v.profile(False)
-            ach = ALG_BYTES[st] * lups / launches_per_step / (ktv[0] * 1e-6) / 1e9 if ktv[0] > 0 else None
+            per_lup = step_bytes(st, v, n_levels) / lups
+            ach = per_lup * lups / launches_per_step / (ktv[0] * 1e-6) / 1e9 if ktv[0] > 0 else None
             variants[st] = {"value": round(lups * args.steps / dtv / 1e6, 1), "unit": "MLUPS",
                             "ms_per_step": round(1000 * dtv / args.steps, 4),
                             "k_step_avg_launch_us": round(ktv[0], 3),
                             "achieved_GBps": None if ach is None else round(ach, 1),
                             "frac": None if ach is None else round(ach / HBM_PEAK_GBS, 4),
-                            "alg_bytes_per_lup": ALG_BYTES[st]}
+                            "alg_bytes_per_lup": round(per_lup, 2)}
             log(f"{st} storage: {variants[st]['value']} MLUPS, k_step {ktv[0]:.2f} us")
             v.close()
             del v
@@ -305,7 +325,7 @@ def main():
         "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1000 * dt / args.steps, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": {"f32": "f32", "f16": "f16-store/f32", "bf16": "bf16-store/f32", "f64": "f64"}[args.storage],
+        "dtype": DTYPE[args.storage],
         "data": "synthetic (seeded airfoil-like polylines)",
         "config": {"workload": ("single airfoil-like body, 8 levels c/8..c/1024, 40c domain, "
                                 "Re 6e6, M 0.15, AoA 10 deg") if args.workload == "airfoil" else

@@ -48,14 +48,18 @@ enum lbr_status {
     LBR_ERR_HIP = -3,
     LBR_ERR_GEOMETRY = -4,
     LBR_ERR_DIVERGED = -5,
-    LBR_ERR_STATE = -6
+    LBR_ERR_STATE = -6,
+    LBR_ERR_IO = -7
 };
 
 /* Population storage.  Populations are stored shifted by their lattice
    weight (f_i - w_i); arithmetic is FP64 for LBR_STORE_F64 and FP32
-   otherwise.  The friction-velocity Newton solve, the wall-distance field and
-   the force sums are always FP64. */
-enum lbr_storage { LBR_STORE_F64 = 0, LBR_STORE_F32 = 1, LBR_STORE_F16 = 2, LBR_STORE_BF16 = 3 };
+   otherwise.  LBR_STORE_MIXED keeps FP32 on the two finest levels (the wall
+   nodes and the boundary layer, most of the cell updates of a multilevel
+   grid) and FP16 on the coarser ones.  The friction-velocity Newton solve, the
+   wall-distance field and the force sums are always FP64. */
+enum lbr_storage { LBR_STORE_F64 = 0, LBR_STORE_F32 = 1, LBR_STORE_F16 = 2, LBR_STORE_BF16 = 3,
+                   LBR_STORE_MIXED = 4 };
 
 /* Domain sides: x-lo, x-hi, y-lo, y-hi. */
 enum lbr_bc { LBR_BC_PERIODIC = 0, LBR_BC_INLET = 1, LBR_BC_OUTLET = 2, LBR_BC_SYMMETRY = 3,
@@ -234,6 +238,21 @@ int lbr_residual(lbr_ctx* ctx, double* residual);
    residual.  Returns LBR_ERR_DIVERGED if the state becomes non-finite. */
 int lbr_run_to_steady(lbr_ctx* ctx, double tol, int64_t max_steps, int64_t check_every,
                       int64_t* steps_done, double* residual);
+
+/* Checkpoint of the whole solver state: both time levels of the populations,
+   of rho, u and of chi on every level, the friction-velocity state of the wall
+   nodes (the Newton start values of Section 2.3, step 3) and the coarse-step
+   counter (start-up ramp), in one binary file at path, after a header that
+   identifies the grid (per-level box, cell counts and a hash of the cell
+   flags) and ends with a checksum of the data.  lbr_save waits for the
+   context's queued work.  lbr_load needs a context built from the same case
+   with the same storage (else LBR_ERR_INVALID_ARG, nothing changed); it
+   verifies the whole file before touching the device state (LBR_ERR_IO for a
+   missing, foreign, truncated or corrupted file) and restarts the residual
+   monitor.  A run continued from a checkpoint is bit-identical to the
+   uninterrupted run. */
+int lbr_save(lbr_ctx* ctx, const char* path);
+int lbr_load(lbr_ctx* ctx, const char* path);
 
 /* Cell updates per coarse step: sum over levels of n_fluid * 2^l. */
 int64_t lbr_lups_per_coarse_step(lbr_ctx* ctx);

@@ -19,8 +19,8 @@ ABI_VERSION = 3
 MAX_LEVELS = 12
 WALL_STRIDE = 28
 
-STORE_F64, STORE_F32, STORE_F16, STORE_BF16 = 0, 1, 2, 3
-STORAGE = {"f64": STORE_F64, "f32": STORE_F32, "f16": STORE_F16, "bf16": STORE_BF16}
+STORE_F64, STORE_F32, STORE_F16, STORE_BF16, STORE_MIXED = 0, 1, 2, 3, 4
+STORAGE = {"f64": STORE_F64, "f32": STORE_F32, "f16": STORE_F16, "bf16": STORE_BF16, "mixed": STORE_MIXED}
 FIELD_RHO, FIELD_UX, FIELD_UY, FIELD_CHI, FIELD_NUT, FIELD_TYPE, FIELD_DIST = range(7)
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -83,6 +83,8 @@ def lib():
         L.lbr_last_error.restype = C.c_char_p
         L.lbr_destroy.argtypes = [p]
         L.lbr_destroy.restype = None
+        L.lbr_save.argtypes = [p, C.c_char_p]
+        L.lbr_load.argtypes = [p, C.c_char_p]
         L.lbr_batch_create.argtypes = [i32, C.POINTER(p), C.POINTER(p)]
         L.lbr_batch_advance.argtypes = [p, i64]
         L.lbr_batch_use_graph.argtypes = [p, i32]
@@ -261,6 +263,12 @@ class Solver:
         done, r = C.c_int64(), C.c_double()
         self._check(lib().lbr_run_to_steady(self.h, tol, max_steps, check_every, C.byref(done), C.byref(r)))
         return done.value, r.value
+
+    def save(self, path):
+        self._check(lib().lbr_save(self.h, os.fsencode(path)))
+
+    def load(self, path):
+        self._check(lib().lbr_load(self.h, os.fsencode(path)))
 
     def lups_per_coarse_step(self):
         return int(lib().lbr_lups_per_coarse_step(self.h))

@@ -30,6 +30,8 @@ struct Node {
 
 struct Level {
     int l = 0;
+    Prec st = P_F32;                 // population storage of this level
+    size_t ssize = 4;
     Box box{};
     int bx0 = 0, by0 = 0, bnx = 0, bny = 0;   // I/O box
     double scale = 1, nu = 0, fx = 0, fy = 0;
@@ -131,6 +133,10 @@ int set_err(lbr_ctx* c, int code, const char* fmt, ...) {
     if (c) c->err = buf;
     return code;
 }
+
+// Population storage of level l: the configured format, or with mixed storage
+// FP32 on the two finest levels and FP16 below (FP32 arithmetic throughout).
+Prec level_storage(const lbr_ctx* c, int l);
 
 #define HIPCHK(ctx, expr)                                                                  \
     do {                                                                                   \
@@ -633,7 +639,14 @@ void mark_restriction_tiles(lbr_ctx* c, Level& L) {
     }
 }
 
+Prec level_storage(const lbr_ctx* c, int l) {
+    if (c->cfg.storage != LBR_STORE_MIXED) return c->prec;
+    return l >= c->cfg.n_levels - 2 ? P_F32 : P_F16;
+}
+
 int alloc_level(lbr_ctx* c, Level& L) {
+    L.st = level_storage(c, L.l);
+    L.ssize = L.st == P_F64 ? 8 : (L.st == P_F32 ? 4 : 2);
     const size_t n = L.box.plane;
     const size_t pad = (size_t)L.box.pitch + 1;    // k_step reads one row beyond both ends
     // k_step addresses each array through a buffer resource with 32-bit byte offsets
@@ -641,15 +654,15 @@ int alloc_level(lbr_ctx* c, Level& L) {
         return set_err(c, LBR_ERR_INVALID_ARG, "level %d: storage box of %zu cells exceeds the "
                        "2 GiB per-array limit", L.l, n);
     for (int b = 0; b < 2; ++b) {
-        L.f[b] = dalloc_padded(c, 9 * n, c->ssize, pad);
+        L.f[b] = dalloc_padded(c, 9 * n, L.ssize, pad);
         L.mac[b] = dalloc_padded(c, 3 * n, c->csize, pad);
         L.chi[b] = dalloc_padded(c, n, c->csize, pad);
         if (!L.f[b] || !L.mac[b] || !L.chi[b]) return set_err(c, LBR_ERR_OOM, "level %d: out of device memory", L.l);
-        HIPCHK(c, hipMemsetAsync(static_cast<char*>(L.f[b]) - pad * c->ssize, 0, (9 * n + 2 * pad) * c->ssize, c->stream));
+        HIPCHK(c, hipMemsetAsync(static_cast<char*>(L.f[b]) - pad * L.ssize, 0, (9 * n + 2 * pad) * L.ssize, c->stream));
         HIPCHK(c, hipMemsetAsync(static_cast<char*>(L.mac[b]) - pad * c->csize, 0, (3 * n + 2 * pad) * c->csize, c->stream));
         HIPCHK(c, hipMemsetAsync(static_cast<char*>(L.chi[b]) - pad * c->csize, 0, (n + 2 * pad) * c->csize, c->stream));
     }
-    L.bytes += 2 * (n + 2 * pad) * (9 * c->ssize + 4 * c->csize);
+    L.bytes += 2 * (n + 2 * pad) * (9 * L.ssize + 4 * c->csize);
     std::vector<double> dclamp(L.d);
     if (c->prec != P_F64)
         for (double& v : dclamp) v = std::min(v, 1e18);
@@ -821,7 +834,8 @@ void fill_step_args(lbr_ctx* c, int l, int substep, StepArgs<ST, CT>& a) {
     a.substep = substep;
     if (l > 0) {
         Level& P = c->lv[l - 1];
-        a.fcoarse = (const ST*)P.f[P.cur];
+        a.fcoarse = P.f[P.cur];
+        a.cst = P.st;
         a.cbox = P.box;
         a.cmac = (const CT*)P.mac[P.cur];
         a.cchi = (const CT*)P.chi[P.cur];
@@ -829,16 +843,19 @@ void fill_step_args(lbr_ctx* c, int l, int substep, StepArgs<ST, CT>& a) {
         a.rchi = (CT*)P.chi[1 - P.cur];
     } else {
         a.fcoarse = nullptr;
+        a.cst = L.st;
         a.cbox = Box{};
         a.cmac = a.cchi = nullptr;
         a.rmac = a.rchi = nullptr;
     }
     if (l + 1 < (int)c->lv.size()) {
         Level& F = c->lv[l + 1];
-        a.ffine = (const ST*)F.f[F.cur];
+        a.ffine = F.f[F.cur];
+        a.fst = F.st;
         a.fbox = F.box;
     } else {
         a.ffine = nullptr;
+        a.fst = L.st;
         a.fbox = Box{};
     }
 }
@@ -891,7 +908,7 @@ Timing prof_events(lbr_ctx* c, int kind) {
 int do_step(lbr_ctx* c, int l, int substep) {
     Level& L = c->lv[l];
     alignas(16) unsigned char buf[sizeof(StepArgs<double, double>)];
-    switch (c->prec) {
+    switch (L.st) {
         case P_F64: fill_step_args(c, l, substep, *reinterpret_cast<StepArgs<double, double>*>(buf)); break;
         case P_F32: fill_step_args(c, l, substep, *reinterpret_cast<StepArgs<float, float>*>(buf)); break;
         case P_F16: fill_step_args(c, l, substep, *reinterpret_cast<StepArgs<__half, float>*>(buf)); break;
@@ -900,7 +917,7 @@ int do_step(lbr_ctx* c, int l, int substep) {
     // one launch per level sub-step: tiles, wall nodes and domain-edge cells are
     // workgroups of the same grid (disjoint cells, same source state)
     const int kind = l + 1 == (int)c->lv.size() ? EV_STEP_FINE : (l == 0 ? EV_STEP_L0 : EV_STEP);
-    HIPCHK(c, launch_step(c->prec, buf, c->stream, prof_events(c, kind)));
+    HIPCHK(c, launch_step(L.st, buf, c->stream, prof_events(c, kind)));
     L.cur ^= 1;
     return 0;
 }
@@ -972,7 +989,7 @@ int init_level(lbr_ctx* c, int l, const double* rho, const double* ux, const dou
     a.pitch = L.box.pitch; a.gx0 = L.box.gx0; a.gy0 = L.box.gy0;
     a.nxd = c->cfg.nx0 << l; a.nyd = c->cfg.ny0 << l;
     a.sp = absorber(c, l, ramp(c, c->step_count));
-    HIPCHK(c, launch_init(c->prec, a, c->stream));
+    HIPCHK(c, launch_init(L.st, a, c->stream));
     HIPCHK(c, hipMemsetAsync(L.bstate, 0, std::max<size_t>(L.nodes.size(), 1) * 8 * sizeof(double), c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     dfree(c, dv);
@@ -1106,7 +1123,7 @@ int lbr_create(const lbr_config* cfg, lbr_ctx** out) {
     *out = nullptr;
     if (!cfg || cfg->version != LBR_ABI_VERSION) return LBR_ERR_INVALID_ARG;
     if (cfg->n_levels < 1 || cfg->n_levels > LBR_MAX_LEVELS || cfg->nx0 < 4 || cfg->ny0 < 4 ||
-        !(cfg->dx0 > 0) || cfg->storage < 0 || cfg->storage > 3 || cfg->outlet < 0 || cfg->outlet > 2 ||
+        !(cfg->dx0 > 0) || cfg->storage < 0 || cfg->storage > LBR_STORE_MIXED || cfg->outlet < 0 || cfg->outlet > 2 ||
         cfg->sponge_width < 0 || cfg->sponge_strength < 0 || cfg->sponge_strength > 1 ||
         cfg->ramp_steps < 0 || cfg->ramp_start < 0 || cfg->ramp_start > 1)
         return LBR_ERR_INVALID_ARG;
@@ -1118,8 +1135,10 @@ int lbr_create(const lbr_config* cfg, lbr_ctx** out) {
     lbr_ctx* c = new lbr_ctx();
     c->cfg = *cfg;
     c->stream = static_cast<hipStream_t>(cfg->stream);
-    c->prec = static_cast<Prec>(cfg->storage);
-    c->ssize = cfg->storage == LBR_STORE_F64 ? 8 : (cfg->storage == LBR_STORE_F32 ? 4 : 2);
+    // prec selects the arithmetic of the kernels that touch no populations (and the
+    // storage of every level unless it is mixed)
+    c->prec = cfg->storage == LBR_STORE_MIXED ? P_F32 : static_cast<Prec>(cfg->storage);
+    c->ssize = cfg->storage == LBR_STORE_F64 ? 8 : (cfg->storage == LBR_STORE_F16 || cfg->storage == LBR_STORE_BF16 ? 2 : 4);
     c->csize = cfg->storage == LBR_STORE_F64 ? 8 : 4;
     c->u_ref = cfg->u_ref > 0 ? cfg->u_ref : cfg->mach * std::sqrt(1.0 / 3.0);
     c->nu0 = cfg->nu0 > 0 ? cfg->nu0 : c->u_ref * (cfg->ref_length / cfg->dx0) / cfg->reynolds;
@@ -1279,6 +1298,157 @@ int lbr_advance(lbr_ctx* c, int64_t n) {
         }
         for (int f = 0; f < 4; ++f) c->prof_out[f] = cnt[f] ? 1000.0 * sum[f] / cnt[f] : 0.0;
     }
+    return LBR_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// checkpoint: both time levels of every field, the wall-model state and the
+// step counter, behind a header that pins the grid the data belongs to
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr char CKPT_MAGIC[8] = {'L', 'B', 'R', 'S', 'T', 'A', 'T', '1'};
+
+struct CkptHead {
+    char magic[8];
+    int32_t abi, prec, n_levels, ssize, csize, reserved;
+    int64_t step_count;
+};
+
+struct CkptLevel {
+    int64_t pitch, ny, plane, gx0, gy0, n_fluid, n_nodes;
+    uint64_t flag_hash;
+    int32_t cur, storage;
+};
+
+uint64_t fnv1a(const void* p, size_t n, uint64_t h = 1469598103934665603ull) {
+    const unsigned char* b = static_cast<const unsigned char*>(p);
+    for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 1099511628211ull;
+    return h;
+}
+
+CkptLevel ckpt_level(const Level& L) {
+    CkptLevel d{};
+    d.pitch = L.box.pitch;
+    d.ny = L.box.ny;
+    d.plane = L.box.plane;
+    d.gx0 = L.box.gx0;
+    d.gy0 = L.box.gy0;
+    d.n_fluid = L.n_fluid;
+    d.n_nodes = (int64_t)L.nodes.size();
+    d.flag_hash = fnv1a(L.flag.data(), L.flag.size());
+    d.cur = L.cur;
+    d.storage = (int32_t)L.st;
+    return d;
+}
+
+// device regions of one level, in file order
+std::vector<std::pair<void*, size_t>> ckpt_regions(lbr_ctx* c, Level& L) {
+    const size_t n = (size_t)L.box.plane;
+    std::vector<std::pair<void*, size_t>> r;
+    for (int b = 0; b < 2; ++b) r.push_back({L.f[b], 9 * n * L.ssize});
+    for (int b = 0; b < 2; ++b) r.push_back({L.mac[b], 3 * n * c->csize});
+    for (int b = 0; b < 2; ++b) r.push_back({L.chi[b], n * c->csize});
+    r.push_back({L.bstate, std::max<size_t>(L.nodes.size(), 1) * 8 * sizeof(double)});
+    return r;
+}
+
+struct File {
+    FILE* f = nullptr;
+    ~File() { if (f) fclose(f); }
+};
+
+}  // namespace
+
+extern "C" {
+
+int lbr_save(lbr_ctx* c, const char* path) {
+    if (!c || !path) return LBR_ERR_INVALID_ARG;
+    if (!c->built) return set_err(c, LBR_ERR_STATE, "lbr_build has not been called");
+    File fh;
+    fh.f = fopen(path, "wb");
+    if (!fh.f) return set_err(c, LBR_ERR_IO, "cannot open %s for writing", path);
+    CkptHead h{};
+    memcpy(h.magic, CKPT_MAGIC, 8);
+    h.abi = LBR_ABI_VERSION;
+    h.prec = (int32_t)c->cfg.storage;
+    h.n_levels = (int32_t)c->lv.size();
+    h.ssize = (int32_t)c->ssize;
+    h.csize = (int32_t)c->csize;
+    h.step_count = c->step_count;
+    bool ok = fwrite(&h, sizeof h, 1, fh.f) == 1;
+    for (const Level& L : c->lv) {
+        const CkptLevel d = ckpt_level(L);
+        ok = ok && fwrite(&d, sizeof d, 1, fh.f) == 1;
+    }
+    std::vector<unsigned char> host;
+    uint64_t sum = 1469598103934665603ull;
+    for (Level& L : c->lv)
+        for (const auto& reg : ckpt_regions(c, L)) {
+            host.resize(reg.second);
+            HIPCHK(c, hipMemcpyAsync(host.data(), reg.first, reg.second, hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            sum = fnv1a(host.data(), host.size(), sum);
+            ok = ok && fwrite(host.data(), 1, host.size(), fh.f) == host.size();
+        }
+    ok = ok && fwrite(&sum, sizeof sum, 1, fh.f) == 1;
+    const bool closed = fclose(fh.f) == 0;
+    fh.f = nullptr;
+    if (!ok || !closed) return set_err(c, LBR_ERR_IO, "write to %s failed", path);
+    return LBR_OK;
+}
+
+int lbr_load(lbr_ctx* c, const char* path) {
+    if (!c || !path) return LBR_ERR_INVALID_ARG;
+    if (!c->built) return set_err(c, LBR_ERR_STATE, "lbr_build has not been called");
+    File fh;
+    fh.f = fopen(path, "rb");
+    if (!fh.f) return set_err(c, LBR_ERR_IO, "cannot open %s", path);
+    CkptHead h{};
+    if (fread(&h, sizeof h, 1, fh.f) != 1 || memcmp(h.magic, CKPT_MAGIC, 8) != 0)
+        return set_err(c, LBR_ERR_IO, "%s is not a checkpoint of this library", path);
+    if (h.abi != LBR_ABI_VERSION || h.prec != (int32_t)c->cfg.storage || h.n_levels != (int32_t)c->lv.size() ||
+        h.ssize != (int32_t)c->ssize || h.csize != (int32_t)c->csize)
+        return set_err(c, LBR_ERR_INVALID_ARG, "checkpoint %s: different library version, storage or level count",
+                       path);
+    std::vector<CkptLevel> lv(c->lv.size());
+    for (size_t l = 0; l < lv.size(); ++l) {
+        if (fread(&lv[l], sizeof lv[l], 1, fh.f) != 1) return set_err(c, LBR_ERR_IO, "checkpoint %s truncated", path);
+        const CkptLevel mine = ckpt_level(c->lv[l]);
+        if (lv[l].pitch != mine.pitch || lv[l].ny != mine.ny || lv[l].plane != mine.plane ||
+            lv[l].gx0 != mine.gx0 || lv[l].gy0 != mine.gy0 || lv[l].n_fluid != mine.n_fluid ||
+            lv[l].n_nodes != mine.n_nodes || lv[l].flag_hash != mine.flag_hash || lv[l].storage != mine.storage ||
+            (lv[l].cur != 0 && lv[l].cur != 1))
+            return set_err(c, LBR_ERR_INVALID_ARG, "checkpoint %s: level %d was saved on a different grid",
+                           path, (int)l);
+    }
+    // read and verify everything before the device state changes
+    std::vector<std::vector<unsigned char>> data;
+    uint64_t sum = 1469598103934665603ull;
+    for (Level& L : c->lv)
+        for (const auto& reg : ckpt_regions(c, L)) {
+            data.emplace_back(reg.second);
+            if (fread(data.back().data(), 1, reg.second, fh.f) != reg.second)
+                return set_err(c, LBR_ERR_IO, "checkpoint %s truncated", path);
+            sum = fnv1a(data.back().data(), reg.second, sum);
+        }
+    uint64_t stored = 0;
+    if (fread(&stored, sizeof stored, 1, fh.f) != 1 || stored != sum)
+        return set_err(c, LBR_ERR_IO, "checkpoint %s: checksum mismatch", path);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    size_t k = 0;
+    for (Level& L : c->lv)
+        for (const auto& reg : ckpt_regions(c, L)) {
+            HIPCHK(c, hipMemcpyAsync(reg.first, data[k].data(), reg.second, hipMemcpyHostToDevice, c->stream));
+            ++k;
+        }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (size_t l = 0; l < lv.size(); ++l) c->lv[l].cur = lv[l].cur;
+    c->step_count = h.step_count;
+    c->resid_init = false;
+    c->resid_steps = 0;
     return LBR_OK;
 }
 
@@ -1496,10 +1666,10 @@ struct lbr_batch {
     std::vector<lbr_ctx*> all;         // the cases, in the caller's order
     std::vector<lbr_ctx*> cases;       // the cases the launch tables cover
     int lmax = 0;
-    Prec prec = P_F32;
     hipStream_t stream = nullptr;
-    size_t args_size = 0;
-    struct Launch { int part0, nparts, nblocks, v; };
+    // one launch: its StepArgs start at byte off of the table, its part starts
+    // at index part0; every part of a launch has the same population storage
+    struct Launch { size_t off; int part0, nparts, nblocks, v; Prec st; };
     std::vector<Launch> launches;      // the launches of two super steps, in order
     int per_super = 0;                 // launches per super step
     void* parts_dev = nullptr;         // StepArgs of every part of every launch
@@ -1549,27 +1719,31 @@ int batch_build(lbr_batch* b) {
     alignas(16) unsigned char buf[sizeof(StepArgs<double, double>)];
     for (int rep = 0; rep < 2; ++rep)
         for (const auto& vs : seq) {
-            lbr_batch::Launch ln{(int)starts.size(), 0, 0, vs.first};
+            lbr_batch::Launch ln{parts.size(), (int)starts.size(), 0, 0, vs.first, P_F32};
             for (lbr_ctx* c : b->cases) {
                 const int l = vs.first - (b->lmax - (int)c->lv.size());
                 if (l < 0) continue;
                 Level& L = c->lv[l];
+                if (ln.nparts == 0) ln.st = L.st;
+                else if (L.st != ln.st)
+                    return bset_err(b, LBR_ERR_INVALID_ARG, "cases store one virtual level in different formats");
                 const int sub = l == 0 ? 0 : vs.second;       // a case's level 0 has no parent
                 int wb = 0, tb = 0;
-                switch (c->prec) {
+                size_t sz = 0;
+                switch (L.st) {
                     case P_F64: { auto& a = *reinterpret_cast<StepArgs<double, double>*>(buf);
-                        fill_step_args(c, l, sub, a); wb = a.wall_blocks; tb = a.tile_blocks; break; }
+                        fill_step_args(c, l, sub, a); wb = a.wall_blocks; tb = a.tile_blocks; sz = sizeof a; break; }
                     case P_F32: { auto& a = *reinterpret_cast<StepArgs<float, float>*>(buf);
-                        fill_step_args(c, l, sub, a); wb = a.wall_blocks; tb = a.tile_blocks; break; }
+                        fill_step_args(c, l, sub, a); wb = a.wall_blocks; tb = a.tile_blocks; sz = sizeof a; break; }
                     case P_F16: { auto& a = *reinterpret_cast<StepArgs<__half, float>*>(buf);
-                        fill_step_args(c, l, sub, a); wb = a.wall_blocks; tb = a.tile_blocks; break; }
+                        fill_step_args(c, l, sub, a); wb = a.wall_blocks; tb = a.tile_blocks; sz = sizeof a; break; }
                     default: { auto& a = *reinterpret_cast<StepArgs<__hip_bfloat16, float>*>(buf);
-                        fill_step_args(c, l, sub, a); wb = a.wall_blocks; tb = a.tile_blocks; break; }
+                        fill_step_args(c, l, sub, a); wb = a.wall_blocks; tb = a.tile_blocks; sz = sizeof a; break; }
                 }
                 // parts start on multiples of 8 blocks, so that each part's own
                 // block-to-XCD mapping holds inside the shared grid
                 const int eb = 8 * (((int)L.edge.size() + 8 * TILE_X * TILE_Y - 1) / (8 * TILE_X * TILE_Y));
-                parts.insert(parts.end(), buf, buf + b->args_size);
+                parts.insert(parts.end(), buf, buf + sz);
                 starts.push_back(ln.nblocks);
                 ln.nblocks += wb + tb + eb;
                 ln.nparts++;
@@ -1629,11 +1803,11 @@ int batch_super_step(lbr_batch* b) {
     const int first = b->parity * b->per_super;
     for (int k = 0; k < b->per_super; ++k) {
         const lbr_batch::Launch& ln = b->launches[first + k];
-        const void* parts = static_cast<const unsigned char*>(b->parts_dev) + (size_t)ln.part0 * b->args_size;
+        const void* parts = static_cast<const unsigned char*>(b->parts_dev) + ln.off;
         Timing tm;
         if (b->prof)
             if (hipEvent_t* e = batch_prof_events(b, ln.v)) { tm.start = e[0]; tm.stop = e[1]; }
-        if (launch_step_batch(b->prec, parts, b->start_dev + ln.part0, ln.nparts, ln.nblocks, b->stream, tm) !=
+        if (launch_step_batch(ln.st, parts, b->start_dev + ln.part0, ln.nparts, ln.nblocks, b->stream, tm) !=
             hipSuccess)
             return bset_err(b, LBR_ERR_HIP, "batched k_step launch failed");
     }
@@ -1732,7 +1906,8 @@ int lbr_batch_create(int32_t n, lbr_ctx* const* cases, lbr_batch** out) {
     *out = nullptr;
     if (n < 1 || !cases) return LBR_ERR_INVALID_ARG;
     for (int k = 0; k < n; ++k) {
-        if (!cases[k] || !cases[k]->built || cases[k]->prec != cases[0]->prec) return LBR_ERR_INVALID_ARG;
+        if (!cases[k] || !cases[k]->built || cases[k]->cfg.storage != cases[0]->cfg.storage)
+            return LBR_ERR_INVALID_ARG;
         for (int j = 0; j < k; ++j)
             if (cases[j] == cases[k]) return LBR_ERR_INVALID_ARG;   // one case, two slots: a race
     }
@@ -1743,14 +1918,7 @@ int lbr_batch_create(int32_t n, lbr_ctx* const* cases, lbr_batch** out) {
     if (!b) return LBR_ERR_OOM;
     *out = b;
     b->all.assign(cases, cases + n);
-    b->prec = cases[0]->prec;
     b->stream = cases[0]->stream;
-    switch (b->prec) {
-        case P_F64: b->args_size = sizeof(StepArgs<double, double>); break;
-        case P_F32: b->args_size = sizeof(StepArgs<float, float>); break;
-        case P_F16: b->args_size = sizeof(StepArgs<__half, float>); break;
-        default: b->args_size = sizeof(StepArgs<__hip_bfloat16, float>); break;
-    }
     for (lbr_ctx* c : b->all)
         if (hipStreamSynchronize(c->stream) != hipSuccess) return bset_err(b, LBR_ERR_HIP, "synchronize failed");
     b->ev.assign(b->all.size(), nullptr);

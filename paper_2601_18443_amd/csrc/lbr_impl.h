@@ -90,10 +90,12 @@ struct StepArgs {
                                      // (a multiple of 8 blocks),
                                      // tile blocks (a multiple of 8), then edge-cell blocks
     Absorber sp;                     // absorbing layer (level 0 only; width 0 elsewhere)
-    const ST* fcoarse; Box cbox;     // parent level populations (ghost transfer)
+    const void* fcoarse; Box cbox;   // parent level populations (ghost transfer), stored as
+    int cst;                         // Prec cst (mixed storage: FP32 or FP16, else as ST)
     const CT* cmac;  const CT* cchi; // parent level rho, u and chi of the current parent step
     CT* rmac;        CT* rchi;       // parent level buffers of the next parent step (restriction)
-    const ST* ffine;   Box fbox;     // child level populations (coalescence)
+    const void* ffine; Box fbox;     // child level populations (coalescence), stored as
+    int fst;                         // Prec fst
     WallData wall;                   // boundary nodes of this level (k_boundary)
     double* wstate;                  // [nb][8] u_tau, u_Rt (x, y), rho_W, u_W (x, y), spare
 };

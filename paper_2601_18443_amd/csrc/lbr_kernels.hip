@@ -13,6 +13,7 @@
 #include <hip/hip_ext.h>
 
 #include <cmath>
+#include <type_traits>
 
 namespace lbr {
 namespace {
@@ -391,10 +392,33 @@ __device__ void wall_model(const WallData& w, int b, const CT* mac, long P, doub
 // ---------------------------------------------------------------------------
 // Pieces of the per-cell update shared by k_step and k_boundary.
 // ---------------------------------------------------------------------------
+// A population of a neighbouring level.  With mixed storage (FP32 arithmetic)
+// that level may hold FP32 or FP16 where this one holds the other; the kind is
+// uniform over a launch, so the test is a scalar branch.
+template <class ST, class CT>
+__device__ __forceinline__ CT ld_pop(const void* base, long k, int kind) {
+    if constexpr (std::is_same<CT, float>::value) {
+        if (kind == P_F16) return Cv<__half, float>::ld(static_cast<const __half*>(base) + k);
+        if (kind == P_F32) return Cv<float, float>::ld(static_cast<const float*>(base) + k);
+    }
+    return Cv<ST, CT>::ld(static_cast<const ST*>(base) + k);
+}
+
 template <class ST, class CT>
 __device__ __forceinline__ CT coarse_val(const StepArgs<ST, CT>& a, int i, int gx, int gy) {
     const long cc = (long)((gy >> 1) - a.cbox.gy0) * a.cbox.pitch + ((gx >> 1) - a.cbox.gx0);
-    return Cv<ST, CT>::ld(a.fcoarse + i * a.cbox.plane + cc);
+    return ld_pop<ST, CT>(a.fcoarse, i * a.cbox.plane + cc, a.cst);
+}
+
+// coalescence: mean of the four children of the finer band, for each direction
+template <class FT, class CT>
+__device__ __forceinline__ void coalesce(const FT* f, long plane, long pitch, long f0, CT s[9]) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const FT* p = f + i * plane + f0;
+        s[i] = CT(0.25) * ((Cv<FT, CT>::ld(p) + Cv<FT, CT>::ld(p + 1)) +
+                           (Cv<FT, CT>::ld(p + pitch) + Cv<FT, CT>::ld(p + pitch + 1)));
+    }
 }
 
 // Pull of direction i into (gx, gy): domain rules of level 0 (periodic wrap,
@@ -803,11 +827,15 @@ __device__ __forceinline__ void step_block(const StepArgs<ST, CT>& a, const int 
         if (fl & F_IFACE) {
             // coalescence: mean of the four children of the finer band
             const long f0 = (long)(2 * gy - a.fbox.gy0) * a.fbox.pitch + (2 * gx - a.fbox.gx0);
-#pragma unroll
-            for (int i = 0; i < 9; ++i) {
-                const ST* p = a.ffine + i * a.fbox.plane + f0;
-                s[i] = CT(0.25) * ((Cv<ST, CT>::ld(p) + Cv<ST, CT>::ld(p + 1)) +
-                                   (Cv<ST, CT>::ld(p + a.fbox.pitch) + Cv<ST, CT>::ld(p + a.fbox.pitch + 1)));
+            if constexpr (std::is_same<CT, float>::value) {
+                if (a.fst == P_F16)
+                    coalesce<__half, CT>(static_cast<const __half*>(a.ffine), a.fbox.plane, a.fbox.pitch, f0, s);
+                else if (a.fst == P_F32)
+                    coalesce<float, CT>(static_cast<const float*>(a.ffine), a.fbox.plane, a.fbox.pitch, f0, s);
+                else
+                    coalesce<ST, CT>(static_cast<const ST*>(a.ffine), a.fbox.plane, a.fbox.pitch, f0, s);
+            } else {
+                coalesce<ST, CT>(static_cast<const ST*>(a.ffine), a.fbox.plane, a.fbox.pitch, f0, s);
             }
         } else if ((fl & F_NEARGHOST) && a.substep == 1) {
             // next to the fine band on the first sub-step: exploded coarse populations
