@@ -131,10 +131,9 @@ def run_sweep(args):
     per = [batch.steps_per_super_step(k) for k in range(len(cases))]
     lups = batch.lups_per_super_step()
     lmax = max(c["n_levels"] for c in cases)
-    launches = 2 ** lmax - 1
     if args.graph:
         batch.use_graph(True)
-    log(f"{n_cells} cells, {lups} cell updates per super step ({launches} launches); warmup {args.warmup}")
+    log(f"{n_cells} cells, {lups} cell updates per super step; warmup {args.warmup}")
     batch.advance(args.warmup)
     batch.synchronize()
     torch.cuda.synchronize()
@@ -148,8 +147,9 @@ def run_sweep(args):
     batch.synchronize()
     kt = batch.profile(False)
     batch.close()
+    launches = kt[3] if kt[3] > 0 else 2 ** lmax - 1            # per super step
     log(f"batched: {args.steps} super steps in {dt:.3f} s; k_step_batch {kt[0]:.2f} us/launch, "
-        f"finest {kt[1]:.2f}, level 0 {kt[2]:.2f}")
+        f"finest {kt[1]:.2f}, level 0 {kt[2]:.2f}, {launches:.0f} launches per super step")
     # the same cases one after another, each with its own graph
     seq = 0.0
     for s, p in zip(sims, per):
@@ -174,6 +174,7 @@ def run_sweep(args):
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                 "kernel": "k_step_batch (all virtual levels)", "avg_launch_us": round(kt[0], 3),
+                "launches_per_step": round(launches, 2),
                 "finest_level_avg_launch_us": round(kt[1], 3), "level0_avg_launch_us": round(kt[2], 3),
                 "alg_bytes_per_launch": round(bytes_per_launch, 0)}
     out = {
@@ -261,8 +262,8 @@ def main():
     sim.advance(args.steps)
     sim.synchronize()
     kt = sim.profile(False)
-    log(f"event-timed kernels (us/launch): k_step all levels {kt[0]:.2f}, finest {kt[1]:.2f}, "
-        f"level 0 {kt[2]:.2f}")
+    log(f"event-timed kernels (us/launch): all launches {kt[0]:.2f}, finest {kt[1]:.2f}, "
+        f"level 0 {kt[2]:.2f}; {kt[3]:.1f} launches per coarse step")
     mlups = lups * args.steps / dt / 1e6
     f = sim.forces()
     n_cells = int(sum(sim.level_info(l)["n_fluid"] for l in range(case["n_levels"])))
@@ -272,7 +273,7 @@ def main():
     # roofline of the dominant kernel (k_step, all levels): algorithmic bytes per
     # launch = ALG_BYTES x cell updates per launch; duration from the HIP events
     n_levels = case["n_levels"]
-    launches_per_step = sum(2 ** l for l in range(n_levels))
+    launches_per_step = kt[3] if kt[3] > 0 else sum(2 ** l for l in range(n_levels))
     bytes_per_launch = step_bytes(args.storage, sim, n_levels) / launches_per_step
     roof = None
     if kt[0] > 0:
@@ -281,7 +282,8 @@ def main():
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None if traffic is None else round(traffic, 0),
-                "kernel": "k_step (all levels)", "avg_launch_us": round(kt[0], 3),
+                "kernel": "k_step_batch (merged schedule, all levels)", "avg_launch_us": round(kt[0], 3),
+                "launches_per_step": round(launches_per_step, 2),
                 "finest_level_avg_launch_us": round(kt[1], 3),
                 "level0_avg_launch_us": round(kt[2], 3),
                 "alg_bytes_per_launch": round(bytes_per_launch, 0)}
@@ -307,10 +309,11 @@ def main():
             v.synchronize()
             ktv = v.profile(False)
             per_lup = step_bytes(st, v, n_levels) / lups
-            ach = per_lup * lups / launches_per_step / (ktv[0] * 1e-6) / 1e9 if ktv[0] > 0 else None
+            lv = ktv[3] if ktv[3] > 0 else launches_per_step
+            ach = per_lup * lups / lv / (ktv[0] * 1e-6) / 1e9 if ktv[0] > 0 else None
             variants[st] = {"value": round(lups * args.steps / dtv / 1e6, 1), "unit": "MLUPS",
                             "ms_per_step": round(1000 * dtv / args.steps, 4),
-                            "k_step_avg_launch_us": round(ktv[0], 3),
+                            "k_step_avg_launch_us": round(ktv[0], 3), "launches_per_step": round(lv, 2),
                             "achieved_GBps": None if ach is None else round(ach, 1),
                             "frac": None if ach is None else round(ach / HBM_PEAK_GBS, 4),
                             "alg_bytes_per_lup": round(per_lup, 2)}

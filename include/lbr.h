@@ -257,18 +257,27 @@ int lbr_load(lbr_ctx* ctx, const char* path);
 /* Cell updates per coarse step: sum over levels of n_fluid * 2^l. */
 int64_t lbr_lups_per_coarse_step(lbr_ctx* ctx);
 
-/* Captures one coarse step in a HIP graph and replays it in lbr_advance
-   (enable != 0), or returns to direct launches (enable == 0). */
+/* enable != 0: after the start-up ramp, lbr_advance replays two coarse steps
+   at a time from a HIP graph of the merged launch schedule; enable == 0:
+   direct launches of the recursive cycle (Section 2.1), one k_step launch per
+   level sub-step.  The merged schedule runs each sub-step of a level at least
+   three below the finest inside the grid of the next launch of a finer level
+   (the two touch disjoint state: the coarse step reads its parent, itself and
+   its child, writes itself and the restriction into its parent), so a coarse
+   step of an 8-level grid takes 195 launches instead of 255.  Every cell is
+   computed by the same code from the same state as in the direct cycle: the
+   results are bit-identical. */
 int lbr_use_graph(lbr_ctx* ctx, int32_t enable);
 
-/* Average device time per launch of the step kernel k_step over the last
+/* Average device time per launch of the step kernel over the last
    lbr_advance, in microseconds, from start / stop events attached to each
-   dispatch (hipExtLaunchKernelGGL): out[0] all levels, out[1] the finest
-   level, out[2] level 0, out[3] unused (0).  One k_step launch covers a whole
-   level sub-step: tiles, wall nodes and domain-edge cells.  enable != 0 turns
-   the timing on for the following lbr_advance calls (direct launches: the
-   graph is not replayed while timing); enable == 0 turns it off.  out may be
-   NULL; it receives the figures of the last timed lbr_advance. */
+   dispatch (hipExtLaunchKernelGGL): out[0] all launches, out[1] the launches
+   that step the finest level, out[2] those of level 0 alone, out[3] launches
+   per coarse step.  After the start-up ramp the timed run uses the merged
+   schedule of lbr_use_graph, launched directly (the graph is not replayed
+   while timing).  enable != 0 turns the timing on for the following
+   lbr_advance calls; enable == 0 turns it off.  out may be NULL; it receives
+   the figures of the last timed lbr_advance. */
 int lbr_profile(lbr_ctx* ctx, int32_t enable, double out[4]);
 
 /* Last error message of the context (never NULL). */

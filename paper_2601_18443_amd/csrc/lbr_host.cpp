@@ -108,11 +108,10 @@ struct lbr_ctx {
     std::vector<void*> allocs;
     int64_t resid_steps = 0;
     bool resid_init = false;
-    // graph replay of one coarse step (two when level 0 alternates buffers)
+    // after the start-up ramp, graph replay and timed runs go through a batch of
+    // this one case (the merged launch schedule)
     bool use_graph = false;
-    hipGraphExec_t graph = nullptr;
-    int graph_steps = 0;
-    int graph_parity = 0;          // buffer index of level 0 the graph was captured with
+    lbr_batch* self = nullptr;
     int64_t step_count = 0;        // coarse steps completed (start-up ramp)
     // profiling
     bool prof = false;
@@ -1085,31 +1084,9 @@ int surface_eval(lbr_ctx* c, int body, double* cp, double* cf, double sums[4]) {
     return 0;
 }
 
-int capture_graph(lbr_ctx* c) {
-    if (c->graph) { (void)hipGraphExecDestroy(c->graph); c->graph = nullptr; }
-    // level 0 takes one step per coarse step, so two coarse steps bring every
-    // level back to the same buffer parity
-    c->graph_steps = 2;
-    const bool prof = c->prof;
-    c->prof = false;
-    hipGraph_t g;
-    HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-    int r = 0;
-    for (int k = 0; k < c->graph_steps && !r; ++k) r = cycle(c, 0, 0);
-    hipError_t e = hipStreamEndCapture(c->stream, &g);
-    c->prof = prof;
-    if (r) return r;
-    if (e != hipSuccess) return set_err(c, LBR_ERR_HIP, "graph capture: %s", hipGetErrorString(e));
-    // capture advanced the buffer indices without running: undo
-    for (Level& L : c->lv) L.cur ^= (c->graph_steps << L.l) & 1;
-    // the graph holds the buffer addresses of this parity; finer levels take an
-    // even number of sub-steps per coarse step, so level 0 alone decides it
-    c->graph_parity = c->lv[0].cur;
-    e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (e != hipSuccess) return set_err(c, LBR_ERR_HIP, "graph instantiate: %s", hipGetErrorString(e));
-    return 0;
-}
+// Advances a case past its start-up ramp through the merged schedule of a
+// batch of that case alone (defined with the batch code).
+int self_advance(lbr_ctx* c, int64_t n);
 
 }  // namespace
 
@@ -1264,20 +1241,12 @@ int lbr_advance(lbr_ctx* c, int64_t n) {
         if (int r = cycle(c, 0, 0)) return r;
         c->step_count++;
     }
-    if (c->use_graph && !c->prof && k < n) {
-        if (!c->graph)
-            if (int r = capture_graph(c)) return r;
-        // after an odd number of direct coarse steps, one more restores the parity
-        if (c->lv[0].cur != c->graph_parity && n - k > c->graph_steps) {
-            if (int r = cycle(c, 0, 0)) return r;
-            c->step_count++;
-            ++k;
-        }
-        for (; k + c->graph_steps <= n && c->lv[0].cur == c->graph_parity; k += c->graph_steps) {
-            HIPCHK(c, hipGraphLaunch(c->graph, c->stream));
-            for (Level& L : c->lv) L.cur ^= (c->graph_steps << L.l) & 1;
-            c->step_count += c->graph_steps;
-        }
+    const int64_t ramp_done = k;
+    if (k < n && (c->use_graph || c->prof)) {
+        // the merged schedule keeps its own step and residual counts
+        if (int r = self_advance(c, n - k)) return r;
+        c->resid_steps += ramp_done;
+        return LBR_OK;
     }
     for (; k < n; ++k) {
         if (int r = cycle(c, 0, 0)) return r;
@@ -1296,7 +1265,8 @@ int lbr_advance(lbr_ctx* c, int64_t n) {
             cnt[kind]++;
             if (kind != EV_STEP) { sum[EV_STEP] += ms; cnt[EV_STEP]++; }
         }
-        for (int f = 0; f < 4; ++f) c->prof_out[f] = cnt[f] ? 1000.0 * sum[f] / cnt[f] : 0.0;
+        for (int f = 0; f < 3; ++f) c->prof_out[f] = cnt[f] ? 1000.0 * sum[f] / cnt[f] : 0.0;
+        c->prof_out[3] = n ? (double)(c->ev_used / 2) / (double)n : 0.0;
     }
     return LBR_OK;
 }
@@ -1628,10 +1598,6 @@ int64_t lbr_lups_per_coarse_step(lbr_ctx* c) {
 int lbr_use_graph(lbr_ctx* c, int32_t enable) {
     if (!c) return LBR_ERR_INVALID_ARG;
     c->use_graph = enable != 0;
-    if (!c->use_graph && c->graph) {
-        (void)hipGraphExecDestroy(c->graph);
-        c->graph = nullptr;
-    }
     return LBR_OK;
 }
 
@@ -1648,7 +1614,7 @@ const char* lbr_last_error(const lbr_ctx* c) { return c ? c->err.c_str() : "null
 void lbr_destroy(lbr_ctx* c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
-    if (c->graph) (void)hipGraphExecDestroy(c->graph);
+    lbr_batch_destroy(c->self);
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     for (void* p : c->allocs) {
         if (c->cfg.free_fn) c->cfg.free_fn(p, c->cfg.alloc_user);
@@ -1666,12 +1632,16 @@ struct lbr_batch {
     std::vector<lbr_ctx*> all;         // the cases, in the caller's order
     std::vector<lbr_ctx*> cases;       // the cases the launch tables cover
     int lmax = 0;
+    bool merge = true;                 // coarse launches ride along with finer ones
     hipStream_t stream = nullptr;
     // one launch: its StepArgs start at byte off of the table, its part starts
-    // at index part0; every part of a launch has the same population storage
+    // at index part0; every part of a launch has the same population storage;
+    // v is the virtual level of its finest part
     struct Launch { size_t off; int part0, nparts, nblocks, v; Prec st; };
-    std::vector<Launch> launches;      // the launches of two super steps, in order
-    int per_super = 0;                 // launches per super step
+    std::vector<Launch> launches;      // the launches of all tables, in order
+    // tables: [0] one super step from parity 0, [1] one from parity 1, [2] two
+    // from parity 0; each ends with every launch of its super steps issued
+    int table[3][2] = {{0, 0}, {0, 0}, {0, 0}};
     void* parts_dev = nullptr;         // StepArgs of every part of every launch
     int* start_dev = nullptr;          // first block of each part, relative to its launch
     int parity = 0;                    // super steps advanced since the tables were built, modulo 2
@@ -1679,7 +1649,7 @@ struct lbr_batch {
     std::vector<hipEvent_t> ev;        // ordering between the case streams and the batch stream
     bool use_graph = false;
     bool ready = false;                // launch tables built and uploaded
-    hipGraphExec_t graph = nullptr;
+    hipGraphExec_t graph = nullptr;    // table 2
     bool prof = false;                 // start / stop events on every launch
     std::vector<hipEvent_t> pev;
     std::vector<int> pev_v;            // virtual level of each event pair
@@ -1706,53 +1676,113 @@ void batch_schedule(lbr_batch* b, int v, int substep, std::vector<std::pair<int,
     seq.push_back({v, substep});
 }
 
-// Launch tables of two super steps for the covered cases, from their current
-// state: the host replays the buffer flips each launch makes, and two super
-// steps bring every buffer index back.
+// One level sub-step of the recursive cycle over every covered case: the
+// StepArgs of each case's part and its block count.
+struct Item {
+    int v;
+    Prec st;
+    size_t size;                       // bytes of one part's StepArgs
+    std::vector<unsigned char> args;   // parts, back to back
+    std::vector<int> blocks;
+};
+
+// Launch groups of items [begin, end), in order.  An item of a virtual level at
+// least three below the finest is deferred and joins the next launch of a
+// finer level (same storage), one deferred item per launch, first in first out.
+// This keeps every dependency of the recursive cycle: a deferred level w is
+// read by its child w + 1 (explosion, ghost values) and by its parent w - 1
+// (coalescence, restriction), and it writes only level w and the restriction
+// into w - 1; its partner is a level of at least w + 2, which touches none of
+// these, and before any later item of level w + 1 the pending items up to the
+// last one of level w are launched on their own.  Deferred items of the chain
+// w, w - 1, ... keep their order.  The buffers each item addresses are those
+// of its place in the unmerged cycle, which the merged order preserves.
+std::vector<std::vector<int>> batch_groups(const lbr_batch* b, const std::vector<Item>& it, int begin, int end) {
+    std::vector<std::vector<int>> g;
+    std::vector<int> pend;                                   // FIFO
+    size_t head = 0;
+    for (int k = begin; k < end; ++k) {
+        const Item& x = it[k];
+        if (b->merge && x.v <= b->lmax - 3) {
+            pend.push_back(k);
+            continue;
+        }
+        size_t last = head;
+        for (size_t j = head; j < pend.size(); ++j)
+            if (it[pend[j]].v == x.v - 1) last = j + 1;
+        for (; head < last; ++head) g.push_back({pend[head]});
+        if (head < pend.size() && it[pend[head]].st == x.st) g.push_back({k, pend[head++]});
+        else g.push_back({k});
+    }
+    for (; head < pend.size(); ++head) g.push_back({pend[head]});
+    return g;
+}
+
+// Launch tables for the covered cases, from their current state: the host
+// fills the arguments of every item in the unmerged order while replaying the
+// buffer flips each launch makes (two super steps bring every index back),
+// then groups the items of each table into launches.
 int batch_build(lbr_batch* b) {
     std::vector<std::pair<int, int>> seq;
     batch_schedule(b, 0, 0, seq);
-    b->per_super = (int)seq.size();
-    std::vector<unsigned char> parts;
-    std::vector<int> starts;
-    b->launches.clear();
+    const int per = (int)seq.size();
+    std::vector<Item> items;
     alignas(16) unsigned char buf[sizeof(StepArgs<double, double>)];
     for (int rep = 0; rep < 2; ++rep)
         for (const auto& vs : seq) {
-            lbr_batch::Launch ln{parts.size(), (int)starts.size(), 0, 0, vs.first, P_F32};
+            Item x{vs.first, P_F32, 0, {}, {}};
             for (lbr_ctx* c : b->cases) {
                 const int l = vs.first - (b->lmax - (int)c->lv.size());
                 if (l < 0) continue;
                 Level& L = c->lv[l];
-                if (ln.nparts == 0) ln.st = L.st;
-                else if (L.st != ln.st)
+                if (x.blocks.empty()) x.st = L.st;
+                else if (L.st != x.st)
                     return bset_err(b, LBR_ERR_INVALID_ARG, "cases store one virtual level in different formats");
                 const int sub = l == 0 ? 0 : vs.second;       // a case's level 0 has no parent
                 int wb = 0, tb = 0;
-                size_t sz = 0;
                 switch (L.st) {
                     case P_F64: { auto& a = *reinterpret_cast<StepArgs<double, double>*>(buf);
-                        fill_step_args(c, l, sub, a); wb = a.wall_blocks; tb = a.tile_blocks; sz = sizeof a; break; }
+                        fill_step_args(c, l, sub, a); wb = a.wall_blocks; tb = a.tile_blocks; x.size = sizeof a; break; }
                     case P_F32: { auto& a = *reinterpret_cast<StepArgs<float, float>*>(buf);
-                        fill_step_args(c, l, sub, a); wb = a.wall_blocks; tb = a.tile_blocks; sz = sizeof a; break; }
+                        fill_step_args(c, l, sub, a); wb = a.wall_blocks; tb = a.tile_blocks; x.size = sizeof a; break; }
                     case P_F16: { auto& a = *reinterpret_cast<StepArgs<__half, float>*>(buf);
-                        fill_step_args(c, l, sub, a); wb = a.wall_blocks; tb = a.tile_blocks; sz = sizeof a; break; }
+                        fill_step_args(c, l, sub, a); wb = a.wall_blocks; tb = a.tile_blocks; x.size = sizeof a; break; }
                     default: { auto& a = *reinterpret_cast<StepArgs<__hip_bfloat16, float>*>(buf);
-                        fill_step_args(c, l, sub, a); wb = a.wall_blocks; tb = a.tile_blocks; sz = sizeof a; break; }
+                        fill_step_args(c, l, sub, a); wb = a.wall_blocks; tb = a.tile_blocks; x.size = sizeof a; break; }
                 }
                 // parts start on multiples of 8 blocks, so that each part's own
                 // block-to-XCD mapping holds inside the shared grid
                 const int eb = 8 * (((int)L.edge.size() + 8 * TILE_X * TILE_Y - 1) / (8 * TILE_X * TILE_Y));
-                parts.insert(parts.end(), buf, buf + sz);
-                starts.push_back(ln.nblocks);
-                ln.nblocks += wb + tb + eb;
-                ln.nparts++;
+                x.args.insert(x.args.end(), buf, buf + x.size);
+                x.blocks.push_back(wb + tb + eb);
                 L.cur ^= 1;                                   // as the launch will
                 if (l == 0) c->step_count++;
             }
-            b->launches.push_back(ln);
+            items.push_back(std::move(x));
         }
     for (lbr_ctx* c : b->cases) c->step_count -= 2 * (int64_t(1) << (b->lmax - (int)c->lv.size()));
+
+    std::vector<unsigned char> parts;
+    std::vector<int> starts;
+    b->launches.clear();
+    const int range[3][2] = {{0, per}, {per, 2 * per}, {0, 2 * per}};
+    for (int t = 0; t < 3; ++t) {
+        b->table[t][0] = (int)b->launches.size();
+        for (const auto& grp : batch_groups(b, items, range[t][0], range[t][1])) {
+            lbr_batch::Launch ln{parts.size(), (int)starts.size(), 0, 0, items[grp[0]].v, items[grp[0]].st};
+            for (int k : grp) {
+                const Item& x = items[k];
+                parts.insert(parts.end(), x.args.begin(), x.args.end());
+                for (int nb : x.blocks) {
+                    starts.push_back(ln.nblocks);
+                    ln.nblocks += nb;
+                    ln.nparts++;
+                }
+            }
+            b->launches.push_back(ln);
+        }
+        b->table[t][1] = (int)b->launches.size();
+    }
     lbr_ctx* c0 = b->all[0];
     b->parts_dev = dalloc(c0, std::max<size_t>(parts.size(), 16));
     b->start_dev = static_cast<int*>(dalloc(c0, std::max<size_t>(starts.size(), 1) * sizeof(int)));
@@ -1777,10 +1807,12 @@ int batch_cover(lbr_batch* b, const std::vector<lbr_ctx*>& cases) {
     b->ready = false;
     b->cases = cases;
     b->lmax = 0;
+    b->merge = true;
     b->cur0.clear();
     for (lbr_ctx* c : cases) {
         b->lmax = std::max(b->lmax, (int)c->lv.size());
         b->cur0.push_back(c->lv[0].cur);
+        if (c->cfg.storage == LBR_STORE_MIXED) b->merge = false;   // no finer partner of the same format
     }
     b->parity = 0;
     return batch_build(b);
@@ -1799,10 +1831,9 @@ hipEvent_t* batch_prof_events(lbr_batch* b, int v) {
     return e;
 }
 
-int batch_super_step(lbr_batch* b) {
-    const int first = b->parity * b->per_super;
-    for (int k = 0; k < b->per_super; ++k) {
-        const lbr_batch::Launch& ln = b->launches[first + k];
+int batch_table(lbr_batch* b, int t) {
+    for (int k = b->table[t][0]; k < b->table[t][1]; ++k) {
+        const lbr_batch::Launch& ln = b->launches[k];
         const void* parts = static_cast<const unsigned char*>(b->parts_dev) + ln.off;
         Timing tm;
         if (b->prof)
@@ -1859,29 +1890,22 @@ int batch_release_cases(lbr_batch* b) {
 
 int batch_run(lbr_batch* b, int64_t n) {
     int64_t k = 0;
-    if (b->use_graph && !b->prof && n >= 2) {
+    if (k < n && b->parity == 1) {
+        if (int r = batch_table(b, 1)) return r;
+        batch_account(b);
+        ++k;
+    }
+    if (n - k >= 2 && b->use_graph && !b->prof) {
         if (!b->graph) {
             hipGraph_t g;
             if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
                 return bset_err(b, LBR_ERR_HIP, "batch graph capture failed");
-            const int p = b->parity;
-            int r = 0;
-            b->parity = 0;                                    // the graph starts at parity 0
-            for (int s = 0; s < 2 && !r; ++s) {
-                r = batch_super_step(b);
-                b->parity ^= 1;
-            }
-            b->parity = p;
+            const int r = batch_table(b, 2);
             if (hipStreamEndCapture(b->stream, &g) != hipSuccess || r)
                 return bset_err(b, LBR_ERR_HIP, "batch graph capture failed");
             const hipError_t e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
             (void)hipGraphDestroy(g);
             if (e != hipSuccess) return bset_err(b, LBR_ERR_HIP, "batch graph instantiate failed");
-        }
-        if (b->parity != 0) {
-            if (int r = batch_super_step(b)) return r;
-            batch_account(b);
-            ++k;
         }
         for (; k + 2 <= n; k += 2) {
             if (hipGraphLaunch(b->graph, b->stream) != hipSuccess)
@@ -1890,11 +1914,42 @@ int batch_run(lbr_batch* b, int64_t n) {
             batch_account(b);
         }
     }
-    for (; k < n; ++k) {
-        if (int r = batch_super_step(b)) return r;
+    for (; k + 2 <= n; k += 2) {
+        if (int r = batch_table(b, 2)) return r;
+        batch_account(b);
+        batch_account(b);
+    }
+    if (k < n) {
+        if (int r = batch_table(b, 0)) return r;
         batch_account(b);
     }
     return 0;
+}
+
+int batch_advance(lbr_batch* b, int64_t n) {
+    if (n < 0) return bset_err(b, LBR_ERR_INVALID_ARG, "negative step count");
+    if (!b->ready) return bset_err(b, LBR_ERR_STATE, "batch launch tables missing");
+    if (int r = batch_check(b)) return r;
+    if (int r = batch_wait_cases(b)) return r;
+    b->pev_used = 0;
+    if (int r = batch_run(b, n)) return r;
+    if (b->prof && b->pev_used) {
+        if (hipStreamSynchronize(b->stream) != hipSuccess) return bset_err(b, LBR_ERR_HIP, "synchronize failed");
+        double sum[3] = {0, 0, 0};
+        int cnt[3] = {0, 0, 0};
+        for (size_t i = 0; i + 1 < b->pev_used; i += 2) {
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, b->pev[i], b->pev[i + 1]);
+            const int v = b->pev_v[i];
+            sum[0] += ms;
+            cnt[0]++;
+            if (v == b->lmax - 1) { sum[1] += ms; cnt[1]++; }
+            if (v == 0) { sum[2] += ms; cnt[2]++; }
+        }
+        for (int f = 0; f < 3; ++f) b->prof_out[f] = cnt[f] ? 1000.0 * sum[f] / cnt[f] : 0.0;
+        b->prof_out[3] = n ? (double)(b->pev_used / 2) / (double)n : 0.0;
+    }
+    return batch_release_cases(b);
 }
 
 }  // namespace
@@ -1930,29 +1985,7 @@ int lbr_batch_create(int32_t n, lbr_ctx* const* cases, lbr_batch** out) {
 
 int lbr_batch_advance(lbr_batch* b, int64_t n) {
     if (!b) return LBR_ERR_INVALID_ARG;
-    if (n < 0) return bset_err(b, LBR_ERR_INVALID_ARG, "negative step count");
-    if (!b->ready) return bset_err(b, LBR_ERR_STATE, "batch launch tables missing");
-    if (int r = batch_check(b)) return r;
-    if (int r = batch_wait_cases(b)) return r;
-    b->pev_used = 0;
-    if (int r = batch_run(b, n)) return r;
-    if (b->prof && b->pev_used) {
-        if (hipStreamSynchronize(b->stream) != hipSuccess) return bset_err(b, LBR_ERR_HIP, "synchronize failed");
-        double sum[3] = {0, 0, 0};
-        int cnt[3] = {0, 0, 0};
-        for (size_t i = 0; i + 1 < b->pev_used; i += 2) {
-            float ms = 0;
-            (void)hipEventElapsedTime(&ms, b->pev[i], b->pev[i + 1]);
-            const int v = b->pev_v[i];
-            sum[0] += ms;
-            cnt[0]++;
-            if (v == b->lmax - 1) { sum[1] += ms; cnt[1]++; }
-            if (v == 0) { sum[2] += ms; cnt[2]++; }
-        }
-        for (int f = 0; f < 3; ++f) b->prof_out[f] = cnt[f] ? 1000.0 * sum[f] / cnt[f] : 0.0;
-        b->prof_out[3] = 0.0;
-    }
-    return batch_release_cases(b);
+    return batch_advance(b, n);
 }
 
 int lbr_batch_run_to_steady(lbr_batch* b, double tol, int64_t max_super_steps, int64_t check_every,
@@ -1971,7 +2004,7 @@ int lbr_batch_run_to_steady(lbr_batch* b, double tol, int64_t max_super_steps, i
     int64_t done = 0;
     while (!rc && done < max_super_steps && !active.empty()) {
         const int64_t k = std::min(check_every, max_super_steps - done);
-        if ((rc = lbr_batch_advance(b, k))) break;
+        if ((rc = batch_advance(b, k))) break;
         done += k;
         std::vector<lbr_ctx*> keep;
         for (size_t j = 0; j < n && !rc; ++j) {
@@ -2045,3 +2078,35 @@ void lbr_batch_destroy(lbr_batch* b) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// a context past its start-up ramp, through the merged schedule
+// ---------------------------------------------------------------------------
+namespace {
+
+int self_advance(lbr_ctx* c, int64_t n) {
+    if (!c->self) {
+        lbr_ctx* one[1] = {c};
+        lbr_batch* b = nullptr;
+        const int r = lbr_batch_create(1, one, &b);
+        if (r) {
+            set_err(c, r, "merged schedule: %s", b ? b->err.c_str() : "batch creation failed");
+            lbr_batch_destroy(b);
+            return r;
+        }
+        c->self = b;
+    } else if (batch_check(c->self)) {
+        // the case was stepped by an odd count outside the schedule (ramp, direct
+        // launches, a checkpoint load): rebuild the tables from its state
+        if (int r = batch_cover(c->self, c->self->all)) return set_err(c, r, "merged schedule: %s", c->self->err.c_str());
+    }
+    lbr_batch* b = c->self;
+    b->use_graph = c->use_graph;
+    b->prof = c->prof;
+    if (int r = batch_advance(b, n)) return set_err(c, r, "merged schedule: %s", b->err.c_str());
+    if (c->prof)
+        for (int f = 0; f < 4; ++f) c->prof_out[f] = b->prof_out[f];
+    return 0;
+}
+
+}  // namespace

@@ -115,25 +115,38 @@ def test_refined_box_conserves_mass_on_gpu():
     assert abs(mass() - m0) / m0 < 1e-14
 
 
-@pytest.mark.parametrize("storage", ["f64", "f32"])
-def test_graph_replay_matches_direct_launches(storage):
-    """Graph replays interleaved with odd numbers of direct coarse steps give the
-    same fields, bit for bit, as the same number of direct steps."""
-    case = LI.case_airfoil_small()
+@pytest.mark.parametrize("storage,levels", [("f64", 3), ("f32", 3), ("f32", 6), ("f16", 6)])
+def test_graph_replay_matches_direct_launches(storage, levels):
+    """The merged schedule (coarse sub-steps inside the launches of finer ones),
+    replayed from a graph with odd numbers of steps in between, and launched
+    directly under timing, gives the same fields, bit for bit, as the direct
+    recursive cycle."""
+    case = (LI.case_airfoil_small() if levels == 3 else
+            LI.case_airfoil(seed=3, finest_cells_per_chord=256, n_levels=levels, domain_chords=8.0,
+                            band_finest=0.0625, n_side=256))
     a = U.gpu_solver(case, storage)
     b = U.gpu_solver(case, storage)
+    c = U.gpu_solver(case, storage)
     a.use_graph(True)
     for n in (1, 3, 2, 1, 5, 4):
         a.advance(n)
         a.synchronize()
         a.field(case["n_levels"] - 1, 1)       # eager work between replays
     b.advance(16)
-    for l in range(case["n_levels"]):
-        for f in (0, 1, 2, 3):
-            x, y = a.field(l, f), b.field(l, f)
-            assert np.array_equal(np.isnan(x), np.isnan(y))
-            m = ~np.isnan(x)
-            assert np.array_equal(x[m], y[m]), (l, f)
+    c.profile(True)
+    c.advance(7)
+    c.advance(9)
+    kt = c.profile(False)
+    full = 2 ** levels - 1
+    assert kt[3] < full if levels >= 3 else kt[3] == full   # merged launches per coarse step
+    for s in (a, c):
+        for l in range(case["n_levels"]):
+            for f in (0, 1, 2, 3):
+                x, y = s.field(l, f), b.field(l, f)
+                assert np.array_equal(np.isnan(x), np.isnan(y))
+                m = ~np.isnan(x)
+                assert np.array_equal(x[m], y[m]), (l, f)
+        assert np.array_equal(s.forces(), b.forces())
 
 
 @pytest.mark.parametrize("variant", [
