@@ -47,7 +47,7 @@ def step_bytes(storage, sim, n_levels, repeat=1):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_airfoil_2M_traffic.txt")
-KERNEL_SRC = os.path.join(ROOT, "paper_2601_18443_amd", "csrc", "lbr_kernels.hip")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2601_18443_amd", "csrc", f) for f in ("lbr_kernels.hip", "lbr_host.cpp")]
 
 
 def log(msg):
@@ -55,8 +55,12 @@ def log(msg):
 
 
 def kernel_source_hash():
-    with open(KERNEL_SRC, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    """Hash of the kernels and of the host code that lays out their launches."""
+    h = hashlib.sha256()
+    for f in KERNEL_SRCS:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(storage):
@@ -69,7 +73,7 @@ def measured_traffic(storage):
         if "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
             vals[k.strip()] = v.strip()
-    if vals.get("kernel_source_sha256") != kernel_source_hash() or vals.get("storage") != storage:
+    if vals.get("source_sha256") != kernel_source_hash() or vals.get("storage") != storage:
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])

@@ -4,10 +4,10 @@ Two reports:
 
 ``stats DIR``
     the per-kernel table of ``--kernel-trace --stats`` (``*kernel_stats.csv``),
-    plus a per-launch-size breakdown of k_step from ``*kernel_trace.csv`` (one
-    grid size per level);
+    plus a per-launch-size breakdown of the step kernels from
+    ``*kernel_trace.csv``;
 ``traffic``
-    HBM bytes per k_step dispatch from two ``--pmc`` runs (FETCH_SIZE, then
+    HBM bytes per step-kernel dispatch from two ``--pmc`` runs (FETCH_SIZE, then
     WRITE_SIZE, in KiB per dispatch), each scaled by what the same counter reads
     for a device copy of known size (``bench.py --copy-calibration``).
 
@@ -30,12 +30,16 @@ import sys
 from collections import defaultdict
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SRC = os.path.join(_HERE, "csrc", "lbr_kernels.hip")
+# the kernels and the host code that lays out their launches
+SOURCES = [os.path.join(_HERE, "csrc", f) for f in ("lbr_kernels.hip", "lbr_host.cpp")]
 
 
 def kernel_source_hash():
-    with open(KERNEL_SRC, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def short_name(name):
@@ -93,7 +97,7 @@ def stats(directory, cmd):
                     g = int(_col(r, "Grid_Size_X", "Grid_Size", "Grid_X"))
                     d = float(_col(r, "End_Timestamp")) - float(_col(r, "Start_Timestamp"))
                     per[(n, g)].append(d)
-        out += ["", "k_step by launch size (one grid size per level)",
+        out += ["", "step kernels by launch size",
                 f"{'kernel':34s} {'threads':>9s} {'blocks':>7s} {'calls':>7s} {'avg us':>9s} {'median us':>10s}"]
         for (n, g), v in sorted(per.items(), key=lambda kv: -kv[0][1]):
             v.sort()
@@ -119,7 +123,7 @@ def _counter(directory, counter, match):
 
 
 def traffic(a):
-    is_step = lambda n: n.startswith("k_step")                       # noqa: E731
+    is_step = lambda n: n.split("<")[0] == a.kernel                  # noqa: E731
     is_copy = lambda n: "copy" in n.lower()                           # noqa: E731
     fetch = _counter(a.fetch, "FETCH_SIZE", is_step)
     write = _counter(a.write, "WRITE_SIZE", is_step)
@@ -133,15 +137,16 @@ def traffic(a):
     wfac = a.copy_bytes / (max(cw) * 1024.0)
     hbm = f_kib * 1024.0 * ffac + w_kib * 1024.0 * wfac
     lines = [
-        "# HBM traffic of k_step (all levels), rocprofv3 --pmc, per dispatch",
+        f"# HBM traffic of {a.kernel} (all levels), rocprofv3 --pmc, per dispatch",
         f"# fetch run: {a.cmd_fetch}",
         f"# write run: {a.cmd_write}",
         f"# calibration runs: {a.cmd_cal}",
-        "# FETCH_SIZE / WRITE_SIZE are averaged over the k_step dispatches and scaled by",
+        f"# FETCH_SIZE / WRITE_SIZE are averaged over the {a.kernel} dispatches and scaled by",
         "# copy bytes / counter reading of a device copy of known size.",
-        f"kernel_source_sha256 = {kernel_source_hash()}",
+        f"source_sha256 = {kernel_source_hash()}",
         f"storage = {a.storage}",
-        f"k_step_dispatches = {len(fetch)}",
+        f"kernel = {a.kernel}",
+        f"dispatches = {len(fetch)}",
         f"fetch_kib_per_dispatch = {f_kib:.1f}",
         f"write_kib_per_dispatch = {w_kib:.1f}",
         f"copy_bytes = {a.copy_bytes}",
@@ -171,6 +176,8 @@ def main(argv=None):
     t.add_argument("--cmd-fetch", required=True)
     t.add_argument("--cmd-write", required=True)
     t.add_argument("--cmd-cal", required=True)
+    t.add_argument("--kernel", default="k_step_batch",
+                   help="kernel whose dispatches are averaged (k_step_batch: the merged schedule)")
     a = ap.parse_args(argv)
     sys.stdout.write(stats(a.dir, a.cmd) if a.what == "stats" else traffic(a))
 
