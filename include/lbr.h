@@ -218,6 +218,22 @@ int lbr_read_field(lbr_ctx* ctx, int32_t level, int32_t field, double* dst);
 int lbr_wall_count(lbr_ctx* ctx, int32_t level);
 int lbr_read_wall(lbr_ctx* ctx, int32_t level, double* dst);
 
+/* y+ of the reference point R, the boundary node B and the virtual node V of
+   every wall node of a level (Section 3.1.3, Figure 6): u_tau y / nu with y
+   the wall distance of each point (d_WR, d_WB, d_WV in lattice units of the
+   level; d_WR = 1.75 with LBR_WALL_NISHIMURA) and u_tau from the wall model
+   on the current state.  dst holds 3 doubles per wall node, in the order of
+   lbr_read_wall; 0 for wall models without a wall function. */
+int lbr_wall_yplus(lbr_ctx* ctx, int32_t level, double* dst);
+
+/* Rake (Section 3.1.4, Figure 10): n points evenly spaced from (x0, y0) to
+   (x1, y1) in the units of the geometry (n = 1: the first point).  Each
+   point takes the values of the owned fluid cell of the finest level that
+   contains it.  dst holds 5 doubles per point: level (-1 where no fluid cell
+   contains the point: solid, outside, and the other four NaN), u_x / U,
+   u_y / U, nu_t / nu = chi f_v1(chi) (0 for chi <= 0), rho. */
+int lbr_rake(lbr_ctx* ctx, double x0, double y0, double x1, double y1, int32_t n, double* dst);
+
 /* Surface Cp and sign-corrected Cf at the centroids of the segments of one
    body (eq. (30) and the interpolation described after it).  cp and cf hold
    n_pts[body] doubles each. */

@@ -83,6 +83,8 @@ def lib():
         L.lbr_last_error.restype = C.c_char_p
         L.lbr_destroy.argtypes = [p]
         L.lbr_destroy.restype = None
+        L.lbr_wall_yplus.argtypes = [p, i32, dp]
+        L.lbr_rake.argtypes = [p, C.c_double, C.c_double, C.c_double, C.c_double, i32, dp]
         L.lbr_save.argtypes = [p, C.c_char_p]
         L.lbr_load.argtypes = [p, C.c_char_p]
         L.lbr_batch_create.argtypes = [i32, C.POINTER(p), C.POINTER(p)]
@@ -263,6 +265,23 @@ class Solver:
         done, r = C.c_int64(), C.c_double()
         self._check(lib().lbr_run_to_steady(self.h, tol, max_steps, check_every, C.byref(done), C.byref(r)))
         return done.value, r.value
+
+    def wall_yplus(self, level):
+        """(n_wall_nodes, 3) array: y+ of R, B and V of each wall node of the level."""
+        n = lib().lbr_wall_count(self.h, level)
+        if n < 0:
+            self._check(n)
+        out = np.zeros((max(n, 1), 3))
+        if n > 0:
+            self._check(lib().lbr_wall_yplus(self.h, level, _dp(out)))
+        return out[:n]
+
+    def rake(self, p0, p1, n):
+        """(n, 5) array along the segment p0 -> p1: level, u_x/U, u_y/U, nu_t/nu, rho."""
+        out = np.zeros((int(n), 5))
+        self._check(lib().lbr_rake(self.h, float(p0[0]), float(p0[1]), float(p1[0]), float(p1[1]),
+                                   int(n), _dp(out)))
+        return out
 
     def save(self, path):
         self._check(lib().lbr_save(self.h, os.fsencode(path)))

@@ -1510,6 +1510,92 @@ int lbr_read_wall(lbr_ctx* c, int32_t level, double* dst) {
     return LBR_OK;
 }
 
+int lbr_wall_yplus(lbr_ctx* c, int32_t level, double* dst) {
+    if (!c || !dst) return LBR_ERR_INVALID_ARG;
+    if (!c->built || level < 0 || level >= (int)c->lv.size())
+        return set_err(c, LBR_ERR_INVALID_ARG, "bad level %d", level);
+    Level& L = c->lv[level];
+    const int nb = (int)L.nodes.size();
+    if (nb == 0) return LBR_OK;
+    if (int r = eval_wall(c, level)) return r;
+    std::vector<double> st((size_t)nb * 8);
+    HIPCHK(c, hipMemcpyAsync(st.data(), L.bout, st.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    // wall distances of R, B and V in lattice units of the level
+    const double dwr = c->cfg.wall_model == LBR_WALL_NISHIMURA ? 1.75 : c->cfg.d_wr, dwv = c->cfg.d_wv;
+    for (int b = 0; b < nb; ++b) {
+        const double s = st[8 * b] / L.nu;                      // u_tau / nu
+        dst[3 * b + 0] = s * dwr;
+        dst[3 * b + 1] = s * L.nodes[b].dwb;
+        dst[3 * b + 2] = s * dwv;
+    }
+    return LBR_OK;
+}
+
+int lbr_rake(lbr_ctx* c, double x0, double y0, double x1, double y1, int32_t n, double* dst) {
+    if (!c || !dst || n < 1) return LBR_ERR_INVALID_ARG;
+    if (!c->built) return set_err(c, LBR_ERR_STATE, "lbr_build has not been called");
+    const int nl = (int)c->lv.size();
+    std::vector<int> lev(n, -1);
+    std::vector<int64_t> cell(n, -1);
+    for (int k = 0; k < n; ++k) {
+        const double t = n > 1 ? (double)k / (double)(n - 1) : 0.0;
+        const double x = x0 + t * (x1 - x0), y = y0 + t * (y1 - y0);
+        for (int l = nl - 1; l >= 0; --l) {
+            const double dx = c->cfg.dx0 / (double)(1 << l);
+            const double fx = std::floor((x - c->cfg.origin[0]) / dx), fy = std::floor((y - c->cfg.origin[1]) / dx);
+            if (!(std::fabs(fx) < 1e9 && std::fabs(fy) < 1e9)) break;     // far outside, or not finite
+            const Level& L = c->lv[l];
+            if (L.type_at((int)fx, (int)fy) == T_FLUID) {
+                lev[k] = l;
+                cell[k] = L.idx((int)fx, (int)fy);
+                break;
+            }
+        }
+    }
+    for (int k = 0; k < n; ++k) {
+        dst[5 * k] = lev[k];
+        for (int f = 1; f < 5; ++f) dst[5 * k + f] = NAN;
+    }
+    for (int l = 0; l < nl; ++l) {
+        std::vector<int64_t> idx;
+        std::vector<int> who;
+        for (int k = 0; k < n; ++k)
+            if (lev[k] == l) { idx.push_back(cell[k]); who.push_back(k); }
+        if (idx.empty()) continue;
+        const int m = (int)idx.size();
+        Level& L = c->lv[l];
+        auto* didx = static_cast<int64_t*>(dalloc(c, (size_t)m * sizeof(int64_t)));
+        auto* dout = static_cast<double*>(dalloc(c, (size_t)m * 4 * sizeof(double)));
+        if (!didx || !dout) { dfree(c, didx); dfree(c, dout); return set_err(c, LBR_ERR_OOM, "rake scratch"); }
+        std::vector<double> v((size_t)m * 4);
+        int r = 0;
+        const char* mac = static_cast<const char*>(L.mac[L.cur]);
+        const size_t pb = (size_t)L.box.plane * c->csize;
+        if (hipMemcpyAsync(didx, idx.data(), idx.size() * sizeof(int64_t), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+            launch_gather(c->prec, mac, didx, m, dout, c->stream) != hipSuccess ||
+            launch_gather(c->prec, mac + pb, didx, m, dout + m, c->stream) != hipSuccess ||
+            launch_gather(c->prec, mac + 2 * pb, didx, m, dout + 2 * m, c->stream) != hipSuccess ||
+            launch_gather(c->prec, L.chi[L.cur], didx, m, dout + 3 * m, c->stream) != hipSuccess ||
+            hipMemcpyAsync(v.data(), dout, v.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+            hipStreamSynchronize(c->stream) != hipSuccess)
+            r = set_err(c, LBR_ERR_HIP, "rake readout failed");
+        dfree(c, didx);
+        dfree(c, dout);
+        if (r) return r;
+        const double cv13 = 7.1 * 7.1 * 7.1;
+        for (int j = 0; j < m; ++j) {
+            double* o = dst + 5 * who[j];
+            const double chi = v[3 * m + j];
+            o[1] = v[m + j] / c->u_ref;
+            o[2] = v[2 * m + j] / c->u_ref;
+            o[3] = chi > 0.0 ? chi * chi * chi * chi / (chi * chi * chi + cv13) : 0.0;   // nu_t / nu = chi f_v1
+            o[4] = v[j];
+        }
+    }
+    return LBR_OK;
+}
+
 int lbr_surface(lbr_ctx* c, int32_t body, double* cp, double* cf) {
     if (!c || !c->built) return LBR_ERR_INVALID_ARG;
     if (body < 0 || body >= (int)c->surf.size() || c->wall_level < 0)

@@ -169,6 +169,8 @@ hipError_t launch_restrict(Prec p, const RestrictArgs& a, hipStream_t s);
 hipError_t launch_init(Prec p, const InitArgs& a, hipStream_t s);
 hipError_t launch_surface(Prec p, const SurfaceArgs& a, int nblocks, hipStream_t s);
 hipError_t launch_sum_partials(const double* partial, int nblocks, double* out, hipStream_t s);
+// dst[k] = src[idx[k]] for the macroscopic / chi planes (CT of precision p)
+hipError_t launch_gather(Prec p, const void* src, const int64_t* idx, int n, double* dst, hipStream_t s);
 hipError_t launch_to_double(Prec p, const void* src, double* dst, long n, hipStream_t s);
 hipError_t launch_residual(Prec p, const void* mac, double* snap, const int32_t* list, int n,
                            long plane, double area, double* partial, int nblocks, hipStream_t s);

@@ -1133,6 +1133,13 @@ __global__ void k_to_double(const CT* src, double* dst, long n) {
     if (k < n) dst[k] = (double)src[k];
 }
 
+// Values of a plane at listed cells (diagnostics): dst[k] = src[idx[k]].
+template <class CT>
+__global__ void k_gather(const CT* src, const int64_t* idx, int n, double* dst) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) dst[k] = (double)src[idx[k]];
+}
+
 inline unsigned nblocks(long n, int b) { return (unsigned)((n + b - 1) / b); }
 
 // Plain launch, or with start / stop events attached to the dispatch itself
@@ -1251,6 +1258,15 @@ hipError_t launch_residual(Prec p, const void* mac, double* snap, const int32_t*
     else
         hipLaunchKernelGGL(k_residual<float>, dim3(nb), dim3(256), 0, s, (const float*)mac, snap,
                            list, n, plane, area, partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(Prec p, const void* src, const int64_t* idx, int n, double* dst, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    if (p == P_F64)
+        hipLaunchKernelGGL(k_gather<double>, dim3(nblocks(n, 256)), dim3(256), 0, s, (const double*)src, idx, n, dst);
+    else
+        hipLaunchKernelGGL(k_gather<float>, dim3(nblocks(n, 256)), dim3(256), 0, s, (const float*)src, idx, n, dst);
     return hipGetLastError();
 }
 
