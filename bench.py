@@ -132,6 +132,9 @@ def run_sweep(args):
     log(f"build {time.perf_counter() - t0:.1f} s")
     n_cells = int(sum(s.level_info(l)["n_fluid"] for s, c in zip(sims, cases) for l in range(c["n_levels"])))
     batch = P.Batch(sims)
+    rows = batch.tune(trials=3) if args.tune else None
+    if rows:
+        log(f"tile heights per virtual level (tuned): {rows}")
     per = [batch.steps_per_super_step(k) for k in range(len(cases))]
     lups = batch.lups_per_super_step()
     lmax = max(c["n_levels"] for c in cases)
@@ -190,7 +193,7 @@ def run_sweep(args):
         "config": {"workload": "batched sweep: 16 airfoil-like cases, AoA -4..16 deg, 3-5 levels to c/512, "
                                "Re 6e6, M 0.15; a step is one super step (2^(5 - L_k) coarse steps of case k)",
                    "cells": n_cells, "lups_per_step": lups, "coarse_steps_per_super_step": per,
-                   "storage": args.storage, "graph": bool(args.graph)},
+                   "storage": args.storage, "graph": bool(args.graph), "tile_rows": rows},
         "roofline": roof, "cpu_baseline": None,
         "one_after_another": {"value": round(lups * args.steps / seq / 1e6, 1), "unit": "MLUPS",
                               "ms_per_step": round(1000 * seq / args.steps, 4)},
@@ -211,6 +214,8 @@ def main():
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the FP16 / BF16 storage runs reported beside the main line")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--tune", type=int, default=1,
+                    help="choose each level's tile height by timing (the library's tuner) before the warm-up")
     ap.add_argument("--workload", default="airfoil", choices=["airfoil", "three_element", "sweep"],
                     help="airfoil: the benchmark line (8 levels, 2.0M cells); three_element: the "
                          "19.4M-cell high-lift case (cycle time per step, run past its start-up ramp); "
@@ -245,6 +250,10 @@ def main():
     log(f"build {time.perf_counter() - t0:.1f} s")
     lups = sim.lups_per_coarse_step()
     finest = sim.level_info(case["n_levels"] - 1)
+    rows = None
+    if args.tune:
+        rows = sim.tune(trials=5)
+        log(f"tile heights per level (tuned): {rows}")
     if args.graph:
         sim.use_graph(True)
     log(f"{lups} cell updates per coarse step; warmup {args.warmup}")
@@ -298,6 +307,8 @@ def main():
         del sim
         for st in ("f16", "bf16", "mixed"):
             v = P.Solver(case, storage=st)
+            if args.tune:
+                v.tune(trials=5)
             if args.graph:
                 v.use_graph(True)
             v.advance(args.warmup)
@@ -341,7 +352,7 @@ def main():
                                 "M 0.2, AoA 8 deg, after the start-up ramp"),
                    "cells": n_cells,
                    "finest_cells": finest["n_fluid"], "lups_per_step": lups,
-                   "storage": args.storage, "graph": bool(args.graph)},
+                   "storage": args.storage, "graph": bool(args.graph), "tile_rows": rows},
         "roofline": roof, "cpu_baseline": cpu,
         "storage_variants": variants or None,
         "forces": {"C_Df": f[0], "C_Dp": f[1], "C_D": f[2], "C_L": f[3]},

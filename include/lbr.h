@@ -160,7 +160,7 @@ typedef struct lbr_level_desc {
     int64_t n_wall_nodes;          /* boundary nodes B */
     int64_t n_cut_links;
     int64_t n_ghost;
-    int64_t n_tiles;               /* active 64 x 4 tiles launched per step */
+    int64_t n_tiles;               /* active 64 x H tiles launched per step (H: the level's tile height) */
     int64_t bytes;                 /* device bytes held by the level */
 } lbr_level_desc;
 
@@ -285,6 +285,18 @@ int64_t lbr_lups_per_coarse_step(lbr_ctx* ctx);
    results are bit-identical. */
 int lbr_use_graph(lbr_ctx* ctx, int32_t enable);
 
+/* Tile shape of the step kernel.  A workgroup updates a tile of 64 x H cells
+   (one 64-wide wavefront per row, H = 2, 4 or 8 rows; 4 by default).  Every
+   cell's result is a function of its stencil alone, so the fields are
+   bit-identical for any choice.  lbr_tune times each height on every level
+   with that level's first sub-step from the current state (trials launches
+   each; the step's outputs are overwritten by the next real step and the wall
+   nodes' Newton state is restored) and keeps the fastest; rows, if not NULL,
+   receives n_levels heights.  lbr_set_tile_rows sets one level's height
+   (level -1: all levels); other values of rows are LBR_ERR_INVALID_ARG. */
+int lbr_tune(lbr_ctx* ctx, int32_t trials, int32_t* rows);
+int lbr_set_tile_rows(lbr_ctx* ctx, int32_t level, int32_t rows);
+
 /* Average device time per launch of the step kernel over the last
    lbr_advance, in microseconds, from start / stop events attached to each
    dispatch (hipExtLaunchKernelGGL): out[0] all launches, out[1] the launches
@@ -347,6 +359,12 @@ int lbr_batch_run_to_steady(lbr_batch* batch, double tol, int64_t max_super_step
 /* Replays two super steps from one HIP graph (enable != 0) or launches
    directly (enable == 0). */
 int lbr_batch_use_graph(lbr_batch* batch, int32_t enable);
+
+/* As lbr_tune for the batch: every virtual level is timed with the parts of all
+   cases in one launch and the fastest height is set on the corresponding level
+   of every case (rows: lmax entries, may be NULL); the launch tables are
+   rebuilt. */
+int lbr_batch_tune(lbr_batch* batch, int32_t trials, int32_t* rows);
 
 /* As lbr_profile, for the batched launches: out[0] all launches, out[1] the
    launches of the finest virtual level, out[2] virtual level 0, out[3] 0. */

@@ -85,6 +85,9 @@ def lib():
         L.lbr_destroy.restype = None
         L.lbr_wall_yplus.argtypes = [p, i32, dp]
         L.lbr_rake.argtypes = [p, C.c_double, C.c_double, C.c_double, C.c_double, i32, dp]
+        L.lbr_tune.argtypes = [p, i32, C.POINTER(C.c_int32)]
+        L.lbr_set_tile_rows.argtypes = [p, i32, i32]
+        L.lbr_batch_tune.argtypes = [p, i32, C.POINTER(C.c_int32)]
         L.lbr_save.argtypes = [p, C.c_char_p]
         L.lbr_load.argtypes = [p, C.c_char_p]
         L.lbr_batch_create.argtypes = [i32, C.POINTER(p), C.POINTER(p)]
@@ -283,6 +286,15 @@ class Solver:
                                    int(n), _dp(out)))
         return out
 
+    def tune(self, trials=5):
+        """Times the tile heights on every level and keeps the fastest; returns them."""
+        rows = (C.c_int32 * self.case["n_levels"])()
+        self._check(lib().lbr_tune(self.h, int(trials), rows))
+        return [int(r) for r in rows]
+
+    def set_tile_rows(self, rows, level=-1):
+        self._check(lib().lbr_set_tile_rows(self.h, int(level), int(rows)))
+
     def save(self, path):
         self._check(lib().lbr_save(self.h, os.fsencode(path)))
 
@@ -345,6 +357,13 @@ class Batch:
         out = (C.c_double * 4)()
         self._check(lib().lbr_batch_profile(self.h, 1 if enable else 0, out))
         return [float(v) for v in out]
+
+    def tune(self, trials=5):
+        """Tile height per virtual level, timed on the batched launches; returns them."""
+        n = max(s.case["n_levels"] for s in self.solvers)
+        rows = (C.c_int32 * n)()
+        self._check(lib().lbr_batch_tune(self.h, int(trials), rows))
+        return [int(r) for r in rows]
 
     def synchronize(self):
         self._check(lib().lbr_batch_synchronize(self.h))

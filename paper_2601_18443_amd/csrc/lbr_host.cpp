@@ -40,7 +40,8 @@ struct Level {
     std::vector<uint8_t> inside;
     std::vector<int32_t> bidx;
     std::vector<Node> nodes;
-    std::vector<uint32_t> rows;      // wave rows of k_step
+    std::vector<uint32_t> rows[NTY]; // k_step tiles of each height (x, y, restriction bit)
+    int ty = TILE_Y_DEFAULT;         // index of the tile height k_step uses on this level
     std::vector<int32_t> owned, ghosts, covb, edge;
     int64_t n_fluid = 0, n_ghost = 0, n_cut = 0;
     // device
@@ -49,7 +50,7 @@ struct Level {
     void* chi[2] = {nullptr, nullptr};
     double* dist_dev = nullptr;
     uint8_t* flag_dev = nullptr;
-    uint32_t* rows_dev = nullptr;
+    uint32_t* rows_dev[NTY] = {};
     uint32_t* lmask_dev = nullptr;
     int32_t* ghosts_dev = nullptr;
     int32_t* covb_dev = nullptr;
@@ -112,6 +113,7 @@ struct lbr_ctx {
     // this one case (the merged launch schedule)
     bool use_graph = false;
     lbr_batch* self = nullptr;
+    bool self_dirty = false;       // tile heights changed since its tables were built
     int64_t step_count = 0;        // coarse steps completed (start-up ramp)
     // profiling
     bool prof = false;
@@ -266,7 +268,7 @@ void set_box(Level& L, int gx0, int gy0, int nx, int ny) {
     L.box.gx0 = gx0;
     L.box.gy0 = gy0;
     L.box.pitch = round_up(nx, TILE_X);
-    L.box.ny = round_up(ny, TILE_Y);
+    L.box.ny = round_up(ny, TILE_Y_MAX);
     L.box.plane = (long)L.box.pitch * L.box.ny;
     L.flag.assign(L.box.plane, T_INACTIVE);
 }
@@ -603,38 +605,46 @@ int stencils(lbr_ctx* c, Level& L, std::vector<int32_t>& sc, std::vector<double>
     return 0;
 }
 
-// 64 x 4 tiles with work for k_step (owned fluid cells other than wall nodes
-// and domain-edge cells, or ghost cells).
+// 64 x H tiles with work for k_step (owned fluid cells other than wall nodes
+// and domain-edge cells, or ghost cells), for every tile height H.
 void make_rows(Level& L) {
-    L.rows.clear();
-    const int ntx = L.box.pitch / TILE_X, nty = L.box.ny / TILE_Y;
-    for (int ty = 0; ty < nty; ++ty)
-        for (int tx = 0; tx < ntx; ++tx) {
-            bool act = false;
-            for (int y = 0; y < TILE_Y && !act; ++y)
-                for (int x = 0; x < TILE_X && !act; ++x) {
-                    const uint8_t f = L.flag[(long)(ty * TILE_Y + y) * L.box.pitch + tx * TILE_X + x];
-                    const int t = f & F_TYPE;
-                    act = (t == T_FLUID && !(f & (F_WALL | F_EDGE))) || t == T_GHOST;
-                }
-            if (act) L.rows.push_back((uint32_t)tx | ((uint32_t)ty << 16));
-        }
+    for (int k = 0; k < NTY; ++k) {
+        const int H = TILE_YS[k];
+        std::vector<uint32_t>& rows = L.rows[k];
+        rows.clear();
+        const int ntx = L.box.pitch / TILE_X, nty = L.box.ny / H;
+        for (int ty = 0; ty < nty; ++ty)
+            for (int tx = 0; tx < ntx; ++tx) {
+                bool act = false;
+                for (int y = 0; y < H && !act; ++y)
+                    for (int x = 0; x < TILE_X && !act; ++x) {
+                        const uint8_t f = L.flag[(long)(ty * H + y) * L.box.pitch + tx * TILE_X + x];
+                        const int t = f & F_TYPE;
+                        act = (t == T_FLUID && !(f & (F_WALL | F_EDGE))) || t == T_GHOST;
+                    }
+                if (act) rows.push_back((uint32_t)tx | ((uint32_t)ty << 16));
+            }
+    }
 }
 
 // Marks the tiles that hold children of restriction targets of the parent level.
 void mark_restriction_tiles(lbr_ctx* c, Level& L) {
     if (L.l == 0) return;
     const Level& P = c->lv[L.l - 1];
-    for (uint32_t& tl : L.rows) {
-        const int tx = tl & 0x7fff, ty = (tl >> 16) & 0x7fff;
-        bool any = false;
-        for (int y = 0; y < TILE_Y && !any; y += 2)
-            for (int x = 0; x < TILE_X && !any; x += 2) {
-                const int gx = L.box.gx0 + tx * TILE_X + x, gy = L.box.gy0 + ty * TILE_Y + y;
-                const long pk = P.idx(gx >> 1, gy >> 1);
-                any = pk >= 0 && (P.flag[pk] & F_COVB) && (L.flag[(long)(ty * TILE_Y + y) * L.box.pitch + tx * TILE_X + x] & F_TYPE) == T_FLUID;
-            }
-        if (any) tl |= 1u << 31;
+    for (int k = 0; k < NTY; ++k) {
+        const int H = TILE_YS[k];
+        for (uint32_t& tl : L.rows[k]) {
+            const int tx = tl & 0x7fff, ty = (tl >> 16) & 0x7fff;
+            bool any = false;
+            for (int y = 0; y < H && !any; y += 2)
+                for (int x = 0; x < TILE_X && !any; x += 2) {
+                    const int gx = L.box.gx0 + tx * TILE_X + x, gy = L.box.gy0 + ty * H + y;
+                    const long pk = P.idx(gx >> 1, gy >> 1);
+                    any = pk >= 0 && (P.flag[pk] & F_COVB) &&
+                          (L.flag[(long)(ty * H + y) * L.box.pitch + tx * TILE_X + x] & F_TYPE) == T_FLUID;
+                }
+            if (any) tl |= 1u << 31;
+        }
     }
 }
 
@@ -676,7 +686,8 @@ int alloc_level(lbr_ctx* c, Level& L) {
     HIPCHK(c, hipMemsetAsync(L.flag_dev - pad, T_INACTIVE, n + 2 * pad, c->stream));
     HIPCHK(c, hipMemcpyAsync(L.flag_dev, L.flag.data(), n, hipMemcpyHostToDevice, c->stream));
     L.bytes += n + 2 * pad;
-    if (int r = upload(c, &L.rows_dev, L.rows, &L.bytes)) return r;
+    for (int k = 0; k < NTY; ++k)
+        if (int r = upload(c, &L.rows_dev[k], L.rows[k], &L.bytes)) return r;
     {
         // static link mask: which pull sources are owned fluid cells / ghosts
         std::vector<uint32_t> lm(n, 0u);
@@ -791,7 +802,7 @@ Absorber absorber(const lbr_ctx* c, int l, double r) {
 }
 
 template <class ST, class CT>
-void fill_step_args(lbr_ctx* c, int l, int substep, StepArgs<ST, CT>& a) {
+void fill_step_args(lbr_ctx* c, int l, int substep, StepArgs<ST, CT>& a, int tk = -1) {
     Level& L = c->lv[l];
     const lbr_config& cfg = c->cfg;
     a.fsrc = (const ST*)L.f[L.cur];
@@ -803,8 +814,10 @@ void fill_step_args(lbr_ctx* c, int l, int substep, StepArgs<ST, CT>& a) {
     a.dist = L.dist_dev;
     a.flag = L.flag_dev;
     a.lmask = L.lmask_dev;
-    a.tiles = L.rows_dev;
-    a.ntiles = (int)L.rows.size();
+    if (tk < 0) tk = L.ty;                                       // tile height
+    a.ty = TILE_YS[tk];
+    a.tiles = L.rows_dev[tk];
+    a.ntiles = (int)L.rows[tk].size();
     a.edge = L.edge_dev;
     a.nedge = (int)L.edge.size();
     a.wall = wall_data(c, L);
@@ -817,7 +830,7 @@ void fill_step_args(lbr_ctx* c, int l, int substep, StepArgs<ST, CT>& a) {
     a.dom.outlet = cfg.outlet;
     a.pad = L.box.pitch + 1;
     a.wall_blocks = 8 * (((int)L.nodes.size() + 8 * WALL_PER_BLOCK - 1) / (8 * WALL_PER_BLOCK));
-    a.tile_blocks = 8 * (((int)L.rows.size() + 7) / 8);
+    a.tile_blocks = 8 * ((a.ntiles + 7) / 8);
     // this launch streams coarse step n = step_count and collides step n + 1
     a.sp = absorber(c, l, ramp(c, c->step_count + 1));
     a.nu = (CT)L.nu;
@@ -1209,7 +1222,7 @@ int lbr_level_info(lbr_ctx* c, int32_t level, lbr_level_desc* out) {
     out->n_wall_nodes = (int64_t)L.nodes.size();
     out->n_cut_links = L.n_cut;
     out->n_ghost = L.n_ghost;
-    out->n_tiles = (int64_t)L.rows.size();
+    out->n_tiles = (int64_t)L.rows[L.ty].size();
     out->bytes = (int64_t)L.bytes;
     return LBR_OK;
 }
@@ -1723,7 +1736,7 @@ struct lbr_batch {
     // one launch: its StepArgs start at byte off of the table, its part starts
     // at index part0; every part of a launch has the same population storage;
     // v is the virtual level of its finest part
-    struct Launch { size_t off; int part0, nparts, nblocks, v; Prec st; };
+    struct Launch { size_t off; int part0, nparts, nblocks, v; Prec st; int ty; };
     std::vector<Launch> launches;      // the launches of all tables, in order
     // tables: [0] one super step from parity 0, [1] one from parity 1, [2] two
     // from parity 0; each ends with every launch of its super steps issued
@@ -1767,7 +1780,7 @@ void batch_schedule(lbr_batch* b, int v, int substep, std::vector<std::pair<int,
 struct Item {
     int v;
     Prec st;
-    size_t size;                       // bytes of one part's StepArgs
+    size_t size = 0;                   // bytes of one part's StepArgs
     std::vector<unsigned char> args;   // parts, back to back
     std::vector<int> blocks;
 };
@@ -1804,58 +1817,98 @@ std::vector<std::vector<int>> batch_groups(const lbr_batch* b, const std::vector
     return g;
 }
 
-// Launch tables for the covered cases, from their current state: the host
-// fills the arguments of every item in the unmerged order while replaying the
-// buffer flips each launch makes (two super steps bring every index back),
-// then groups the items of each table into launches.
+// Fills the arguments of items [a, e) with tile heights tk, in the unmerged
+// order, from the current state advanced by the items [0, a): the host replays
+// the buffer flips each launch makes, then restores every buffer index and step
+// counter.
+int batch_fill(lbr_batch* b, std::vector<Item>& it, int a, int e, const std::vector<int>& tk,
+               const std::vector<std::pair<int, int>>& seq2) {
+    std::vector<std::vector<int>> cur0;
+    std::vector<int64_t> steps0;
+    for (lbr_ctx* c : b->cases) {
+        cur0.emplace_back();
+        for (const Level& L : c->lv) cur0.back().push_back(L.cur);
+        steps0.push_back(c->step_count);
+    }
+    alignas(16) unsigned char buf[sizeof(StepArgs<double, double>)];
+    int err = 0;
+    for (int k = 0; k < e && !err; ++k) {
+        const int v = seq2[k].first;
+        Item& x = it[k];
+        if (k >= a) { x.args.clear(); x.blocks.clear(); }
+        for (lbr_ctx* c : b->cases) {
+            const int l = v - (b->lmax - (int)c->lv.size());
+            if (l < 0) continue;
+            Level& L = c->lv[l];
+            if (k >= a) {
+                const int sub = l == 0 ? 0 : seq2[k].second;  // a case's level 0 has no parent
+                int wb = 0, tb = 0;
+                switch (L.st) {
+                    case P_F64: { auto& s = *reinterpret_cast<StepArgs<double, double>*>(buf);
+                        fill_step_args(c, l, sub, s, tk[k]); wb = s.wall_blocks; tb = s.tile_blocks; x.size = sizeof s; break; }
+                    case P_F32: { auto& s = *reinterpret_cast<StepArgs<float, float>*>(buf);
+                        fill_step_args(c, l, sub, s, tk[k]); wb = s.wall_blocks; tb = s.tile_blocks; x.size = sizeof s; break; }
+                    case P_F16: { auto& s = *reinterpret_cast<StepArgs<__half, float>*>(buf);
+                        fill_step_args(c, l, sub, s, tk[k]); wb = s.wall_blocks; tb = s.tile_blocks; x.size = sizeof s; break; }
+                    default: { auto& s = *reinterpret_cast<StepArgs<__hip_bfloat16, float>*>(buf);
+                        fill_step_args(c, l, sub, s, tk[k]); wb = s.wall_blocks; tb = s.tile_blocks; x.size = sizeof s; break; }
+                }
+                // parts start on multiples of 8 blocks, so that each part's own
+                // block-to-XCD mapping holds inside the shared grid
+                const int nt = TILE_X * TILE_YS[tk[k]];
+                const int eb = 8 * (((int)L.edge.size() + 8 * nt - 1) / (8 * nt));
+                x.args.insert(x.args.end(), buf, buf + x.size);
+                x.blocks.push_back(wb + tb + eb);
+            }
+            L.cur ^= 1;                                       // as the launch will
+            if (l == 0) c->step_count++;
+        }
+    }
+    for (size_t i = 0; i < b->cases.size(); ++i) {
+        lbr_ctx* c = b->cases[i];
+        for (size_t l = 0; l < c->lv.size(); ++l) c->lv[l].cur = cur0[i][l];
+        c->step_count = steps0[i];
+    }
+    return err;
+}
+
+// Launch tables for the covered cases from their current state.  Each table's
+// groups decide the tile height of every item (a merged launch takes its main
+// part's); the arguments are then filled for that table.
 int batch_build(lbr_batch* b) {
     std::vector<std::pair<int, int>> seq;
     batch_schedule(b, 0, 0, seq);
     const int per = (int)seq.size();
-    std::vector<Item> items;
-    alignas(16) unsigned char buf[sizeof(StepArgs<double, double>)];
-    for (int rep = 0; rep < 2; ++rep)
-        for (const auto& vs : seq) {
-            Item x{vs.first, P_F32, 0, {}, {}};
-            for (lbr_ctx* c : b->cases) {
-                const int l = vs.first - (b->lmax - (int)c->lv.size());
-                if (l < 0) continue;
-                Level& L = c->lv[l];
-                if (x.blocks.empty()) x.st = L.st;
-                else if (L.st != x.st)
-                    return bset_err(b, LBR_ERR_INVALID_ARG, "cases store one virtual level in different formats");
-                const int sub = l == 0 ? 0 : vs.second;       // a case's level 0 has no parent
-                int wb = 0, tb = 0;
-                switch (L.st) {
-                    case P_F64: { auto& a = *reinterpret_cast<StepArgs<double, double>*>(buf);
-                        fill_step_args(c, l, sub, a); wb = a.wall_blocks; tb = a.tile_blocks; x.size = sizeof a; break; }
-                    case P_F32: { auto& a = *reinterpret_cast<StepArgs<float, float>*>(buf);
-                        fill_step_args(c, l, sub, a); wb = a.wall_blocks; tb = a.tile_blocks; x.size = sizeof a; break; }
-                    case P_F16: { auto& a = *reinterpret_cast<StepArgs<__half, float>*>(buf);
-                        fill_step_args(c, l, sub, a); wb = a.wall_blocks; tb = a.tile_blocks; x.size = sizeof a; break; }
-                    default: { auto& a = *reinterpret_cast<StepArgs<__hip_bfloat16, float>*>(buf);
-                        fill_step_args(c, l, sub, a); wb = a.wall_blocks; tb = a.tile_blocks; x.size = sizeof a; break; }
-                }
-                // parts start on multiples of 8 blocks, so that each part's own
-                // block-to-XCD mapping holds inside the shared grid
-                const int eb = 8 * (((int)L.edge.size() + 8 * TILE_X * TILE_Y - 1) / (8 * TILE_X * TILE_Y));
-                x.args.insert(x.args.end(), buf, buf + x.size);
-                x.blocks.push_back(wb + tb + eb);
-                L.cur ^= 1;                                   // as the launch will
-                if (l == 0) c->step_count++;
-            }
-            items.push_back(std::move(x));
+    std::vector<std::pair<int, int>> seq2(seq);
+    seq2.insert(seq2.end(), seq.begin(), seq.end());
+    // storage and tile height of every virtual level (the first case that has it decides)
+    std::vector<Prec> stv(b->lmax, P_F32);
+    std::vector<int> tyv(b->lmax, -1);
+    for (int v = 0; v < b->lmax; ++v)
+        for (lbr_ctx* c : b->cases) {
+            const int l = v - (b->lmax - (int)c->lv.size());
+            if (l < 0) continue;
+            if (tyv[v] < 0) { stv[v] = c->lv[l].st; tyv[v] = c->lv[l].ty; }
+            else if (c->lv[l].st != stv[v])
+                return bset_err(b, LBR_ERR_INVALID_ARG, "cases store one virtual level in different formats");
         }
-    for (lbr_ctx* c : b->cases) c->step_count -= 2 * (int64_t(1) << (b->lmax - (int)c->lv.size()));
+    std::vector<Item> items(2 * per);
+    for (int k = 0; k < 2 * per; ++k) { items[k].v = seq2[k].first; items[k].st = stv[seq2[k].first]; }
 
     std::vector<unsigned char> parts;
     std::vector<int> starts;
     b->launches.clear();
     const int range[3][2] = {{0, per}, {per, 2 * per}, {0, 2 * per}};
     for (int t = 0; t < 3; ++t) {
+        const auto groups = batch_groups(b, items, range[t][0], range[t][1]);
+        std::vector<int> tk(2 * per, TILE_Y_DEFAULT);
+        for (const auto& grp : groups)
+            for (int k : grp) tk[k] = tyv[items[grp[0]].v];
+        if (int r = batch_fill(b, items, range[t][0], range[t][1], tk, seq2)) return r;
         b->table[t][0] = (int)b->launches.size();
-        for (const auto& grp : batch_groups(b, items, range[t][0], range[t][1])) {
-            lbr_batch::Launch ln{parts.size(), (int)starts.size(), 0, 0, items[grp[0]].v, items[grp[0]].st};
+        for (const auto& grp : groups) {
+            const Item& m = items[grp[0]];
+            lbr_batch::Launch ln{parts.size(), (int)starts.size(), 0, 0, m.v, m.st, TILE_YS[tk[grp[0]]]};
             for (int k : grp) {
                 const Item& x = items[k];
                 parts.insert(parts.end(), x.args.begin(), x.args.end());
@@ -1924,7 +1977,7 @@ int batch_table(lbr_batch* b, int t) {
         Timing tm;
         if (b->prof)
             if (hipEvent_t* e = batch_prof_events(b, ln.v)) { tm.start = e[0]; tm.stop = e[1]; }
-        if (launch_step_batch(ln.st, parts, b->start_dev + ln.part0, ln.nparts, ln.nblocks, b->stream, tm) !=
+        if (launch_step_batch(ln.st, parts, b->start_dev + ln.part0, ln.nparts, ln.nblocks, ln.ty, b->stream, tm) !=
             hipSuccess)
             return bset_err(b, LBR_ERR_HIP, "batched k_step launch failed");
     }
@@ -2166,6 +2219,157 @@ void lbr_batch_destroy(lbr_batch* b) {
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
+// tile-height tuner
+// ---------------------------------------------------------------------------
+namespace {
+
+// Times every tile height on every virtual level of the cases (level
+// v - (lmax - L_k) of case k, all cases in one launch) and returns the
+// fastest per virtual level.  Each trial runs the level's first sub-step from
+// the current state: it writes only the buffers of the next time level, which
+// the next real step overwrites, and the wall nodes' friction velocities, which
+// are restored afterwards; every cell's result is independent of the tile
+// height.
+int tune_levels(const std::vector<lbr_ctx*>& cases, int lmax, int trials, std::vector<int>& best,
+                std::string& err) {
+    lbr_ctx* c0 = cases[0];
+    hipStream_t s = c0->stream;
+    for (lbr_ctx* c : cases)
+        if (hipStreamSynchronize(c->stream) != hipSuccess) { err = "synchronize failed"; return LBR_ERR_HIP; }
+    // wall-node state, saved
+    std::vector<std::pair<double*, std::vector<double>>> saved;
+    for (lbr_ctx* c : cases)
+        for (Level& L : c->lv) {
+            const size_t n = std::max<size_t>(L.nodes.size(), 1) * 8;
+            saved.push_back({L.bstate, std::vector<double>(n)});
+            if (hipMemcpy(saved.back().second.data(), L.bstate, n * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) {
+                err = "tuner: state copy failed";
+                return LBR_ERR_HIP;
+            }
+        }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    void* parts_dev = nullptr;
+    int* start_dev = nullptr;
+    int rc = 0;
+    best.assign(lmax, TILE_Y_DEFAULT);
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) { err = "tuner: events"; rc = LBR_ERR_HIP; }
+    size_t cap = 0;
+    alignas(16) unsigned char buf[sizeof(StepArgs<double, double>)];
+    for (int v = 0; v < lmax && !rc; ++v) {
+        float best_ms = 0.0f;
+        for (int k = 0; k < NTY && !rc; ++k) {
+            std::vector<unsigned char> parts;
+            std::vector<int> starts;
+            int nblocks = 0;
+            Prec st = P_F32;
+            for (lbr_ctx* c : cases) {
+                const int l = v - (lmax - (int)c->lv.size());
+                if (l < 0) continue;
+                Level& L = c->lv[l];
+                st = L.st;
+                const int sub = l == 0 ? 0 : 1;
+                int wb = 0, tb = 0;
+                size_t sz = 0;
+                switch (L.st) {
+                    case P_F64: { auto& a = *reinterpret_cast<StepArgs<double, double>*>(buf);
+                        fill_step_args(c, l, sub, a, k); wb = a.wall_blocks; tb = a.tile_blocks; sz = sizeof a; break; }
+                    case P_F32: { auto& a = *reinterpret_cast<StepArgs<float, float>*>(buf);
+                        fill_step_args(c, l, sub, a, k); wb = a.wall_blocks; tb = a.tile_blocks; sz = sizeof a; break; }
+                    case P_F16: { auto& a = *reinterpret_cast<StepArgs<__half, float>*>(buf);
+                        fill_step_args(c, l, sub, a, k); wb = a.wall_blocks; tb = a.tile_blocks; sz = sizeof a; break; }
+                    default: { auto& a = *reinterpret_cast<StepArgs<__hip_bfloat16, float>*>(buf);
+                        fill_step_args(c, l, sub, a, k); wb = a.wall_blocks; tb = a.tile_blocks; sz = sizeof a; break; }
+                }
+                const int nt = TILE_X * TILE_YS[k];
+                parts.insert(parts.end(), buf, buf + sz);
+                starts.push_back(nblocks);
+                nblocks += wb + tb + 8 * (((int)L.edge.size() + 8 * nt - 1) / (8 * nt));
+            }
+            if (parts.size() > cap) {
+                dfree(c0, parts_dev);
+                dfree(c0, start_dev);
+                cap = parts.size();
+                parts_dev = dalloc(c0, cap);
+                start_dev = static_cast<int*>(dalloc(c0, cap / 64 * sizeof(int) + sizeof(int)));
+                if (!parts_dev || !start_dev) { err = "tuner: out of device memory"; rc = LBR_ERR_OOM; break; }
+            }
+            float ms = 0.0f;
+            bool ok = hipMemcpy(parts_dev, parts.data(), parts.size(), hipMemcpyHostToDevice) == hipSuccess &&
+                      hipMemcpy(start_dev, starts.data(), starts.size() * sizeof(int), hipMemcpyHostToDevice) == hipSuccess;
+            const int np = (int)starts.size();
+            ok = ok && launch_step_batch(st, parts_dev, start_dev, np, nblocks, TILE_YS[k], s) == hipSuccess;  // warm-up
+            ok = ok && hipEventRecord(e0, s) == hipSuccess;
+            for (int r = 0; r < trials && ok; ++r)
+                ok = launch_step_batch(st, parts_dev, start_dev, np, nblocks, TILE_YS[k], s) == hipSuccess;
+            ok = ok && hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+                 hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+            if (!ok) { err = "tuner: launch failed"; rc = LBR_ERR_HIP; break; }
+            if (k == 0 || ms < best_ms) { best_ms = ms; best[v] = k; }
+        }
+    }
+    if (hipStreamSynchronize(s) != hipSuccess && !rc) { err = "synchronize failed"; rc = LBR_ERR_HIP; }
+    for (auto& sv : saved)
+        if (hipMemcpy(sv.first, sv.second.data(), sv.second.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess && !rc) {
+            err = "tuner: state restore failed";
+            rc = LBR_ERR_HIP;
+        }
+    dfree(c0, parts_dev);
+    dfree(c0, start_dev);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbr_tune(lbr_ctx* c, int32_t trials, int32_t* rows) {
+    if (!c || trials < 1) return LBR_ERR_INVALID_ARG;
+    if (!c->built) return set_err(c, LBR_ERR_STATE, "lbr_build has not been called");
+    std::vector<int> best;
+    std::string err;
+    if (int r = tune_levels({c}, (int)c->lv.size(), trials, best, err)) return set_err(c, r, "%s", err.c_str());
+    for (size_t l = 0; l < c->lv.size(); ++l) {
+        c->lv[l].ty = best[l];
+        if (rows) rows[l] = TILE_YS[best[l]];
+    }
+    c->self_dirty = true;
+    return LBR_OK;
+}
+
+int lbr_set_tile_rows(lbr_ctx* c, int32_t level, int32_t rows) {
+    if (!c) return LBR_ERR_INVALID_ARG;
+    if (!c->built) return set_err(c, LBR_ERR_STATE, "lbr_build has not been called");
+    int k = -1;
+    for (int j = 0; j < NTY; ++j)
+        if (TILE_YS[j] == rows) k = j;
+    if (k < 0 || level < -1 || level >= (int)c->lv.size())
+        return set_err(c, LBR_ERR_INVALID_ARG, "tile rows %d on level %d", rows, level);
+    for (size_t l = 0; l < c->lv.size(); ++l)
+        if (level < 0 || (int)l == level) c->lv[l].ty = k;
+    c->self_dirty = true;
+    return LBR_OK;
+}
+
+int lbr_batch_tune(lbr_batch* b, int32_t trials, int32_t* rows) {
+    if (!b || trials < 1) return LBR_ERR_INVALID_ARG;
+    if (!b->ready) return bset_err(b, LBR_ERR_STATE, "batch launch tables missing");
+    std::vector<int> best;
+    if (int r = tune_levels(b->cases, b->lmax, trials, best, b->err)) return r;
+    for (lbr_ctx* c : b->cases) {
+        const int off = b->lmax - (int)c->lv.size();
+        for (size_t l = 0; l < c->lv.size(); ++l) c->lv[l].ty = best[l + off];
+        c->self_dirty = true;
+    }
+    for (int v = 0; v < b->lmax; ++v)
+        if (rows) rows[v] = TILE_YS[best[v]];
+    return batch_cover(b, b->cases);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
 // a context past its start-up ramp, through the merged schedule
 // ---------------------------------------------------------------------------
 namespace {
@@ -2181,11 +2385,12 @@ int self_advance(lbr_ctx* c, int64_t n) {
             return r;
         }
         c->self = b;
-    } else if (batch_check(c->self)) {
+    } else if (c->self_dirty || batch_check(c->self)) {
         // the case was stepped by an odd count outside the schedule (ramp, direct
         // launches, a checkpoint load): rebuild the tables from its state
         if (int r = batch_cover(c->self, c->self->all)) return set_err(c, r, "merged schedule: %s", c->self->err.c_str());
     }
+    c->self_dirty = false;
     lbr_batch* b = c->self;
     b->use_graph = c->use_graph;
     b->prof = c->prof;

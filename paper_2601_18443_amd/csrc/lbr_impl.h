@@ -24,7 +24,12 @@ enum : uint8_t {
 
 constexpr int WALL_PER_BLOCK = 16;   // wall nodes per k_step workgroup
 constexpr int TILE_X = 64;   // one wavefront per tile row
-constexpr int TILE_Y = 4;    // four wavefronts per 256-thread workgroup
+// tile heights (wavefronts per workgroup) k_step is built for; the host tunes
+// one per level
+constexpr int NTY = 3;
+constexpr int TILE_YS[NTY] = {2, 4, 8};
+constexpr int TILE_Y_DEFAULT = 1;   // index of 4 rows
+constexpr int TILE_Y_MAX = 8;       // level boxes hold whole tiles of any height
 constexpr int MAX_STENCIL = 16;
 constexpr int ROWS_PER_GROUP = 4;   // wave rows per workgroup
 
@@ -86,6 +91,7 @@ struct StepArgs {
     int substep;                     // 1 or 2 within the parent's step (0 on level 0)
     int pad;                         // spare elements before and after every field array
                                      // of the level (one row plus one cell)
+    int ty;                          // tile height of the tile list (2, 4 or 8 rows)
     int wall_blocks, tile_blocks;    // k_step grid: wall-node blocks of WALL_PER_BLOCK nodes
                                      // (a multiple of 8 blocks),
                                      // tile blocks (a multiple of 8), then edge-cell blocks
@@ -161,7 +167,7 @@ struct Timing {
 hipError_t launch_step(Prec p, const void* args, hipStream_t s, const Timing& tm = Timing{});
 // parts: device array of nparts StepArgs<ST, CT> of the precision p; start: device
 // array of the first block of each part (multiples of 8); nblocks_total: grid size
-hipError_t launch_step_batch(Prec p, const void* parts, const int* start, int nparts, int nblocks_total,
+hipError_t launch_step_batch(Prec p, const void* parts, const int* start, int nparts, int nblocks_total, int ty,
                              hipStream_t s, const Timing& tm = Timing{});
 hipError_t launch_wall(Prec p, const void* args, hipStream_t s);
 hipError_t launch_fill(Prec p, const FillArgs& a, hipStream_t s);

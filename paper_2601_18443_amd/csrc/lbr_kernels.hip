@@ -720,10 +720,15 @@ __device__ __forceinline__ void boundary_node(const StepArgs<ST, CT>& a, int b) 
 }
 
 // One workgroup of a level sub-step; blk is the block index within the level's
-// part of the grid.
-template <class ST, class CT>
+// part of the grid.  Tiles are 64 x TY cells (TY wavefronts, one per row); the
+// tile height is a launch parameter chosen per level by the host's tuner, and
+// every cell's result is the same for any TY.
+template <class ST, class CT, int TY>
 __device__ __forceinline__ void step_block(const StepArgs<ST, CT>& a, const int blk) {
-    __shared__ CT sh_n[TILE_Y + 2][TILE_X + 2], sh_u[TILE_Y + 2][TILE_X + 2], sh_v[TILE_Y + 2][TILE_X + 2];
+    constexpr int NT = TILE_X * TY;                        // threads of the workgroup
+    constexpr int NH = 2 * TILE_X + 2 * (TY + 2);          // halo cells of a tile
+    constexpr int NS = (NH + NT - 1) / NT;                 // halo cells per thread (1, or 2 for TY = 2)
+    __shared__ CT sh_n[TY + 2][TILE_X + 2], sh_u[TY + 2][TILE_X + 2], sh_v[TY + 2][TILE_X + 2];
     // grid: wall-node blocks first (their FP64 Newton iteration is the longest
     // chain), then the tiles, then the level-0 domain-edge cells; each branch is
     // uniform over a workgroup
@@ -738,7 +743,7 @@ __device__ __forceinline__ void step_block(const StepArgs<ST, CT>& a, const int 
     }
     const int bid = blk - a.wall_blocks;                         // a multiple of 8 shifts no XCD
     if (bid >= a.tile_blocks) {
-        const int e = (bid - a.tile_blocks) * TILE_X * TILE_Y + threadIdx.x;
+        const int e = (bid - a.tile_blocks) * NT + threadIdx.x;
         if (e < a.nedge) edge_cell(a, e);
         return;
     }
@@ -749,7 +754,7 @@ __device__ __forceinline__ void step_block(const StepArgs<ST, CT>& a, const int 
     const int pitch = a.box.pitch;
     const long P = a.box.plane;
     const int lane = threadIdx.x & 63, wy = threadIdx.x >> 6;
-    const int tx0 = (int)(tile & 0x7fffu) * TILE_X, ty0 = (int)((tile >> 16) & 0x7fffu) * TILE_Y;
+    const int tx0 = (int)(tile & 0x7fffu) * TILE_X, ty0 = (int)((tile >> 16) & 0x7fffu) * TY;
     const bool restrict_tile = (tile >> 31) && a.substep == 2;   // uniform over the workgroup
     const int lx = tx0 + lane, ly = ty0 + wy;
     const long c = (long)ly * pitch + lx;
@@ -778,33 +783,44 @@ __device__ __forceinline__ void step_block(const StepArgs<ST, CT>& a, const int 
     const uint32_t lm = a.lmask[c];
     CT own_n = bld<CT, CT>(rc, e * CS, 0), own_u = bld<CT, CT>(rm, e * CS, (uint32_t)P * CS),
        own_v = bld<CT, CT>(rm, e * CS, 2u * (uint32_t)P * CS);
-    const bool halo = threadIdx.x < 2 * TILE_X + 2 * (TILE_Y + 2);
-    int hx = 0, hy = 0;
-    if (threadIdx.x < TILE_X) { hx = threadIdx.x; hy = -1; }
-    else if (threadIdx.x < 2 * TILE_X) { hx = threadIdx.x - TILE_X; hy = TILE_Y; }
-    else if (threadIdx.x < 2 * TILE_X + TILE_Y + 2) { hx = -1; hy = threadIdx.x - 2 * TILE_X - 1; }
-    else { hx = TILE_X; hy = threadIdx.x - 2 * TILE_X - (TILE_Y + 2) - 1; }
-    const uint32_t he = (uint32_t)((ty0 + hy) * pitch + tx0 + hx + pad);
-    uint8_t hfl = 0;
-    CT hn = CT(0), hu = CT(0), hv = CT(0);
-    if (halo) {
-        hfl = __builtin_amdgcn_raw_buffer_load_b8(rg, he, 0, 0);
-        hn = bld<CT, CT>(rc, he * CS, 0);
-        hu = bld<CT, CT>(rm, he * CS, (uint32_t)P * CS);
-        hv = bld<CT, CT>(rm, he * CS, 2u * (uint32_t)P * CS);
+    // halo cells: the row below, the row above, the left and the right column
+    bool halo[NS];
+    int hx[NS], hy[NS];
+    uint8_t hfl[NS];
+    CT hn[NS], hu[NS], hv[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        const int h = (int)threadIdx.x + k * NT;
+        halo[k] = h < NH;
+        if (h < TILE_X) { hx[k] = h; hy[k] = -1; }
+        else if (h < 2 * TILE_X) { hx[k] = h - TILE_X; hy[k] = TY; }
+        else if (h < 2 * TILE_X + TY + 2) { hx[k] = -1; hy[k] = h - 2 * TILE_X - 1; }
+        else { hx[k] = TILE_X; hy[k] = h - 2 * TILE_X - (TY + 2) - 1; }
+        hfl[k] = 0;
+        hn[k] = hu[k] = hv[k] = CT(0);
+        if (halo[k]) {
+            const uint32_t he = (uint32_t)((ty0 + hy[k]) * pitch + tx0 + hx[k] + pad);
+            hfl[k] = __builtin_amdgcn_raw_buffer_load_b8(rg, he, 0, 0);
+            hn[k] = bld<CT, CT>(rc, he * CS, 0);
+            hu[k] = bld<CT, CT>(rm, he * CS, (uint32_t)P * CS);
+            hv[k] = bld<CT, CT>(rm, he * CS, 2u * (uint32_t)P * CS);
+        }
     }
     const int type = fl & F_TYPE;
     if (type == T_GHOST) ghost_fill(a.cmac, a.cchi, a.cbox, gx, gy, own_n, own_u, own_v);
     sh_n[wy + 1][lane + 1] = own_n;
     sh_u[wy + 1][lane + 1] = own_u;
     sh_v[wy + 1][lane + 1] = own_v;
-    if (halo) {
-        if ((hfl & F_TYPE) == T_GHOST)
-            ghost_fill(a.cmac, a.cchi, a.cbox, a.box.gx0 + tx0 + hx, a.box.gy0 + ty0 + hy, hn, hu, hv);
-        sh_n[hy + 1][hx + 1] = hn;
-        sh_u[hy + 1][hx + 1] = hu;
-        sh_v[hy + 1][hx + 1] = hv;
-    }
+#pragma unroll
+    for (int k = 0; k < NS; ++k)
+        if (halo[k]) {
+            if ((hfl[k] & F_TYPE) == T_GHOST)
+                ghost_fill(a.cmac, a.cchi, a.cbox, a.box.gx0 + tx0 + hx[k], a.box.gy0 + ty0 + hy[k], hn[k], hu[k],
+                           hv[k]);
+            sh_n[hy[k] + 1][hx[k] + 1] = hn[k];
+            sh_u[hy[k] + 1][hx[k] + 1] = hu[k];
+            sh_v[hy[k] + 1][hx[k] + 1] = hv[k];
+        }
     __syncthreads();
 
     const Rsrc rfo = make_rsrc(a.fdst - pad, 9 * P + 2 * pad);
@@ -875,7 +891,7 @@ __device__ __forceinline__ void step_block(const StepArgs<ST, CT>& a, const int 
     if (!restrict_tile) return;
     // restriction for the next parent step: the new rho, u and chi of each 2 x 2
     // block under a covered coarse cell, averaged by the block's lower-left cell
-    __shared__ CT sh_r[4][TILE_Y][TILE_X];
+    __shared__ CT sh_r[4][TY][TILE_X];
     __syncthreads();
     if (update) {
         sh_r[0][wy][lane] = m_rho;
@@ -900,20 +916,20 @@ __device__ __forceinline__ void step_block(const StepArgs<ST, CT>& a, const int 
 
 
 // One level sub-step of one case.
-template <class ST, class CT>
-__global__ __launch_bounds__(256, 8) void k_step(const StepArgs<ST, CT> a) {
-    step_block(a, (int)blockIdx.x);
+template <class ST, class CT, int TY>
+__global__ __launch_bounds__(TILE_X * TY, 8) void k_step(const StepArgs<ST, CT> a) {
+    step_block<ST, CT, TY>(a, (int)blockIdx.x);
 }
 
 // One launch for the same virtual level of several cases (batched sweep): the
 // grid is split into parts, part p starting at block start[p] (a multiple of 8,
 // so the XCD mapping of each part is kept) with its arguments in parts[p].
-template <class ST, class CT>
-__global__ __launch_bounds__(256, 8) void k_step_batch(const StepArgs<ST, CT>* __restrict__ parts,
+template <class ST, class CT, int TY>
+__global__ __launch_bounds__(TILE_X * TY, 8) void k_step_batch(const StepArgs<ST, CT>* __restrict__ parts,
                                                      const int* __restrict__ start, int nparts) {
     int p = 0;
     while (p + 1 < nparts && (int)blockIdx.x >= start[p + 1]) ++p;
-    step_block(parts[p], (int)blockIdx.x - start[p]);
+    step_block<ST, CT, TY>(parts[p], (int)blockIdx.x - start[p]);
 }
 
 // Wall model on the current state, for output.
@@ -1155,36 +1171,57 @@ inline void launch_timed(K kernel, dim3 g, dim3 b, hipStream_t s, const Timing& 
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-template <class ST, class CT>
-static hipError_t step_t(const void* args, hipStream_t s, const Timing& tm) {
-    const auto& a = *static_cast<const StepArgs<ST, CT>*>(args);
-    const unsigned grid = (unsigned)(a.wall_blocks + a.tile_blocks) + nblocks(a.nedge, TILE_X * TILE_Y);
+template <class ST, class CT, int TY>
+static hipError_t step_ty(const StepArgs<ST, CT>& a, hipStream_t s, const Timing& tm) {
+    const unsigned grid = (unsigned)(a.wall_blocks + a.tile_blocks) + nblocks(a.nedge, TILE_X * TY);
     if (grid == 0) return hipSuccess;
-    launch_timed(k_step<ST, CT>, dim3(grid), dim3(TILE_X * TILE_Y), s, tm, a);
+    launch_timed(k_step<ST, CT, TY>, dim3(grid), dim3(TILE_X * TY), s, tm, a);
     return hipGetLastError();
 }
 
 template <class ST, class CT>
-static hipError_t batch_t(const void* parts, const int* start, int nparts, int nblocks_total, hipStream_t s,
-                          const Timing& tm) {
-    if (nblocks_total == 0) return hipSuccess;
-    const auto* pa = static_cast<const StepArgs<ST, CT>*>(parts);
+static hipError_t step_t(const void* args, hipStream_t s, const Timing& tm) {
+    const auto& a = *static_cast<const StepArgs<ST, CT>*>(args);
+    switch (a.ty) {
+        case 2: return step_ty<ST, CT, 2>(a, s, tm);
+        case 4: return step_ty<ST, CT, 4>(a, s, tm);
+        case 8: return step_ty<ST, CT, 8>(a, s, tm);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <class ST, class CT, int TY>
+static hipError_t batch_ty(const StepArgs<ST, CT>* pa, const int* start, int nparts, int nblocks_total,
+                           hipStream_t s, const Timing& tm) {
     if (tm.start)
-        hipExtLaunchKernelGGL((k_step_batch<ST, CT>), dim3(nblocks_total), dim3(TILE_X * TILE_Y), 0, s,
+        hipExtLaunchKernelGGL((k_step_batch<ST, CT, TY>), dim3(nblocks_total), dim3(TILE_X * TY), 0, s,
                               tm.start, tm.stop, 0, pa, start, nparts);
     else
-        hipLaunchKernelGGL((k_step_batch<ST, CT>), dim3(nblocks_total), dim3(TILE_X * TILE_Y), 0, s,
+        hipLaunchKernelGGL((k_step_batch<ST, CT, TY>), dim3(nblocks_total), dim3(TILE_X * TY), 0, s,
                            pa, start, nparts);
     return hipGetLastError();
 }
 
-hipError_t launch_step_batch(Prec p, const void* parts, const int* start, int nparts, int nblocks_total,
+template <class ST, class CT>
+static hipError_t batch_t(const void* parts, const int* start, int nparts, int nblocks_total, int ty,
+                          hipStream_t s, const Timing& tm) {
+    if (nblocks_total == 0) return hipSuccess;
+    const auto* pa = static_cast<const StepArgs<ST, CT>*>(parts);
+    switch (ty) {
+        case 2: return batch_ty<ST, CT, 2>(pa, start, nparts, nblocks_total, s, tm);
+        case 4: return batch_ty<ST, CT, 4>(pa, start, nparts, nblocks_total, s, tm);
+        case 8: return batch_ty<ST, CT, 8>(pa, start, nparts, nblocks_total, s, tm);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_step_batch(Prec p, const void* parts, const int* start, int nparts, int nblocks_total, int ty,
                              hipStream_t s, const Timing& tm) {
     switch (p) {
-        case P_F64: return batch_t<double, double>(parts, start, nparts, nblocks_total, s, tm);
-        case P_F32: return batch_t<float, float>(parts, start, nparts, nblocks_total, s, tm);
-        case P_F16: return batch_t<__half, float>(parts, start, nparts, nblocks_total, s, tm);
-        default: return batch_t<__hip_bfloat16, float>(parts, start, nparts, nblocks_total, s, tm);
+        case P_F64: return batch_t<double, double>(parts, start, nparts, nblocks_total, ty, s, tm);
+        case P_F32: return batch_t<float, float>(parts, start, nparts, nblocks_total, ty, s, tm);
+        case P_F16: return batch_t<__half, float>(parts, start, nparts, nblocks_total, ty, s, tm);
+        default: return batch_t<__hip_bfloat16, float>(parts, start, nparts, nblocks_total, ty, s, tm);
     }
 }
 
