@@ -295,6 +295,14 @@ int lbr_use_graph(lbr_ctx* ctx, int32_t enable);
    receives n_levels heights.  lbr_set_tile_rows sets one level's height
    (level -1: all levels); other values of rows are LBR_ERR_INVALID_ARG. */
 int lbr_tune(lbr_ctx* ctx, int32_t trials, int32_t* rows);
+
+/* The launch schedule of two coarse steps of an n_levels grid (the table that
+   lbr_use_graph replays; merge = 0: the direct recursive cycle), for
+   inspection, with no device work: for every launch in order, the number m of
+   level sub-steps it runs, then m pairs (level, sub-step 1 or 2; 0 on level
+   0).  Writes at most cap values to out and returns the number the whole
+   schedule needs (LBR_ERR_INVALID_ARG for n_levels outside 1..LBR_MAX_LEVELS). */
+int32_t lbr_schedule(int32_t n_levels, int32_t merge, int32_t* out, int32_t cap);
 int lbr_set_tile_rows(lbr_ctx* ctx, int32_t level, int32_t rows);
 
 /* Average device time per launch of the step kernel over the last

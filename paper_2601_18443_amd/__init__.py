@@ -85,6 +85,8 @@ def lib():
         L.lbr_destroy.restype = None
         L.lbr_wall_yplus.argtypes = [p, i32, dp]
         L.lbr_rake.argtypes = [p, C.c_double, C.c_double, C.c_double, C.c_double, i32, dp]
+        L.lbr_schedule.argtypes = [i32, i32, C.POINTER(C.c_int32), i32]
+        L.lbr_schedule.restype = i32
         L.lbr_tune.argtypes = [p, i32, C.POINTER(C.c_int32)]
         L.lbr_set_tile_rows.argtypes = [p, i32, i32]
         L.lbr_batch_tune.argtypes = [p, i32, C.POINTER(C.c_int32)]
@@ -312,6 +314,23 @@ class Solver:
         cur = 1 if enable else 0
         self._check(lib().lbr_profile(self.h, cur, _dp(out)))
         return out
+
+
+def schedule(n_levels, merge=True):
+    """Launches of two coarse steps of an n_levels grid, each a list of
+    (level, sub-step) pairs (the merged schedule, or the direct cycle)."""
+    L = lib()
+    need = L.lbr_schedule(int(n_levels), 1 if merge else 0, None, 0)
+    if need < 0:
+        raise LbrError(f"lbr_schedule failed ({need})")
+    buf = (C.c_int32 * need)()
+    L.lbr_schedule(int(n_levels), 1 if merge else 0, buf, need)
+    out, k = [], 0
+    while k < need:
+        m = buf[k]
+        out.append([(buf[k + 1 + 2 * j], buf[k + 2 + 2 * j]) for j in range(m)])
+        k += 1 + 2 * m
+    return out
 
 
 class Batch:

@@ -2324,6 +2324,31 @@ int tune_levels(const std::vector<lbr_ctx*>& cases, int lmax, int trials, std::v
 
 extern "C" {
 
+int32_t lbr_schedule(int32_t n_levels, int32_t merge, int32_t* out, int32_t cap) {
+    if (n_levels < 1 || n_levels > LBR_MAX_LEVELS || cap < 0 || (cap > 0 && !out)) return LBR_ERR_INVALID_ARG;
+    lbr_batch b;
+    b.lmax = n_levels;
+    b.merge = merge != 0;
+    std::vector<std::pair<int, int>> seq;
+    batch_schedule(&b, 0, 0, seq);
+    std::vector<std::pair<int, int>> seq2(seq);
+    seq2.insert(seq2.end(), seq.begin(), seq.end());
+    std::vector<Item> items(seq2.size());
+    for (size_t k = 0; k < seq2.size(); ++k) { items[k].v = seq2[k].first; items[k].st = P_F32; }
+    int32_t n = 0;
+    for (const auto& g : batch_groups(&b, items, 0, (int)items.size())) {
+        if (n < cap) out[n] = (int32_t)g.size();
+        ++n;
+        for (int k : g) {
+            if (n < cap) out[n] = seq2[k].first;
+            ++n;
+            if (n < cap) out[n] = seq2[k].second;
+            ++n;
+        }
+    }
+    return n;
+}
+
 int lbr_tune(lbr_ctx* c, int32_t trials, int32_t* rows) {
     if (!c || trials < 1) return LBR_ERR_INVALID_ARG;
     if (!c->built) return set_err(c, LBR_ERR_STATE, "lbr_build has not been called");
