@@ -780,7 +780,9 @@ __device__ __forceinline__ void step_block(const StepArgs<ST, CT>& a, const int 
         s[i] = bld<ST, CT>(rf, e * SS, (uint32_t)(i * P - CX[i] - CY[i] * pitch) * SS);
     const double dist = Bf<double>::ld(rd, e * 8u, 0);
     const uint8_t fl = __builtin_amdgcn_raw_buffer_load_b8(rg, e, 0, 0);
-    const uint32_t lm = a.lmask[c];
+    // link mask: only cells of the ghost band, next to it, or anchoring a
+    // restriction block use it (most tiles have none)
+    const uint32_t lm = ((fl & F_TYPE) == T_GHOST || (fl & F_NEARGHOST) || restrict_tile) ? a.lmask[c] : 0u;
     CT own_n = bld<CT, CT>(rc, e * CS, 0), own_u = bld<CT, CT>(rm, e * CS, (uint32_t)P * CS),
        own_v = bld<CT, CT>(rm, e * CS, 2u * (uint32_t)P * CS);
     // halo cells: the row below, the row above, the left and the right column
