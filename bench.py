@@ -29,12 +29,15 @@ HBM_PEAK_GBS = 8000.0
 ALG_BYTES = {"f32": 18 * 4 + 8 + 8 + 1, "f16": 18 * 2 + 8 + 8 + 1, "bf16": 18 * 2 + 8 + 8 + 1,
              "f64": 18 * 8 + 16 + 8 + 1}
 DTYPE = {"f32": "f32", "f16": "f16-store/f32", "bf16": "bf16-store/f32", "f64": "f64",
-         "mixed": "f32-store on the two finest levels, f16-store below/f32"}
+         "mixed": "f32-store on the two finest levels, f16-store below/f32",
+         "f16s": "f16-store (free-stream shift)/f32", "bf16s": "bf16-store (free-stream shift)/f32",
+         "mixeds": "f32-store on the two finest levels, f16-store (free-stream shift) below/f32"}
 
 
 def lup_bytes(storage, level, n_levels):
     """Algorithmic bytes of one cell update on a level (mixed storage: FP32 on the
     two finest levels, FP16 below)."""
+    storage = {"f16s": "f16", "bf16s": "bf16", "mixeds": "mixed"}.get(storage, storage)
     if storage == "mixed":
         return ALG_BYTES["f32"] if level >= n_levels - 2 else ALG_BYTES["f16"]
     return ALG_BYTES[storage]
@@ -208,7 +211,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16", "f64", "mixed"])
+    ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16", "f64", "mixed", "f16s", "bf16s", "mixeds"])
     ap.add_argument("--graph", type=int, default=1, help="replay the coarse step from a HIP graph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true",
@@ -305,7 +308,7 @@ def main():
     if not args.no_variants and args.storage == "f32":
         sim.close()
         del sim
-        for st in ("f16", "bf16", "mixed"):
+        for st in ("f16", "bf16", "mixed", "f16s", "bf16s", "mixeds"):
             v = P.Solver(case, storage=st)
             if args.tune:
                 v.tune(trials=5)

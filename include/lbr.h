@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define LBR_ABI_VERSION 3
+#define LBR_ABI_VERSION 4
 #define LBR_MAX_LEVELS 12
 
 enum lbr_status {
@@ -143,6 +143,11 @@ typedef struct lbr_config {
                                       default initial state moves at ramp_start u_ref
                                       (N = 0: impulsive start at u_ref) */
     double ramp_start;             /* r0, in [0, 1] */
+    int32_t shift16;               /* 16-bit population storage (FP16, BF16, the FP16 levels of
+                                      LBR_STORE_MIXED): 0 stores f_i - w_i; 1 stores
+                                      f_i - f_eq_i(rho_ref, u_ref e_x) (free-stream shift, exact
+                                      in FP32 arithmetic on load and store); other storage
+                                      formats ignore it */
     lbr_alloc_fn alloc_fn;         /* optional device allocator */
     lbr_free_fn free_fn;
     void* alloc_user;

@@ -15,12 +15,14 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbr.so")
 
-ABI_VERSION = 3
+ABI_VERSION = 4
 MAX_LEVELS = 12
 WALL_STRIDE = 28
 
 STORE_F64, STORE_F32, STORE_F16, STORE_BF16, STORE_MIXED = 0, 1, 2, 3, 4
 STORAGE = {"f64": STORE_F64, "f32": STORE_F32, "f16": STORE_F16, "bf16": STORE_BF16, "mixed": STORE_MIXED}
+# the 16-bit formats with the free-stream storage shift (lbr_config.shift16 = 1)
+SHIFTED = {"f16s": "f16", "bf16s": "bf16", "mixeds": "mixed"}
 FIELD_RHO, FIELD_UX, FIELD_UY, FIELD_CHI, FIELD_NUT, FIELD_TYPE, FIELD_DIST = range(7)
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -39,7 +41,7 @@ class lbr_config(C.Structure):
         ("force", C.c_double * 2), ("omega_b", C.c_double), ("d_wr", C.c_double),
         ("d_wv", C.c_double), ("u_wall", C.c_double * 4),
         ("sponge_width", C.c_double), ("sponge_strength", C.c_double),
-        ("ramp_steps", C.c_double), ("ramp_start", C.c_double),
+        ("ramp_steps", C.c_double), ("ramp_start", C.c_double), ("shift16", C.c_int32),
         ("alloc_fn", ALLOC_FN), ("free_fn", FREE_FN), ("alloc_user", C.c_void_p),
         ("stream", C.c_void_p),
     ]
@@ -146,6 +148,9 @@ class _TorchAllocator:
 def make_config(case, storage="f32", stream=None, allocator=None) -> lbr_config:
     c = lbr_config()
     c.version = ABI_VERSION
+    shift = isinstance(storage, str) and storage in SHIFTED
+    if shift:
+        storage = SHIFTED[storage]
     c.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
     c.nx0, c.ny0, c.n_levels = case["nx0"], case["ny0"], case["n_levels"]
     for k in range(4):
@@ -170,6 +175,7 @@ def make_config(case, storage="f32", stream=None, allocator=None) -> lbr_config:
     c.sponge_strength = case.get("sponge_strength", 0.0)
     c.ramp_steps = case.get("ramp_steps", 0.0)
     c.ramp_start = case.get("ramp_start", 0.0)
+    c.shift16 = 1 if shift else int(case.get("shift16", 0))
     if allocator is not None:
         c.alloc_fn, c.free_fn = allocator.alloc_cb, allocator.free_cb
     c.stream = stream

@@ -95,6 +95,7 @@ struct lbr_ctx {
     Prec prec = P_F32;
     size_t ssize = 4, csize = 4;
     double u_ref = 0, nu0 = 0;
+    double dsh[9] = {};             // storage shift of 16-bit populations (per direction)
     std::vector<double> polyflat;   // level-0 lattice coordinates
     std::vector<int> npts, off;
     double wall_lat[2] = {0, 0};
@@ -833,6 +834,7 @@ void fill_step_args(lbr_ctx* c, int l, int substep, StepArgs<ST, CT>& a, int tk 
     a.tile_blocks = 8 * ((a.ntiles + 7) / 8);
     // this launch streams coarse step n = step_count and collides step n + 1
     a.sp = absorber(c, l, ramp(c, c->step_count + 1));
+    for (int i = 0; i < 9; ++i) a.dsh[i] = (CT)c->dsh[i];
     a.nu = (CT)L.nu;
     a.fx = (CT)L.fx;
     a.fy = (CT)L.fy;
@@ -1001,6 +1003,7 @@ int init_level(lbr_ctx* c, int l, const double* rho, const double* ux, const dou
     a.pitch = L.box.pitch; a.gx0 = L.box.gx0; a.gy0 = L.box.gy0;
     a.nxd = c->cfg.nx0 << l; a.nyd = c->cfg.ny0 << l;
     a.sp = absorber(c, l, ramp(c, c->step_count));
+    for (int i = 0; i < 9; ++i) a.dsh[i] = c->dsh[i];
     HIPCHK(c, launch_init(L.st, a, c->stream));
     HIPCHK(c, hipMemsetAsync(L.bstate, 0, std::max<size_t>(L.nodes.size(), 1) * 8 * sizeof(double), c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -1115,7 +1118,8 @@ int lbr_create(const lbr_config* cfg, lbr_ctx** out) {
     if (cfg->n_levels < 1 || cfg->n_levels > LBR_MAX_LEVELS || cfg->nx0 < 4 || cfg->ny0 < 4 ||
         !(cfg->dx0 > 0) || cfg->storage < 0 || cfg->storage > LBR_STORE_MIXED || cfg->outlet < 0 || cfg->outlet > 2 ||
         cfg->sponge_width < 0 || cfg->sponge_strength < 0 || cfg->sponge_strength > 1 ||
-        cfg->ramp_steps < 0 || cfg->ramp_start < 0 || cfg->ramp_start > 1)
+        cfg->ramp_steps < 0 || cfg->ramp_start < 0 || cfg->ramp_start > 1 ||
+        cfg->shift16 < 0 || cfg->shift16 > 1)
         return LBR_ERR_INVALID_ARG;
     if ((cfg->bc[0] == LBR_BC_PERIODIC) != (cfg->bc[1] == LBR_BC_PERIODIC) ||
         (cfg->bc[2] == LBR_BC_PERIODIC) != (cfg->bc[3] == LBR_BC_PERIODIC) ||
@@ -1135,6 +1139,18 @@ int lbr_create(const lbr_config* cfg, lbr_ctx** out) {
     if (!(c->nu0 > 0) || !std::isfinite(c->nu0)) {
         delete c;
         return LBR_ERR_INVALID_ARG;
+    }
+    if (cfg->shift16) {
+        // f_eq_i(rho_ref, u_ref e_x) - w_i of eq (4) (with u_y = 0 only the
+        // first- and second-order terms remain)
+        static const int cxh[9] = {0, 1, -1, 0, 0, 1, -1, 1, -1};
+        static const double wh[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
+                                     1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+        const double U = c->u_ref, rho = cfg->rho_ref;
+        for (int i = 0; i < 9; ++i) {
+            const double cu = cxh[i] * U;
+            c->dsh[i] = wh[i] * ((rho - 1.0) + rho * (3.0 * cu + 4.5 * (cu * cu - U * U / 3.0)));
+        }
     }
     c->wall_lat[0] = (cfg->wall_y[0] - cfg->origin[1]) / cfg->dx0;
     c->wall_lat[1] = (cfg->wall_y[1] - cfg->origin[1]) / cfg->dx0;
@@ -1360,6 +1376,7 @@ int lbr_save(lbr_ctx* c, const char* path) {
     h.n_levels = (int32_t)c->lv.size();
     h.ssize = (int32_t)c->ssize;
     h.csize = (int32_t)c->csize;
+    h.reserved = c->cfg.shift16;
     h.step_count = c->step_count;
     bool ok = fwrite(&h, sizeof h, 1, fh.f) == 1;
     for (const Level& L : c->lv) {
@@ -1393,7 +1410,7 @@ int lbr_load(lbr_ctx* c, const char* path) {
     if (fread(&h, sizeof h, 1, fh.f) != 1 || memcmp(h.magic, CKPT_MAGIC, 8) != 0)
         return set_err(c, LBR_ERR_IO, "%s is not a checkpoint of this library", path);
     if (h.abi != LBR_ABI_VERSION || h.prec != (int32_t)c->cfg.storage || h.n_levels != (int32_t)c->lv.size() ||
-        h.ssize != (int32_t)c->ssize || h.csize != (int32_t)c->csize)
+        h.ssize != (int32_t)c->ssize || h.csize != (int32_t)c->csize || h.reserved != c->cfg.shift16)
         return set_err(c, LBR_ERR_INVALID_ARG, "checkpoint %s: different library version, storage or level count",
                        path);
     std::vector<CkptLevel> lv(c->lv.size());

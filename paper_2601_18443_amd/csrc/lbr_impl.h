@@ -96,6 +96,7 @@ struct StepArgs {
                                      // (a multiple of 8 blocks),
                                      // tile blocks (a multiple of 8), then edge-cell blocks
     Absorber sp;                     // absorbing layer (level 0 only; width 0 elsewhere)
+    CT dsh[9];                       // 16-bit storage holds s_i - dsh[i] (0, or the free-stream shift)
     const void* fcoarse; Box cbox;   // parent level populations (ghost transfer), stored as
     int cst;                         // Prec cst (mixed storage: FP32 or FP16, else as ST)
     const CT* cmac;  const CT* cchi; // parent level rho, u and chi of the current parent step
@@ -140,6 +141,7 @@ struct InitArgs {
     double nu, fx, fy, omega_b;
     int pitch, gx0, gy0, nxd, nyd;   // storage box origin and domain size (absorbing layer)
     Absorber sp;
+    double dsh[9];                   // 16-bit storage holds s_i - dsh[i]
 };
 
 struct SurfaceArgs {

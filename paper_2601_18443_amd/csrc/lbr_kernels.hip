@@ -137,6 +137,21 @@ __device__ __forceinline__ void bst(Rsrc r, uint32_t vo, uint32_t so, CT v) {
     Bf<ST>::st(r, vo, so, Cv<ST, CT>::st_val(v));
 }
 
+// 16-bit population storage holds s_i - d_i, with d_i = 0 (plain shifted
+// storage, f_i - w_i) or d_i = f_eq_i(rho_ref, U) - w_i (free-stream shift:
+// near the free stream the stored values are small and keep their 11- or
+// 8-bit relative precision); wider formats store s_i.  d is uniform per launch.
+template <class ST, class CT>
+__device__ __forceinline__ CT unshift(CT v, const CT* d, int i) {
+    if constexpr (sizeof(ST) == 2) return v + d[i];
+    else return v;
+}
+template <class ST, class CT>
+__device__ __forceinline__ CT toshift(CT v, const CT* d, int i) {
+    if constexpr (sizeof(ST) == 2) return v - d[i];
+    else return v;
+}
+
 // ---------------------------------------------------------------------------
 // Central-moment collision (eqs (5)-(10)) in shifted variables.  The second
 // central moments are formed from the raw moments of s, the shear pair
@@ -396,28 +411,29 @@ __device__ void wall_model(const WallData& w, int b, const CT* mac, long P, doub
 // that level may hold FP32 or FP16 where this one holds the other; the kind is
 // uniform over a launch, so the test is a scalar branch.
 template <class ST, class CT>
-__device__ __forceinline__ CT ld_pop(const void* base, long k, int kind) {
+__device__ __forceinline__ CT ld_pop(const void* base, long k, int kind, const CT* d, int i) {
     if constexpr (std::is_same<CT, float>::value) {
-        if (kind == P_F16) return Cv<__half, float>::ld(static_cast<const __half*>(base) + k);
+        if (kind == P_F16) return Cv<__half, float>::ld(static_cast<const __half*>(base) + k) + d[i];
         if (kind == P_F32) return Cv<float, float>::ld(static_cast<const float*>(base) + k);
     }
-    return Cv<ST, CT>::ld(static_cast<const ST*>(base) + k);
+    return unshift<ST, CT>(Cv<ST, CT>::ld(static_cast<const ST*>(base) + k), d, i);
 }
 
 template <class ST, class CT>
 __device__ __forceinline__ CT coarse_val(const StepArgs<ST, CT>& a, int i, int gx, int gy) {
     const long cc = (long)((gy >> 1) - a.cbox.gy0) * a.cbox.pitch + ((gx >> 1) - a.cbox.gx0);
-    return ld_pop<ST, CT>(a.fcoarse, i * a.cbox.plane + cc, a.cst);
+    return ld_pop<ST, CT>(a.fcoarse, i * a.cbox.plane + cc, a.cst, a.dsh, i);
 }
 
 // coalescence: mean of the four children of the finer band, for each direction
 template <class FT, class CT>
-__device__ __forceinline__ void coalesce(const FT* f, long plane, long pitch, long f0, CT s[9]) {
+__device__ __forceinline__ void coalesce(const FT* f, long plane, long pitch, long f0, const CT* d, CT s[9]) {
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
         const FT* p = f + i * plane + f0;
-        s[i] = CT(0.25) * ((Cv<FT, CT>::ld(p) + Cv<FT, CT>::ld(p + 1)) +
-                           (Cv<FT, CT>::ld(p + pitch) + Cv<FT, CT>::ld(p + pitch + 1)));
+        s[i] = unshift<FT, CT>(CT(0.25) * ((Cv<FT, CT>::ld(p) + Cv<FT, CT>::ld(p + 1)) +
+                                           (Cv<FT, CT>::ld(p + pitch) + Cv<FT, CT>::ld(p + pitch + 1))),
+                               d, i);
     }
 }
 
@@ -443,7 +459,7 @@ __device__ bool pull_general(const StepArgs<ST, CT>& a, uint8_t fl, int i, int g
     if ((fl & F_NEARGHOST) && a.substep == 1 && (a.flag[cs] & F_TYPE) == T_GHOST)
         out = coarse_val(a, di, sx, sy);
     else
-        out = Cv<ST, CT>::ld(a.fsrc + di * a.box.plane + cs);
+        out = unshift<ST, CT>(Cv<ST, CT>::ld(a.fsrc + di * a.box.plane + cs), a.dsh, di);
     return true;
 }
 
@@ -480,7 +496,7 @@ __device__ __forceinline__ CT poststream(const StepArgs<ST, CT>& a, int i, int g
         else { sy = gy; di = MIRY[i]; }
     }
     const long cs = (long)(sy - a.box.gy0) * a.box.pitch + (sx - a.box.gx0);
-    return Cv<ST, CT>::ld(a.fsrc + di * a.box.plane + cs);
+    return unshift<ST, CT>(Cv<ST, CT>::ld(a.fsrc + di * a.box.plane + cs), a.dsh, di);
 }
 
 // Moments (eq (3) with the half-force shift) and the collision with
@@ -545,7 +561,7 @@ __device__ __forceinline__ void finish_cell(const StepArgs<ST, CT>& a, long c, C
     a.mdst[2 * P + c] = uy;
     a.cdst[c] = chi_new;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) Cv<ST, CT>::st(a.fdst + i * P + c, s[i]);
+    for (int i = 0; i < 9; ++i) Cv<ST, CT>::st(a.fdst + i * P + c, toshift<ST, CT>(s[i], a.dsh, i));
 }
 
 // ---------------------------------------------------------------------------
@@ -685,9 +701,9 @@ __device__ __forceinline__ void boundary_node(const StepArgs<ST, CT>& a, int b) 
         }
         const uint32_t src = (uint32_t)((gy - CY[i] - a.box.gy0) * pitch + (sx - a.box.gx0) + pad);
         const uint32_t f2 = (uint32_t)((gy + CY[i] - a.box.gy0) * pitch + (fx - a.box.gx0) + pad);
-        pull[i] = bld<ST, CT>(rf, src * SS, (uint32_t)(i * P) * SS);
-        own[i] = bld<ST, CT>(rf, e * SS, (uint32_t)(i * P) * SS);
-        nxt[i] = bld<ST, CT>(rf, f2 * SS, (uint32_t)(OPP[i] * P) * SS);   // f*_o at F2
+        pull[i] = unshift<ST, CT>(bld<ST, CT>(rf, src * SS, (uint32_t)(i * P) * SS), a.dsh, i);
+        own[i] = unshift<ST, CT>(bld<ST, CT>(rf, e * SS, (uint32_t)(i * P) * SS), a.dsh, i);
+        nxt[i] = unshift<ST, CT>(bld<ST, CT>(rf, f2 * SS, (uint32_t)(OPP[i] * P) * SS), a.dsh, OPP[i]);   // f*_o at F2
         f2fl[i] = __builtin_amdgcn_raw_buffer_load_b8(rg, f2, 0, 0);
     }
     const CT rhow = CT(wm[3]), uwx = CT(wm[4]), uwy = CT(wm[5]);
@@ -777,7 +793,7 @@ __device__ __forceinline__ void step_block(const StepArgs<ST, CT>& a, const int 
     CT s[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i)
-        s[i] = bld<ST, CT>(rf, e * SS, (uint32_t)(i * P - CX[i] - CY[i] * pitch) * SS);
+        s[i] = unshift<ST, CT>(bld<ST, CT>(rf, e * SS, (uint32_t)(i * P - CX[i] - CY[i] * pitch) * SS), a.dsh, i);
     const double dist = Bf<double>::ld(rd, e * 8u, 0);
     const uint8_t fl = __builtin_amdgcn_raw_buffer_load_b8(rg, e, 0, 0);
     // link mask: only cells of the ghost band, next to it, or anchoring a
@@ -838,7 +854,7 @@ __device__ __forceinline__ void step_block(const StepArgs<ST, CT>& a, const int 
             CT w = s[i];
             if (!(src_fluid || (src_ghost && a.substep == 2)))
                 w = coarse_val(a, i, gx - k * CX[i], gy - k * CY[i]);
-            bst<ST, CT>(rfo, e * SS, (uint32_t)(i * P) * SS, w);
+            bst<ST, CT>(rfo, e * SS, (uint32_t)(i * P) * SS, toshift<ST, CT>(w, a.dsh, i));
         }
     } else if (type == T_FLUID && !(fl & (F_WALL | F_EDGE))) {   // others: side-stream kernels
         update = true;
@@ -847,13 +863,13 @@ __device__ __forceinline__ void step_block(const StepArgs<ST, CT>& a, const int 
             const long f0 = (long)(2 * gy - a.fbox.gy0) * a.fbox.pitch + (2 * gx - a.fbox.gx0);
             if constexpr (std::is_same<CT, float>::value) {
                 if (a.fst == P_F16)
-                    coalesce<__half, CT>(static_cast<const __half*>(a.ffine), a.fbox.plane, a.fbox.pitch, f0, s);
+                    coalesce<__half, CT>(static_cast<const __half*>(a.ffine), a.fbox.plane, a.fbox.pitch, f0, a.dsh, s);
                 else if (a.fst == P_F32)
-                    coalesce<float, CT>(static_cast<const float*>(a.ffine), a.fbox.plane, a.fbox.pitch, f0, s);
+                    coalesce<float, CT>(static_cast<const float*>(a.ffine), a.fbox.plane, a.fbox.pitch, f0, a.dsh, s);
                 else
-                    coalesce<ST, CT>(static_cast<const ST*>(a.ffine), a.fbox.plane, a.fbox.pitch, f0, s);
+                    coalesce<ST, CT>(static_cast<const ST*>(a.ffine), a.fbox.plane, a.fbox.pitch, f0, a.dsh, s);
             } else {
-                coalesce<ST, CT>(static_cast<const ST*>(a.ffine), a.fbox.plane, a.fbox.pitch, f0, s);
+                coalesce<ST, CT>(static_cast<const ST*>(a.ffine), a.fbox.plane, a.fbox.pitch, f0, a.dsh, s);
             }
         } else if ((fl & F_NEARGHOST) && a.substep == 1) {
             // next to the fine band on the first sub-step: exploded coarse populations
@@ -888,7 +904,7 @@ __device__ __forceinline__ void step_block(const StepArgs<ST, CT>& a, const int 
         bst<CT, CT>(rmo, e * CS, 2u * (uint32_t)P * CS, m_uy);
         bst<CT, CT>(rco, e * CS, 0, chi_new);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) bst<ST, CT>(rfo, e * SS, (uint32_t)(i * P) * SS, s[i]);
+        for (int i = 0; i < 9; ++i) bst<ST, CT>(rfo, e * SS, (uint32_t)(i * P) * SS, toshift<ST, CT>(s[i], a.dsh, i));
     }
     if (!restrict_tile) return;
     // restriction for the next parent step: the new rho, u and chi of each 2 x 2
@@ -1030,7 +1046,9 @@ __global__ void k_init(const InitArgs a) {
     collide(s, drho, ux, uy, omega, CT(a.omega_b), CT(a.fx), CT(a.fy));
     absorb<CT>(a.sp, a.nxd, a.nyd, (int)(c % a.pitch) + a.gx0, (int)(c / a.pitch) + a.gy0, s);
     ST* f = (ST*)a.f;
-    for (int i = 0; i < 9; ++i) Cv<ST, CT>::st(f + i * a.plane + c, s[i]);
+    CT d[9];
+    for (int i = 0; i < 9; ++i) d[i] = CT(a.dsh[i]);
+    for (int i = 0; i < 9; ++i) Cv<ST, CT>::st(f + i * a.plane + c, toshift<ST, CT>(s[i], d, i));
 }
 
 // ---------------------------------------------------------------------------

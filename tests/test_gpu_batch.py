@@ -38,7 +38,7 @@ def _assert_same(a, b, n_levels, tag):
     assert np.array_equal(a.forces(), b.forces()), tag
 
 
-@pytest.mark.parametrize("storage", ["f32", "f64", "mixed"])
+@pytest.mark.parametrize("storage", ["f32", "f64", "mixed", "mixeds"])
 def test_batched_sweep_matches_cases_advanced_alone(storage):
     import paper_2601_18443_amd as P
     cases = _cases()

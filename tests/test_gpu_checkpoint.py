@@ -26,7 +26,7 @@ def _same(a, b):
     return all(np.array_equal(x, y, equal_nan=True) for x, y in zip(a, b))
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16", "mixed"])
+@pytest.mark.parametrize("storage", ["f32", "f16", "mixed", "f16s"])
 def test_restart_is_bit_identical_to_the_uninterrupted_run(tmp_path, storage):
     import paper_2601_18443_amd as P
     case = dict(LI.case_airfoil_small(), ramp_steps=6, ramp_start=0.5)   # restart inside the ramp
@@ -61,6 +61,12 @@ def test_foreign_and_damaged_files_are_refused(tmp_path):
         other.load(good)
     with pytest.raises(P.LbrError):
         P.Solver(case, storage="f64").load(good)                            # another storage
+    h16 = P.Solver(case, storage="f16")
+    h16.advance(1)
+    h16_path = str(tmp_path / "h16.lbr")
+    h16.save(h16_path)
+    with pytest.raises(P.LbrError):
+        P.Solver(case, storage="f16s").load(h16_path)                       # another storage shift
 
     raw = open(good, "rb").read()
     cut = str(tmp_path / "cut.lbr")

@@ -19,7 +19,13 @@ storage is checked against the oracle's surface Cp, Cf and forces:
   * mixed: Cp 1.2e-2, Cf 6e-3 max|Cf|, C_D and C_L 5.5e-3 (measured 4.4e-3,
     2.3e-3, 2.2e-3, 1.8e-3): FP16 on the coarsest level alone costs most of the
     FP16 error, so the pressure level set by the far field, not the wall layer,
-    limits the 16-bit formats.
+    limits the 16-bit formats;
+  * the same three 16-bit formats with the free-stream storage shift (the
+    stored value is f_i - f_eq_i(rho_ref, U) instead of f_i - w_i):
+    FP16 Cp 5.5e-3, Cf 1.4e-3, C_D and C_L 1.2e-3 (measured 2.2e-3, 5.5e-4,
+    4.6e-4, 1.4e-4); BF16 Cp 4e-2, Cf 6e-3, C_D and C_L 1.2e-2 (measured
+    1.5e-2, 2.3e-3, 4.9e-3, 3.4e-6); mixed Cp 3.5e-4, Cf 1e-4 (the FP32 Cf
+    bound), C_D and C_L 2.5e-4 (measured 1.3e-4, 3.5e-5, 9.9e-5, 8.5e-5).
 
 The 16-bit bounds are the measured errors with a margin of about 2.5: they
 record how much accuracy each format gives up, so that a regression shows.
@@ -40,6 +46,9 @@ BOUNDS = {  # storage: (Cp max-abs, Cf max-abs / max|Cf|, C_D and C_L relative)
     "f16": (3e-2, 1e-2, 6e-3),
     "bf16": (0.2, 5e-2, 8e-2),
     "mixed": (1.2e-2, 6e-3, 5.5e-3),
+    "f16s": (5.5e-3, 1.4e-3, 1.2e-3),
+    "bf16s": (4e-2, 6e-3, 1.2e-2),
+    "mixeds": (3.5e-4, 1e-4, 2.5e-4),
 }
 
 
@@ -52,7 +61,7 @@ def converged_oracle():
     return case, cp, cf, o.forces()
 
 
-@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16", "mixed"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16", "mixed", "f16s", "bf16s", "mixeds"])
 def test_converged_surface_data_per_storage(converged_oracle, storage):
     case, cpo, cfo, fo = converged_oracle
     g = U.gpu_solver(case, storage)
