@@ -58,16 +58,15 @@ def log(msg):
 
 
 def kernel_source_hash():
-    """Hash of the kernels and of the host code that lays out their launches."""
-    h = hashlib.sha256()
-    for f in KERNEL_SRCS:
-        with open(f, "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+    """Hash of the code (comments and whitespace stripped) of the kernels and of
+    the host code that lays out their launches; the same as the profile
+    summaries record."""
+    from paper_2601_18443_amd.prof_summary import kernel_source_hash as h
+    return h()
 
 
 def measured_traffic(storage):
-    """HBM bytes per k_step launch from the committed rocprofv3 counter summary,
+    """HBM bytes per step-kernel launch from the committed rocprofv3 counter summary,
     or None when the summary is missing or the kernel changed since."""
     if not os.path.exists(TRAFFIC_FILE):
         return None

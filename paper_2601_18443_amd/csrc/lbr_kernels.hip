@@ -1,14 +1,15 @@
 // Device code of liblbr (gfx950).
 //
-// The hot kernel is k_step: one pass per (sub-)step of a level that, for each
-// owned fluid cell, advances the SA-neg variable, pulls the nine populations
-// (with bounce-back at cut links, domain rules, the coarse/fine transfer),
-// forms rho and u, and applies the central-moment collision.  Populations are
-// stored shifted by their lattice weight (s_i = f_i - w_i) in planes of a
-// level's storage box; one 64 x 4 tile per 256-thread workgroup, one
-// wavefront per tile row, so every population plane is read and written in
-// coalesced 64-wide rows.  The work is bandwidth-bound and uses no matrix
-// cores.
+// The hot kernel is k_step (and k_step_batch, the same work for several
+// parts of one grid): one pass per (sub-)step of a level that, for each owned
+// fluid cell, advances the SA-neg variable, pulls the nine populations (with
+// bounce-back at cut links, domain rules, the coarse/fine transfer), forms rho
+// and u, and applies the central-moment collision.  Populations are stored
+// shifted (s_i = f_i - w_i, or minus the free-stream equilibrium in the 16-bit
+// formats) in planes of a level's storage box; one 64 x H tile per workgroup
+// (H = 2, 4 or 8), one wavefront per tile row, so every population plane is
+// read and written in coalesced 64-wide rows.  The work is bandwidth-bound and
+// uses no matrix cores.
 #include "lbr_impl.h"
 #include <hip/hip_ext.h>
 
@@ -567,7 +568,7 @@ __device__ __forceinline__ void finish_cell(const StepArgs<ST, CT>& a, long c, C
 // ---------------------------------------------------------------------------
 // k_step: all owned fluid cells of a level except the wall nodes and the
 // domain edge (side-stream kernels), and the ghost band.  One workgroup per
-// active 64 x 4 tile, one wavefront per tile row: the nine pulled populations
+// active 64 x H tile, one wavefront per tile row: the nine pulled populations
 // are read straight from memory (coalesced rows), the 3 x 3 SA stencil of
 // chi, u_x and u_y is staged in LDS with a one-cell halo (allocations carry
 // one spare row at both ends, so every halo address is valid).

@@ -35,10 +35,14 @@ SOURCES = [os.path.join(_HERE, "csrc", f) for f in ("lbr_kernels.hip", "lbr_host
 
 
 def kernel_source_hash():
+    """Hash of the code (comments and whitespace stripped) of the kernels and
+    of the host code that lays out their launches."""
     h = hashlib.sha256()
     for f in SOURCES:
-        with open(f, "rb") as fh:
-            h.update(fh.read())
+        with open(f) as fh:
+            text = re.sub(r"/\*.*?\*/", " ", fh.read(), flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 
