@@ -279,26 +279,32 @@ def case_sweep(k: int, seed: int = 0, finest_cells_per_chord: int = 512):
     alpha = -4 + 4k/3 degrees, 3 + (k mod 3) levels, finest c/512, and a domain
     width S in [8c, 20c] and finest band D0 in [0.25c, 1c] chosen so that the
     estimated cell count is closest to a seeded target drawn log-uniformly in
-    [0.5M, 4M] (the level-1 band must stay clear of the absorbing layer)."""
+    [0.5M, 4M] (the level-1 band must stay clear of the absorbing layer).  The
+    case records its estimate and the range of estimates the feasible domains
+    and bands span: a target outside that range is met at its nearest end."""
     rng = np.random.default_rng(5000 + seed)
     targets = np.exp(rng.uniform(np.log(0.5e6), np.log(4e6), size=16))
     L = 3 + (k % 3)
     alpha = -4.0 + 4.0 * k / 3.0
     best = None
+    lo, hi = np.inf, 0.0
     for S in np.linspace(8.0, 20.0, 49):
         dx0 = 2.0 ** (L - 1) / finest_cells_per_chord
         for D0 in np.linspace(0.25, 1.0, 31):
             band1 = D0 * 2 ** (L - 2)
             if band1 + 0.5 > 0.425 * S - 4 * dx0 * 2:
                 continue
-            err = abs(np.log(_estimate_cells(S, D0, L, finest_cells_per_chord) / targets[k]))
+            est = _estimate_cells(S, D0, L, finest_cells_per_chord)
+            lo, hi = min(lo, est), max(hi, est)
+            err = abs(np.log(est / targets[k]))
             if best is None or err < best[0]:
-                best = (err, S, D0)
-    _, S, D0 = best
+                best = (err, S, D0, est)
+    _, S, D0, est = best
     case = case_airfoil(seed=100 + seed * 16 + k, finest_cells_per_chord=finest_cells_per_chord,
                         n_levels=L, domain_chords=float(S), band_finest=float(D0),
                         alpha_deg=alpha, n_side=512)
-    case.update(name=f"sweep{k}", target_cells=float(targets[k]))
+    case.update(name=f"sweep{k}", target_cells=float(targets[k]), cells_estimate=float(est),
+                feasible_cells=(float(lo), float(hi)))
     return case
 
 
