@@ -179,6 +179,33 @@ def test_airfoil_small_variants_fp64(variant):
     np.testing.assert_allclose(g.forces(), o.forces(), rtol=1e-9, atol=1e-12)
 
 
+def test_three_element_small_fp64():
+    """Three bodies with narrow gaps (slat, main element, flap; 4 levels to
+    c/256): grids, cut links and wall records built independently must agree,
+    then four FP64 coarse steps match the oracle in every field, in the
+    friction velocity of every wall node and in the forces and surface data of
+    each body."""
+    case = LI.case_three_element(finest_cells_per_chord=256, n_levels=4, domain_chords=8.0,
+                                 band_finest=0.1, n_side=256)
+    case.update(ramp_steps=0.0, ramp_start=0.0)
+    o, g = _pair(case, "f64")
+    L = case["n_levels"]
+    assert U.structure_mismatch(g, o, L, case["nx0"]) == []
+    o.advance(4)
+    g.advance(4)
+    assert U.velocity_error(g, o, L) < 1e-10
+    err = U.field_errors(g, o, L, names=("chi",))
+    assert max(err.values()) < 1e-10, err
+    assert U.density_error(g, o, L) < 1e-12
+    np.testing.assert_allclose(g.wall(L - 1)[:, 8], o.wall(L - 1)[:, 8], rtol=1e-10)
+    for body in (0, 1, 2, -1):
+        np.testing.assert_allclose(g.forces(body), o.forces(body), rtol=1e-9, atol=1e-12)
+    for body in (0, 1, 2):
+        (cpg, cfg), (cpo, cfo) = g.surface(body), o.surface(body)
+        np.testing.assert_allclose(cpg, cpo, rtol=1e-9, atol=1e-12)
+        np.testing.assert_allclose(cfg, cfo, rtol=1e-9, atol=1e-12)
+
+
 def test_full_size_airfoil_fp32_against_oracle():
     """The benchmark workload itself (8 levels, ~2.0M cells, FP32, graph replay as
     timed by bench.py) against the FP64 oracle after two coarse steps (510 k_step
