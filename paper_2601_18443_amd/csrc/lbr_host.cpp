@@ -1125,7 +1125,9 @@ int lbr_create(const lbr_config* cfg, lbr_ctx** out) {
         (cfg->bc[2] == LBR_BC_PERIODIC) != (cfg->bc[3] == LBR_BC_PERIODIC) ||
         cfg->bc[0] == LBR_BC_WALL || cfg->bc[1] == LBR_BC_WALL)
         return LBR_ERR_INVALID_ARG;
-    if ((long)cfg->nx0 << (cfg->n_levels - 1) > (1L << 28)) return LBR_ERR_INVALID_ARG;
+    // global cell indices of the finest level stay well inside 32 bits
+    if ((long)cfg->nx0 << (cfg->n_levels - 1) > (1L << 28) || (long)cfg->ny0 << (cfg->n_levels - 1) > (1L << 28))
+        return LBR_ERR_INVALID_ARG;
     lbr_ctx* c = new lbr_ctx();
     c->cfg = *cfg;
     c->stream = static_cast<hipStream_t>(cfg->stream);

@@ -52,3 +52,38 @@ def test_config_validation_without_gpu():
     bad = P.make_config(case, "f64")
     bad.bc[0] = LI.BC_INLET          # periodic sides come in pairs
     assert L.lbr_create(ctypes.byref(bad), ctypes.byref(h)) == -1
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="liblbr.so not built")
+@pytest.mark.parametrize("field,value", [
+    ("n_levels", 0), ("n_levels", 13),                       # 1..LBR_MAX_LEVELS
+    ("nx0", 3), ("ny0", 2),                                  # at least 4 cells
+    ("nx0", 1 << 22), ("ny0", 1 << 22),                      # finest indices past 2^28 (8 levels)
+    ("dx0", 0.0), ("dx0", -1.0),
+    ("storage", -1), ("storage", 5),
+    ("outlet", 3), ("sponge_width", -1.0), ("sponge_strength", 1.5),
+    ("ramp_steps", -1.0), ("ramp_start", 1.5), ("shift16", 2),
+    ("reynolds", 0.0),                                       # no finite viscosity
+])
+def test_create_refuses_out_of_range_config(field, value):
+    import paper_2601_18443_amd as P
+    import lbr_inputs as LI
+    L = P.lib()
+    case = LI.case_airfoil_small()
+    cfg = P.make_config(dict(case, n_levels=8) if field in ("nx0", "ny0") and value > 1000 else case, "f32")
+    setattr(cfg, field, value)
+    h = ctypes.c_void_p()
+    assert L.lbr_create(ctypes.byref(cfg), ctypes.byref(h)) == -1
+    assert not h.value
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="liblbr.so not built")
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16", "mixed", "f16s", "bf16s", "mixeds"])
+def test_create_accepts_every_storage(storage):
+    import paper_2601_18443_amd as P
+    import lbr_inputs as LI
+    L = P.lib()
+    cfg = P.make_config(LI.case_airfoil_small(), storage)
+    h = ctypes.c_void_p()
+    assert L.lbr_create(ctypes.byref(cfg), ctypes.byref(h)) == 0
+    L.lbr_destroy(h)
