@@ -116,6 +116,26 @@ def copy_calibration(nbytes=1 << 30):
     print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "dispatches": 3}))
 
 
+def copy_bandwidth(nbytes=1 << 30, reps=10):
+    """Read + write GB/s of a plain device copy (torch copy_) of nbytes: what this
+    part sustains for a pure stream, the reference for the kernel's HBM rate."""
+    import torch
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    gbps = 2.0 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del x, y
+    torch.cuda.empty_cache()
+    return gbps
+
+
 def run_sweep(args):
     """Batched angle-of-attack sweep: 16 seeded cases (alpha -4..16 deg, 3-5 levels,
     finest c/512, 0.5M-3.4M cells each, 27M in all) advanced by shared launches, one
@@ -302,6 +322,14 @@ def main():
                 "finest_level_avg_launch_us": round(kt[1], 3),
                 "level0_avg_launch_us": round(kt[2], 3),
                 "alg_bytes_per_launch": round(bytes_per_launch, 0)}
+        # context: the measured HBM rate of the kernel against a plain device copy
+        copy = copy_bandwidth()
+        roof["copy_GBps"] = round(copy, 1)
+        if traffic is not None:
+            hbm = traffic / (kt[0] * 1e-6) / 1e9
+            roof["hbm_GBps"] = round(hbm, 1)
+            roof["hbm_over_copy"] = round(hbm / copy, 4)
+        log(f"device copy {copy:.0f} GB/s")
     # the same workload with 16-bit population storage (FP32 arithmetic), same timing
     variants = {}
     if not args.no_variants and args.storage == "f32":
