@@ -25,8 +25,10 @@ sys.path.insert(0, ROOT)
 METRIC = "MLUPS & % HBM peak, D2Q9 LBM-RANS step; FP16-store vs FP32 at equal Cf error"
 HBM_PEAK_GBS = 8000.0
 # algorithmic bytes per cell update: populations read + write (18 x storage),
-# nu-tilde read + write (2 x 4), FP64 wall distance (8), one flag byte
-ALG_BYTES = {"f32": 18 * 4 + 8 + 8 + 1, "f16": 18 * 2 + 8 + 8 + 1, "bf16": 18 * 2 + 8 + 8 + 1,
+# nu-tilde read + write (2 x its precision), the wall distance in the step's
+# arithmetic precision (the FP64 field, which the FP32 steps read rounded to
+# FP32), one flag byte
+ALG_BYTES = {"f32": 18 * 4 + 8 + 4 + 1, "f16": 18 * 2 + 8 + 4 + 1, "bf16": 18 * 2 + 8 + 4 + 1,
              "f64": 18 * 8 + 16 + 8 + 1}
 DTYPE = {"f32": "f32", "f16": "f16-store/f32", "bf16": "bf16-store/f32", "f64": "f64",
          "mixed": "f32-store on the two finest levels, f16-store below/f32",

@@ -48,7 +48,7 @@ struct Level {
     void* f[2] = {nullptr, nullptr};
     void* mac[2] = {nullptr, nullptr};
     void* chi[2] = {nullptr, nullptr};
-    double* dist_dev = nullptr;
+    void* dist_dev = nullptr;     // wall distance for the step kernels, in their arithmetic precision
     uint8_t* flag_dev = nullptr;
     uint32_t* rows_dev[NTY] = {};
     uint32_t* lmask_dev = nullptr;
@@ -673,14 +673,24 @@ int alloc_level(lbr_ctx* c, Level& L) {
         HIPCHK(c, hipMemsetAsync(static_cast<char*>(L.chi[b]) - pad * c->csize, 0, (n + 2 * pad) * c->csize, c->stream));
     }
     L.bytes += 2 * (n + 2 * pad) * (9 * L.ssize + 4 * c->csize);
+    // The wall distance is computed in FP64 (k_geometry).  The FP64 step reads
+    // it as such; the FP32-arithmetic steps round it to FP32 at every use, so
+    // they read that rounding, stored once (the same values, half the bytes).
     std::vector<double> dclamp(L.d);
     if (c->prec != P_F64)
         for (double& v : dclamp) v = std::min(v, 1e18);
-    L.dist_dev = static_cast<double*>(dalloc_padded(c, n, sizeof(double), pad));
+    L.dist_dev = dalloc_padded(c, n, c->csize, pad);
     if (!L.dist_dev) return set_err(c, LBR_ERR_OOM, "level %d: out of device memory", L.l);
-    HIPCHK(c, hipMemsetAsync(L.dist_dev - pad, 0, (n + 2 * pad) * sizeof(double), c->stream));
-    HIPCHK(c, hipMemcpyAsync(L.dist_dev, dclamp.data(), n * sizeof(double), hipMemcpyHostToDevice, c->stream));
-    L.bytes += (n + 2 * pad) * sizeof(double);
+    HIPCHK(c, hipMemsetAsync(static_cast<char*>(L.dist_dev) - pad * c->csize, 0, (n + 2 * pad) * c->csize, c->stream));
+    std::vector<float> d32;
+    if (c->prec == P_F64) {
+        HIPCHK(c, hipMemcpyAsync(L.dist_dev, dclamp.data(), n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    } else {
+        d32.assign(dclamp.begin(), dclamp.end());
+        HIPCHK(c, hipMemcpyAsync(L.dist_dev, d32.data(), n * sizeof(float), hipMemcpyHostToDevice, c->stream));
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));                    // the host copies die here
+    L.bytes += (n + 2 * pad) * c->csize;
     // flags carry the same spare row at both ends (T_INACTIVE): the k_step halo reads them
     L.flag_dev = static_cast<uint8_t*>(dalloc_padded(c, n, 1, pad));
     if (!L.flag_dev) return set_err(c, LBR_ERR_OOM, "level %d: out of device memory", L.l);
@@ -812,7 +822,7 @@ void fill_step_args(lbr_ctx* c, int l, int substep, StepArgs<ST, CT>& a, int tk 
     a.mdst = (CT*)L.mac[1 - L.cur];
     a.csrc = (const CT*)L.chi[L.cur];
     a.cdst = (CT*)L.chi[1 - L.cur];
-    a.dist = L.dist_dev;
+    a.dist = static_cast<const CT*>(L.dist_dev);
     a.flag = L.flag_dev;
     a.lmask = L.lmask_dev;
     if (tk < 0) tk = L.ty;                                       // tile height

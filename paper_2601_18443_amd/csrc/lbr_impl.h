@@ -75,7 +75,7 @@ struct StepArgs {
     const ST* fsrc;  ST* fdst;       // 9 population planes (shifted by w_i)
     const CT* msrc;  CT* mdst;       // 3 planes: rho, ux, uy
     const CT* csrc;  CT* cdst;       // chi = nu~ / nu
-    const double* dist;              // wall distance (level lattice units)
+    const CT* dist;                  // wall distance (level lattice units), in CT
     const uint8_t* flag;
     const uint32_t* lmask;           // per cell: bit i, source c - c_i is owned fluid;
                                      // bit 16 + i, source is a ghost; bit 31, lower-left

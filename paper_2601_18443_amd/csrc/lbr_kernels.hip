@@ -616,7 +616,7 @@ __device__ __forceinline__ void edge_cell(const StepArgs<ST, CT>& a, int e) {
     const long P = a.box.plane;
     const long c = a.edge[e];
     const int gx = (int)(c % pitch) + a.box.gx0, gy = (int)(c / pitch) + a.box.gy0;
-    const double dist = a.dist[c];
+    const CT dist = a.dist[c];
     CT s[9], nt[9], u[9], v[9];
     const bool at_inlet = gx == 0 && a.dom.bc[0] == BC_INLET;
     const bool at_outlet = gx == a.dom.nxd - 1 && a.dom.bc[1] == BC_OUTLET;
@@ -656,7 +656,7 @@ __device__ __forceinline__ void edge_cell(const StepArgs<ST, CT>& a, int e) {
     } else {
 #pragma unroll
         for (int k = 0; k < 9; ++k) nt[k] *= a.nu;
-        chi_new = fdiv(sa_update(nt, u, v, a.nu, CT(dist), a.sa_mode == 2), a.nu);
+        chi_new = fdiv(sa_update(nt, u, v, a.nu, dist, a.sa_mode == 2), a.nu);
     }
     finish_cell(a, c, s, chi_new, gx, gy);
 }
@@ -795,7 +795,7 @@ __device__ __forceinline__ void step_block(const StepArgs<ST, CT>& a, const int 
 #pragma unroll
     for (int i = 0; i < 9; ++i)
         s[i] = unshift<ST, CT>(bld<ST, CT>(rf, e * SS, (uint32_t)(i * P - CX[i] - CY[i] * pitch) * SS), a.dsh, i);
-    const double dist = Bf<double>::ld(rd, e * 8u, 0);
+    const CT dist = bld<CT, CT>(rd, e * CS, 0);
     const uint8_t fl = __builtin_amdgcn_raw_buffer_load_b8(rg, e, 0, 0);
     // link mask: only cells of the ghost band, next to it, or anchoring a
     // restriction block use it (most tiles have none)
@@ -893,7 +893,7 @@ __device__ __forceinline__ void step_block(const StepArgs<ST, CT>& a, const int 
                     u[k] = sh_u[wy + 1 + dy][lane + 1 + dx];
                     v[k] = sh_v[wy + 1 + dy][lane + 1 + dx];
                 }
-            chi_new = fdiv(sa_update(nt, u, v, a.nu, CT(dist), a.sa_mode == 2), a.nu);
+            chi_new = fdiv(sa_update(nt, u, v, a.nu, dist, a.sa_mode == 2), a.nu);
         }
         relax_cell(a, s, chi_new, m_rho, m_ux, m_uy);
         absorb(a, gx, gy, s);
