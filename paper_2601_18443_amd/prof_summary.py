@@ -101,9 +101,9 @@ def stats(directory, cmd):
                     g = int(_col(r, "Grid_Size_X", "Grid_Size", "Grid_X"))
                     d = float(_col(r, "End_Timestamp")) - float(_col(r, "Start_Timestamp"))
                     per[(n, g)].append(d)
-        out += ["", "step kernels by launch size",
+        out += ["", "step kernels by launch size (the 20 largest)",
                 f"{'kernel':34s} {'threads':>9s} {'blocks':>7s} {'calls':>7s} {'avg us':>9s} {'median us':>10s}"]
-        for (n, g), v in sorted(per.items(), key=lambda kv: -kv[0][1]):
+        for (n, g), v in sorted(per.items(), key=lambda kv: -kv[0][1])[:20]:
             v.sort()
             out.append(f"{n:34s} {g:9d} {g // 256:7d} {len(v):7d} {sum(v) / len(v) / 1e3:9.2f} "
                        f"{v[len(v) // 2] / 1e3:10.2f}")
