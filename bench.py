@@ -247,8 +247,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: the multi-GPU path is not part of this build "
-              "(see DESIGN.md for how the step would shard)", file=sys.stderr)
+        print("bench.py measures one GPU: running the step over several GPUs is not implemented",
+              file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
@@ -266,7 +266,7 @@ def main():
         args.warmup = max(args.warmup, int(case["ramp_steps"]) + 10)
         args.no_cpu_baseline = True
     else:
-        case = LI.case_airfoil_cfg1()
+        case = LI.case_airfoil_2M()
     log(f"building the {case['n_levels']}-level {args.workload} grid on the GPU")
     t0 = time.perf_counter()
     sim = P.Solver(case, storage=args.storage)

@@ -308,8 +308,9 @@ def case_sweep(k: int, seed: int = 0, finest_cells_per_chord: int = 512):
     return case
 
 
-def case_airfoil_cfg1(seed: int = 0):
-    """Single body, FP32: Re 6e6, Mach 0.15, 10 deg, finest c/1024, 40-chord domain."""
+def case_airfoil_2M(seed: int = 0):
+    """The benchmark airfoil: one body, 8 levels from c/8 to c/1024 (about 2.0M cells),
+    40-chord domain, Re 6e6, Mach 0.15, 10 degrees."""
     return case_airfoil(seed=seed)
 
 

@@ -211,7 +211,7 @@ def test_full_size_airfoil_fp32_against_oracle():
     timed by bench.py) against the FP64 oracle after two coarse steps (510 k_step
     launches, 2.5e8 cell updates): velocity and chi within 1e-5 relative on every
     level, density within 1e-6, forces within 1e-4."""
-    case = LI.case_airfoil_cfg1()
+    case = LI.case_airfoil_2M()
     o, g = _pair(case, "f32")
     assert U.structure_mismatch(g, o, case["n_levels"], case["nx0"]) == []
     g.use_graph(True)
