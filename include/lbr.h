@@ -216,6 +216,13 @@ int lbr_synchronize(lbr_ctx* ctx);
    cell type for every cell). */
 int lbr_read_field(lbr_ctx* ctx, int32_t level, int32_t field, double* dst);
 
+/* As lbr_read_field, into device memory: dst is a device array of at least
+   capacity doubles (ny x nx of the level's I/O box, else LBR_ERR_INVALID_ARG),
+   written asynchronously on the context's stream.  LBR_FIELD_DIST reads the
+   distance as the step kernels hold it (FP64 in FP64 contexts, its FP32
+   rounding otherwise). */
+int lbr_read_field_device(lbr_ctx* ctx, int32_t level, int32_t field, double* dst, int64_t capacity);
+
 /* Number of wall nodes on a level, and their records (LBR_WALL_STRIDE doubles
    each, in row-major cell order).  The records hold the wall model evaluated
    on the current state (steps 1-5 of the VN procedure, Section 2.3) and the

@@ -85,6 +85,7 @@ def lib():
         L.lbr_last_error.restype = C.c_char_p
         L.lbr_destroy.argtypes = [p]
         L.lbr_destroy.restype = None
+        L.lbr_read_field_device.argtypes = [p, i32, i32, C.c_void_p, i64]
         L.lbr_wall_yplus.argtypes = [p, i32, dp]
         L.lbr_rake.argtypes = [p, C.c_double, C.c_double, C.c_double, C.c_double, i32, dp]
         L.lbr_schedule.argtypes = [i32, i32, C.POINTER(C.c_int32), i32]
@@ -245,6 +246,16 @@ class Solver:
         inf = self.level_info(level)
         out = np.empty((inf["ny"], inf["nx"]))
         self._check(lib().lbr_read_field(self.h, level, which, _dp(out)))
+        return out
+
+    def field_device(self, level, which):
+        """One field of a level as a float64 device tensor (ny, nx), written by the
+        library on its stream; torch's current stream waits for it."""
+        import torch
+        inf = self.level_info(level)
+        out = torch.empty((inf["ny"], inf["nx"]), dtype=torch.float64, device=self.device)
+        self._check(lib().lbr_read_field_device(self.h, level, which, C.c_void_p(out.data_ptr()), out.numel()))
+        torch.cuda.current_stream(self.device).wait_stream(self.torch_stream)
         return out
 
     def wall(self, level):

@@ -1512,6 +1512,32 @@ int lbr_read_field(lbr_ctx* c, int32_t level, int32_t field, double* dst) {
     return LBR_OK;
 }
 
+int lbr_read_field_device(lbr_ctx* c, int32_t level, int32_t field, double* dst, int64_t capacity) {
+    if (!c || !dst) return LBR_ERR_INVALID_ARG;
+    if (!c->built || level < 0 || level >= (int)c->lv.size())
+        return set_err(c, LBR_ERR_INVALID_ARG, "bad level %d", level);
+    if (field < 0 || field > LBR_FIELD_DIST) return set_err(c, LBR_ERR_INVALID_ARG, "bad field %d", field);
+    Level& L = c->lv[level];
+    if (capacity < (int64_t)L.bnx * L.bny)
+        return set_err(c, LBR_ERR_INVALID_ARG, "level %d needs %lld doubles", level, (long long)L.bnx * L.bny);
+    FieldArgs a{};
+    const size_t pb = (size_t)L.box.plane * c->csize;
+    if (field == LBR_FIELD_CHI || field == LBR_FIELD_NUT) a.src = L.chi[L.cur];
+    else if (field <= LBR_FIELD_UY) a.src = static_cast<const char*>(L.mac[L.cur]) + (size_t)field * pb;
+    a.dist = L.dist_dev;
+    a.flag = L.flag_dev;
+    a.pitch = L.box.pitch;
+    a.ox = L.bx0 - L.box.gx0;
+    a.oy = L.by0 - L.box.gy0;
+    a.bnx = L.bnx;
+    a.bny = L.bny;
+    a.field = field;
+    a.nu = L.nu;
+    a.out = dst;
+    HIPCHK(c, launch_field(c->prec, a, c->stream));
+    return LBR_OK;
+}
+
 int lbr_wall_count(lbr_ctx* c, int32_t level) {
     if (!c || !c->built || level < 0 || level >= (int)c->lv.size()) return LBR_ERR_INVALID_ARG;
     return (int)c->lv[level].nodes.size();

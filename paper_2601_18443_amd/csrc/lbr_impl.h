@@ -177,6 +177,18 @@ hipError_t launch_restrict(Prec p, const RestrictArgs& a, hipStream_t s);
 hipError_t launch_init(Prec p, const InitArgs& a, hipStream_t s);
 hipError_t launch_surface(Prec p, const SurfaceArgs& a, int nblocks, hipStream_t s);
 hipError_t launch_sum_partials(const double* partial, int nblocks, double* out, hipStream_t s);
+// One field over a level's I/O box into device memory (field codes of lbr.h)
+struct FieldArgs {
+    const void* src;                 // the rho / u_x / u_y or chi plane (CT)
+    const void* dist;                // wall distance (CT)
+    const uint8_t* flag;
+    long pitch;
+    int ox, oy, bnx, bny;            // I/O box origin in the storage box, and its size
+    int field;
+    double nu;
+    double* out;                     // [bny][bnx]
+};
+hipError_t launch_field(Prec p, const FieldArgs& a, hipStream_t s);
 // dst[k] = src[idx[k]] for the macroscopic / chi planes (CT of precision p)
 hipError_t launch_gather(Prec p, const void* src, const int64_t* idx, int n, double* dst, hipStream_t s);
 hipError_t launch_to_double(Prec p, const void* src, double* dst, long n, hipStream_t s);

@@ -1170,6 +1170,28 @@ __global__ void k_to_double(const CT* src, double* dst, long n) {
     if (k < n) dst[k] = (double)src[k];
 }
 
+// One field of a level over its I/O box, into a device array (the layout of
+// the host readout): the cell type for TYPE, NaN outside the owned fluid, and
+// nu_t = nu chi f_v1(chi) for NUT.
+template <class CT>
+__global__ void k_field(const FieldArgs a) {
+#pragma clang fp contract(off)   // the same roundings as the host readout (no fused multiply-add)
+    const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (long)a.bnx * a.bny) return;
+    const long i = k % a.bnx, j = k / a.bnx;
+    const long c = (a.oy + j) * a.pitch + (a.ox + i);
+    const int t = a.flag[c] & F_TYPE;
+    double o;
+    if (a.field == 5) o = t;
+    else if (t != T_FLUID) o = __builtin_nan("");
+    else if (a.field == 6) o = (double)static_cast<const CT*>(a.dist)[c];
+    else {
+        const double x = (double)static_cast<const CT*>(a.src)[c];
+        o = a.field == 4 ? (x > 0 ? a.nu * x * x * x * x / (x * x * x + 7.1 * 7.1 * 7.1) : 0.0) : x;
+    }
+    a.out[k] = o;
+}
+
 // Values of a plane at listed cells (diagnostics): dst[k] = src[idx[k]].
 template <class CT>
 __global__ void k_gather(const CT* src, const int64_t* idx, int n, double* dst) {
@@ -1316,6 +1338,14 @@ hipError_t launch_residual(Prec p, const void* mac, double* snap, const int32_t*
     else
         hipLaunchKernelGGL(k_residual<float>, dim3(nb), dim3(256), 0, s, (const float*)mac, snap,
                            list, n, plane, area, partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_field(Prec p, const FieldArgs& a, hipStream_t s) {
+    const long n = (long)a.bnx * a.bny;
+    if (n == 0) return hipSuccess;
+    if (p == P_F64) hipLaunchKernelGGL(k_field<double>, dim3(nblocks(n, 256)), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_field<float>, dim3(nblocks(n, 256)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

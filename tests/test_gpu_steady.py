@@ -1,4 +1,4 @@
-"""Convergence monitor of the HIP library (needs an MI355X).
+"""Convergence monitor and field readout of the HIP library (needs an MI355X).
 
 The residual is the relative change of the velocity field since the previous
 call, per coarse step: ||u(t) - u(t - n)||_2 / (n ||u(t)||_2) over all owned
@@ -75,3 +75,22 @@ def test_run_to_steady_stops_at_the_first_check_below_tolerance():
     s2 = P.Solver(case, storage="f32")
     done, r = s2.run_to_steady(0.0, 35, 10)              # never met: stops at max_steps
     assert done == 35 and np.isfinite(r)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_device_field_readout_matches_the_host_readout(storage):
+    import paper_2601_18443_amd as P
+    case = LI.case_airfoil_small()
+    s = P.Solver(case, storage=storage)
+    s.advance(4)
+    for lvl in range(case["n_levels"]):
+        for f in range(7):
+            host = s.field(lvl, f)
+            dev = s.field_device(lvl, f).cpu().numpy()
+            if f == 6 and storage != "f64":                 # the distance as the FP32 steps hold it
+                host = np.where(np.isfinite(host), host.astype(np.float32).astype(np.float64), host)
+            assert np.array_equal(dev, host, equal_nan=True), (lvl, f)
+    import ctypes
+    import torch
+    small = torch.empty(4, dtype=torch.float64, device=s.device)     # too small for any level
+    assert P.lib().lbr_read_field_device(s.h, 0, 0, ctypes.c_void_p(small.data_ptr()), small.numel()) == -1
