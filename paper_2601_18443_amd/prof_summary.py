@@ -73,7 +73,7 @@ def _col(row, *names):
     raise KeyError(f"none of {names} in {list(row)}")
 
 
-def stats(directory, cmd):
+def stats(directory, cmd, tail=0):
     out = [f"# rocprofv3 kernel statistics", f"# command: {cmd}", ""]
     rows = []
     for path in _find(directory, "*kernel_stats.csv"):
@@ -92,6 +92,7 @@ def stats(directory, cmd):
     traces = glob.glob(os.path.join(directory, "**", "*kernel_trace.csv"), recursive=True)
     if traces:
         per = defaultdict(list)
+        seq = []
         for path in traces:
             with open(path) as fh:
                 for r in csv.DictReader(fh):
@@ -99,8 +100,15 @@ def stats(directory, cmd):
                     if not n.startswith("k_step"):
                         continue
                     g = int(_col(r, "Grid_Size_X", "Grid_Size", "Grid_X"))
-                    d = float(_col(r, "End_Timestamp")) - float(_col(r, "Start_Timestamp"))
+                    t0 = float(_col(r, "Start_Timestamp"))
+                    d = float(_col(r, "End_Timestamp")) - t0
                     per[(n, g)].append(d)
+                    seq.append((t0, d))
+        if tail and seq:
+            seq.sort()
+            last = [d for _, d in seq[-tail:]]
+            out += ["", f"step kernels, the last {len(last)} dispatches (the direct launches that "
+                    f"bench.py times with dispatch events): average {sum(last) / len(last) / 1e3:.2f} us"]
         out += ["", "step kernels by launch size (the 20 largest)",
                 f"{'kernel':34s} {'threads':>9s} {'blocks':>7s} {'calls':>7s} {'avg us':>9s} {'median us':>10s}"]
         for (n, g), v in sorted(per.items(), key=lambda kv: -kv[0][1])[:20]:
@@ -171,6 +179,8 @@ def main(argv=None):
     s = sub.add_parser("stats")
     s.add_argument("dir")
     s.add_argument("--cmd", required=True)
+    s.add_argument("--tail", type=int, default=0,
+                   help="also average the last TAIL step-kernel dispatches")
     t = sub.add_parser("traffic")
     for k in ("fetch", "write", "cal_fetch", "cal_write"):
         t.add_argument("--" + k.replace("_", "-"), dest=k, required=True)
@@ -183,7 +193,7 @@ def main(argv=None):
     t.add_argument("--kernel", default="k_step_batch",
                    help="kernel whose dispatches are averaged (k_step_batch: the merged schedule)")
     a = ap.parse_args(argv)
-    sys.stdout.write(stats(a.dir, a.cmd) if a.what == "stats" else traffic(a))
+    sys.stdout.write(stats(a.dir, a.cmd, a.tail) if a.what == "stats" else traffic(a))
 
 
 if __name__ == "__main__":
