@@ -176,8 +176,14 @@ typedef struct lbr_level_desc {
 #define LBR_WALL_STRIDE 28
 
 /* Creates a context and validates the config (Section 2.1 parameters:
-   omega_b, d_WR = 2, d_WV = 1 unless changed).  cfg is copied.
-   Errors: LBR_ERR_INVALID_ARG for an inconsistent config. */
+   omega_b, d_WR = 2, d_WV = 1 unless changed).  cfg is copied; no device
+   work is done.  Errors: LBR_ERR_INVALID_ARG for an inconsistent config: a
+   wrong version, an enum value outside its range, periodic sides that do not
+   come in pairs, a wall on an x side, fewer than 4 level-0 cells per side,
+   finest-level indices beyond 2^28, rho_ref, d_wr or d_wv not positive,
+   omega_b outside (0, 2), a viscosity that is not positive and finite, a
+   negative or non-finite band of a level in use, or any other non-finite
+   parameter. */
 int lbr_create(const lbr_config* cfg, lbr_ctx** out);
 
 /* Wall geometry (Section 2.3: surface segments in 2D): n_bodies closed

@@ -1135,6 +1135,23 @@ int lbr_create(const lbr_config* cfg, lbr_ctx** out) {
         (cfg->bc[2] == LBR_BC_PERIODIC) != (cfg->bc[3] == LBR_BC_PERIODIC) ||
         cfg->bc[0] == LBR_BC_WALL || cfg->bc[1] == LBR_BC_WALL)
         return LBR_ERR_INVALID_ARG;
+    for (int k = 0; k < 4; ++k)
+        if (cfg->bc[k] < LBR_BC_PERIODIC || cfg->bc[k] > LBR_BC_WALL) return LBR_ERR_INVALID_ARG;
+    if (cfg->wall_model < LBR_WALL_VN || cfg->wall_model > LBR_WALL_PRESCRIBED || cfg->bb < LBR_BB_AUTO ||
+        cfg->bb > LBR_BB_HALFWAY || cfg->sa < LBR_SA_FROZEN || cfg->sa > LBR_SA_UPWIND1 ||
+        cfg->body_mode < LBR_BODY_SOLID || cfg->body_mode > LBR_BODY_REFINE_ONLY)
+        return LBR_ERR_INVALID_ARG;
+    // physical parameters: positive density and wall distances, a bulk relaxation
+    // frequency of a stable BGK-type rate, finite everything else
+    if (!(cfg->rho_ref > 0) || !std::isfinite(cfg->rho_ref) || !(cfg->omega_b > 0 && cfg->omega_b < 2) ||
+        !(cfg->d_wr > 0) || !std::isfinite(cfg->d_wr) || !(cfg->d_wv > 0) || !std::isfinite(cfg->d_wv) ||
+        !std::isfinite(cfg->chi_inlet) || !std::isfinite(cfg->chi_init) || !std::isfinite(cfg->force[0]) ||
+        !std::isfinite(cfg->force[1]) || !std::isfinite(cfg->origin[0]) || !std::isfinite(cfg->origin[1]) ||
+        !std::isfinite(cfg->u_ref) || !std::isfinite(cfg->nu0) || !std::isfinite(cfg->dx0) ||
+        !std::isfinite(cfg->sponge_width) || !std::isfinite(cfg->ramp_steps))
+        return LBR_ERR_INVALID_ARG;
+    for (int l = 1; l < cfg->n_levels; ++l)
+        if (!(cfg->band[l] >= 0) || !std::isfinite(cfg->band[l])) return LBR_ERR_INVALID_ARG;
     // global cell indices of the finest level stay well inside 32 bits
     if ((long)cfg->nx0 << (cfg->n_levels - 1) > (1L << 28) || (long)cfg->ny0 << (cfg->n_levels - 1) > (1L << 28))
         return LBR_ERR_INVALID_ARG;

@@ -52,6 +52,13 @@ def test_config_validation_without_gpu():
     bad = P.make_config(case, "f64")
     bad.bc[0] = LI.BC_INLET          # periodic sides come in pairs
     assert L.lbr_create(ctypes.byref(bad), ctypes.byref(h)) == -1
+    for k, v in ((2, 5), (3, -1)):   # not a boundary kind
+        bad = P.make_config(case, "f64")
+        bad.bc[k] = v
+        assert L.lbr_create(ctypes.byref(bad), ctypes.byref(h)) == -1
+    bad = P.make_config(LI.case_airfoil_small(), "f32")
+    bad.band[1] = float("nan")       # refinement bands of the levels in use
+    assert L.lbr_create(ctypes.byref(bad), ctypes.byref(h)) == -1
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="liblbr.so not built")
@@ -64,6 +71,12 @@ def test_config_validation_without_gpu():
     ("outlet", 3), ("sponge_width", -1.0), ("sponge_strength", 1.5),
     ("ramp_steps", -1.0), ("ramp_start", 1.5), ("shift16", 2),
     ("reynolds", 0.0),                                       # no finite viscosity
+    ("wall_model", 4), ("bb", 3), ("sa", -1), ("sa", 3),     # enums
+    ("body_mode", 2),
+    ("rho_ref", 0.0), ("rho_ref", float("nan")),
+    ("omega_b", 0.0), ("omega_b", 2.0),                      # bulk rate in (0, 2)
+    ("d_wr", 0.0), ("d_wv", -1.0), ("chi_init", float("inf")),
+    ("u_ref", float("nan")), ("sponge_width", float("inf")),
 ])
 def test_create_refuses_out_of_range_config(field, value):
     import paper_2601_18443_amd as P
