@@ -1502,11 +1502,12 @@ int lbr_read_field(lbr_ctx* c, int32_t level, int32_t field, double* dst) {
         else src = static_cast<const char*>(L.mac[L.cur]) + (size_t)field * n * c->csize;
         double* tmp = static_cast<double*>(dalloc(c, n * sizeof(double)));
         if (!tmp) return set_err(c, LBR_ERR_OOM, "readout scratch");
-        HIPCHK(c, launch_to_double(c->prec, src, tmp, n, c->stream));
         v.resize(n);
-        HIPCHK(c, hipMemcpyAsync(v.data(), tmp, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(c, hipStreamSynchronize(c->stream));
+        hipError_t e = launch_to_double(c->prec, src, tmp, n, c->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(v.data(), tmp, n * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
         dfree(c, tmp);
+        if (e != hipSuccess) return set_err(c, LBR_ERR_HIP, "field readout: %s", hipGetErrorString(e));
     } else {
         HIPCHK(c, hipStreamSynchronize(c->stream));
     }
