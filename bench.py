@@ -181,24 +181,43 @@ def run_sweep(args):
     launches = kt[3] if kt[3] > 0 else 2 ** lmax - 1            # per super step
     log(f"batched: {args.steps} super steps in {dt:.3f} s; k_step_batch {kt[0]:.2f} us/launch, "
         f"finest {kt[1]:.2f}, level 0 {kt[2]:.2f}, {launches:.0f} launches per super step")
-    # the same cases one after another, each with its own graph
-    seq = 0.0
-    for s, p in zip(sims, per):
-        if args.graph:
-            s.use_graph(True)
-        s.advance(2 * p)
-        s.synchronize()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        s.advance(args.steps * p)
-        s.synchronize()
-        torch.cuda.synchronize()
-        seq += time.perf_counter() - t0
-    log(f"one after another: {seq:.3f} s")
     finite = all(np.all(np.isfinite(s.forces())) for s in sims)
-    mlups = lups * args.steps / dt / 1e6
     bytes_per_launch = sum(step_bytes(args.storage, s, c["n_levels"], p)
                            for s, c, p in zip(sims, cases, per)) / launches
+
+    def one_after_another(solvers):
+        """The same cases advanced one after another, each with its own graph and
+        tuned tile heights, the same coarse steps per case."""
+        total = 0.0
+        for s, p in zip(solvers, per):
+            if args.tune:
+                s.tune(trials=3)
+            if args.graph:
+                s.use_graph(True)
+            s.advance(2 * p)
+            s.synchronize()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.advance(args.steps * p)
+            s.synchronize()
+            torch.cuda.synchronize()
+            total += time.perf_counter() - t0
+        return total
+
+    seq = one_after_another(sims)
+    log(f"one after another ({args.storage}): {seq:.3f} s")
+    seq32 = None
+    if args.storage != "f32":
+        # the baseline of the sweep: the same cases one after another in plain FP32
+        for s in sims:
+            s.close()
+        sims32 = [P.Solver(c, storage="f32") for c in cases]
+        seq32 = one_after_another(sims32)
+        log(f"one after another (f32): {seq32:.3f} s")
+        finite = finite and all(np.all(np.isfinite(s.forces())) for s in sims32)
+        for s in sims32:
+            s.close()
+    mlups = lups * args.steps / dt / 1e6
     roof = None
     if kt[0] > 0:
         achieved = bytes_per_launch / (kt[0] * 1e-6) / 1e9
@@ -222,6 +241,10 @@ def run_sweep(args):
         "one_after_another": {"value": round(lups * args.steps / seq / 1e6, 1), "unit": "MLUPS",
                               "ms_per_step": round(1000 * seq / args.steps, 4)},
         "batched_over_one_after_another": round(seq / dt, 3),
+        "one_after_another_f32": None if seq32 is None else
+        {"value": round(lups * args.steps / seq32 / 1e6, 1), "unit": "MLUPS",
+         "ms_per_step": round(1000 * seq32 / args.steps, 4)},
+        "batched_over_one_after_another_f32": None if seq32 is None else round(seq32 / dt, 3),
         "finite": bool(finite),
     }
     print(json.dumps(out), flush=True)
