@@ -2,8 +2,9 @@
 
 Argument marshalling only: every step of the method runs in the HIP library.
 PyTorch provides device memory (through the allocator callbacks of the
-config) and the stream.  Importing the package loads liblbr.so and raises if
-it has not been built (``python -m paper_2601_18443_amd.build``).
+config) and the stream.  The first call into the library (``lib()``,
+``Solver``, ``Batch``, ``schedule``) loads liblbr.so and raises if it has not
+been built (``python -m paper_2601_18443_amd.build``); there is no fallback.
 """
 from __future__ import annotations
 
@@ -232,8 +233,14 @@ class Solver:
         return {k: int(getattr(d, k)) for k, _ in lbr_level_desc._fields_}
 
     def init(self, level, rho=None, ux=None, uy=None, chi=None):
+        """Equilibrium initialisation of one level from (ny, nx) arrays over its I/O box."""
+        inf = self.level_info(level)
+        shape = (inf["ny"], inf["nx"])
         arrs = [None if a is None else np.ascontiguousarray(a, dtype=np.float64)
                 for a in (rho, ux, uy, chi)]
+        for name, a in zip(("rho", "ux", "uy", "chi"), arrs):
+            if a is not None and a.shape != shape:
+                raise ValueError(f"{name} has shape {a.shape}; level {level} needs {shape}")
         self._check(lib().lbr_init_fields(self.h, level, *[_dp(a) for a in arrs]))
 
     def advance(self, n):
