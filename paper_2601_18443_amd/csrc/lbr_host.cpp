@@ -856,6 +856,7 @@ void fill_step_args(lbr_ctx* c, int l, int substep, StepArgs<ST, CT>& a, int tk 
     a.frozen = cfg.sa == LBR_SA_FROZEN;
     a.bb_halfway = cfg.bb == LBR_BB_HALFWAY;
     a.substep = substep;
+    a.sst = L.st;
     if (l > 0) {
         Level& P = c->lv[l - 1];
         a.fcoarse = P.f[P.cur];
@@ -1807,8 +1808,9 @@ struct lbr_batch {
     bool merge = true;                 // coarse launches ride along with finer ones
     hipStream_t stream = nullptr;
     // one launch: its StepArgs start at byte off of the table, its part starts
-    // at index part0; every part of a launch has the same population storage;
-    // v is the virtual level of its finest part
+    // at index part0; st is the population storage of all its parts, or
+    // P_MIXED for FP32 and FP16 parts of mixed storage; v is the virtual level
+    // of its finest part
     struct Launch { size_t off; int part0, nparts, nblocks, v; Prec st; int ty; };
     std::vector<Launch> launches;      // the launches of all tables, in order
     // tables: [0] one super step from parity 0, [1] one from parity 1, [2] two
@@ -1858,9 +1860,17 @@ struct Item {
     std::vector<int> blocks;
 };
 
+// Two items can share a launch when their populations have the same format, or
+// are the FP32 and FP16 levels of mixed storage (the mixed kernel picks the
+// instantiation per part).
+bool shares_launch(Prec a, Prec b) {
+    return a == b || ((a == P_F32 || a == P_F16) && (b == P_F32 || b == P_F16));
+}
+
 // Launch groups of items [begin, end), in order.  An item of a virtual level at
 // least three below the finest is deferred and joins the next launch of a
-// finer level (same storage), one deferred item per launch, first in first out.
+// finer level (whose format it shares), one deferred item per launch, first in
+// first out.
 // This keeps every dependency of the recursive cycle: a deferred level w is
 // read by its child w + 1 (explosion, ghost values) and by its parent w - 1
 // (coalescence, restriction), and it writes only level w and the restriction
@@ -1883,7 +1893,7 @@ std::vector<std::vector<int>> batch_groups(const lbr_batch* b, const std::vector
         for (size_t j = head; j < pend.size(); ++j)
             if (it[pend[j]].v == x.v - 1) last = j + 1;
         for (; head < last; ++head) g.push_back({pend[head]});
-        if (head < pend.size() && it[pend[head]].st == x.st) g.push_back({k, pend[head++]});
+        if (head < pend.size() && shares_launch(it[pend[head]].st, x.st)) g.push_back({k, pend[head++]});
         else g.push_back({k});
     }
     for (; head < pend.size(); ++head) g.push_back({pend[head]});
@@ -1981,7 +1991,10 @@ int batch_build(lbr_batch* b) {
         b->table[t][0] = (int)b->launches.size();
         for (const auto& grp : groups) {
             const Item& m = items[grp[0]];
-            lbr_batch::Launch ln{parts.size(), (int)starts.size(), 0, 0, m.v, m.st, TILE_YS[tk[grp[0]]]};
+            Prec st = m.st;
+            for (int k : grp)
+                if (items[k].st != m.st) st = P_MIXED;
+            lbr_batch::Launch ln{parts.size(), (int)starts.size(), 0, 0, m.v, st, TILE_YS[tk[grp[0]]]};
             for (int k : grp) {
                 const Item& x = items[k];
                 parts.insert(parts.end(), x.args.begin(), x.args.end());
@@ -2024,7 +2037,6 @@ int batch_cover(lbr_batch* b, const std::vector<lbr_ctx*>& cases) {
     for (lbr_ctx* c : cases) {
         b->lmax = std::max(b->lmax, (int)c->lv.size());
         b->cur0.push_back(c->lv[0].cur);
-        if (c->cfg.storage == LBR_STORE_MIXED) b->merge = false;   // no finer partner of the same format
     }
     b->parity = 0;
     return batch_build(b);

@@ -103,6 +103,8 @@ struct StepArgs {
     CT* rmac;        CT* rchi;       // parent level buffers of the next parent step (restriction)
     const void* ffine; Box fbox;     // child level populations (coalescence), stored as
     int fst;                         // Prec fst
+    int sst;                         // Prec of this level's own populations (selects the
+                                     // instantiation in a mixed launch)
     WallData wall;                   // boundary nodes of this level (k_boundary)
     double* wstate;                  // [nb][8] u_tau, u_Rt (x, y), rho_W, u_W (x, y), spare
 };
@@ -156,8 +158,10 @@ struct SurfaceArgs {
     double* partial;                 // [nblocks][5]
 };
 
-// launchers (lbr_kernels.hip); `prec` selects the storage/compute pair
-enum Prec { P_F64 = 0, P_F32 = 1, P_F16 = 2, P_BF16 = 3 };
+// launchers (lbr_kernels.hip); `prec` selects the storage/compute pair.
+// P_MIXED is never a level's storage: it tags a batched launch whose parts are
+// FP32- and FP16-stored levels of mixed-storage cases.
+enum Prec { P_F64 = 0, P_F32 = 1, P_F16 = 2, P_BF16 = 3, P_MIXED = 4 };
 
 hipError_t launch_geometry(int nx, int ny, int gx0, int gy0, double scale, int nbody,
                            const int* npts_off, const double* poly, int solid,

@@ -740,12 +740,29 @@ __device__ __forceinline__ void boundary_node(const StepArgs<ST, CT>& a, int b) 
 // part of the grid.  Tiles are 64 x TY cells (TY wavefronts, one per row); the
 // tile height is a launch parameter chosen per level by the host's tuner, and
 // every cell's result is the same for any TY.
+// LDS of a tile workgroup: the 3 x 3 stencil values of the tile and its halo,
+// and the restriction staging.  Keyed on the arithmetic type and tile height
+// only, so that the storage formats of a mixed launch share one allocation.
+template <class CT, int TY>
+struct TileShared {
+    CT n[TY + 2][TILE_X + 2], u[TY + 2][TILE_X + 2], v[TY + 2][TILE_X + 2];
+    CT r[4][TY][TILE_X];
+};
+template <class CT, int TY>
+__device__ __forceinline__ TileShared<CT, TY>& tile_shared() {
+    __shared__ TileShared<CT, TY> sh;
+    return sh;
+}
+
 template <class ST, class CT, int TY>
 __device__ __forceinline__ void step_block(const StepArgs<ST, CT>& a, const int blk) {
     constexpr int NT = TILE_X * TY;                        // threads of the workgroup
     constexpr int NH = 2 * TILE_X + 2 * (TY + 2);          // halo cells of a tile
     constexpr int NS = (NH + NT - 1) / NT;                 // halo cells per thread (1, or 2 for TY = 2)
-    __shared__ CT sh_n[TY + 2][TILE_X + 2], sh_u[TY + 2][TILE_X + 2], sh_v[TY + 2][TILE_X + 2];
+    TileShared<CT, TY>& lds = tile_shared<CT, TY>();
+    auto& sh_n = lds.n;
+    auto& sh_u = lds.u;
+    auto& sh_v = lds.v;
     // grid: wall-node blocks first (their FP64 Newton iteration is the longest
     // chain), then the tiles, then the level-0 domain-edge cells; each branch is
     // uniform over a workgroup
@@ -910,7 +927,7 @@ __device__ __forceinline__ void step_block(const StepArgs<ST, CT>& a, const int 
     if (!restrict_tile) return;
     // restriction for the next parent step: the new rho, u and chi of each 2 x 2
     // block under a covered coarse cell, averaged by the block's lower-left cell
-    __shared__ CT sh_r[4][TY][TILE_X];
+    auto& sh_r = lds.r;
     __syncthreads();
     if (update) {
         sh_r[0][wy][lane] = m_rho;
@@ -949,6 +966,25 @@ __global__ __launch_bounds__(TILE_X * TY, 8) void k_step_batch(const StepArgs<ST
     int p = 0;
     while (p + 1 < nparts && (int)blockIdx.x >= start[p + 1]) ++p;
     step_block<ST, CT, TY>(parts[p], (int)blockIdx.x - start[p]);
+}
+
+// The same for the launches of mixed-storage cases that hold FP32- and
+// FP16-stored levels (FP32 arithmetic both): each part's own format (sst)
+// selects the instantiation, a branch uniform over the workgroup.  The two
+// argument types differ only in the pointee type of the population pointers.
+static_assert(sizeof(StepArgs<float, float>) == sizeof(StepArgs<__half, float>) &&
+                  alignof(StepArgs<float, float>) == alignof(StepArgs<__half, float>),
+              "mixed launch tables hold both argument types");
+template <int TY>
+__global__ __launch_bounds__(TILE_X * TY, 8) void k_step_batch_mixed(const StepArgs<float, float>* __restrict__ parts,
+                                                           const int* __restrict__ start, int nparts) {
+    int p = 0;
+    while (p + 1 < nparts && (int)blockIdx.x >= start[p + 1]) ++p;
+    const int blk = (int)blockIdx.x - start[p];
+    if (parts[p].sst == P_F16)
+        step_block<__half, float, TY>(*reinterpret_cast<const StepArgs<__half, float>*>(parts + p), blk);
+    else
+        step_block<float, float, TY>(parts[p], blk);
 }
 
 // Wall model on the current state, for output.
@@ -1258,9 +1294,34 @@ static hipError_t batch_t(const void* parts, const int* start, int nparts, int n
     }
 }
 
+template <int TY>
+static hipError_t batch_mixed_ty(const StepArgs<float, float>* pa, const int* start, int nparts, int nblocks_total,
+                                 hipStream_t s, const Timing& tm) {
+    if (tm.start)
+        hipExtLaunchKernelGGL((k_step_batch_mixed<TY>), dim3(nblocks_total), dim3(TILE_X * TY), 0, s,
+                              tm.start, tm.stop, 0, pa, start, nparts);
+    else
+        hipLaunchKernelGGL((k_step_batch_mixed<TY>), dim3(nblocks_total), dim3(TILE_X * TY), 0, s,
+                           pa, start, nparts);
+    return hipGetLastError();
+}
+
+static hipError_t batch_mixed(const void* parts, const int* start, int nparts, int nblocks_total, int ty,
+                              hipStream_t s, const Timing& tm) {
+    if (nblocks_total == 0) return hipSuccess;
+    const auto* pa = static_cast<const StepArgs<float, float>*>(parts);
+    switch (ty) {
+        case 2: return batch_mixed_ty<2>(pa, start, nparts, nblocks_total, s, tm);
+        case 4: return batch_mixed_ty<4>(pa, start, nparts, nblocks_total, s, tm);
+        case 8: return batch_mixed_ty<8>(pa, start, nparts, nblocks_total, s, tm);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t launch_step_batch(Prec p, const void* parts, const int* start, int nparts, int nblocks_total, int ty,
                              hipStream_t s, const Timing& tm) {
     switch (p) {
+        case P_MIXED: return batch_mixed(parts, start, nparts, nblocks_total, ty, s, tm);
         case P_F64: return batch_t<double, double>(parts, start, nparts, nblocks_total, ty, s, tm);
         case P_F32: return batch_t<float, float>(parts, start, nparts, nblocks_total, ty, s, tm);
         case P_F16: return batch_t<__half, float>(parts, start, nparts, nblocks_total, ty, s, tm);

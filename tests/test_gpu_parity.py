@@ -115,7 +115,7 @@ def test_refined_box_conserves_mass_on_gpu():
     assert abs(mass() - m0) / m0 < 1e-14
 
 
-@pytest.mark.parametrize("storage,levels", [("f64", 3), ("f32", 3), ("f32", 6), ("f16", 6)])
+@pytest.mark.parametrize("storage,levels", [("f64", 3), ("f32", 3), ("f32", 6), ("f16", 6), ("mixeds", 6)])
 def test_graph_replay_matches_direct_launches(storage, levels):
     """The merged schedule (coarse sub-steps inside the launches of finer ones),
     replayed from a graph with odd numbers of steps in between, and launched
