@@ -1,7 +1,8 @@
 // Device code of liblbr (gfx950).
 //
 // The hot kernel is k_step (and k_step_batch, the same work for several
-// parts of one grid): one pass per (sub-)step of a level that, for each owned
+// parts of one grid; k_step_batch_mixed when those parts are FP32- and
+// FP16-stored levels of mixed storage): one pass per (sub-)step of a level that, for each owned
 // fluid cell, advances the SA-neg variable, pulls the nine populations (with
 // bounce-back at cut links, domain rules, the coarse/fine transfer), forms rho
 // and u, and applies the central-moment collision.  Populations are stored
