@@ -197,7 +197,10 @@ int lbr_set_geometry(lbr_ctx* ctx, int32_t n_bodies, const int32_t* n_pts, const
    and allocates device state (Sections 2.1 and 2.3).  Initialises every level
    to the uniform reference state.  Errors: LBR_ERR_GEOMETRY when a refined
    level reaches the domain edge or an interface comes too close to a body or
-   to another interface; LBR_ERR_OOM; LBR_ERR_HIP. */
+   to another interface; LBR_ERR_INVALID_ARG when a level's storage box (its
+   cells rounded up to whole tiles) is too large for the 32-bit addressing of
+   the step kernels: (9 cells + 2 pitch + 2) x 8 bytes must stay below 2 GiB,
+   i.e. about 29.8M cells per level; LBR_ERR_OOM; LBR_ERR_HIP. */
 int lbr_build(lbr_ctx* ctx);
 
 /* Level layout after lbr_build. */
