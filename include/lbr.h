@@ -200,7 +200,8 @@ int lbr_set_geometry(lbr_ctx* ctx, int32_t n_bodies, const int32_t* n_pts, const
    to another interface; LBR_ERR_INVALID_ARG when a level's storage box (its
    cells rounded up to whole tiles) is too large for the 32-bit addressing of
    the step kernels: (9 cells + 2 pitch + 2) x 8 bytes must stay below 2 GiB,
-   i.e. about 29.8M cells per level; LBR_ERR_OOM; LBR_ERR_HIP. */
+   i.e. about 29.8M cells per level, and the box may span at most 2,097,088
+   columns and 65,534 rows (15-bit tile indices); LBR_ERR_OOM; LBR_ERR_HIP. */
 int lbr_build(lbr_ctx* ctx);
 
 /* Level layout after lbr_build. */

@@ -1240,6 +1240,12 @@ int lbr_build(lbr_ctx* c) {
     for (Level& L : c->lv)
         if (int r = build_walls(c, L, seg)) return r;
     for (Level& L : c->lv) {
+        // a tile is addressed by 15-bit column and row indices (for every tile
+        // height the tuner may pick)
+        if (L.box.pitch / TILE_X > 0x7fff || L.box.ny / TILE_YS[0] > 0x7fff)
+            return set_err(c, LBR_ERR_INVALID_ARG, "level %d: storage box of %d x %d cells exceeds the tile "
+                           "index range (%d columns, %d rows)", L.l, L.box.pitch, L.box.ny, 0x7fff * TILE_X,
+                           0x7fff * TILE_YS[0]);
         make_rows(L);
         mark_restriction_tiles(c, L);
         if (int r = alloc_level(c, L)) return r;

@@ -63,3 +63,10 @@ def test_largest_level_box_steps_like_a_narrow_one():
 def test_level_box_past_the_addressing_limit_is_refused():
     with pytest.raises(P.LbrError, match="per-array limit"):
         U.gpu_solver(LI.case_channel(nx=8192, ny=4096), "f32")
+
+
+def test_level_box_past_the_tile_index_range_is_refused():
+    """4.5M cells, well inside the byte limit, but 70,004 rows: more 2-row tile
+    rows than a 15-bit index holds."""
+    with pytest.raises(P.LbrError, match="tile index range"):
+        U.gpu_solver(LI.case_channel(nx=64, ny=70000), "f32")
