@@ -189,7 +189,10 @@ int lbr_create(const lbr_config* cfg, lbr_ctx** out);
 /* Wall geometry (Section 2.3: surface segments in 2D): n_bodies closed
    polylines, counter-clockwise (fluid on the right), given as consecutive
    (x, y) pairs without repeating the first point; n_pts[b] >= 3.
-   Must be called before lbr_build (it may be called with n_bodies = 0). */
+   Must be called before lbr_build (it may be called with n_bodies = 0).
+   Errors: LBR_ERR_GEOMETRY for fewer than 3 points, a non-finite point or a
+   body whose signed area is not positive (clockwise); LBR_ERR_STATE after
+   lbr_build. */
 int lbr_set_geometry(lbr_ctx* ctx, int32_t n_bodies, const int32_t* n_pts, const double* xy);
 
 /* Builds the multilevel grid, the cut-link list with wall fractions q, the

@@ -1199,14 +1199,21 @@ int lbr_set_geometry(lbr_ctx* c, int32_t n_bodies, const int32_t* n_pts, const d
     const double* p = xy;
     for (int b = 0; b < n_bodies; ++b) {
         if (n_pts[b] < 3) return set_err(c, LBR_ERR_GEOMETRY, "body %d has fewer than 3 points", b);
+        double area2 = 0.0;                       // twice the signed area (shoelace)
         for (int k = 0; k < n_pts[b]; ++k) {
             const double x = (p[2 * k] - c->cfg.origin[0]) / c->cfg.dx0;
             const double y = (p[2 * k + 1] - c->cfg.origin[1]) / c->cfg.dx0;
             if (!std::isfinite(x) || !std::isfinite(y))
                 return set_err(c, LBR_ERR_GEOMETRY, "body %d has a non-finite point", b);
+            const int k1 = (k + 1) % n_pts[b];
+            area2 += p[2 * k] * p[2 * k1 + 1] - p[2 * k1] * p[2 * k + 1];
             c->polyflat.push_back(x);
             c->polyflat.push_back(y);
         }
+        // the segment tangents, and with them the sign of Cf, follow the
+        // counter-clockwise orientation
+        if (!(area2 > 0.0))
+            return set_err(c, LBR_ERR_GEOMETRY, "body %d is not a counter-clockwise polyline", b);
         p += 2 * n_pts[b];
         c->npts.push_back(n_pts[b]);
         c->off.push_back(c->off.back() + n_pts[b]);

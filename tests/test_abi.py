@@ -100,3 +100,35 @@ def test_create_accepts_every_storage(storage):
     h = ctypes.c_void_p()
     assert L.lbr_create(ctypes.byref(cfg), ctypes.byref(h)) == 0
     L.lbr_destroy(h)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="liblbr.so not built")
+def test_set_geometry_checks_the_polylines_on_the_host():
+    """lbr_set_geometry is host work: it refuses short, non-finite and clockwise
+    bodies, accepts the generated counter-clockwise ones, and no device call is
+    needed for either answer."""
+    import numpy as np
+    import paper_2601_18443_amd as P
+    import lbr_inputs as LI
+    L = P.lib()
+    case = LI.case_airfoil_small()
+    body = np.ascontiguousarray(case["bodies"][0], dtype=np.float64)
+
+    def set_geo(pts):
+        cfg = P.make_config(case, "f32")
+        h = ctypes.c_void_p()
+        assert L.lbr_create(ctypes.byref(cfg), ctypes.byref(h)) == 0
+        n = (ctypes.c_int32 * 1)(len(pts))
+        xy = np.ascontiguousarray(pts, dtype=np.float64)
+        rc = L.lbr_set_geometry(h, 1, n, xy.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        msg = L.lbr_last_error(h).decode()
+        L.lbr_destroy(h)
+        return rc, msg
+
+    assert set_geo(body) == (0, "")
+    rc, msg = set_geo(body[::-1])                     # clockwise
+    assert rc == -4 and "counter-clockwise" in msg
+    assert set_geo(body[:2])[0] == -4                 # fewer than 3 points
+    bad = body.copy()
+    bad[5, 1] = np.nan
+    assert set_geo(bad)[0] == -4
