@@ -336,9 +336,10 @@ int lbr_set_tile_rows(lbr_ctx* ctx, int32_t level, int32_t rows);
    that step the finest level, out[2] those of level 0 alone, out[3] launches
    per coarse step.  After the start-up ramp the timed run uses the merged
    schedule of lbr_use_graph, launched directly (the graph is not replayed
-   while timing).  enable != 0 turns the timing on for the following
-   lbr_advance calls; enable == 0 turns it off.  out may be NULL; it receives
-   the figures of the last timed lbr_advance. */
+   while timing).  Events go to the first 65,536 launches of a call only;
+   out[3] counts every launch.  enable != 0 turns the timing on for the
+   following lbr_advance calls; enable == 0 turns it off.  out may be NULL;
+   it receives the figures of the last timed lbr_advance. */
 int lbr_profile(lbr_ctx* ctx, int32_t enable, double out[4]);
 
 /* Last error message of the context (never NULL). */
@@ -400,7 +401,8 @@ int lbr_batch_use_graph(lbr_batch* batch, int32_t enable);
 int lbr_batch_tune(lbr_batch* batch, int32_t trials, int32_t* rows);
 
 /* As lbr_profile, for the batched launches: out[0] all launches, out[1] the
-   launches of the finest virtual level, out[2] virtual level 0, out[3] 0. */
+   launches of the finest virtual level, out[2] virtual level 0, out[3]
+   launches per super step. */
 int lbr_batch_profile(lbr_batch* batch, int32_t enable, double out[4]);
 
 /* Waits for the batch stream; afterwards every per-context call (fields,

@@ -17,6 +17,8 @@ using namespace lbr;
 namespace {
 
 constexpr int G = 2;   // guard ring of every storage box
+// a timed advance attaches start / stop events to its first launches only
+constexpr size_t MAX_TIMED_LAUNCHES = 1 << 16;
 constexpr int CXH[9] = {0, 1, -1, 0, 0, 1, -1, 1, -1};
 constexpr int CYH[9] = {0, 0, 0, 1, -1, 1, -1, -1, 1};
 constexpr double KAPPA_H = 0.41;
@@ -121,6 +123,7 @@ struct lbr_ctx {
     std::vector<hipEvent_t> ev;
     std::vector<int> ev_kind;
     size_t ev_used = 0;
+    int64_t prof_launches = 0;     // launches of the last timed call (timed or not)
     double prof_out[4] = {0, 0, 0, 0};
 };
 
@@ -917,6 +920,8 @@ enum { EV_STEP = 0, EV_STEP_FINE = 1, EV_STEP_L0 = 2 };
 Timing prof_events(lbr_ctx* c, int kind) {
     Timing tm;
     if (!c->prof) return tm;
+    c->prof_launches++;
+    if (c->ev_used + 2 > 2 * MAX_TIMED_LAUNCHES) return tm;   // the first launches of the call
     while (c->ev.size() < c->ev_used + 2) {
         hipEvent_t e;
         if (hipEventCreate(&e) != hipSuccess) return tm;
@@ -1307,6 +1312,7 @@ int lbr_advance(lbr_ctx* c, int64_t n) {
     if (!c->built) return set_err(c, LBR_ERR_STATE, "lbr_build has not been called");
     if (n < 0) return set_err(c, LBR_ERR_INVALID_ARG, "negative step count");
     c->ev_used = 0;
+    c->prof_launches = 0;
     int64_t k = 0;
     // during the start-up ramp the launch arguments change every step: direct launches
     for (; k < n && (double)c->step_count < c->cfg.ramp_steps; ++k) {
@@ -1338,7 +1344,7 @@ int lbr_advance(lbr_ctx* c, int64_t n) {
             if (kind != EV_STEP) { sum[EV_STEP] += ms; cnt[EV_STEP]++; }
         }
         for (int f = 0; f < 3; ++f) c->prof_out[f] = cnt[f] ? 1000.0 * sum[f] / cnt[f] : 0.0;
-        c->prof_out[3] = n ? (double)(c->ev_used / 2) / (double)n : 0.0;
+        c->prof_out[3] = n ? (double)c->prof_launches / (double)n : 0.0;
     }
     return LBR_OK;
 }
@@ -1841,6 +1847,7 @@ struct lbr_batch {
     std::vector<hipEvent_t> pev;
     std::vector<int> pev_v;            // virtual level of each event pair
     size_t pev_used = 0;
+    int64_t prof_launches = 0;         // launches of the last timed call (timed or not)
     double prof_out[4] = {0, 0, 0, 0};
     std::string err;
 };
@@ -2056,6 +2063,8 @@ int batch_cover(lbr_batch* b, const std::vector<lbr_ctx*>& cases) {
 }
 
 hipEvent_t* batch_prof_events(lbr_batch* b, int v) {
+    b->prof_launches++;
+    if (b->pev_used + 2 > 2 * MAX_TIMED_LAUNCHES) return nullptr;   // the first launches of the call
     while (b->pev.size() < b->pev_used + 2) {
         hipEvent_t e;
         if (hipEventCreate(&e) != hipSuccess) return nullptr;
@@ -2169,6 +2178,7 @@ int batch_advance(lbr_batch* b, int64_t n) {
     if (int r = batch_check(b)) return r;
     if (int r = batch_wait_cases(b)) return r;
     b->pev_used = 0;
+    b->prof_launches = 0;
     if (int r = batch_run(b, n)) return r;
     if (b->prof && b->pev_used) {
         if (hipStreamSynchronize(b->stream) != hipSuccess) return bset_err(b, LBR_ERR_HIP, "synchronize failed");
@@ -2184,7 +2194,7 @@ int batch_advance(lbr_batch* b, int64_t n) {
             if (v == 0) { sum[2] += ms; cnt[2]++; }
         }
         for (int f = 0; f < 3; ++f) b->prof_out[f] = cnt[f] ? 1000.0 * sum[f] / cnt[f] : 0.0;
-        b->prof_out[3] = n ? (double)(b->pev_used / 2) / (double)n : 0.0;
+        b->prof_out[3] = n ? (double)b->prof_launches / (double)n : 0.0;
     }
     return batch_release_cases(b);
 }
