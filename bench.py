@@ -250,6 +250,66 @@ def run_sweep(args):
     print(json.dumps(out), flush=True)
 
 
+def run_precision(args):
+    """Storage precision at the converged state of the 8-level airfoil: every
+    storage runs the same number of coarse steps from the same start (graph
+    replay, default tile heights), and its surface data are compared with
+    those of the FP64 path (itself pinned to the FP64 oracle).  The Cf bound is
+    the one the FP32 path is held to: max |Cf - Cf_FP64| <= 1 % of max |Cf_FP64|."""
+    import torch
+    import lbr_inputs as LI
+    import paper_2601_18443_amd as P
+
+    case = LI.case_airfoil_2M()
+    steps = args.converge_steps
+
+    def run(st):
+        s = P.Solver(case, storage=st)
+        s.use_graph(True)
+        s.advance(1)
+        s.synchronize()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.advance(steps - 1)
+        s.synchronize()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        cp, cf = s.surface(0)
+        f = s.forces()
+        s.residual()
+        s.advance(100)
+        r = s.residual()
+        lups = s.lups_per_coarse_step()
+        s.close()
+        log(f"{st}: {steps} coarse steps in {dt:.1f} s, residual {r:.1e}")
+        return cp, cf, f, r, lups * (steps - 1) / dt / 1e6
+
+    ref = run("f64")
+    out = {}
+    for st in ("f32", "f16", "f16s", "mixed", "mixeds", "bf16", "bf16s"):
+        cp, cf, f, r, mlups = run(st)
+        cf_err = float(np.max(np.abs(cf - ref[1])) / np.max(np.abs(ref[1])))
+        out[st] = {"cp_max_abs": float(np.max(np.abs(cp - ref[0]))), "cf_max_abs_over_max_cf": cf_err,
+                   "cd_rel": float(abs(f[2] - ref[2][2]) / abs(ref[2][2])),
+                   "cl_rel": float(abs(f[3] - ref[2][3]) / abs(ref[2][3])),
+                   "residual": r, "meets_cf_bound": bool(cf_err <= 0.01), "mlups": round(mlups, 1)}
+    ok = [st for st in out if out[st]["meets_cf_bound"]]
+    best = max(ok, key=lambda st: out[st]["mlups"]) if ok else None
+    line = {
+        "metric": METRIC, "value": None if best is None else out[best]["mlups"], "unit": "MLUPS", "n_gpus": 1,
+        "steps": steps, "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": None if best is None else DTYPE[best],
+        "data": "synthetic (seeded airfoil-like polylines)",
+        "config": {"workload": "precision at the converged state: single airfoil-like body, 8 levels "
+                               "c/8..c/1024, Re 6e6, M 0.15, AoA 10 deg; every storage against the FP64 path",
+                   "coarse_steps": steps, "fastest_within_cf_bound": best,
+                   "fp64_forces": [float(v) for v in ref[2]], "fp64_residual": ref[3]},
+        "roofline": None, "cpu_baseline": None,
+        "storages": out,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -263,10 +323,14 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--tune", type=int, default=1,
                     help="choose each level's tile height by timing (the library's tuner) before the warm-up")
-    ap.add_argument("--workload", default="airfoil", choices=["airfoil", "three_element", "sweep"],
+    ap.add_argument("--workload", default="airfoil", choices=["airfoil", "three_element", "sweep", "precision"],
                     help="airfoil: the benchmark line (8 levels, 2.0M cells); three_element: the "
                          "19.4M-cell high-lift case (cycle time per step, run past its start-up ramp); "
-                         "sweep: 16 cases in shared launches against the same cases one after another")
+                         "sweep: 16 cases in shared launches against the same cases one after another; "
+                         "precision: surface data of every storage at the converged airfoil state "
+                         "against the FP64 path, and which storages meet the FP32 Cf bound")
+    ap.add_argument("--converge-steps", type=int, default=5000,
+                    help="coarse steps of every storage in the precision workload")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -278,6 +342,9 @@ def main():
         return
     if args.workload == "sweep":
         run_sweep(args)
+        return
+    if args.workload == "precision":
+        run_precision(args)
         return
 
     import torch
