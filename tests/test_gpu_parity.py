@@ -86,6 +86,34 @@ def test_airfoil_small_fp64():
     np.testing.assert_allclose(cfg, cfo, rtol=1e-9, atol=1e-14)
 
 
+@pytest.mark.parametrize("levels", [1, 2])
+def test_airfoil_with_one_or_two_levels_fp64(levels):
+    """Degenerate depths of the recursion: one level (wall nodes, domain edges
+    and the absorbing layer on the same level, no transfers) and two levels (a
+    refinement, but no level deep enough to merge), direct launches and graph
+    replay, against the oracle."""
+    case = LI.case_airfoil(seed=5, finest_cells_per_chord=64, n_levels=levels, domain_chords=8.0,
+                           band_finest=0.25, n_side=128)
+    o, g = _pair(case, "f64")
+    h = U.gpu_solver(case, "f64")
+    h.use_graph(True)
+    o.advance(4)
+    g.advance(4)
+    h.advance(1)
+    h.advance(3)
+    assert U.velocity_error(g, o, levels) < 1e-10
+    err = U.field_errors(g, o, levels, names=("chi",))
+    assert max(err.values()) < 1e-10, err
+    assert U.density_error(g, o, levels) < 1e-12
+    np.testing.assert_allclose(g.forces(), o.forces(), rtol=1e-9, atol=1e-12)
+    for l in range(levels):
+        for f in (0, 1, 2, 3):
+            x, y = h.field(l, f), g.field(l, f)
+            assert np.array_equal(np.isnan(x), np.isnan(y))
+            m = ~np.isnan(x)
+            assert np.array_equal(x[m], y[m]), (l, f)
+
+
 def test_airfoil_small_fp32_window():
     case = LI.case_airfoil_small()
     o, g = _pair(case, "f32")
