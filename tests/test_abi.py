@@ -132,3 +132,45 @@ def test_set_geometry_checks_the_polylines_on_the_host():
     bad = body.copy()
     bad[5, 1] = np.nan
     assert set_geo(bad)[0] == -4
+
+
+C_CLIENT = r"""
+#include "lbr.h"
+#include <stdio.h>
+int main(void) {
+    lbr_config cfg = {0};
+    lbr_ctx* ctx = NULL;
+    cfg.version = LBR_ABI_VERSION;
+    if (lbr_create(&cfg, &ctx) != LBR_ERR_INVALID_ARG || ctx) return 1;   /* zero grid */
+    cfg.storage = LBR_STORE_F32;
+    cfg.nx0 = 64; cfg.ny0 = 32; cfg.n_levels = 1;
+    cfg.bc[0] = cfg.bc[1] = LBR_BC_PERIODIC; cfg.bc[2] = cfg.bc[3] = LBR_BC_WALL;
+    cfg.wall_model = LBR_WALL_VN; cfg.bb = LBR_BB_AUTO; cfg.sa = LBR_SA_LW;
+    cfg.dx0 = 1.0; cfg.wall_y[1] = 32.0; cfg.mach = 0.1; cfg.u_ref = 0.05; cfg.nu0 = 1e-3;
+    cfg.rho_ref = 1.0; cfg.chi_inlet = 3.0; cfg.chi_init = 3.0; cfg.omega_b = 1.0;
+    cfg.d_wr = 2.0; cfg.d_wv = 1.0;
+    if (lbr_create(&cfg, &ctx) != LBR_OK || !ctx) return 2;
+    if (lbr_set_geometry(ctx, 0, NULL, NULL) != LBR_OK) return 3;
+    if (lbr_advance(ctx, 1) != LBR_ERR_STATE) return 4;      /* not built yet */
+    printf("%s\n", lbr_last_error(ctx));
+    lbr_destroy(ctx);
+    return 0;
+}
+"""
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="liblbr.so not built")
+def test_header_serves_a_plain_c_client(tmp_path):
+    """include/lbr.h compiles as strict C99, and a C program linked against
+    liblbr.so drives the host-side calls (no device work)."""
+    import subprocess
+    src = tmp_path / "client.c"
+    src.write_text(C_CLIENT)
+    exe = tmp_path / "client"
+    inc = os.path.join(ROOT, "include")
+    libdir = os.path.dirname(LIB)
+    subprocess.run(["gcc", "-std=c99", "-pedantic", "-Wall", "-Wextra", "-Werror", "-I" + inc, str(src),
+                    "-L" + libdir, "-llbr", "-Wl,-rpath," + libdir, "-o", str(exe)], check=True)
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, (r.returncode, r.stdout, r.stderr)
+    assert "lbr_build" in r.stdout
