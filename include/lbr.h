@@ -307,7 +307,9 @@ int64_t lbr_lups_per_coarse_step(lbr_ctx* ctx);
    its child, writes itself and the restriction into its parent), so a coarse
    step of an 8-level grid takes 195 launches instead of 255.  Every cell is
    computed by the same code from the same state as in the direct cycle: the
-   results are bit-identical. */
+   results are bit-identical.  The default (NULL) stream cannot be captured:
+   enabling the graph on a context created with stream NULL is
+   LBR_ERR_INVALID_ARG. */
 int lbr_use_graph(lbr_ctx* ctx, int32_t enable);
 
 /* Tile shape of the step kernel.  A workgroup updates a tile of 64 x H cells
@@ -391,7 +393,8 @@ int lbr_batch_run_to_steady(lbr_batch* batch, double tol, int64_t max_super_step
                             int64_t* steps_done, double* residual);
 
 /* Replays two super steps from one HIP graph (enable != 0) or launches
-   directly (enable == 0). */
+   directly (enable == 0).  As lbr_use_graph, it needs the batch's stream (its
+   first case's) not to be the default stream. */
 int lbr_batch_use_graph(lbr_batch* batch, int32_t enable);
 
 /* As lbr_tune for the batch: every virtual level is timed with the parts of all

@@ -62,6 +62,11 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError("liblbr.so is not built: run `python -m paper_2601_18443_amd.build`")
+        # PyTorch first: its HIP runtime is then the one liblbr binds to, so the
+        # device memory and streams PyTorch hands over belong to the same
+        # runtime (loading liblbr first would bring a second HIP runtime into
+        # the process, and PyTorch's would then fail to find the GPU)
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         p, i32, i64, dp = C.c_void_p, C.c_int32, C.c_int64, C.POINTER(C.c_double)
         L.lbr_create.argtypes = [C.POINTER(lbr_config), C.POINTER(p)]

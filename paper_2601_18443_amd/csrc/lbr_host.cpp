@@ -1789,6 +1789,9 @@ int64_t lbr_lups_per_coarse_step(lbr_ctx* c) {
 
 int lbr_use_graph(lbr_ctx* c, int32_t enable) {
     if (!c) return LBR_ERR_INVALID_ARG;
+    // the legacy default stream cannot be captured into a graph
+    if (enable && !c->stream)
+        return set_err(c, LBR_ERR_INVALID_ARG, "graph replay needs a stream other than the default stream");
     c->use_graph = enable != 0;
     return LBR_OK;
 }
@@ -2277,6 +2280,8 @@ int lbr_batch_run_to_steady(lbr_batch* b, double tol, int64_t max_super_steps, i
 
 int lbr_batch_use_graph(lbr_batch* b, int32_t enable) {
     if (!b) return LBR_ERR_INVALID_ARG;
+    if (enable && !b->stream)
+        return bset_err(b, LBR_ERR_INVALID_ARG, "graph replay needs a stream other than the default stream");
     b->use_graph = enable != 0;
     return LBR_OK;
 }
