@@ -10,6 +10,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import weakref
 
 import numpy as np
 
@@ -203,6 +204,7 @@ class Solver:
         self.torch_stream = torch.cuda.Stream(self.device)
         self.alloc = _TorchAllocator(self.device) if use_torch_memory else None
         self.case = case
+        self._batches = weakref.WeakSet()      # batches that borrow this context
         self.cfg = make_config(case, storage, C.c_void_p(self.torch_stream.cuda_stream), self.alloc)
         h = C.c_void_p()
         rc = L.lbr_create(C.byref(self.cfg), C.byref(h))
@@ -222,6 +224,10 @@ class Solver:
         return rc
 
     def close(self):
+        """Destroys the context; a batch that borrows it is closed first (its
+        launch tables point into this context's memory)."""
+        for b in list(getattr(self, "_batches", ())):
+            b.close()
         if getattr(self, "h", None):
             lib().lbr_destroy(self.h)
             self.h = None
@@ -367,8 +373,8 @@ class Batch:
 
     Super steps run on the first solver's stream; reads through any solver are
     ordered after them.  A solver may be advanced on its own between batch
-    calls by an even number of coarse steps.  Close the batch before the
-    solvers.
+    calls by an even number of coarse steps.  Closing one of the solvers
+    closes the batch first.
     """
 
     def __init__(self, solvers):
@@ -382,6 +388,8 @@ class Batch:
             msg = L.lbr_batch_last_error(self.h).decode() if self.h else ""
             self.close()
             raise LbrError(f"lbr_batch_create failed ({rc}) {msg}")
+        for s in self.solvers:
+            s._batches.add(self)
 
     def _check(self, rc):
         if rc != 0:

@@ -95,6 +95,23 @@ def test_batch_refuses_duplicates_and_mixed_storage():
         P.Batch([a, b])
 
 
+def test_closing_a_solver_closes_the_batch_that_borrows_it():
+    """The batch's launch tables point into its cases' memory: closing a case
+    first closes the batch, which then refuses work instead of launching on
+    freed memory; the other case stays usable."""
+    import paper_2601_18443_amd as P
+    c = LI.case_airfoil_small()
+    a, b = P.Solver(c, storage="f32"), P.Solver(c, storage="f32")
+    batch = P.Batch([a, b])
+    batch.advance(2)
+    a.close()
+    assert batch.h is None
+    with pytest.raises(P.LbrError):
+        batch.advance(1)
+    b.advance(2)
+    assert np.all(np.isfinite(b.forces()))
+
+
 def test_batch_refuses_cases_inside_the_start_up_ramp():
     import paper_2601_18443_amd as P
     c = dict(LI.case_airfoil_small(), ramp_steps=4, ramp_start=0.5)
