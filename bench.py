@@ -250,6 +250,68 @@ def run_sweep(args):
     print(json.dumps(out), flush=True)
 
 
+def run_sweep_steady(args):
+    """The 16-case sweep run to steady state: batched (converged cases leave the
+    launches) against the same cases one after another, each to the same
+    tolerance with the same check interval in coarse steps.  The line's value is
+    the batched wall time to solution."""
+    import torch
+    import lbr_inputs as LI
+    import paper_2601_18443_amd as P
+
+    tol, max_super, every = args.tol, args.max_super_steps, 100
+    cases = [LI.case_sweep(k) for k in range(16)]
+    sims = [P.Solver(c, storage=args.storage) for c in cases]
+    batch = P.Batch(sims)
+    rows = batch.tune(trials=3) if args.tune else None
+    batch.use_graph(True)
+    lmax = max(c["n_levels"] for c in cases)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    steps, res = batch.run_to_steady(tol, max_super, every)
+    batch.synchronize()
+    dt = time.perf_counter() - t0
+    log(f"batched ({args.storage}): all 16 cases to residual < {tol:g} in {dt:.1f} s")
+    per_case = []
+    for k, (c, sim) in enumerate(zip(cases, sims)):
+        f = sim.forces()
+        per_case.append({"alpha_deg": c["alpha_deg"], "levels": c["n_levels"], "coarse_steps": steps[k],
+                         "residual": res[k], "C_L": float(f[3]), "C_D": float(f[2]), "C_Df": float(f[0])})
+    batch.close()
+    for sim in sims:
+        sim.close()
+    seq = 0.0
+    alone = []
+    for k, c in enumerate(cases):
+        sim = P.Solver(c, storage="f32")
+        if args.tune:
+            sim.tune(trials=3)
+        sim.use_graph(True)
+        per = 2 ** (lmax - c["n_levels"])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        n, r = sim.run_to_steady(tol, max_super * per, every * per)
+        sim.synchronize()
+        seq += time.perf_counter() - t1
+        alone.append({"coarse_steps": n, "residual": r, "C_L": float(sim.forces()[3])})
+        sim.close()
+        log(f"alone (f32) case {k}: {n} coarse steps, residual {r:.1e}")
+    log(f"one after another (f32): {seq:.1f} s")
+    line = {
+        "metric": "wall time to steady state of the 16-case sweep", "value": round(dt, 2), "unit": "s",
+        "n_gpus": 1, "steps": None, "warmup": 0, "ms_per_step": None, "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[args.storage],
+        "data": "synthetic (seeded airfoil-like polylines)",
+        "config": {"workload": "batched sweep to steady state: 16 airfoil-like cases, AoA -4..16 deg, 3-5 levels "
+                               "to c/512, Re 6e6, M 0.15; residual checked every 100 super steps",
+                   "tol": tol, "storage": args.storage, "tile_rows": rows},
+        "roofline": None, "cpu_baseline": None,
+        "one_after_another_f32_s": round(seq, 2), "batched_speedup": round(seq / dt, 3),
+        "cases": per_case, "alone_f32": alone,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def run_precision(args):
     """Storage precision at the converged state of the 8-level airfoil: every
     storage runs the same number of coarse steps from the same start (graph
@@ -323,12 +385,16 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--tune", type=int, default=1,
                     help="choose each level's tile height by timing (the library's tuner) before the warm-up")
-    ap.add_argument("--workload", default="airfoil", choices=["airfoil", "three_element", "sweep", "precision"],
+    ap.add_argument("--workload", default="airfoil",
+                    choices=["airfoil", "three_element", "sweep", "sweep_steady", "precision"],
                     help="airfoil: the benchmark line (8 levels, 2.0M cells); three_element: the "
                          "19.4M-cell high-lift case (cycle time per step, run past its start-up ramp); "
                          "sweep: 16 cases in shared launches against the same cases one after another; "
+                         "sweep_steady: the sweep run to steady state, batched against one after another; "
                          "precision: surface data of every storage at the converged airfoil state "
                          "against the FP64 path, and which storages meet the FP32 Cf bound")
+    ap.add_argument("--tol", type=float, default=1e-6, help="residual tolerance of sweep_steady")
+    ap.add_argument("--max-super-steps", type=int, default=6000, help="cap of sweep_steady")
     ap.add_argument("--converge-steps", type=int, default=5000,
                     help="coarse steps of every storage in the precision workload")
     args = ap.parse_args()
@@ -345,6 +411,9 @@ def main():
         return
     if args.workload == "precision":
         run_precision(args)
+        return
+    if args.workload == "sweep_steady":
+        run_sweep_steady(args)
         return
 
     import torch
