@@ -2,6 +2,7 @@
 import ctypes
 import os
 import re
+import sys
 
 import pytest
 
@@ -174,3 +175,19 @@ def test_header_serves_a_plain_c_client(tmp_path):
     r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, (r.returncode, r.stdout, r.stderr)
     assert "lbr_build" in r.stdout
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="liblbr.so not built")
+def test_binding_binds_liblbr_to_pytorchs_hip_runtime():
+    """lib() loads PyTorch before liblbr.so, so the process holds one HIP
+    runtime (PyTorch's): the device memory and streams PyTorch hands to the
+    library belong to it, and PyTorch still finds the GPU afterwards."""
+    import subprocess
+    code = ("import paper_2601_18443_amd as P; P.lib(); "
+            "print(sorted({l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}))")
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr
+    libs = eval(r.stdout.strip().splitlines()[-1])
+    assert len(libs) == 1, libs
+    import torch
+    assert os.path.dirname(libs[0]) == os.path.join(os.path.dirname(torch.__file__), "lib")
