@@ -35,6 +35,7 @@ class Config(C.Structure):
         ("d_wr", C.c_double), ("d_wv", C.c_double), ("u_wall", C.c_double * 4),
         ("sponge_width", C.c_double), ("sponge_strength", C.c_double),
         ("ramp_steps", C.c_double), ("ramp_start", C.c_double),
+        ("sa_mu_cap", C.c_double),
     ]
 
 
@@ -77,7 +78,7 @@ def lib():
         L.lbro_collide.restype = None
         L.lbro_sa_source.argtypes = [d, d, d, d, dp]
         L.lbro_sa_source.restype = None
-        L.lbro_sa_cell.argtypes = [dp, dp, dp, d, d, i32]
+        L.lbro_sa_cell.argtypes = [dp, dp, dp, d, d, i32, d]
         L.lbro_sa_cell.restype = d
         L.lbro_lsq_point.argtypes = [i32, dp, dp, dp, d, d]
         L.lbro_lsq_point.restype = d
@@ -149,9 +150,9 @@ def sa_source(nut, nu, omega, dist):
     return dict(P=out[0], D=out[1], mu=out[2], nu_t=out[3], S_tilde=out[4], r=out[5], f_w=out[6])
 
 
-def sa_cell(nt, ux, uy, nu, dist, mode=1):
+def sa_cell(nt, ux, uy, nu, dist, mode=1, mu_cap=0.0):
     nt, ux, uy = _arr(nt).ravel(), _arr(ux).ravel(), _arr(uy).ravel()
-    return lib().lbro_sa_cell(_dp(nt), _dp(ux), _dp(uy), nu, dist, mode)
+    return lib().lbro_sa_cell(_dp(nt), _dp(ux), _dp(uy), nu, dist, mode, float(mu_cap))
 
 
 def lsq_point(px, py, v, x, y):
@@ -195,6 +196,7 @@ def make_config(case) -> Config:
     c.sponge_strength = case.get("sponge_strength", 0.0)
     c.ramp_steps = case.get("ramp_steps", 0.0)
     c.ramp_start = case.get("ramp_start", 0.0)
+    c.sa_mu_cap = case.get("sa_mu_cap", 0.0)
     return c
 
 

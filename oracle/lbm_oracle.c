@@ -344,7 +344,7 @@ static void lsq_gradient(const double v[9], double* gx, double* gy) {
    nodal diffusivity; c_b2 term outside the divergence as in eq (16).  All
    stencil values are at the old time level; dt = dx = 1. */
 double lbro_sa_cell(const double nt[9], const double ux[9], const double uy[9], double nu,
-                    double dist, int32_t mode) {
+                    double dist, int32_t mode, double mu_cap) {
     double dudx, dudy, dvdx, dvdy;
     lsq_gradient(ux, &dudx, &dudy);
     lsq_gradient(uy, &dvdx, &dvdy);
@@ -364,14 +364,17 @@ double lbro_sa_cell(const double nt[9], const double ux[9], const double uy[9], 
         double dXY = 0.25 * (nt[8] - nt[6] - nt[2] + nt[0]);
         conv = -(u * dX + v * dY) + 0.5 * (u * u * dXX + 2.0 * u * v * dXY + v * v * dYY);
     }
-    /* Face diffusivity capped at 0.2 sigma (lattice units): the explicit update is
-       stable only while (1/sigma) sum_faces mu <= 1, which a large eddy viscosity on
-       a fine level exceeds (the paper does not discuss the bound); below the cap
-       the scheme is unchanged. */
-    const double mu_max = 0.2 * SA_SIGMA;
+    /* Face diffusivity: the mean of the two nodal values (eqs (12), (16)).  With
+       mu_cap > 0 (an addition, off unless configured) it is limited to mu_cap:
+       the explicit update is stable only while (1/sigma) sum_faces mu <= 1, which
+       a large eddy viscosity on a fine level can exceed. */
     double muC = sa_mu(C, nu);
-    double me = fmin(0.5 * (muC + sa_mu(E, nu)), mu_max), mw = fmin(0.5 * (muC + sa_mu(W, nu)), mu_max);
-    double mn = fmin(0.5 * (muC + sa_mu(N, nu)), mu_max), ms = fmin(0.5 * (muC + sa_mu(S, nu)), mu_max);
+    double me = 0.5 * (muC + sa_mu(E, nu)), mw = 0.5 * (muC + sa_mu(W, nu));
+    double mn = 0.5 * (muC + sa_mu(N, nu)), ms = 0.5 * (muC + sa_mu(S, nu));
+    if (mu_cap > 0.0) {
+        me = fmin(me, mu_cap); mw = fmin(mw, mu_cap);
+        mn = fmin(mn, mu_cap); ms = fmin(ms, mu_cap);
+    }
     double diff = me * (E - C) - mw * (C - W) + mn * (N - C) - ms * (C - S) +
                   SA_CB2 * (dX * dX + dY * dY);
     return C + conv + (src[0] - src[1]) + diff / SA_SIGMA;
@@ -1212,7 +1215,7 @@ static int sa_level(const lbro_sim* s, olevel* L) {
                 if (sa_neighbour(s, L, gi + dx, gj + dy, &nt[k], &u[k], &v[k])) err = 1;
             }
         if (err) continue;
-        L->chin[c] = lbro_sa_cell(nt, u, v, L->nu, L->d[c], s->cfg.sa_mode) / L->nu;
+        L->chin[c] = lbro_sa_cell(nt, u, v, L->nu, L->d[c], s->cfg.sa_mode, s->cfg.sa_mu_cap) / L->nu;
     }
     if (err) return fail("SA stencil reached a cell without data on level %d", L->level);
     return 0;

@@ -63,6 +63,8 @@ typedef struct {
                                      the absorbing-layer target rise from ramp_start u_ref to
                                      u_ref (0: none) */
     double ramp_start;            /* initial fraction of u_ref under a start-up ramp */
+    double sa_mu_cap;             /* SA face diffusivity limit in lattice units (not part of
+                                     the method; <= 0: none, the scheme of eqs (12), (16)) */
 } lbro_config;
 
 typedef struct lbro_sim lbro_sim;
@@ -110,7 +112,7 @@ void   lbro_collide(const double f[9], double nu_eff, double omega_b,
 void   lbro_sa_source(double nut, double nu, double omega, double dist, double out[7]);
 /* stencil arrays are [3][3] row-major with index [dy+1][dx+1] */
 double lbro_sa_cell(const double nt[9], const double ux[9], const double uy[9],
-                    double nu, double dist, int32_t mode);
+                    double nu, double dist, int32_t mode, double mu_cap);
 double lbro_lsq_point(int32_t n, const double* px, const double* py, const double* v,
                       double x, double y);
 double lbro_idw_point(int32_t n, const double* px, const double* py, const double* v,

@@ -202,6 +202,81 @@ def test_symmetric_body_at_zero_incidence_has_no_lift():
     assert abs(f[3]) < 1e-9 * max(1.0, abs(f[2]))
 
 
+def test_wall_node_dirichlet_value_is_the_log_layer_solution():
+    """The SA value imposed at a wall node B is the log-layer solution nt = kappa u_tau y
+    (eq. (20)) at y = d_WB: on the channel, whose half-way walls put every B at
+    d_WB = 1/2, chi_B / y_B+ is kappa for every node, and a step imposes at B the
+    value of the wall model evaluated on the state that step starts from."""
+    c = LI.case_channel()
+    s = oracle.Sim(c)
+    ux, uy = LI.channel_initial_velocity(c)
+    s.init(0, rho=np.ones_like(ux), ux=ux, uy=uy, chi=np.full_like(ux, 3.0))
+    s.advance(50)
+    w = s.wall(0)
+    np.testing.assert_array_equal(w[:, 6], 0.5)
+    yplus_b = w[:, 8] * w[:, 6] / c["nu0"]
+    np.testing.assert_allclose(w[:, 16] / yplus_b, 0.41, rtol=1e-13)
+    s.advance(1)
+    chi = s.field(0, oracle.F_CHI)
+    gi, gj = w[:, 0].astype(int), w[:, 1].astype(int)
+    np.testing.assert_allclose(chi[gj, gi], w[:, 16], rtol=1e-12)
+
+
+def _segments(P):
+    d = np.roll(P, -1, axis=0) - P
+    ds = np.hypot(d[:, 0], d[:, 1])
+    return d / ds[:, None], ds
+
+
+@pytest.mark.parametrize("alpha", [0.0, 6.0])
+def test_friction_force_sign_rule_in_uniform_flow(alpha):
+    """Uniform flow u = U e_x on the initial state: the tangential velocity at every
+    reference point is the wall-parallel part of U e_x, so the sign rule of the
+    surface friction makes each segment's Cf carry the sign of its tangent's x
+    component, and every segment adds |Cf| |t_x| ds >= 0 to the friction drag
+    (eq. (30)): C_Df > 0, and equal to the sum over the segments.  A flipped sign
+    rule, or the normal in place of the tangent, fails."""
+    c = LI.case_airfoil_small(alpha_deg=alpha)
+    s = oracle.Sim(c)
+    P = c["bodies"][0]
+    t, ds = _segments(P)
+    cp, cf = s.surface(0)
+    f = s.forces()
+    clear = np.abs(t[:, 0]) > 0.3
+    assert np.all(np.sign(cf[clear]) == np.sign(t[clear, 0]))
+    assert f[0] > 0
+    assert f[0] == pytest.approx(np.sum(cf * t[:, 0] * ds), rel=1e-12)
+    assert f[4] == pytest.approx(np.sum(cf * t[:, 1] * ds), rel=1e-12, abs=1e-15)
+    if alpha == 0.0:                                   # mirror-symmetric body and grid
+        assert abs(f[4]) < 1e-10 * f[0]
+
+
+def test_pressure_force_points_down_the_pressure_gradient():
+    """A density that falls with height (Cp higher below the body) pushes the body
+    up: C_L > 0, of the size -(2 c_s^2 dRho/dy / U^2) x (body area) given by the
+    divergence theorem (within the reference-point offset of two cells at c/64),
+    and C_P = -(1/c) sum Cp n ds with n = (t_y, -t_x) into the fluid (eq. (30))."""
+    c = LI.case_airfoil_small(alpha_deg=0.0)
+    s = oracle.Sim(c)
+    g = -2e-4                                          # d rho / d y per chord
+    for l in range(c["n_levels"]):
+        inf = s.level_info(l)
+        dx = c["dx0"] / 2 ** l
+        y = c["origin"][1] + (inf["gy0"] + np.arange(inf["ny"]) + 0.5) * dx
+        rho = np.repeat((1.0 + g * y)[:, None], inf["nx"], axis=1)
+        s.init(l, rho=rho, ux=np.zeros_like(rho), uy=np.zeros_like(rho))
+    P = c["bodies"][0]
+    t, ds = _segments(P)
+    area = 0.5 * np.sum(P[:, 0] * np.roll(P[:, 1], -1) - np.roll(P[:, 0], -1) * P[:, 1])
+    U = c["mach"] / math.sqrt(3.0)
+    cp, cf = s.surface(0)
+    f = s.forces()
+    expect = -(2.0 / 3.0) * g / U**2 * area
+    assert 0.5 * expect < f[3] < 2.0 * expect
+    assert f[1] == pytest.approx(-np.sum(cp * t[:, 1] * ds), rel=1e-12, abs=1e-14)
+    assert f[3] == pytest.approx(np.sum(cp * t[:, 0] * ds), rel=1e-12)
+
+
 def _point_in_polygon(P, x, y):
     n = len(P)
     inside = False

@@ -156,13 +156,105 @@ def test_idw_exact_for_constants_and_at_nodes():
 
 
 @pytest.mark.parametrize("chi", [10.0, 1e3, 1e5, 1e7])
-def test_explicit_diffusion_stays_within_the_stencil_at_any_eddy_viscosity(chi):
-    """Pure diffusion (no velocity, wall far away) of a centre value below its four
-    face neighbours: the update must not overshoot them, whatever the diffusivity,
-    so the face diffusivity is bounded (0.2 sigma per face)."""
+def test_limited_face_diffusivity_keeps_the_update_within_the_stencil(chi):
+    """With the optional face-diffusivity limit of 0.2 sigma, pure diffusion (no
+    velocity, wall far away) of a centre value below its four face neighbours
+    never overshoots them, whatever the eddy viscosity."""
     nu, d = 1e-4, 1e12
     hi = chi * nu
     nt = np.full(9, hi)
     nt[4] = 0.5 * hi
-    new = oracle.sa_cell(nt, np.zeros(9), np.zeros(9), nu, d, 1)
+    new = oracle.sa_cell(nt, np.zeros(9), np.zeros(9), nu, d, 1, mu_cap=0.2 * SA["sigma"])
     assert 0.5 * hi < new <= hi
+
+
+@pytest.mark.parametrize("chi", [10.0, 1e3, 1e5])
+def test_unlimited_face_diffusivity_is_the_printed_scheme(chi):
+    """Without the limit (the default), the centred diffusion of eq. (12) uses the
+    mean of the two nodal diffusivities nu + nt at every face.  A centre value C
+    whose four face neighbours hold 2C (no velocity, wall far away, so the sources
+    vanish and the centred gradient, hence the c_b2 term, is zero) gains
+    (1/sigma) 4 ((nu + C) + (nu + 2C)) / 2 C.  A limit above every face value
+    changes nothing, bit for bit."""
+    nu, d = 1e-4, 1e12
+    C = 0.5 * chi * nu
+    nt = np.full(9, C)
+    nt[[1, 3, 5, 7]] = 2 * C
+    expect = C + 4 * (0.5 * ((nu + C) + (nu + 2 * C))) * C / SA["sigma"]
+    got = oracle.sa_cell(nt, np.zeros(9), np.zeros(9), nu, d, 1)
+    assert got == pytest.approx(expect, rel=1e-12)
+    assert oracle.sa_cell(nt, np.zeros(9), np.zeros(9), nu, d, 1, mu_cap=10 * (nu + 2 * C)) == got
+
+
+def _fw_sweep():
+    """(r, f_w) over a sweep of the vorticity at fixed nt and d: r = nt / (S~ kappa^2 d^2)
+    runs from far below 1 up to its limit r_lim."""
+    nu, d = 1e-5, 0.05
+    nt = 0.95 * nu                                 # 0 < f_v2 < 0.1: r -> 1 / f_v2 > r_lim as Omega -> 0
+    out = []
+    for omega in np.logspace(-12, 2, 300):
+        src = oracle.sa_source(nt, nu, omega, d)
+        out.append((src["r"], src["f_w"], src["D"], nt, d))
+    return out
+
+
+def test_destruction_function_limits():
+    """eq. (15): for r -> 0, g -> (1 - c_w2) r and f_w / r -> (1 - c_w2) ((1 + c_w3^6) / c_w3^6)^(1/6);
+    at the clip r = r_lim, g = r_lim + c_w2 (r_lim^6 - r_lim) is about 3e5 and f_w equals
+    (1 + c_w3^6)^(1/6) to 1e-12; f_w = 1 at r = 1 (see the log-layer test)."""
+    cw2, cw3 = SA["c_w2"], SA["c_w3"]
+    sweep = _fw_sweep()
+    r_small, fw_small = min(sweep)[:2]
+    assert r_small < 1e-3
+    assert fw_small / r_small == pytest.approx((1 - cw2) * ((1 + cw3**6) / cw3**6) ** (1 / 6), rel=1e-9)
+    r_big, fw_big = max(sweep)[:2]
+    assert r_big == SA["r_lim"]
+    assert fw_big == pytest.approx((1 + cw3**6) ** (1 / 6), rel=1e-12)
+
+
+def test_destruction_function_is_increasing_and_enters_the_destruction_term():
+    """f_w never decreases with r, increases strictly until it saturates at
+    (1 + c_w3^6)^(1/6) (g ~ 1e3 from r ~ 4 on, where the difference drops below
+    FP64 resolution), and D = c_w1 f_w (nt / d)^2 (eq. (13))."""
+    sweep = sorted(_fw_sweep())
+    rs = np.array([x[0] for x in sweep])
+    fws = np.array([x[1] for x in sweep])
+    assert np.all(np.diff(fws) >= -4e-16 * fws[1:])               # rounding of pow() at saturation
+    rising = fws < 0.999 * (1 + SA["c_w3"] ** 6) ** (1 / 6)
+    assert rising.sum() > 50 and np.all(np.diff(fws[rising]) > 0)
+    for r, fw, D, nt, d in sweep[::37]:
+        assert D == pytest.approx(3.2390678167757 * fw * (nt / d) ** 2, rel=1e-12)
+
+
+@pytest.mark.parametrize("chi,fn,mu_over_nu", [(-1.0, 15.0 / 17.0, 2.0 / 17.0), (-2.0, 1.0 / 3.0, 1.0 / 3.0)])
+def test_negative_branch_hand_values(chi, fn, mu_over_nu):
+    """eqs. (16)-(17) at chi = -1 and -2 with c_n1 = 16: f_n = (16 + chi^3) / (16 - chi^3)
+    is 15/17 and 1/3, so the nodal diffusivity nu + nt f_n is 2 nu / 17 and nu / 3.
+    With nu = 1e-5, Omega = 2e-3 and d = 0.01, worked by hand from the printed
+    constants: P_n = c_b1 (1 - c_t3) Omega nt = -5.42e-5 nt (5.42e-10 and 1.084e-9),
+    D_n = -c_w1 (nt / d)^2 (-c_w1 1e-6 and -c_w1 4e-6), and nu_t = 0 (eq. (11))."""
+    nu, omega, d = 1e-5, 2e-3, 0.01
+    nt = chi * nu
+    src = oracle.sa_source(nt, nu, omega, d)
+    assert src["mu"] / nu == pytest.approx(mu_over_nu, rel=1e-13)
+    assert (src["mu"] - nu) / nt == pytest.approx(fn, rel=1e-13)
+    expect_P = {-1.0: 5.42e-10, -2.0: 1.084e-9}[chi]            # -0.0271 * 2e-3 * nt
+    expect_D = {-1.0: -3.2390678167757e-6, -2.0: -1.29562712671028e-5}[chi]   # -c_w1 (nt/d)^2
+    assert src["P"] == pytest.approx(expect_P, rel=1e-12)
+    assert src["D"] == pytest.approx(expect_D, rel=1e-12)
+    assert src["nu_t"] == 0.0
+
+
+def test_lax_wendroff_cross_term_advects_a_bilinear_field_exactly():
+    """nt = b + c x y is advected by a uniform (u, v) to b + c (x - u)(y - v); at the
+    centre after one step the increment is c u v, which only the corner cross term
+    delta_xy of the unsplit scheme produces (the first and second centred differences
+    of x y vanish at the centre).  A dropped factor 2 or a wrong sign fails."""
+    nu, d, b, c = 1e-5, 1e12, 1e-3, 2e-4
+    nt = _stencil(lambda dx, dy: b + c * dx * dy)
+    zero = _stencil(lambda dx, dy: 0.0)
+    for u, v in ((0.03, 0.05), (-0.07, 0.02), (0.04, -0.06)):
+        ux = _stencil(lambda dx, dy: u)
+        uy = _stencil(lambda dx, dy: v)
+        diff = oracle.sa_cell(nt, ux, uy, nu, d, 1) - oracle.sa_cell(nt, zero, zero, nu, d, 1)
+        assert diff == pytest.approx(c * u * v, rel=1e-9)

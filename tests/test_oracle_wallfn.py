@@ -84,3 +84,31 @@ def test_slip_velocity_closed_form(yv):
     uw = oracle.slip(utau, dwv, nu)
     assert uw / utau == pytest.approx(oracle.uplus(yv) - yv / (1.0 + KAPPA * yv), rel=1e-13)
     assert 0.0 < uw < utau * oracle.uplus(yv)
+
+
+@pytest.mark.parametrize("yv", [0.5, 10.0, 30.0, 50.0, 100.0, 200.0, 400.0, 3000.0])
+def test_slip_velocity_from_the_integrated_wall_law(yv):
+    """Steps 4-5 of the VN procedure built from independent pieces: u_V comes from
+    integrating eq. (21) numerically from the wall (plus the wall value of eq. (22),
+    pinned above), and the slip is the wall intercept of the straight line through
+    (d_WV, u_V) whose slope is the wall shear stress u_tau^2 divided by the total
+    viscosity nu + (nu_t)_V at V, with (nu_t)_V = nu kappa y_V+ (eq. (28))."""
+    nu, dwv = 2e-5, 1.0
+    utau = yv * nu / dwv
+    u_v = utau * (oracle.uplus(0.0) + quad(eq21, 0.0, yv, limit=400, epsabs=1e-13, epsrel=1e-12)[0])
+    slope = utau**2 / (nu + nu * KAPPA * yv)
+    assert oracle.slip(utau, dwv, nu) == pytest.approx(u_v - slope * dwv, rel=1e-10)
+
+
+def test_slip_velocity_limits():
+    """Deep in the viscous sublayer the line through V hits the wall at the wall value
+    of eq. (22) plus a second-order remainder (u_W / u_tau ~ u+(0) + kappa y_V+^2); in
+    the log layer the slip tends to u_V - u_tau / kappa."""
+    nu, dwv = 2e-5, 1.0
+    for yv in (1e-3, 1e-2):
+        utau = yv * nu / dwv
+        rest = oracle.slip(utau, dwv, nu) / utau - oracle.uplus(0.0)
+        assert rest == pytest.approx(KAPPA * yv * yv, rel=2e-2)
+    yv = 1e7
+    utau = yv * nu / dwv
+    assert oracle.slip(utau, dwv, nu) / utau == pytest.approx(oracle.uplus(yv) - 1.0 / KAPPA, abs=1e-6)
