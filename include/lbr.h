@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define LBR_ABI_VERSION 4
+#define LBR_ABI_VERSION 5
 #define LBR_MAX_LEVELS 12
 
 enum lbr_status {
@@ -61,7 +61,10 @@ enum lbr_status {
 enum lbr_storage { LBR_STORE_F64 = 0, LBR_STORE_F32 = 1, LBR_STORE_F16 = 2, LBR_STORE_BF16 = 3,
                    LBR_STORE_MIXED = 4 };
 
-/* Domain sides: x-lo, x-hi, y-lo, y-hi. */
+/* Domain sides: x-lo, x-hi, y-lo, y-hi.  Supported per side (lbr_create
+   refuses the rest): x-lo PERIODIC or INLET, x-hi PERIODIC or OUTLET, y-lo and
+   y-hi PERIODIC, SYMMETRY or WALL (channel walls at wall_y); periodic sides
+   come in pairs. */
 enum lbr_bc { LBR_BC_PERIODIC = 0, LBR_BC_INLET = 1, LBR_BC_OUTLET = 2, LBR_BC_SYMMETRY = 3,
               LBR_BC_WALL = 4 };
 
@@ -148,6 +151,14 @@ typedef struct lbr_config {
                                       f_i - f_eq_i(rho_ref, u_ref e_x) (free-stream shift, exact
                                       in FP32 arithmetic on load and store); other storage
                                       formats ignore it */
+    double sa_mu_cap;              /* SA face diffusivity limit, lattice units of each level (not
+                                      part of the paper's method; <= 0: none, the centred
+                                      diffusion of eqs (12) and (16) as printed).  The explicit
+                                      update is stable only while (1/sigma) times the sum of the
+                                      four face diffusivities stays below 1; a limit of
+                                      0.2 sigma keeps it there where a large eddy viscosity on a
+                                      fine level would not.  Below the limit the scheme is
+                                      unchanged, bit for bit. */
     lbr_alloc_fn alloc_fn;         /* optional device allocator */
     lbr_free_fn free_fn;
     void* alloc_user;
@@ -179,7 +190,8 @@ typedef struct lbr_level_desc {
    omega_b, d_WR = 2, d_WV = 1 unless changed).  cfg is copied; no device
    work is done.  Errors: LBR_ERR_INVALID_ARG for an inconsistent config: a
    wrong version, an enum value outside its range, periodic sides that do not
-   come in pairs, a wall on an x side, fewer than 4 level-0 cells per side,
+   come in pairs, a side condition the step does not implement (see enum
+   lbr_bc), fewer than 4 level-0 cells per side,
    finest-level indices beyond 2^28, rho_ref, d_wr or d_wv not positive,
    omega_b outside (0, 2), a viscosity that is not positive and finite, a
    negative or non-finite band of a level in use, or any other non-finite

@@ -17,7 +17,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbr.so")
 
-ABI_VERSION = 4
+ABI_VERSION = 5
 MAX_LEVELS = 12
 WALL_STRIDE = 28
 
@@ -44,6 +44,7 @@ class lbr_config(C.Structure):
         ("d_wv", C.c_double), ("u_wall", C.c_double * 4),
         ("sponge_width", C.c_double), ("sponge_strength", C.c_double),
         ("ramp_steps", C.c_double), ("ramp_start", C.c_double), ("shift16", C.c_int32),
+        ("sa_mu_cap", C.c_double),
         ("alloc_fn", ALLOC_FN), ("free_fn", FREE_FN), ("alloc_user", C.c_void_p),
         ("stream", C.c_void_p),
     ]
@@ -130,19 +131,30 @@ class LbrError(RuntimeError):
 
 
 class _TorchAllocator:
-    """Device memory for the library from PyTorch's caching allocator."""
+    """Device memory for the library from PyTorch's caching allocator.
 
-    def __init__(self, device):
-        import torch
-        self.torch = torch
+    Blocks are taken on the library's own stream, the one every kernel of the
+    context runs on: the caching allocator then hands a block freed by the
+    library (a readout scratch, say) only to later work on that same stream, so
+    its reuse is ordered after the kernels that still read it."""
+
+    def __init__(self, device, stream=None, torch_module=None):
+        if torch_module is None:
+            import torch as torch_module
+        self.torch = torch_module
         self.device = device
+        self.stream = stream
         self.live = {}
         self.alloc_cb = ALLOC_FN(self._alloc)
         self.free_cb = FREE_FN(self._free)
 
     def _alloc(self, nbytes, user):
         try:
-            t = self.torch.empty(int(nbytes), dtype=self.torch.uint8, device=self.device)
+            if self.stream is not None:
+                with self.torch.cuda.stream(self.stream):
+                    t = self.torch.empty(int(nbytes), dtype=self.torch.uint8, device=self.device)
+            else:
+                t = self.torch.empty(int(nbytes), dtype=self.torch.uint8, device=self.device)
         except Exception:
             return None
         ptr = t.data_ptr()
@@ -184,6 +196,7 @@ def make_config(case, storage="f32", stream=None, allocator=None) -> lbr_config:
     c.ramp_steps = case.get("ramp_steps", 0.0)
     c.ramp_start = case.get("ramp_start", 0.0)
     c.shift16 = 1 if shift else int(case.get("shift16", 0))
+    c.sa_mu_cap = float(case.get("sa_mu_cap", 0.0))
     if allocator is not None:
         c.alloc_fn, c.free_fn = allocator.alloc_cb, allocator.free_cb
     c.stream = stream
@@ -202,7 +215,7 @@ class Solver:
         torch.cuda.set_device(self.device)
         # a stream of its own (default priority): the legacy default stream cannot be captured
         self.torch_stream = torch.cuda.Stream(self.device)
-        self.alloc = _TorchAllocator(self.device) if use_torch_memory else None
+        self.alloc = _TorchAllocator(self.device, self.torch_stream) if use_torch_memory else None
         self.case = case
         self._batches = weakref.WeakSet()      # batches that borrow this context
         self.cfg = make_config(case, storage, C.c_void_p(self.torch_stream.cuda_stream), self.alloc)
@@ -266,14 +279,21 @@ class Solver:
         self._check(lib().lbr_read_field(self.h, level, which, _dp(out)))
         return out
 
-    def field_device(self, level, which):
+    def field_device(self, level, which, torch_module=None):
         """One field of a level as a float64 device tensor (ny, nx), written by the
-        library on its stream; torch's current stream waits for it."""
-        import torch
+        library on its stream.  The tensor comes from torch's current stream, whose
+        earlier work may still use that block: the library stream waits for the
+        current stream before the write, and the current stream waits for the
+        library stream after it."""
+        torch = torch_module
+        if torch is None:
+            import torch
         inf = self.level_info(level)
+        cur = torch.cuda.current_stream(self.device)
         out = torch.empty((inf["ny"], inf["nx"]), dtype=torch.float64, device=self.device)
+        self.torch_stream.wait_stream(cur)
         self._check(lib().lbr_read_field_device(self.h, level, which, C.c_void_p(out.data_ptr()), out.numel()))
-        torch.cuda.current_stream(self.device).wait_stream(self.torch_stream)
+        cur.wait_stream(self.torch_stream)
         return out
 
     def wall(self, level):

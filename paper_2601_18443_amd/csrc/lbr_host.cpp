@@ -856,6 +856,7 @@ void fill_step_args(lbr_ctx* c, int l, int substep, StepArgs<ST, CT>& a, int tk 
     a.chi_in = (CT)cfg.chi_inlet;
     a.rho_out = (CT)cfg.rho_ref;
     a.sa_mode = cfg.sa;
+    a.mu_cap = cfg.sa_mu_cap > 0 ? (CT)cfg.sa_mu_cap : (CT)INFINITY;
     a.frozen = cfg.sa == LBR_SA_FROZEN;
     a.bb_halfway = cfg.bb == LBR_BB_HALFWAY;
     a.substep = substep;
@@ -1154,7 +1155,15 @@ int lbr_create(const lbr_config* cfg, lbr_ctx** out) {
         !std::isfinite(cfg->chi_inlet) || !std::isfinite(cfg->chi_init) || !std::isfinite(cfg->force[0]) ||
         !std::isfinite(cfg->force[1]) || !std::isfinite(cfg->origin[0]) || !std::isfinite(cfg->origin[1]) ||
         !std::isfinite(cfg->u_ref) || !std::isfinite(cfg->nu0) || !std::isfinite(cfg->dx0) ||
-        !std::isfinite(cfg->sponge_width) || !std::isfinite(cfg->ramp_steps))
+        !std::isfinite(cfg->sponge_width) || !std::isfinite(cfg->ramp_steps) || !std::isfinite(cfg->sa_mu_cap))
+        return LBR_ERR_INVALID_ARG;
+    // side conditions the step implements: the inlet rule on x-lo, the outlet rules on
+    // x-hi, symmetry and channel walls on the y sides (any other pairing would leave
+    // the populations entering across that side undefined)
+    if ((cfg->bc[0] != LBR_BC_PERIODIC && cfg->bc[0] != LBR_BC_INLET) ||
+        (cfg->bc[1] != LBR_BC_PERIODIC && cfg->bc[1] != LBR_BC_OUTLET) ||
+        cfg->bc[2] == LBR_BC_INLET || cfg->bc[2] == LBR_BC_OUTLET ||
+        cfg->bc[3] == LBR_BC_INLET || cfg->bc[3] == LBR_BC_OUTLET)
         return LBR_ERR_INVALID_ARG;
     for (int l = 1; l < cfg->n_levels; ++l)
         if (!(cfg->band[l] >= 0) || !std::isfinite(cfg->band[l])) return LBR_ERR_INVALID_ARG;

@@ -87,6 +87,7 @@ struct StepArgs {
     Box box;
     Domain dom;
     CT nu, fx, fy, omega_b, u_in, chi_in, rho_out;
+    CT mu_cap;                       // SA face diffusivity limit (+inf: none)
     int sa_mode, bb_halfway, frozen;
     int substep;                     // 1 or 2 within the parent's step (0 on level 0)
     int pad;                         // spare elements before and after every field array

@@ -237,7 +237,7 @@ __device__ __forceinline__ T sa_mu(T nt, T nu) {
 }
 
 template <class T>
-__device__ T sa_update(const T nt[9], const T u[9], const T v[9], T nu, T d, int upwind) {
+__device__ T sa_update(const T nt[9], const T u[9], const T v[9], T nu, T d, int upwind, T cap) {
     const T six = T(1.0 / 6.0);
     const T dudy = ((u[7] - u[1]) + (u[8] - u[2]) + (u[6] - u[0])) * six;
     const T dvdx = ((v[5] - v[3]) + (v[8] - v[6]) + (v[2] - v[0])) * six;
@@ -281,10 +281,9 @@ __device__ T sa_update(const T nt[9], const T u[9], const T v[9], T nu, T d, int
                          T(0.5) * uc * vc * (nt[8] - nt[6] - nt[2] + nt[0]) +
                          vc * vc * (N - T(2) * C + S));
     }
-    // face diffusivity capped at 0.2 sigma: the explicit update is stable only while
-    // (1/sigma) sum_faces mu <= 1, which a large eddy viscosity on a fine level
-    // exceeds; below the cap the scheme is unchanged
-    const T mC = sa_mu(C, nu), cap = T(0.2 * SIGMA);
+    // face diffusivity: mean of the nodal values (eqs (12), (16)), limited to cap
+    // when one is configured (+inf otherwise: dmin then returns the mean itself)
+    const T mC = sa_mu(C, nu);
     const T diff = dmin(T(0.5) * (mC + sa_mu(E, nu)), cap) * (E - C) -
                    dmin(T(0.5) * (mC + sa_mu(W, nu)), cap) * (C - W) +
                    dmin(T(0.5) * (mC + sa_mu(N, nu)), cap) * (N - C) -
@@ -657,7 +656,7 @@ __device__ __forceinline__ void edge_cell(const StepArgs<ST, CT>& a, int e) {
     } else {
 #pragma unroll
         for (int k = 0; k < 9; ++k) nt[k] *= a.nu;
-        chi_new = fdiv(sa_update(nt, u, v, a.nu, dist, a.sa_mode == 2), a.nu);
+        chi_new = fdiv(sa_update(nt, u, v, a.nu, dist, a.sa_mode == 2, a.mu_cap), a.nu);
     }
     finish_cell(a, c, s, chi_new, gx, gy);
 }
@@ -911,7 +910,7 @@ __device__ __forceinline__ void step_block(const StepArgs<ST, CT>& a, const int 
                     u[k] = sh_u[wy + 1 + dy][lane + 1 + dx];
                     v[k] = sh_v[wy + 1 + dy][lane + 1 + dx];
                 }
-            chi_new = fdiv(sa_update(nt, u, v, a.nu, dist, a.sa_mode == 2), a.nu);
+            chi_new = fdiv(sa_update(nt, u, v, a.nu, dist, a.sa_mode == 2, a.mu_cap), a.nu);
         }
         relax_cell(a, s, chi_new, m_rho, m_ux, m_uy);
         absorb(a, gx, gy, s);

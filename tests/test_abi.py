@@ -77,7 +77,7 @@ def test_config_validation_without_gpu():
     ("rho_ref", 0.0), ("rho_ref", float("nan")),
     ("omega_b", 0.0), ("omega_b", 2.0),                      # bulk rate in (0, 2)
     ("d_wr", 0.0), ("d_wv", -1.0), ("chi_init", float("inf")),
-    ("u_ref", float("nan")), ("sponge_width", float("inf")),
+    ("u_ref", float("nan")), ("sponge_width", float("inf")), ("sa_mu_cap", float("nan")),
 ])
 def test_create_refuses_out_of_range_config(field, value):
     import paper_2601_18443_amd as P
@@ -89,6 +89,30 @@ def test_create_refuses_out_of_range_config(field, value):
     h = ctypes.c_void_p()
     assert L.lbr_create(ctypes.byref(cfg), ctypes.byref(h)) == -1
     assert not h.value
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="liblbr.so not built")
+@pytest.mark.parametrize("side,kind", [
+    (0, "OUTLET"), (0, "SYMMETRY"),                          # x-lo: periodic or inlet only
+    (1, "INLET"), (1, "SYMMETRY"),                           # x-hi: periodic or outlet only
+    (2, "INLET"), (2, "OUTLET"), (3, "INLET"), (3, "OUTLET"),  # y sides: symmetry, wall, periodic
+])
+def test_create_refuses_side_conditions_the_step_does_not_implement(side, kind):
+    """The step applies the inlet rule on x-lo only and the outlet rules on x-hi
+    only; any other pairing would leave the populations entering across that side
+    undefined, so lbr_create refuses it (host check, no device work)."""
+    import paper_2601_18443_amd as P
+    import lbr_inputs as LI
+    L = P.lib()
+    cfg = P.make_config(LI.case_airfoil_small(), "f32")
+    cfg.bc[side] = getattr(LI, "BC_" + kind)
+    h = ctypes.c_void_p()
+    assert L.lbr_create(ctypes.byref(cfg), ctypes.byref(h)) == -1
+    assert not h.value
+    ok = P.make_config(LI.case_airfoil_small(), "f32")
+    ok.bc[2] = ok.bc[3] = LI.BC_WALL                         # channel walls on the y sides
+    assert L.lbr_create(ctypes.byref(ok), ctypes.byref(h)) == 0
+    L.lbr_destroy(h)
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="liblbr.so not built")
