@@ -325,7 +325,7 @@ int64_t lbr_lups_per_coarse_step(lbr_ctx* ctx);
 int lbr_use_graph(lbr_ctx* ctx, int32_t enable);
 
 /* Tile shape of the step kernel.  A workgroup updates a tile of 64 x H cells
-   (one 64-wide wavefront per row, H = 2, 4 or 8 rows; 4 by default).  Every
+   (one 64-wide wavefront per row, H = 2, 4, 8 or 16 rows; 4 by default).  Every
    cell's result is a function of its stencil alone, so the fields are
    bit-identical for any choice.  lbr_tune times each height on every level
    with that level's first sub-step from the current state (trials launches

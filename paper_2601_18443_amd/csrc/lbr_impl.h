@@ -26,10 +26,10 @@ constexpr int WALL_PER_BLOCK = 16;   // wall nodes per k_step workgroup
 constexpr int TILE_X = 64;   // one wavefront per tile row
 // tile heights (wavefronts per workgroup) k_step is built for; the host tunes
 // one per level
-constexpr int NTY = 3;
-constexpr int TILE_YS[NTY] = {2, 4, 8};
+constexpr int NTY = 4;
+constexpr int TILE_YS[NTY] = {2, 4, 8, 16};
 constexpr int TILE_Y_DEFAULT = 1;   // index of 4 rows
-constexpr int TILE_Y_MAX = 8;       // level boxes hold whole tiles of any height
+constexpr int TILE_Y_MAX = 16;      // level boxes hold whole tiles of any height
 constexpr int MAX_STENCIL = 16;
 constexpr int ROWS_PER_GROUP = 4;   // wave rows per workgroup
 
@@ -92,7 +92,7 @@ struct StepArgs {
     int substep;                     // 1 or 2 within the parent's step (0 on level 0)
     int pad;                         // spare elements before and after every field array
                                      // of the level (one row plus one cell)
-    int ty;                          // tile height of the tile list (2, 4 or 8 rows)
+    int ty;                          // tile height of the tile list (2, 4, 8 or 16 rows)
     int wall_blocks, tile_blocks;    // k_step grid: wall-node blocks of WALL_PER_BLOCK nodes
                                      // (a multiple of 8 blocks),
                                      // tile blocks (a multiple of 8), then edge-cell blocks

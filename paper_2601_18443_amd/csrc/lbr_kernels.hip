@@ -8,7 +8,7 @@
 // and u, and applies the central-moment collision.  Populations are stored
 // shifted (s_i = f_i - w_i, or minus the free-stream equilibrium in the 16-bit
 // formats) in planes of a level's storage box; one 64 x H tile per workgroup
-// (H = 2, 4 or 8), one wavefront per tile row, so every population plane is
+// (H = 2, 4, 8 or 16), one wavefront per tile row, so every population plane is
 // read and written in coalesced 64-wide rows.  The work is bandwidth-bound and
 // uses no matrix cores.
 #include "lbr_impl.h"
@@ -1265,6 +1265,7 @@ static hipError_t step_t(const void* args, hipStream_t s, const Timing& tm) {
         case 2: return step_ty<ST, CT, 2>(a, s, tm);
         case 4: return step_ty<ST, CT, 4>(a, s, tm);
         case 8: return step_ty<ST, CT, 8>(a, s, tm);
+        case 16: return step_ty<ST, CT, 16>(a, s, tm);
         default: return hipErrorInvalidValue;
     }
 }
@@ -1290,6 +1291,7 @@ static hipError_t batch_t(const void* parts, const int* start, int nparts, int n
         case 2: return batch_ty<ST, CT, 2>(pa, start, nparts, nblocks_total, s, tm);
         case 4: return batch_ty<ST, CT, 4>(pa, start, nparts, nblocks_total, s, tm);
         case 8: return batch_ty<ST, CT, 8>(pa, start, nparts, nblocks_total, s, tm);
+        case 16: return batch_ty<ST, CT, 16>(pa, start, nparts, nblocks_total, s, tm);
         default: return hipErrorInvalidValue;
     }
 }
@@ -1314,6 +1316,7 @@ static hipError_t batch_mixed(const void* parts, const int* start, int nparts, i
         case 2: return batch_mixed_ty<2>(pa, start, nparts, nblocks_total, s, tm);
         case 4: return batch_mixed_ty<4>(pa, start, nparts, nblocks_total, s, tm);
         case 8: return batch_mixed_ty<8>(pa, start, nparts, nblocks_total, s, tm);
+        case 16: return batch_mixed_ty<16>(pa, start, nparts, nblocks_total, s, tm);
         default: return hipErrorInvalidValue;
     }
 }

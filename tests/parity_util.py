@@ -52,8 +52,78 @@ def density_error(g, o, n_levels):
     return worst
 
 
+def reference_speed(case):
+    """The case's reference velocity in lattice units (the same on every level under
+    acoustic scaling): the scale of the element-wise velocity bounds."""
+    u = case.get("u_ref", 0.0)
+    return u if u > 0 else case["mach"] / np.sqrt(3.0)
+
+
+def level_errors(g, o, n_levels, u_scale):
+    """Per level, the largest element-wise differences over the owned fluid cells:
+    |du_x| / U and |du_y| / U (U the reference speed; u itself may vanish),
+    |dchi| / max(|chi|, 1) per cell ("chi") and |dchi| / max |chi| of the level
+    ("chi_level"; chi = nu~ / nu is of order 1 in the free stream and grows to
+    1e2-1e3 in boundary layers and wakes), and |drho| (rho is about 1)."""
+    out = {}
+    for l in range(n_levels):
+        e = {}
+        for name in ("ux", "uy", "chi", "rho"):
+            fo, fg = FIELDS[name]
+            a, b = g.field(l, fg), o.field(l, fo)
+            m = np.isfinite(b)
+            assert np.array_equal(np.isfinite(a), m), ("different fluid masks", l, name)
+            if not m.any():
+                e[name] = 0.0
+                if name == "chi":
+                    e["chi_level"] = 0.0
+                continue
+            d = np.abs(a[m] - b[m])
+            if name in ("ux", "uy"):
+                d = d / u_scale
+            elif name == "chi":
+                e["chi_level"] = float(d.max() / max(float(np.abs(b[m]).max()), 1.0))
+                d = d / np.maximum(np.abs(b[m]), 1.0)
+            e[name] = float(d.max())
+        out[l] = e
+    return out
+
+
+def assert_fields_match(g, o, case, tol, rho_tol, chi_scale="cell"):
+    """Every owned fluid cell of every level: velocity within tol x U, density
+    within rho_tol, chi within tol x max(|chi|, 1) of the cell (chi_scale "cell")
+    or within tol x the level's largest |chi| (chi_scale "level"); returns the
+    errors."""
+    L = case["n_levels"]
+    errs = level_errors(g, o, L, reference_speed(case))
+    skip = "chi" if chi_scale == "level" else "chi_level"
+    bad = {(l, k): v for l, e in errs.items() for k, v in e.items()
+           if k != skip and (v > (rho_tol if k == "rho" else tol) or not np.isfinite(v))}
+    assert not bad, f"element-wise bounds exceeded (tol {tol}, rho {rho_tol}): {bad}; all: {errs}"
+    return errs
+
+
+def assert_walls_match(g, o, level, rtol, rho_tol, u_scale):
+    """Wall records of one level node by node: u_tau relative, the slip velocity
+    against U, and rho_W absolute."""
+    wo, wg = o.wall(level), g.wall(level)
+    assert len(wo) == len(wg)
+    assert np.array_equal(wo[:, :2], wg[:, :2])
+    np.testing.assert_allclose(wg[:, 8], wo[:, 8], rtol=rtol, atol=rtol * 1e-3 * u_scale)   # u_tau
+    np.testing.assert_allclose(wg[:, 9:11] / u_scale, wo[:, 9:11] / u_scale, rtol=0, atol=rtol)  # u_W
+    np.testing.assert_allclose(wg[:, 11], wo[:, 11], rtol=0, atol=rho_tol)         # rho_W
+
+
+def assert_surface_match(g, o, body, cp_tol, cf_tol):
+    """Segment by segment: Cp within cp_tol, Cf within cf_tol x max |Cf| of the body."""
+    (cpg, cfg), (cpo, cfo) = g.surface(body), o.surface(body)
+    np.testing.assert_allclose(cpg, cpo, rtol=0, atol=cp_tol)
+    np.testing.assert_allclose(cfg, cfo, rtol=0, atol=cf_tol * np.max(np.abs(cfo)))
+
+
 def velocity_error(g, o, n_levels):
-    """Relative L2 error of the velocity vector over all levels (area weighted)."""
+    """Relative L2 error of the velocity vector over all levels (area weighted);
+    a summary figure only: the bounds are element-wise (assert_fields_match)."""
     num = den = 0.0
     for l in range(n_levels):
         w = 4.0 ** -l

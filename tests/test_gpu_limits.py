@@ -44,10 +44,13 @@ def test_largest_level_box_steps_like_a_narrow_one():
     g = U.gpu_solver(narrow, "f32")
     small = _run(g, narrow, steps)
     g.close()
-    # the narrow channel against the oracle (FP32 window bar)
-    for f in (1, 3):
-        assert U.rel_l2(small[f], ref[f]) < 1e-5, f
-    assert np.max(np.abs(small[0] - ref[0])) < 1e-6
+    # the narrow channel against the oracle, cell by cell (FP32 bounds: u within
+    # 1e-5 U, chi within 1e-5 of its largest value, rho within 1e-6)
+    assert np.array_equal(np.isfinite(small[1]), np.isfinite(ref[1]))
+    m = np.isfinite(ref[1])
+    assert np.max(np.abs(small[1][m] - ref[1][m])) < 1e-5 * narrow["u_ref"]
+    assert np.max(np.abs(small[3][m] - ref[3][m])) < 1e-5 * np.max(np.abs(ref[3][m]))
+    assert np.max(np.abs(small[0][m] - ref[0][m])) < 1e-6
     w = U.gpu_solver(wide, "f32")
     assert w.level_info(0)["nx"] == 8000
     big = _run(w, wide, steps)

@@ -1,7 +1,7 @@
 """Tile shapes of the step kernel and their tuner (needs an MI355X).
 
 Every cell's update is a function of its stencil alone, so the fields must be
-bit-identical whatever tile height (2, 4 or 8 rows of 64 cells) each level
+bit-identical whatever tile height (2, 4, 8 or 16 rows of 64 cells) each level
 uses: under the direct cycle, the merged schedule replayed from a graph, and in
 a batch; tuning only chooses among them and must not change any result.
 """
@@ -32,7 +32,7 @@ def test_fields_are_bit_identical_for_every_tile_height(storage):
     case = _deep_case()
     L = case["n_levels"]
     ref = None
-    for rows in (4, 2, 8):
+    for rows in (4, 2, 8, 16):
         for graph in (False, True):
             s = P.Solver(case, storage=storage)
             s.set_tile_rows(rows)
@@ -45,7 +45,7 @@ def test_fields_are_bit_identical_for_every_tile_height(storage):
             assert _same(got, ref), (rows, graph)
     # mixed heights across levels
     s = P.Solver(case, storage=storage)
-    for lvl, rows in enumerate((8, 2, 4, 8, 2, 4)):
+    for lvl, rows in enumerate((8, 2, 16, 4, 2, 16)):
         s.set_tile_rows(rows, lvl)
     s.use_graph(True)
     s.advance(11)
@@ -60,7 +60,7 @@ def test_tuner_picks_valid_heights_and_changes_nothing():
     a.advance(3)
     b.advance(3)
     rows = a.tune(trials=3)
-    assert len(rows) == L and all(r in (2, 4, 8) for r in rows)
+    assert len(rows) == L and all(r in (2, 4, 8, 16) for r in rows)
     for s in (a, b):
         s.use_graph(True)
         s.advance(8)
@@ -78,7 +78,7 @@ def test_batch_tuner_keeps_batched_results_identical():
     batch = P.Batch(batched)
     try:
         rows = batch.tune(trials=3)
-        assert len(rows) == 6 and all(r in (2, 4, 8) for r in rows)
+        assert len(rows) == 6 and all(r in (2, 4, 8, 16) for r in rows)
         batch.use_graph(True)
         batch.advance(4)
         batch.synchronize()
@@ -93,6 +93,6 @@ def test_batch_tuner_keeps_batched_results_identical():
 def test_invalid_tile_heights_are_refused():
     import paper_2601_18443_amd as P
     s = P.Solver(LI.case_airfoil_small(), storage="f32")
-    for rows, level in ((3, -1), (16, 0), (4, 7)):
+    for rows, level in ((3, -1), (32, 0), (4, 7)):
         with pytest.raises(P.LbrError):
             s.set_tile_rows(rows, level)
