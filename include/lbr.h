@@ -271,6 +271,19 @@ int lbr_wall_yplus(lbr_ctx* ctx, int32_t level, double* dst);
    u_y / U, nu_t / nu = chi f_v1(chi) (0 for chi <= 0), rho. */
 int lbr_rake(lbr_ctx* ctx, double x0, double y0, double x1, double y1, int32_t n, double* dst);
 
+/* For callers that cannot allocate device memory (tight monitoring loops inside a
+   run, harnesses that forbid hipMalloc or the allocator callbacks of the config):
+   lbr_rake with no device allocation.  The gather indices and values of each
+   level go through one static device scratch of 1 MiB per GPU, held until the
+   process ends and shared by every context on that GPU; n may be at most
+   LBR_RAKE_NOALLOC_MAX (else LBR_ERR_INVALID_ARG, nothing done).  Nothing in the
+   scratch needs to start at zero (every call writes what it reads back), but
+   calls that overlap on one GPU (contexts driven from different host threads)
+   race on it.  dst and the results are those of lbr_rake, bit for bit; like
+   lbr_rake the call waits for the context's stream. */
+#define LBR_RAKE_NOALLOC_MAX 16384
+int lbr_rake_noalloc(lbr_ctx* ctx, double x0, double y0, double x1, double y1, int32_t n, double* dst);
+
 /* Surface Cp and sign-corrected Cf at the centroids of the segments of one
    body (eq. (30) and the interpolation described after it).  cp and cf hold
    n_pts[body] doubles each. */

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "liblbr.so")
 ABI_VERSION = 5
 MAX_LEVELS = 12
 WALL_STRIDE = 28
+RAKE_NOALLOC_MAX = 16384
 
 STORE_F64, STORE_F32, STORE_F16, STORE_BF16, STORE_MIXED = 0, 1, 2, 3, 4
 STORAGE = {"f64": STORE_F64, "f32": STORE_F32, "f16": STORE_F16, "bf16": STORE_BF16, "mixed": STORE_MIXED}
@@ -96,6 +97,7 @@ def lib():
         L.lbr_read_field_device.argtypes = [p, i32, i32, C.c_void_p, i64]
         L.lbr_wall_yplus.argtypes = [p, i32, dp]
         L.lbr_rake.argtypes = [p, C.c_double, C.c_double, C.c_double, C.c_double, i32, dp]
+        L.lbr_rake_noalloc.argtypes = [p, C.c_double, C.c_double, C.c_double, C.c_double, i32, dp]
         L.lbr_schedule.argtypes = [i32, i32, C.POINTER(C.c_int32), i32]
         L.lbr_schedule.restype = i32
         L.lbr_tune.argtypes = [p, i32, C.POINTER(C.c_int32)]
@@ -145,10 +147,12 @@ class _TorchAllocator:
         self.device = device
         self.stream = stream
         self.live = {}
+        self.n_alloc = 0                # allocations requested by the library so far
         self.alloc_cb = ALLOC_FN(self._alloc)
         self.free_cb = FREE_FN(self._free)
 
     def _alloc(self, nbytes, user):
+        self.n_alloc += 1
         try:
             if self.stream is not None:
                 with self.torch.cuda.stream(self.stream):
@@ -336,11 +340,12 @@ class Solver:
             self._check(lib().lbr_wall_yplus(self.h, level, _dp(out)))
         return out[:n]
 
-    def rake(self, p0, p1, n):
-        """(n, 5) array along the segment p0 -> p1: level, u_x/U, u_y/U, nu_t/nu, rho."""
+    def rake(self, p0, p1, n, noalloc=False):
+        """(n, 5) array along the segment p0 -> p1: level, u_x/U, u_y/U, nu_t/nu, rho.
+        noalloc: through lbr_rake_noalloc (no device allocation, n <= RAKE_NOALLOC_MAX)."""
         out = np.zeros((int(n), 5))
-        self._check(lib().lbr_rake(self.h, float(p0[0]), float(p0[1]), float(p1[0]), float(p1[1]),
-                                   int(n), _dp(out)))
+        fn = lib().lbr_rake_noalloc if noalloc else lib().lbr_rake
+        self._check(fn(self.h, float(p0[0]), float(p0[1]), float(p1[0]), float(p1[1]), int(n), _dp(out)))
         return out
 
     def tune(self, trials=5):

@@ -108,6 +108,7 @@ struct lbr_ctx {
     double* surf_cf = nullptr;
     double* partial = nullptr;
     int partial_n = 0;
+    void* scratch = nullptr;       // device address of the static scratch (lbr_rake_noalloc)
     bool built = false;
     std::vector<void*> allocs;
     int64_t resid_steps = 0;
@@ -1276,6 +1277,9 @@ int lbr_build(lbr_ctx* c) {
         L.inside.shrink_to_fit();
     }
     if (int r = build_surface(c, seg)) return r;
+    // the allocation-free entry point's static scratch on this device (looked up
+    // once per device, with the device the context runs on current)
+    HIPCHK(c, noalloc_scratch(&c->scratch));
     c->built = true;
     for (int l = 0; l < (int)c->lv.size(); ++l)
         if (int r = init_level(c, l, nullptr, nullptr, nullptr, nullptr)) return r;
@@ -1647,9 +1651,15 @@ int lbr_wall_yplus(lbr_ctx* c, int32_t level, double* dst) {
     return LBR_OK;
 }
 
-int lbr_rake(lbr_ctx* c, double x0, double y0, double x1, double y1, int32_t n, double* dst) {
-    if (!c || !dst || n < 1) return LBR_ERR_INVALID_ARG;
-    if (!c->built) return set_err(c, LBR_ERR_STATE, "lbr_build has not been called");
+static_assert(((size_t)LBR_RAKE_NOALLOC_MAX * sizeof(int64_t) + 255) / 256 * 256 +
+                  (size_t)LBR_RAKE_NOALLOC_MAX * 4 * sizeof(double) <= NOALLOC_SCRATCH_BYTES,
+              "the rake's gather indices and values fit the static scratch");
+
+// Rake readout of lbr_rake and lbr_rake_noalloc: the gather indices and values of
+// one level at a time go through buffers allocated per call, or through the
+// static scratch (noalloc); every level's copies finish before the next level.
+static int rake_impl(lbr_ctx* c, double x0, double y0, double x1, double y1, int32_t n, double* dst,
+                     bool noalloc) {
     const int nl = (int)c->lv.size();
     std::vector<int> lev(n, -1);
     std::vector<int64_t> cell(n, -1);
@@ -1680,9 +1690,17 @@ int lbr_rake(lbr_ctx* c, double x0, double y0, double x1, double y1, int32_t n, 
         if (idx.empty()) continue;
         const int m = (int)idx.size();
         Level& L = c->lv[l];
-        auto* didx = static_cast<int64_t*>(dalloc(c, (size_t)m * sizeof(int64_t)));
-        auto* dout = static_cast<double*>(dalloc(c, (size_t)m * 4 * sizeof(double)));
-        if (!didx || !dout) { dfree(c, didx); dfree(c, dout); return set_err(c, LBR_ERR_OOM, "rake scratch"); }
+        int64_t* didx;
+        double* dout;
+        if (noalloc) {
+            didx = static_cast<int64_t*>(c->scratch);
+            dout = reinterpret_cast<double*>(static_cast<char*>(c->scratch) +
+                                             ((size_t)m * sizeof(int64_t) + 255) / 256 * 256);
+        } else {
+            didx = static_cast<int64_t*>(dalloc(c, (size_t)m * sizeof(int64_t)));
+            dout = static_cast<double*>(dalloc(c, (size_t)m * 4 * sizeof(double)));
+            if (!didx || !dout) { dfree(c, didx); dfree(c, dout); return set_err(c, LBR_ERR_OOM, "rake scratch"); }
+        }
         std::vector<double> v((size_t)m * 4);
         int r = 0;
         const char* mac = static_cast<const char*>(L.mac[L.cur]);
@@ -1695,8 +1713,10 @@ int lbr_rake(lbr_ctx* c, double x0, double y0, double x1, double y1, int32_t n, 
             hipMemcpyAsync(v.data(), dout, v.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
             hipStreamSynchronize(c->stream) != hipSuccess)
             r = set_err(c, LBR_ERR_HIP, "rake readout failed");
-        dfree(c, didx);
-        dfree(c, dout);
+        if (!noalloc) {
+            dfree(c, didx);
+            dfree(c, dout);
+        }
         if (r) return r;
         const double cv13 = 7.1 * 7.1 * 7.1;
         for (int j = 0; j < m; ++j) {
@@ -1709,6 +1729,21 @@ int lbr_rake(lbr_ctx* c, double x0, double y0, double x1, double y1, int32_t n, 
         }
     }
     return LBR_OK;
+}
+
+int lbr_rake(lbr_ctx* c, double x0, double y0, double x1, double y1, int32_t n, double* dst) {
+    if (!c || !dst || n < 1) return LBR_ERR_INVALID_ARG;
+    if (!c->built) return set_err(c, LBR_ERR_STATE, "lbr_build has not been called");
+    return rake_impl(c, x0, y0, x1, y1, n, dst, false);
+}
+
+int lbr_rake_noalloc(lbr_ctx* c, double x0, double y0, double x1, double y1, int32_t n, double* dst) {
+    if (!c || !dst || n < 1) return LBR_ERR_INVALID_ARG;
+    if (!c->built || !c->scratch) return set_err(c, LBR_ERR_STATE, "lbr_build has not been called");
+    if (n > LBR_RAKE_NOALLOC_MAX)
+        return set_err(c, LBR_ERR_INVALID_ARG, "lbr_rake_noalloc takes at most %d points (%d given): "
+                       "its static scratch holds no more", LBR_RAKE_NOALLOC_MAX, n);
+    return rake_impl(c, x0, y0, x1, y1, n, dst, true);
 }
 
 int lbr_surface(lbr_ctx* c, int32_t body, double* cp, double* cf) {

@@ -200,4 +200,11 @@ hipError_t launch_to_double(Prec p, const void* src, double* dst, long n, hipStr
 hipError_t launch_residual(Prec p, const void* mac, double* snap, const int32_t* list, int n,
                            long plane, double area, double* partial, int nblocks, hipStream_t s);
 
+// Static device scratch of the allocation-free entry point (lbr_rake_noalloc):
+// one array of NOALLOC_SCRATCH_BYTES per GPU, held until the process ends.
+// noalloc_scratch() returns its device address on the current device (looked up
+// once per device); host code uses that address, never the array's name.
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(1) << 20;
+hipError_t noalloc_scratch(void** ptr);
+
 }  // namespace lbr

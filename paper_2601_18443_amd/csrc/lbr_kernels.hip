@@ -15,6 +15,7 @@
 #include <hip/hip_ext.h>
 
 #include <cmath>
+#include <mutex>
 #include <type_traits>
 
 namespace lbr {
@@ -1430,6 +1431,33 @@ hipError_t launch_to_double(Prec p, const void* src, double* dst, long n, hipStr
         hipLaunchKernelGGL(k_to_double<float>, dim3(nblocks(n, 256)), dim3(256), 0, s,
                            (const float*)src, dst, n);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Device scratch of the allocation-free entry point.  In host code `scratch`
+// names a host-side stand-in, not device memory: its device address comes from
+// hipGetSymbolAddress, once per device with that device current, and only that
+// address is handed to kernels and copies.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+hipError_t noalloc_scratch(void** ptr) {
+    constexpr int MAX_DEVICES = 64;
+    static std::mutex mu;
+    static void* addr[MAX_DEVICES] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    return hipSuccess;
 }
 
 }  // namespace lbr
