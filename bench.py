@@ -24,34 +24,41 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MLUPS & % HBM peak, D2Q9 LBM-RANS step; FP16-store vs FP32 at equal Cf error"
 HBM_PEAK_GBS = 8000.0
-# algorithmic bytes per cell update: populations read + write (18 x storage),
-# nu-tilde read + write (2 x its precision), the wall distance in the step's
-# arithmetic precision (the FP64 field, which the FP32 steps read rounded to
-# FP32), one flag byte
-ALG_BYTES = {"f32": 18 * 4 + 8 + 4 + 1, "f16": 18 * 2 + 8 + 4 + 1, "bf16": 18 * 2 + 8 + 4 + 1,
+# algorithmic bytes per cell update, as the method defines the work: populations
+# read + write (18 x storage), nu-tilde read + write (2 x its precision), the
+# wall distance in FP64, one flag byte
+ALG_BYTES = {"f32": 18 * 4 + 8 + 8 + 1, "f16": 18 * 2 + 8 + 8 + 1, "bf16": 18 * 2 + 8 + 8 + 1,
              "f64": 18 * 8 + 16 + 8 + 1}
+# what the step kernel moves per cell update by design: the algorithmic arrays with
+# the wall distance in the arithmetic precision (4 B in FP32 arithmetic), plus the
+# stored rho, u (written, 3 x CT) and the u of the SA stencil (read, 2 x CT)
+IMPL_BYTES = {"f32": 18 * 4 + 8 + 4 + 1 + 20, "f16": 18 * 2 + 8 + 4 + 1 + 20,
+              "bf16": 18 * 2 + 8 + 4 + 1 + 20, "f64": 18 * 8 + 16 + 8 + 1 + 40}
+TARGET_FRAC = 0.60
 DTYPE = {"f32": "f32", "f16": "f16-store/f32", "bf16": "bf16-store/f32", "f64": "f64",
          "mixed": "f32-store on the two finest levels, f16-store below/f32",
          "f16s": "f16-store (free-stream shift)/f32", "bf16s": "bf16-store (free-stream shift)/f32",
          "mixeds": "f32-store on the two finest levels, f16-store (free-stream shift) below/f32"}
 
 
-def lup_bytes(storage, level, n_levels):
+def lup_bytes(storage, level, n_levels, table=None):
     """Algorithmic bytes of one cell update on a level (mixed storage: FP32 on the
-    two finest levels, FP16 below)."""
+    two finest levels, FP16 below); table=IMPL_BYTES for the kernel's own."""
+    table = table or ALG_BYTES
     storage = {"f16s": "f16", "bf16s": "bf16", "mixeds": "mixed"}.get(storage, storage)
     if storage == "mixed":
-        return ALG_BYTES["f32"] if level >= n_levels - 2 else ALG_BYTES["f16"]
-    return ALG_BYTES[storage]
+        return table["f32"] if level >= n_levels - 2 else table["f16"]
+    return table[storage]
 
 
-def step_bytes(storage, sim, n_levels, repeat=1):
+def step_bytes(storage, sim, n_levels, repeat=1, table=None):
     """Algorithmic bytes of one coarse step of a solver (times repeat)."""
-    return repeat * sum(lup_bytes(storage, l, n_levels) * sim.level_info(l)["n_fluid"] * 2 ** l
+    return repeat * sum(lup_bytes(storage, l, n_levels, table) * sim.level_info(l)["n_fluid"] * 2 ** l
                         for l in range(n_levels))
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_airfoil_2M_traffic.txt")
+THREE_ELEMENT_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_batch_three_element_19M_traffic.txt")
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2601_18443_amd", "csrc", f) for f in ("lbr_kernels.hip", "lbr_host.cpp")]
 
 
@@ -67,13 +74,15 @@ def kernel_source_hash():
     return h()
 
 
-def measured_traffic(storage):
-    """HBM bytes per step-kernel launch from the committed rocprofv3 counter summary,
-    or None when the summary is missing or the kernel changed since."""
-    if not os.path.exists(TRAFFIC_FILE):
+def measured_traffic(storage, path=None):
+    """HBM bytes per step-kernel launch from the committed rocprofv3 counter summary
+    (default: the benchmark airfoil's), or None when the summary is missing or the
+    kernel changed since."""
+    path = path or TRAFFIC_FILE
+    if not os.path.exists(path):
         return None
     vals = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
             vals[k.strip()] = v.strip()
@@ -103,6 +112,91 @@ def cpu_baseline(case, min_seconds=10.0, max_steps=4):
     return {"value": lups * steps / dt / 1e6, "unit": "MLUPS", "cores": oracle.threads(), "kind": "oracle",
             "sample": f"{steps} coarse steps ({lups * steps} cell updates) of the same 8-level airfoil "
                       f"grid from the uniform initial state, FP64, OpenMP; grid build ({tb:.0f} s) untimed"}
+
+
+def equal_cf(case, steps):
+    """Storage precision at the converged state of the workload: FP32, FP16 and
+    mixed storage (both with the free-stream shift) each run the same coarse
+    steps from the same start (graph replay) and their surface data are compared
+    with the FP64 path's, which is itself within 1e-10 of the FP64 oracle (the
+    oracle would need hours for these steps).  The Cf bound is the one the FP32
+    path is held to: max |Cf - Cf_FP64| <= 1 % of max |Cf_FP64|."""
+    import paper_2601_18443_amd as P
+
+    def run(st):
+        s = P.Solver(case, storage=st)
+        s.use_graph(True)
+        s.advance(steps)
+        s.synchronize()
+        cp, cf = s.surface(0)
+        f = s.forces()
+        s.residual()
+        s.advance(100)
+        r = s.residual()
+        s.close()
+        log(f"equal-Cf check: {st} after {steps} coarse steps, residual {r:.1e}")
+        return cp, cf, f, r
+
+    ref = run("f64")
+    out = {"coarse_steps": steps, "reference": "f64 path (within 1e-10 of the FP64 oracle)",
+           "cf_bound": "max |dCf| <= 0.01 max |Cf|", "f64_residual": ref[3],
+           "f64_forces": {"C_Df": ref[2][0], "C_D": ref[2][2], "C_L": ref[2][3]}}
+    for st in ("f32", "f16s", "mixeds"):
+        cp, cf, f, r = run(st)
+        cf_err = float(np.max(np.abs(cf - ref[1])) / np.max(np.abs(ref[1])))
+        out[st] = {"cp_max_abs": float(np.max(np.abs(cp - ref[0]))), "cf_max_abs_over_max_cf": cf_err,
+                   "cd_rel": float(abs(f[2] - ref[2][2]) / abs(ref[2][2])),
+                   "cl_rel": float(abs(f[3] - ref[2][3]) / abs(ref[2][3])),
+                   "residual": r, "meets_cf_bound": bool(cf_err <= 0.01)}
+    return out
+
+
+def three_element_roofline(steps=10):
+    """The FP32 step on the 19.5M-cell three-element case, whose working set
+    (about 5 GB) is far beyond the 256 MB Infinity Cache: the HBM fraction of the
+    step without cache help.  The start-up ramp is shortened to one coarse step,
+    since only the kernel durations are measured here."""
+    import torch
+    import lbr_inputs as LI
+    import paper_2601_18443_amd as P
+    case = LI.case_three_element()
+    case.update(ramp_steps=1.0)
+    t0 = time.perf_counter()
+    s = P.Solver(case, storage="f32")
+    s.synchronize()
+    log(f"three-element grid built in {time.perf_counter() - t0:.1f} s")
+    rows = s.tune(trials=3)
+    s.use_graph(True)
+    s.advance(3)
+    s.synchronize()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.advance(steps)
+    s.synchronize()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    s.profile(True)
+    s.advance(steps)
+    s.synchronize()
+    kt = s.profile(False)
+    L = case["n_levels"]
+    lups = s.lups_per_coarse_step()
+    launches = kt[3] if kt[3] > 0 else 2 ** L - 1
+    bpl = step_bytes("f32", s, L) / launches
+    achieved = bpl / (kt[0] * 1e-6) / 1e9
+    traffic = measured_traffic("f32", THREE_ELEMENT_TRAFFIC_FILE)
+    out = {"workload": "three-element high-lift-like case, 8 levels c/32..c/4096, FP32",
+           "cells": int(sum(s.level_info(l)["n_fluid"] for l in range(L))), "lups_per_step": lups,
+           "ms_per_step": round(1000 * dt / steps, 3), "mlups": round(lups * steps / dt / 1e6, 1),
+           "tile_rows": rows, "avg_launch_us": round(kt[0], 3), "launches_per_step": round(launches, 2),
+           "alg_bytes_per_launch": round(bpl, 0), "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+           "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+           "traffic": None if traffic is None else round(traffic, 0)}
+    if traffic is not None:
+        out["hbm_GBps"] = round(traffic / (kt[0] * 1e-6) / 1e9, 1)
+    s.close()
+    log(f"three-element FP32: {out['ms_per_step']} ms per step, frac {out['frac']}")
+    return out
 
 
 def copy_calibration(nbytes=1 << 30):
@@ -397,6 +491,10 @@ def main():
     ap.add_argument("--max-super-steps", type=int, default=6000, help="cap of sweep_steady")
     ap.add_argument("--converge-steps", type=int, default=5000,
                     help="coarse steps of every storage in the precision workload")
+    ap.add_argument("--equal-cf-steps", type=int, default=3000,
+                    help="coarse steps of the equal-Cf check of the default line (0: skip it)")
+    ap.add_argument("--no-three-element", action="store_true",
+                    help="skip the three-element FP32 roofline record of the default line")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -482,7 +580,10 @@ def main():
                 "launches_per_step": round(launches_per_step, 2),
                 "finest_level_avg_launch_us": round(kt[1], 3),
                 "level0_avg_launch_us": round(kt[2], 3),
-                "alg_bytes_per_launch": round(bytes_per_launch, 0)}
+                "alg_bytes_per_launch": round(bytes_per_launch, 0),
+                "alg_bytes_per_lup": round(step_bytes(args.storage, sim, n_levels) / lups, 2),
+                "impl_bytes_per_lup": round(step_bytes(args.storage, sim, n_levels, table=IMPL_BYTES) / lups, 2),
+                "target_frac": TARGET_FRAC, "gap_to_target": round(TARGET_FRAC - achieved / HBM_PEAK_GBS, 4)}
         # context: the measured HBM rate of the kernel against a plain device copy
         copy = copy_bandwidth()
         roof["copy_GBps"] = round(copy, 1)
@@ -526,6 +627,24 @@ def main():
             log(f"{st} storage: {variants[st]['value']} MLUPS, k_step {ktv[0]:.2f} us")
             v.close()
             del v
+    eq = None
+    if args.workload == "airfoil" and args.storage == "f32" and args.equal_cf_steps > 0:
+        if "sim" in locals():
+            sim.close()
+            del sim
+        eq = equal_cf(case, args.equal_cf_steps)
+        mlups_of = {"f32": round(mlups, 1)}
+        mlups_of.update({k: v["value"] for k, v in variants.items()})
+        for st in ("f32", "f16s", "mixeds"):
+            eq[st]["mlups"] = mlups_of.get(st)
+        ok = [st for st in ("f32", "f16s", "mixeds") if eq[st]["meets_cf_bound"] and eq[st]["mlups"]]
+        best = max(ok, key=lambda st: eq[st]["mlups"]) if ok else None
+        eq["fastest_within_cf_bound"] = best
+        eq["speedup_over_f32_at_equal_cf"] = (None if best is None or not eq["f32"]["mlups"]
+                                              else round(eq[best]["mlups"] / eq["f32"]["mlups"], 3))
+    te = None
+    if args.workload == "airfoil" and args.storage == "f32" and not args.no_three_element:
+        te = three_element_roofline()
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on the same workload")
@@ -546,6 +665,8 @@ def main():
                    "storage": args.storage, "graph": bool(args.graph), "tile_rows": rows},
         "roofline": roof, "cpu_baseline": cpu,
         "storage_variants": variants or None,
+        "equal_cf": eq,
+        "three_element_fp32": te,
         "forces": {"C_Df": f[0], "C_Dp": f[1], "C_D": f[2], "C_L": f[3]},
     }
     print(json.dumps(out), flush=True)

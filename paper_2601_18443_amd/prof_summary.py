@@ -9,7 +9,13 @@ Two reports:
 ``traffic``
     HBM bytes per step-kernel dispatch from two ``--pmc`` runs (FETCH_SIZE, then
     WRITE_SIZE, in KiB per dispatch), each scaled by what the same counter reads
-    for a device copy of known size (``bench.py --copy-calibration``).
+    for a device copy of known size (``bench.py --copy-calibration``);
+``gaps``
+    the idle time between consecutive step-kernel dispatches of a stream of
+    super steps (``*kernel_trace.csv``): per super step of M launches, the span
+    from the first start to the last end, the summed kernel durations and the
+    summed gaps, the part of the span a single persistent launch could at most
+    remove by running the same work without launch boundaries.
 
 Usage::
 
@@ -173,6 +179,46 @@ def traffic(a):
     return "\n".join(lines) + "\n"
 
 
+def gaps(a):
+    """Idle gaps between the first a.first dispatches of a.kernel (by start time),
+    grouped into super steps of a.per_step launches."""
+    rows = []
+    for path in _find(a.dir, "*kernel_trace.csv"):
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                n = short_name(_col(r, "Kernel_Name"))
+                if n.split("<")[0] != a.kernel:
+                    continue
+                rows.append((float(_col(r, "Start_Timestamp")), float(_col(r, "End_Timestamp"))))
+    rows.sort()
+    rows = rows[a.skip:a.skip + a.first]
+    m = a.per_step
+    nsup = len(rows) // m
+    if nsup < 1:
+        sys.exit("fewer dispatches than one super step")
+    span = busy = inner = between = 0.0
+    for k in range(nsup):
+        grp = rows[k * m:(k + 1) * m]
+        span += grp[-1][1] - grp[0][0]
+        busy += sum(e - s for s, e in grp)
+        inner += sum(max(0.0, grp[j + 1][0] - grp[j][1]) for j in range(m - 1))
+        if k + 1 < nsup:
+            between += max(0.0, rows[(k + 1) * m][0] - grp[-1][1])
+    lines = [
+        f"# dispatch gaps of {a.kernel}, rocprofv3 --kernel-trace",
+        f"# command: {a.cmd}",
+        f"source_sha256 = {kernel_source_hash()}",
+        f"kernel = {a.kernel}",
+        f"dispatches = {nsup * m} (dispatch {a.skip} on, {nsup} super steps of {m} launches)",
+        f"span_us_per_super_step = {span / nsup / 1e3:.2f}",
+        f"kernel_us_per_super_step = {busy / nsup / 1e3:.2f}",
+        f"gaps_inside_us_per_super_step = {inner / nsup / 1e3:.2f}",
+        f"gap_between_super_steps_us = {between / max(nsup - 1, 1) / 1e3:.2f}",
+        f"gaps_over_span = {(inner + between) / (span + between):.4f}",
+    ]
+    return "\n".join(lines) + "\n"
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="what", required=True)
@@ -192,8 +238,20 @@ def main(argv=None):
     t.add_argument("--cmd-cal", required=True)
     t.add_argument("--kernel", default="k_step_batch",
                    help="kernel whose dispatches are averaged (k_step_batch: the merged schedule)")
+    g = sub.add_parser("gaps")
+    g.add_argument("dir")
+    g.add_argument("--cmd", required=True)
+    g.add_argument("--kernel", default="k_step_batch")
+    g.add_argument("--skip", type=int, default=0, help="dispatches to skip first (warm-up)")
+    g.add_argument("--first", type=int, required=True, help="dispatches to analyse")
+    g.add_argument("--per-step", type=int, required=True, help="launches per super step")
     a = ap.parse_args(argv)
-    sys.stdout.write(stats(a.dir, a.cmd, a.tail) if a.what == "stats" else traffic(a))
+    if a.what == "stats":
+        sys.stdout.write(stats(a.dir, a.cmd, a.tail))
+    elif a.what == "gaps":
+        sys.stdout.write(gaps(a))
+    else:
+        sys.stdout.write(traffic(a))
 
 
 if __name__ == "__main__":

@@ -20,19 +20,23 @@ def test_more_than_one_gpu_is_refused_before_any_gpu_work():
 
 
 def test_algorithmic_bytes_per_cell_update():
-    # populations read + write, nu-tilde read + write, wall distance, flag byte
-    assert bench.lup_bytes("f32", 0, 8) == 9 * 4 * 2 + 4 * 2 + 4 + 1 == 85
-    assert bench.lup_bytes("f16", 3, 8) == 9 * 2 * 2 + 4 * 2 + 4 + 1 == 49
-    assert bench.lup_bytes("f16s", 3, 8) == bench.lup_bytes("bf16", 3, 8) == 49
+    # populations read + write, nu-tilde read + write, wall distance (FP64), flag byte
+    assert bench.lup_bytes("f32", 0, 8) == 9 * 4 * 2 + 4 * 2 + 8 + 1 == 89
+    assert bench.lup_bytes("f16", 3, 8) == 9 * 2 * 2 + 4 * 2 + 8 + 1 == 53
+    assert bench.lup_bytes("f16s", 3, 8) == bench.lup_bytes("bf16", 3, 8) == 53
     assert bench.lup_bytes("f64", 0, 1) == 9 * 8 * 2 + 8 * 2 + 8 + 1 == 169
     # mixed storage: FP32 on the two finest levels only
-    assert [bench.lup_bytes("mixeds", l, 5) for l in range(5)] == [49, 49, 49, 85, 85]
+    assert [bench.lup_bytes("mixeds", l, 5) for l in range(5)] == [53, 53, 53, 89, 89]
+    # the kernel's own bytes: the wall distance in the arithmetic precision, plus the
+    # stored rho, u (3 x CT written) and the stencil's u (2 x CT read)
+    assert bench.lup_bytes("f32", 0, 8, bench.IMPL_BYTES) == 72 + 8 + 4 + 1 + 12 + 8 == 105
+    assert bench.lup_bytes("f16s", 0, 8, bench.IMPL_BYTES) == 36 + 8 + 4 + 1 + 12 + 8 == 69
 
     class Sim:
         def level_info(self, l):
             return {"n_fluid": [100, 40, 7][l]}
     # every level l updates its cells 2^l times per coarse step
-    assert bench.step_bytes("mixed", Sim(), 3, repeat=2) == 2 * (49 * 100 + 85 * 40 * 2 + 85 * 7 * 4)
+    assert bench.step_bytes("mixed", Sim(), 3, repeat=2) == 2 * (53 * 100 + 89 * 40 * 2 + 89 * 7 * 4)
 
 
 def _write_traffic(path, sha, storage="f32", hbm=81000000):
@@ -93,3 +97,27 @@ def test_stats_summary_averages_the_timed_dispatches(tmp_path):
 ])
 def test_kernel_names_are_shortened(name, short):
     assert PS.short_name(name) == short
+
+
+def test_gap_summary_of_a_dispatch_stream(tmp_path):
+    """Two super steps of three launches: 10 us kernels, 2 us between the
+    launches of a super step, 5 us between the super steps."""
+    d = tmp_path / "tr"
+    d.mkdir()
+    with open(d / "run_kernel_trace.csv", "w") as fh:
+        fh.write('"Kernel_Name","Start_Timestamp","End_Timestamp","Grid_Size_X"\n')
+        t = 0
+        for sup in range(2):
+            for k in range(3):
+                fh.write(f'"void lbr::k_step_batch<float, float, 4>(x)",{t},{t + 10000},1024\n')
+                t += 10000 + (2000 if k < 2 else 5000)
+        fh.write('"k_geometry(y)",0,1,64\n')
+
+    class A:
+        dir, cmd, kernel, skip, first, per_step = str(d), "rocprofv3 ...", "k_step_batch", 0, 6, 3
+    out = PS.gaps(A())
+    assert "span_us_per_super_step = 34.00" in out
+    assert "kernel_us_per_super_step = 30.00" in out
+    assert "gaps_inside_us_per_super_step = 4.00" in out
+    assert "gap_between_super_steps_us = 5.00" in out
+    assert "gaps_over_span = 0.1781" in out          # (2 x 4 + 5) / (2 x 34 + 5)
