@@ -49,7 +49,10 @@ enum lbr_status {
     LBR_ERR_GEOMETRY = -4,
     LBR_ERR_DIVERGED = -5,
     LBR_ERR_STATE = -6,
-    LBR_ERR_IO = -7
+    LBR_ERR_IO = -7,
+    LBR_ERR_NEWTON = -8,           /* a wall node's friction velocity (Section 2.3, step 3)
+                                      is not finite */
+    LBR_ERR_NOT_CONVERGED = -9     /* a run to steady state reached its step limit first */
 };
 
 /* Population storage.  Populations are stored shifted by their lattice
@@ -151,6 +154,12 @@ typedef struct lbr_config {
                                       f_i - f_eq_i(rho_ref, u_ref e_x) (free-stream shift, exact
                                       in FP32 arithmetic on load and store); other storage
                                       formats ignore it */
+    int32_t health_every;          /* health check of lbr_advance (0: none): after every
+                                      health_every-th coarse step the state of every level is
+                                      scanned on the device (density finite and positive,
+                                      |u| <= c_s, the wall nodes' friction velocity finite);
+                                      lbr_advance waits for the scans at its end and returns
+                                      LBR_ERR_DIVERGED or LBR_ERR_NEWTON if one failed */
     double sa_mu_cap;              /* SA face diffusivity limit, lattice units of each level (not
                                       part of the paper's method; <= 0: none, the centred
                                       diffusion of eqs (12) and (16) as printed).  The explicit
@@ -230,7 +239,11 @@ int lbr_init_fields(lbr_ctx* ctx, int32_t level, const double* rho, const double
 
 /* Advances n coarse (level-0) steps: the recursive multilevel cycle of
    Section 2.1, in which level l takes 2^l sub-steps.  Asynchronous on the
-   context's stream. */
+   context's stream, unless the health check of the config is on: then the
+   call waits for its scans at the end and returns LBR_ERR_DIVERGED (density
+   not finite or not positive, or |u| > c_s, anywhere) or LBR_ERR_NEWTON (a
+   non-finite friction velocity), with the first level and cell found in the
+   message; the state is left as the failing steps made it. */
 int lbr_advance(lbr_ctx* ctx, int64_t n_coarse_steps);
 
 /* Waits for the context's stream. */
@@ -301,7 +314,9 @@ int lbr_residual(lbr_ctx* ctx, double* residual);
 
 /* Steps until lbr_residual (evaluated every check_every coarse steps) drops
    below tol or max_steps is reached; returns the steps taken and the last
-   residual.  Returns LBR_ERR_DIVERGED if the state becomes non-finite. */
+   residual.  Returns LBR_ERR_NOT_CONVERGED (steps_done and residual still
+   written) when max_steps is reached first, LBR_ERR_DIVERGED if the state
+   becomes non-finite. */
 int lbr_run_to_steady(lbr_ctx* ctx, double tol, int64_t max_steps, int64_t check_every,
                       int64_t* steps_done, double* residual);
 
@@ -412,8 +427,9 @@ int lbr_batch_advance(lbr_batch* batch, int64_t n_super_steps);
    residual is below tol leaves the launches, so the others run on without its
    cell updates; at return the batch covers every case again.  steps_done[k]
    receives the coarse steps case k took and residual[k] its last residual
-   (arrays of n entries, either may be NULL).  Returns LBR_ERR_DIVERGED if a
-   case's state becomes non-finite. */
+   (arrays of n entries, either may be NULL).  Returns LBR_ERR_NOT_CONVERGED
+   (both arrays still written) when some case has not converged after
+   max_super_steps, LBR_ERR_DIVERGED if a case's state becomes non-finite. */
 int lbr_batch_run_to_steady(lbr_batch* batch, double tol, int64_t max_super_steps, int64_t check_every,
                             int64_t* steps_done, double* residual);
 

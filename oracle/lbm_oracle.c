@@ -67,6 +67,9 @@ static const double WQ[9] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9
 static const int OPP[9] = {0, 2, 1, 4, 3, 6, 5, 8, 7};
 static const int MIRY[9] = {0, 1, 2, 4, 3, 7, 8, 5, 6}; /* reflection c_y -> -c_y */
 #define CS2 (1.0 / 3.0)
+/* Per-cell loops over fewer cells run on one thread: every cell's update is
+   independent, so this changes the timing only, never a result. */
+#define OMP_MIN_CELLS 16384
 
 /* ------------------------------------------------------------------------- */
 /* Analytic SA-consistent wall function, Section 2.2 eqs (21)-(22).           */
@@ -963,7 +966,7 @@ int lbro_init(lbro_sim* s, int32_t level, const double* rho, const double* ux, c
 /* ------------------------------------------------------------------------- */
 static void macros(olevel* L) {
     int n = L->nx * L->ny;
-#pragma omp parallel for
+#pragma omp parallel for if (n > OMP_MIN_CELLS)
     for (int c = 0; c < n; ++c)
         if (L->type[c] == T_FLUID) moments(&L->f[9 * c], L->fx, L->fy, &L->rho[c], &L->ux[c], &L->uy[c]);
 }
@@ -1053,14 +1056,14 @@ static void wall_node(const lbro_sim* s, const olevel* L, obnode* b, double* rho
 }
 
 static void wall_model_level(lbro_sim* s, olevel* L) {
-#pragma omp parallel for schedule(dynamic, 16)
+#pragma omp parallel for schedule(dynamic, 16) if (L->nb > 64)
     for (int k = 0; k < L->nb; ++k) wall_node(s, L, &L->B[k], NULL);
 }
 
 static void collide_level(const lbro_sim* s, olevel* L) {
     int n = L->nx * L->ny;
     double F[2] = {L->fx, L->fy};
-#pragma omp parallel for
+#pragma omp parallel for if (n > OMP_MIN_CELLS)
     for (int c = 0; c < n; ++c) {
         if (L->type[c] != T_FLUID) continue;
         double nut = sa_nut(L->chi[c] * L->nu, L->nu);
@@ -1191,7 +1194,7 @@ static int sa_level(const lbro_sim* s, olevel* L) {
     int n = L->nx * L->ny;
     int err = 0;
     int nxd = dom_nx(s, L->level);
-#pragma omp parallel for reduction(| : err)
+#pragma omp parallel for reduction(| : err) if (n > OMP_MIN_CELLS)
     for (int c = 0; c < n; ++c) {
         L->chin[c] = L->chi[c];
         if (L->type[c] != T_FLUID || s->cfg.sa_mode == LBRO_SA_FROZEN) continue;
@@ -1289,7 +1292,7 @@ static int stream_level(lbro_sim* s, int l) {
     int n = L->nx * L->ny;
     int nxd = dom_nx(s, l);
     int err = 0;
-#pragma omp parallel for reduction(| : err)
+#pragma omp parallel for reduction(| : err) if (n > OMP_MIN_CELLS)
     for (int c = 0; c < n; ++c) {
         unsigned char t = L->type[c];
         int gi = c % L->nx + L->gx0, gj = c / L->nx + L->gy0;

@@ -27,6 +27,7 @@ STORAGE = {"f64": STORE_F64, "f32": STORE_F32, "f16": STORE_F16, "bf16": STORE_B
 # the 16-bit formats with the free-stream storage shift (lbr_config.shift16 = 1)
 SHIFTED = {"f16s": "f16", "bf16s": "bf16", "mixeds": "mixed"}
 FIELD_RHO, FIELD_UX, FIELD_UY, FIELD_CHI, FIELD_NUT, FIELD_TYPE, FIELD_DIST = range(7)
+ERR_DIVERGED, ERR_NEWTON, ERR_NOT_CONVERGED = -5, -8, -9
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
@@ -45,7 +46,7 @@ class lbr_config(C.Structure):
         ("d_wv", C.c_double), ("u_wall", C.c_double * 4),
         ("sponge_width", C.c_double), ("sponge_strength", C.c_double),
         ("ramp_steps", C.c_double), ("ramp_start", C.c_double), ("shift16", C.c_int32),
-        ("sa_mu_cap", C.c_double),
+        ("health_every", C.c_int32), ("sa_mu_cap", C.c_double),
         ("alloc_fn", ALLOC_FN), ("free_fn", FREE_FN), ("alloc_user", C.c_void_p),
         ("stream", C.c_void_p),
     ]
@@ -201,6 +202,7 @@ def make_config(case, storage="f32", stream=None, allocator=None) -> lbr_config:
     c.ramp_start = case.get("ramp_start", 0.0)
     c.shift16 = 1 if shift else int(case.get("shift16", 0))
     c.sa_mu_cap = float(case.get("sa_mu_cap", 0.0))
+    c.health_every = int(case.get("health_every", 0))
     if allocator is not None:
         c.alloc_fn, c.free_fn = allocator.alloc_cb, allocator.free_cb
     c.stream = stream
@@ -326,8 +328,13 @@ class Solver:
         return r.value
 
     def run_to_steady(self, tol, max_steps, check_every=100):
+        """(steps taken, last residual); converged tells whether the residual went
+        below tol within max_steps (LBR_ERR_NOT_CONVERGED otherwise, not raised)."""
         done, r = C.c_int64(), C.c_double()
-        self._check(lib().lbr_run_to_steady(self.h, tol, max_steps, check_every, C.byref(done), C.byref(r)))
+        rc = lib().lbr_run_to_steady(self.h, tol, max_steps, check_every, C.byref(done), C.byref(r))
+        self.converged = rc == 0
+        if rc != ERR_NOT_CONVERGED:
+            self._check(rc)
         return done.value, r.value
 
     def wall_yplus(self, level):
@@ -430,8 +437,10 @@ class Batch:
         """Returns (coarse steps taken per case, last residual per case)."""
         n = len(self.solvers)
         steps, res = (C.c_int64 * n)(), (C.c_double * n)()
-        self._check(lib().lbr_batch_run_to_steady(self.h, float(tol), int(max_super_steps),
-                                                  int(check_every), steps, res))
+        rc = lib().lbr_batch_run_to_steady(self.h, float(tol), int(max_super_steps), int(check_every), steps, res)
+        self.converged = rc == 0
+        if rc != ERR_NOT_CONVERGED:
+            self._check(rc)
         return [int(v) for v in steps], [float(v) for v in res]
 
     def profile(self, enable=True):

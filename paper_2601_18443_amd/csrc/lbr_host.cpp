@@ -109,6 +109,7 @@ struct lbr_ctx {
     double* partial = nullptr;
     int partial_n = 0;
     void* scratch = nullptr;       // device address of the static scratch (lbr_rake_noalloc)
+    int* health = nullptr;         // device result of the health scans: failure bits, level, index, count
     bool built = false;
     std::vector<void*> allocs;
     int64_t resid_steps = 0;
@@ -1137,7 +1138,7 @@ int lbr_create(const lbr_config* cfg, lbr_ctx** out) {
         !(cfg->dx0 > 0) || cfg->storage < 0 || cfg->storage > LBR_STORE_MIXED || cfg->outlet < 0 || cfg->outlet > 2 ||
         cfg->sponge_width < 0 || cfg->sponge_strength < 0 || cfg->sponge_strength > 1 ||
         cfg->ramp_steps < 0 || cfg->ramp_start < 0 || cfg->ramp_start > 1 ||
-        cfg->shift16 < 0 || cfg->shift16 > 1)
+        cfg->shift16 < 0 || cfg->shift16 > 1 || cfg->health_every < 0)
         return LBR_ERR_INVALID_ARG;
     if ((cfg->bc[0] == LBR_BC_PERIODIC) != (cfg->bc[1] == LBR_BC_PERIODIC) ||
         (cfg->bc[2] == LBR_BC_PERIODIC) != (cfg->bc[3] == LBR_BC_PERIODIC) ||
@@ -1320,10 +1321,48 @@ int lbr_init_fields(lbr_ctx* c, int32_t level, const double* rho, const double* 
     return LBR_OK;
 }
 
+static int advance_steps(lbr_ctx* c, int64_t n);
+
+// Health check (lbr_config::health_every): scans of every level's density and
+// velocity and of the wall nodes' friction velocity after every health_every-th
+// coarse step, read back once at the end of the call.
 int lbr_advance(lbr_ctx* c, int64_t n) {
     if (!c) return LBR_ERR_INVALID_ARG;
     if (!c->built) return set_err(c, LBR_ERR_STATE, "lbr_build has not been called");
     if (n < 0) return set_err(c, LBR_ERR_INVALID_ARG, "negative step count");
+    const int64_t every = c->cfg.health_every;
+    if (every <= 0) return advance_steps(c, n);
+    if (!c->health) {
+        c->health = static_cast<int*>(dalloc(c, 4 * sizeof(int)));
+        if (!c->health) return set_err(c, LBR_ERR_OOM, "health check scratch");
+    }
+    HIPCHK(c, launch_health_reset(c->health, c->stream));
+    int64_t k = 0;
+    while (k < n) {
+        const int64_t m = std::min(every - c->step_count % every, n - k);
+        if (int r = advance_steps(c, m)) return r;
+        k += m;
+        if (c->step_count % every) continue;
+        for (Level& L : c->lv) {
+            HIPCHK(c, launch_health(c->prec, L.mac[L.cur], L.owned_dev, (int)L.owned.size(), L.box.plane, L.l,
+                                    c->health, c->stream));
+            HIPCHK(c, launch_health_wall(L.bstate, (int)L.nodes.size(), L.l, c->health, c->stream));
+        }
+    }
+    int h[4] = {0, 0, 0, 0};
+    HIPCHK(c, hipMemcpyAsync(h, c->health, sizeof h, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (h[0] & 1)
+        return set_err(c, LBR_ERR_DIVERGED, "health check after coarse step %lld: %d cells with a non-finite or "
+                       "non-positive density or |u| > c_s (one on level %d, storage index %d)",
+                       (long long)c->step_count, h[3], h[1], h[2]);
+    if (h[0] & 2)
+        return set_err(c, LBR_ERR_NEWTON, "health check after coarse step %lld: non-finite friction velocity "
+                       "on level %d (wall node %d)", (long long)c->step_count, h[1], h[2]);
+    return LBR_OK;
+}
+
+static int advance_steps(lbr_ctx* c, int64_t n) {
     c->ev_used = 0;
     c->prof_launches = 0;
     int64_t k = 0;
@@ -1821,6 +1860,9 @@ int lbr_run_to_steady(lbr_ctx* c, double tol, int64_t max_steps, int64_t check_e
     }
     if (steps_done) *steps_done = done;
     if (residual) *residual = r;
+    if (!(r < tol))
+        return set_err(c, LBR_ERR_NOT_CONVERGED, "residual %.3e after %lld coarse steps (tolerance %.3e)", r,
+                       (long long)done, tol);
     return LBR_OK;
 }
 
@@ -2319,6 +2361,13 @@ int lbr_batch_run_to_steady(lbr_batch* b, double tol, int64_t max_super_steps, i
         if (steps_done) steps_done[k] = b->all[k]->step_count - start[k];
         if (residual) residual[k] = r[k];
     }
+    if (!rc)
+        for (size_t k = 0; k < n; ++k)
+            if (!(r[k] < tol)) {
+                char msg[160];
+                snprintf(msg, sizeof msg, "case %zu: residual %.3e after %lld super steps", k, r[k], (long long)done);
+                return bset_err(b, LBR_ERR_NOT_CONVERGED, msg);
+            }
     return rc;
 }
 

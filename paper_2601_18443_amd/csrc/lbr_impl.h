@@ -197,6 +197,14 @@ hipError_t launch_field(Prec p, const FieldArgs& a, hipStream_t s);
 // dst[k] = src[idx[k]] for the macroscopic / chi planes (CT of precision p)
 hipError_t launch_gather(Prec p, const void* src, const int64_t* idx, int n, double* dst, hipStream_t s);
 hipError_t launch_to_double(Prec p, const void* src, double* dst, long n, hipStream_t s);
+// Health scans (lbr_config::health_every): out[0] |= 1 when a listed cell's density is
+// not finite or not positive or |u| > c_s, |= 2 when a wall node's friction velocity
+// is not finite; out[1], out[2]: level and cell (or wall node) of one failure,
+// out[3]: failing cells counted.  launch_health_reset clears out[0..3].
+hipError_t launch_health_reset(int* out, hipStream_t s);
+hipError_t launch_health(Prec p, const void* mac, const int32_t* list, int n, long plane, int level, int* out,
+                         hipStream_t s);
+hipError_t launch_health_wall(const double* bstate, int nb, int level, int* out, hipStream_t s);
 hipError_t launch_residual(Prec p, const void* mac, double* snap, const int32_t* list, int n,
                            long plane, double area, double* partial, int nblocks, hipStream_t s);
 

@@ -1395,6 +1395,61 @@ hipError_t launch_surface(Prec p, const SurfaceArgs& a, int nb, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Health scans: a cell fails when its density is not finite or not positive or its
+// speed exceeds the lattice sound speed; a wall node when its friction velocity is
+// not finite.  Each failure sets its bit and one (level, index) pair (vector atomics).
+template <class CT>
+__global__ void k_health(const CT* mac, const int32_t* list, int n, long plane, int level, int* out) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const long c = list[k];
+    const double rho = (double)mac[c], ux = (double)mac[plane + c], uy = (double)mac[2 * plane + c];
+    const bool ok = isfinite(rho) && rho > 0.0 && isfinite(ux) && isfinite(uy) && ux * ux + uy * uy <= 1.0 / 3.0;
+    if (!ok) {
+        atomicOr(out, 1);
+        atomicExch(out + 1, level);
+        atomicExch(out + 2, (int)c);
+        atomicAdd(out + 3, 1);
+    }
+}
+
+__global__ void k_health_wall(const double* bstate, int nb, int level, int* out) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nb) return;
+    if (!isfinite(bstate[8 * b])) {
+        atomicOr(out, 2);
+        atomicExch(out + 1, level);
+        atomicExch(out + 2, b);
+    }
+}
+
+__global__ void k_health_reset(int* out) {
+    if (threadIdx.x < 4) out[threadIdx.x] = 0;
+}
+
+hipError_t launch_health_reset(int* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_health_reset, dim3(1), dim3(64), 0, s, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_health(Prec p, const void* mac, const int32_t* list, int n, long plane, int level, int* out,
+                         hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    if (p == P_F64)
+        hipLaunchKernelGGL(k_health<double>, dim3(nblocks(n, 256)), dim3(256), 0, s, (const double*)mac, list, n,
+                           plane, level, out);
+    else
+        hipLaunchKernelGGL(k_health<float>, dim3(nblocks(n, 256)), dim3(256), 0, s, (const float*)mac, list, n,
+                           plane, level, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_health_wall(const double* bstate, int nb, int level, int* out, hipStream_t s) {
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_health_wall, dim3(nblocks(nb, 256)), dim3(256), 0, s, bstate, nb, level, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_residual(Prec p, const void* mac, double* snap, const int32_t* list, int n,
                            long plane, double area, double* partial, int nb, hipStream_t s) {
     if (p == P_F64)
