@@ -191,7 +191,8 @@ typedef struct lbr_level_desc {
 
 /* Number of doubles per wall-node record from lbr_read_wall: gi, gj, IW (x,y),
    normal (x,y), d_WB, number of cut links, u_tau, u_W (x,y), rho_W, |u_Rt|,
-   Cp, Cf, body, chi_B, u_Rt (x,y), q[1..8] (-1: not cut), spare.  Positions
+   Cp, Cf, body, chi_B, u_Rt (x,y), q[1..8] (-1: not cut; directions as in
+   lbr_set_cut_links), spare.  Positions
    and distances are in lattice units of the node's level. */
 #define LBR_WALL_STRIDE 28
 
@@ -215,6 +216,55 @@ int lbr_create(const lbr_config* cfg, lbr_ctx** out);
    body whose signed area is not positive (clockwise); LBR_ERR_STATE after
    lbr_build. */
 int lbr_set_geometry(lbr_ctx* ctx, int32_t n_bodies, const int32_t* n_pts, const double* xy);
+
+/* Number of doubles per record of a precomputed cut-link list: gi, gj, IW
+   (x, y), normal (x, y), d_WB, body, q[1..8] (-1: not cut).  The same
+   quantities as the wall records of lbr_read_wall, in the same units. */
+#define LBR_CUT_STRIDE 16
+
+/* Precomputed link-wise wall data of one level (Section 2.1: the
+   preprocessor's geometry and cut-link list; Section 2.3: per boundary node B
+   the wall point IW, the unit normal into the fluid, the distance d_WB and the
+   wall fraction q of every cut link).  rec holds n records of LBR_CUT_STRIDE
+   doubles, row-major:
+     gi, gj      the node's cell in level-l lattice indices (integral values);
+     IW, normal  in level-l lattice units, |normal| = 1 within 1e-6;
+     d_WB        >= 0, level-l lattice units;
+     body        index of a body of lbr_set_geometry, or -1 / -2 for the
+                 lower / upper wall side of level 0;
+     q[o]        for link o = 1..8, c_1..c_8 = (1,0), (-1,0), (0,1), (0,-1),
+                 (1,1), (-1,-1), (1,-1), (-1,1): the fraction of the link
+                 B -> B + c_o that lies in the fluid, in (0, 1], or exactly -1
+                 where the link is not cut; at least one link per record is
+                 cut.
+   lbr_build then takes these nodes for level l instead of intersecting the
+   links with the polylines; the cell types, the wall-distance field and the
+   surface segments of Cp and Cf still come from the polylines.  The
+   reference-point stencils are derived from IW and the normal as for
+   generated nodes.  Call after lbr_create and before lbr_build; a second call
+   for a level replaces its list, n = 0 withdraws it.  The records are copied.
+   Errors: LBR_ERR_INVALID_ARG for a level outside the config's levels, n < 0,
+   rec NULL with n > 0, or a record that breaks the ranges above (the message
+   names it); LBR_ERR_STATE after lbr_build.  lbr_build returns
+   LBR_ERR_GEOMETRY when a node is not an owned fluid cell of its level or
+   lies next to a level interface, a cell is listed twice, a body index names
+   no body, a reference-point stencil reaches a cell that the level does not
+   own, or a link from an owned
+   fluid cell into a solid cell (or through a wall side of level 0) is not
+   listed as cut: the step would otherwise stream from a solid cell. */
+int lbr_set_cut_links(lbr_ctx* ctx, int32_t level, int64_t n, const double* rec);
+
+/* The lists of lbr_set_cut_links for any number of levels, read from a text
+   file (a case file of an external preprocessor).  Format: '#' starts a
+   comment to the end of its line; tokens are separated by white space; the
+   first two tokens are "lbr-cut-links 1"; then blocks of "level <l> <n>"
+   followed by n x LBR_CUT_STRIDE numbers (strtod syntax; 17 significant
+   digits round-trip a double).  Levels not named keep generated cut links.
+   Errors: LBR_ERR_IO when the file cannot be read; LBR_ERR_INVALID_ARG for a
+   malformed file (wrong header, a bad token, a truncated block, a level
+   listed twice) or a record out of range, with nothing set; LBR_ERR_STATE
+   after lbr_build. */
+int lbr_load_cut_links(lbr_ctx* ctx, const char* path);
 
 /* Builds the multilevel grid, the cut-link list with wall fractions q, the
    wall records (IW, normal, R-stencil weights), the FP64 wall-distance field,

@@ -358,3 +358,52 @@ def channel_initial_velocity(case):
     ux = prof[:, None] + amp * xi_x
     uy = amp * xi_y
     return np.ascontiguousarray(ux), np.ascontiguousarray(uy)
+
+
+# Precomputed cut-link lists: the record layout of both codes' cut-link input
+# (gi, gj, IW x, IW y, normal x, normal y, d_WB, body, q1..q8; q = -1 where a
+# link is not cut) and its text file.
+CUT_STRIDE = 16
+_WALL_COLUMNS = (0, 1, 2, 3, 4, 5, 6, 15) + tuple(range(19, 27))
+
+
+def cut_link_records(wall: np.ndarray) -> np.ndarray:
+    """The cut-link records of a wall-record table (28 columns: gi, gj, IW,
+    normal, d_WB, ..., body in column 15, q1..q8 in columns 19-26)."""
+    return np.ascontiguousarray(np.asarray(wall, dtype=np.float64)[:, _WALL_COLUMNS])
+
+
+def perturbed_cut_links(rec: np.ndarray, seed: int, dq: float = 0.15, q_min: float = 0.05,
+                        d_iw: float = 0.05, d_angle: float = 0.05, d_dwb: float = 0.05) -> np.ndarray:
+    """A seeded stand-in for the output of another preprocessor: every cut link's
+    q moved by up to dq (kept in [q_min, 1]), IW by up to d_iw per coordinate,
+    the normal turned by up to d_angle radians (still a unit vector) and d_WB
+    moved by up to d_dwb (kept >= 0).  Uncut links stay -1."""
+    rng = np.random.default_rng(seed)
+    r = np.array(rec, dtype=np.float64, copy=True)
+    n = len(r)
+    q = r[:, 8:16]
+    cut = q >= 0
+    q[cut] = np.clip(q[cut] + dq * rng.uniform(-1.0, 1.0, int(cut.sum())), q_min, 1.0)
+    r[:, 2:4] += d_iw * rng.uniform(-1.0, 1.0, (n, 2))
+    a = d_angle * rng.uniform(-1.0, 1.0, n)
+    nx, ny = r[:, 4].copy(), r[:, 5].copy()
+    r[:, 4] = np.cos(a) * nx - np.sin(a) * ny
+    r[:, 5] = np.sin(a) * nx + np.cos(a) * ny
+    r[:, 6] = np.maximum(r[:, 6] + d_dwb * rng.uniform(-1.0, 1.0, n), 0.0)
+    return r
+
+
+def write_cut_links(path, lists: dict, comment: str = "") -> None:
+    """Writes {level: (n, CUT_STRIDE) records} as a cut-link file ("lbr-cut-links 1",
+    then "level l n" blocks; 17 significant digits, so every double round-trips)."""
+    with open(path, "w") as fh:
+        if comment:
+            for line in comment.splitlines():
+                fh.write(f"# {line}\n")
+        fh.write("lbr-cut-links 1\n")
+        for level in sorted(lists):
+            rec = np.asarray(lists[level], dtype=np.float64).reshape(-1, CUT_STRIDE)
+            fh.write(f"level {int(level)} {len(rec)}\n")
+            for row in rec:
+                fh.write(" ".join(f"{v:.17g}" for v in row) + "\n")

@@ -18,6 +18,7 @@ _lib = None
 MAX_LEVELS = 12
 WALL_STRIDE = 28
 F_RHO, F_UX, F_UY, F_CHI, F_NUT, F_TYPE, F_DIST = range(7)
+T_INACTIVE, T_FLUID, T_SOLID, T_GHOST, T_COVERED, T_VIRT = range(6)   # values of F_TYPE
 
 
 class Config(C.Structure):
@@ -50,6 +51,8 @@ def lib():
         dp = C.POINTER(C.c_double)
         L.lbro_error.restype = C.c_char_p
         L.lbro_create.argtypes = [C.POINTER(Config), i32, C.POINTER(C.c_int32), dp, C.POINTER(p)]
+        L.lbro_create_with_links.argtypes = [C.POINTER(Config), i32, C.POINTER(C.c_int32), dp, C.c_char_p,
+                                             C.POINTER(p)]
         L.lbro_destroy.argtypes = [p]
         L.lbro_destroy.restype = None
         L.lbro_level_info.argtypes = [p, i32, C.POINTER(C.c_int64)]
@@ -201,9 +204,11 @@ def make_config(case) -> Config:
 
 
 class Sim:
-    """One oracle simulation built from a case dictionary (see lbr_inputs)."""
+    """One oracle simulation built from a case dictionary (see lbr_inputs);
+    cut_links: path of a precomputed cut-link file whose levels replace the
+    polyline intersections (None: all generated)."""
 
-    def __init__(self, case):
+    def __init__(self, case, cut_links=None):
         L = lib()
         self.case = case
         self.cfg = make_config(case)
@@ -212,7 +217,8 @@ class Sim:
         xy = np.ascontiguousarray(np.concatenate(bodies, axis=0) if bodies else np.zeros((1, 2)))
         self._xy = xy
         h = C.c_void_p()
-        if L.lbro_create(C.byref(self.cfg), len(bodies), npts, _dp(xy), C.byref(h)) != 0:
+        path = None if cut_links is None else os.fsencode(cut_links)
+        if L.lbro_create_with_links(C.byref(self.cfg), len(bodies), npts, _dp(xy), path, C.byref(h)) != 0:
             raise RuntimeError("oracle: " + L.lbro_error().decode())
         self.h = h
         self.n_levels = case["n_levels"]

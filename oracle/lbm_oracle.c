@@ -24,6 +24,7 @@
  */
 #include "oracle.h"
 
+#include <ctype.h>
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
@@ -837,8 +838,179 @@ static int build_walls(lbro_sim* s, int l) {
     return 0;
 }
 
+/* ------------------------------------------------------------------------- */
+/* Precomputed cut-link lists (Section 2.1: the preprocessor hands over the    */
+/* geometry and the cut-link list; Section 2.3: per boundary node the wall     */
+/* point, normal, d_WB and the wall fraction q of each cut link).             */
+/* File: "lbr-cut-links 1", then blocks "level l n" of n records of 16 numbers */
+/* (gi gj IWx IWy nx ny d_WB body q1..q8, q = -1 where not cut); '#' starts a  */
+/* comment.                                                                    */
+/* ------------------------------------------------------------------------- */
+#define LINK_REC 16
+
+typedef struct {
+    int64_t n[LBRO_MAX_LEVELS];
+    double* rec[LBRO_MAX_LEVELS];
+    int given[LBRO_MAX_LEVELS];
+} olinks;
+
+static void links_free(olinks* k) {
+    for (int l = 0; l < LBRO_MAX_LEVELS; ++l) free(k->rec[l]);
+}
+
+/* Next white-space separated token, comments skipped; 0 at the end. */
+static int link_token(FILE* f, char* tok, size_t cap) {
+    int ch;
+    for (;;) {
+        ch = fgetc(f);
+        if (ch == EOF) return 0;
+        if (ch == '#') {
+            while (ch != EOF && ch != '\n') ch = fgetc(f);
+            continue;
+        }
+        if (!isspace(ch)) break;
+    }
+    size_t n = 0;
+    while (ch != EOF && !isspace(ch) && ch != '#') {
+        if (n + 1 < cap) tok[n++] = (char)ch;
+        ch = fgetc(f);
+    }
+    if (ch == '#') ungetc(ch, f);
+    tok[n] = 0;
+    return 1;
+}
+
+static int link_number(FILE* f, double* v) {
+    char tok[128], *end;
+    if (!link_token(f, tok, sizeof tok)) return 0;
+    *v = strtod(tok, &end);
+    return *end == 0 && end != tok;
+}
+
+static int read_links(const char* path, int nl, olinks* k) {
+    memset(k, 0, sizeof *k);
+    FILE* f = fopen(path, "r");
+    if (!f) return fail("cannot open %s", path);
+    char tok[128];
+    if (!link_token(f, tok, sizeof tok) || strcmp(tok, "lbr-cut-links") ||
+        !link_token(f, tok, sizeof tok) || strcmp(tok, "1")) {
+        fclose(f);
+        return fail("%s: not a cut-link file", path);
+    }
+    while (link_token(f, tok, sizeof tok)) {
+        double lv, cnt;
+        if (strcmp(tok, "level") || !link_number(f, &lv) || !link_number(f, &cnt) || lv != floor(lv) ||
+            lv < 0 || lv >= nl || cnt != floor(cnt) || cnt < 0 || k->given[(int)lv]) {
+            fclose(f);
+            links_free(k);
+            return fail("%s: bad level block", path);
+        }
+        int l = (int)lv;
+        k->given[l] = 1;
+        k->n[l] = (int64_t)cnt;
+        k->rec[l] = malloc((size_t)(k->n[l] > 0 ? k->n[l] : 1) * LINK_REC * sizeof(double));
+        for (int64_t j = 0; j < k->n[l] * LINK_REC; ++j)
+            if (!link_number(f, &k->rec[l][j])) {
+                fclose(f);
+                links_free(k);
+                return fail("%s: level %d: truncated or not a number", path, l);
+            }
+    }
+    fclose(f);
+    return 0;
+}
+
+/* True where the link from (gi, gj) along c_o ends in a solid cell or crosses a
+   channel wall of level 0 (the links that must be cut). */
+static int link_blocked(const lbro_sim* s, const olevel* L, int l, int gi, int gj, int o) {
+    int ti = gi + CX[o], tj = gj + CY[o];
+    if (l == 0 && ((tj < 0 && s->cfg.bc[2] == LBRO_BC_WALL) ||
+                   (tj >= dom_ny(s, l) && s->cfg.bc[3] == LBRO_BC_WALL)))
+        return 1;
+    if (s->cfg.bc[0] == LBRO_BC_PERIODIC && l == 0) ti = (ti % dom_nx(s, l) + dom_nx(s, l)) % dom_nx(s, l);
+    return type_at(L, ti, tj) == T_SOLID;
+}
+
+/* Boundary nodes of level l taken from a precomputed list instead of the
+   polyline intersections of build_walls. */
+static int walls_from_links(lbro_sim* s, int l, const double* rec, int64_t n) {
+    olevel* L = &s->lv[l];
+    obnode* B = calloc((size_t)(n > 0 ? n : 1), sizeof(obnode));
+    int64_t ncut = 0;
+    for (int64_t r = 0; r < n; ++r) {
+        const double* p = rec + LINK_REC * r;
+        obnode* b = &B[r];
+        for (int j = 0; j < LINK_REC; ++j)
+            if (!isfinite(p[j])) { free(B); return fail("level %d record %lld: not finite", l, (long long)r); }
+        if (p[0] != floor(p[0]) || p[1] != floor(p[1]) || p[7] != floor(p[7])) {
+            free(B);
+            return fail("level %d record %lld: gi, gj, body must be integers", l, (long long)r);
+        }
+        b->gi = (int)p[0]; b->gj = (int)p[1]; b->body = (int)p[7];
+        b->cell = idx(L, b->gi, b->gj);
+        if (b->cell < 0 || L->type[b->cell] != T_FLUID || L->bid[b->cell] >= 0) {
+            free(B);
+            return fail("level %d record %lld: (%d, %d) is not a fluid cell or is listed twice", l,
+                        (long long)r, b->gi, b->gj);
+        }
+        int near_iface = L->iface[b->cell];
+        for (int o = 1; o < 9; ++o)
+            if (type_at(L, b->gi + CX[o], b->gj + CY[o]) == T_GHOST) near_iface = 1;
+        if (near_iface) {
+            free(B);
+            return fail("level %d record %lld: (%d, %d) lies next to a level interface", l, (long long)r,
+                        b->gi, b->gj);
+        }
+        int body_ok = (b->body >= 0) ? (s->cfg.body_mode != 1 && b->body < s->nbody)
+                                     : (l == 0 && ((b->body == -1 && s->cfg.bc[2] == LBRO_BC_WALL) ||
+                                                   (b->body == -2 && s->cfg.bc[3] == LBRO_BC_WALL)));
+        double nn = sqrt(p[4] * p[4] + p[5] * p[5]);
+        if (!body_ok || fabs(nn - 1.0) > 1e-6 || p[6] < 0.0) {
+            free(B);
+            return fail("level %d record %lld: bad body, normal or d_WB", l, (long long)r);
+        }
+        b->iw[0] = p[2]; b->iw[1] = p[3];
+        b->nrm[0] = p[4]; b->nrm[1] = p[5];
+        b->dwb = p[6];
+        b->q[0] = -1.0;
+        int cut = 0;
+        for (int o = 1; o < 9; ++o) {
+            double q = p[7 + o];
+            if (q != -1.0 && !(q > 0.0 && q <= 1.0)) {
+                free(B);
+                return fail("level %d record %lld: q%d outside (0, 1]", l, (long long)r, o);
+            }
+            b->q[o] = q;
+            if (q > 0.0) cut++;
+        }
+        if (!cut) { free(B); return fail("level %d record %lld: no cut link", l, (long long)r); }
+        ncut += cut;
+        L->bid[b->cell] = (int)r;
+    }
+    int n_cells = L->nx * L->ny;
+    for (int c = 0; c < n_cells; ++c) {
+        if (L->type[c] != T_FLUID) continue;
+        int gi = c % L->nx + L->gx0, gj = c / L->nx + L->gy0;
+        for (int o = 1; o < 9; ++o)
+            if (link_blocked(s, L, l, gi, gj, o) && (L->bid[c] < 0 || B[L->bid[c]].q[o] < 0.0)) {
+                free(B);
+                return fail("level %d: link from (%d, %d) along c_%d reaches a wall but is not listed", l, gi,
+                            gj, o);
+            }
+    }
+    L->nb = (int)n;
+    L->B = B;
+    L->n_cut = ncut;
+    return 0;
+}
+
 int lbro_create(const lbro_config* cfg, int32_t n_bodies, const int32_t* n_pts, const double* xy,
                 lbro_sim** out) {
+    return lbro_create_with_links(cfg, n_bodies, n_pts, xy, NULL, out);
+}
+
+int lbro_create_with_links(const lbro_config* cfg, int32_t n_bodies, const int32_t* n_pts,
+                           const double* xy, const char* links_path, lbro_sim** out) {
     *out = NULL;
     if (!cfg || cfg->n_levels < 1 || cfg->n_levels > LBRO_MAX_LEVELS || cfg->nx0 < 4 ||
         cfg->ny0 < 4 || !(cfg->dx0 > 0.0) || cfg->outlet < 0 || cfg->outlet > 2 ||
@@ -850,6 +1022,9 @@ int lbro_create(const lbro_config* cfg, int32_t n_bodies, const int32_t* n_pts, 
         return fail("periodic boundaries must come in pairs");
     if (cfg->bc[0] == LBRO_BC_WALL || cfg->bc[1] == LBRO_BC_WALL)
         return fail("wall boundaries are supported on the y sides only");
+    olinks lk;
+    memset(&lk, 0, sizeof lk);
+    if (links_path && read_links(links_path, cfg->n_levels, &lk)) return -1;
     lbro_sim* s = calloc(1, sizeof *s);
     s->cfg = *cfg;
     s->nl = cfg->n_levels;
@@ -858,13 +1033,13 @@ int lbro_create(const lbro_config* cfg, int32_t n_bodies, const int32_t* n_pts, 
     s->u_ref = (cfg->u_ref > 0.0) ? cfg->u_ref : cfg->mach * sqrt(CS2);
     s->nu0 = (cfg->nu0 > 0.0) ? cfg->nu0
                               : s->u_ref * (cfg->ref_length / cfg->dx0) / cfg->reynolds;
-    if (!(s->nu0 > 0.0)) { free(s); return fail("viscosity must be positive"); }
+    if (!(s->nu0 > 0.0)) { free(s); links_free(&lk); return fail("viscosity must be positive"); }
     s->nbody = n_bodies;
     s->npts = calloc(n_bodies > 0 ? n_bodies : 1, sizeof(int));
     s->poly = calloc(n_bodies > 0 ? n_bodies : 1, sizeof(double*));
     const double* p = xy;
     for (int b = 0; b < n_bodies; ++b) {
-        if (n_pts[b] < 3) { lbro_destroy(s); return fail("body %d has fewer than 3 points", b); }
+        if (n_pts[b] < 3) { lbro_destroy(s); links_free(&lk); return fail("body %d has fewer than 3 points", b); }
         s->npts[b] = n_pts[b];
         s->poly[b] = malloc(2 * n_pts[b] * sizeof(double));
         for (int k = 0; k < n_pts[b]; ++k) {
@@ -876,8 +1051,8 @@ int lbro_create(const lbro_config* cfg, int32_t n_bodies, const int32_t* n_pts, 
     s->wall_lat[0] = (cfg->wall_y[0] - cfg->origin[1]) / cfg->dx0;
     s->wall_lat[1] = (cfg->wall_y[1] - cfg->origin[1]) / cfg->dx0;
     for (int l = 0; l < s->nl; ++l)
-        if (build_level(s, l)) { lbro_destroy(s); return -1; }
-    if (check_nesting(s)) { lbro_destroy(s); return -1; }
+        if (build_level(s, l)) { lbro_destroy(s); links_free(&lk); return -1; }
+    if (check_nesting(s)) { lbro_destroy(s); links_free(&lk); return -1; }
     for (int l = 0; l < s->nl; ++l) {
         olevel* L = &s->lv[l];
         int n = L->nx * L->ny;
@@ -900,7 +1075,9 @@ int lbro_create(const lbro_config* cfg, int32_t n_bodies, const int32_t* n_pts, 
             int gi = c % L->nx + L->gx0, gj = c / L->nx + L->gy0;
             L->d[c] = (L->type[c] == T_FLUID) ? wall_dist(s, L, gi, gj) : 0.0;
         }
-        if (build_walls(s, l)) { lbro_destroy(s); return -1; }
+        int wr = (lk.given[l] && lk.n[l] > 0) ? walls_from_links(s, l, lk.rec[l], lk.n[l])
+                                              : build_walls(s, l);
+        if (wr) { lbro_destroy(s); links_free(&lk); return -1; }
         for (int k = 0; k < L->nb; ++k) {
             /* reference stencils must lie in owned cells of this level */
             obnode* b = &L->B[k];
@@ -914,12 +1091,13 @@ int lbro_create(const lbro_config* cfg, int32_t n_bodies, const int32_t* n_pts, 
                     unsigned char t = type_at(L, gi, gj);
                     int outside = (l == 0) && (gj < 0 || gj >= dom_ny(s, 0));
                     if (!outside && t != T_FLUID && t != T_SOLID) {
-                        lbro_destroy(s);
+                        lbro_destroy(s); links_free(&lk);
                         return fail("level %d: wall stencil reaches a non-owned cell", l);
                     }
                 }
         }
     }
+    links_free(&lk);
     /* default initial state: uniform reference flow (at rest under a start-up ramp) */
     for (int l = 0; l < s->nl; ++l) lbro_init(s, l, NULL, NULL, NULL, NULL);
     *out = s;

@@ -82,6 +82,14 @@ const char* lbro_error(void);
 
 int  lbro_create(const lbro_config* cfg, int32_t n_bodies, const int32_t* n_pts,
                  const double* xy, lbro_sim** out);
+/* The same with the boundary nodes of some levels read from a precomputed
+   cut-link file (links_path; NULL: none), in place of the polyline
+   intersections (Section 2.1: the preprocessor's cut-link list; Section 2.3:
+   the link-wise wall data).  Format: "lbr-cut-links 1", then blocks
+   "level l n" of n records gi gj IWx IWy nx ny d_WB body q1..q8 (q = -1: not
+   cut); '#' starts a comment.  A block with n = 0 keeps the generated nodes. */
+int  lbro_create_with_links(const lbro_config* cfg, int32_t n_bodies, const int32_t* n_pts,
+                            const double* xy, const char* links_path, lbro_sim** out);
 void lbro_destroy(lbro_sim* s);
 /* info: gx0, gy0, nx, ny (I/O box: bounding box of owned and ghost cells, in
    global level-l cell indices), n_fluid, n_bnodes, n_cut_links, n_ghost */

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "liblbr.so")
 ABI_VERSION = 5
 MAX_LEVELS = 12
 WALL_STRIDE = 28
+CUT_STRIDE = 16
 RAKE_NOALLOC_MAX = 16384
 
 STORE_F64, STORE_F32, STORE_F16, STORE_BF16, STORE_MIXED = 0, 1, 2, 3, 4
@@ -27,7 +28,9 @@ STORAGE = {"f64": STORE_F64, "f32": STORE_F32, "f16": STORE_F16, "bf16": STORE_B
 # the 16-bit formats with the free-stream storage shift (lbr_config.shift16 = 1)
 SHIFTED = {"f16s": "f16", "bf16s": "bf16", "mixeds": "mixed"}
 FIELD_RHO, FIELD_UX, FIELD_UY, FIELD_CHI, FIELD_NUT, FIELD_TYPE, FIELD_DIST = range(7)
+ERR_INVALID_ARG, ERR_GEOMETRY, ERR_STATE, ERR_IO = -1, -4, -6, -7
 ERR_DIVERGED, ERR_NEWTON, ERR_NOT_CONVERGED = -5, -8, -9
+CELL_INACTIVE, CELL_FLUID, CELL_SOLID, CELL_GHOST, CELL_COVERED = range(5)   # values of FIELD_TYPE
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
@@ -75,6 +78,8 @@ def lib():
         p, i32, i64, dp = C.c_void_p, C.c_int32, C.c_int64, C.POINTER(C.c_double)
         L.lbr_create.argtypes = [C.POINTER(lbr_config), C.POINTER(p)]
         L.lbr_set_geometry.argtypes = [p, i32, C.POINTER(C.c_int32), dp]
+        L.lbr_set_cut_links.argtypes = [p, i32, i64, dp]
+        L.lbr_load_cut_links.argtypes = [p, C.c_char_p]
         L.lbr_build.argtypes = [p]
         L.lbr_level_info.argtypes = [p, i32, C.POINTER(lbr_level_desc)]
         L.lbr_init_fields.argtypes = [p, i32, dp, dp, dp, dp]
@@ -210,9 +215,12 @@ def make_config(case, storage="f32", stream=None, allocator=None) -> lbr_config:
 
 
 class Solver:
-    """One liblbr context: lbr_create + lbr_set_geometry + lbr_build from a case dict."""
+    """One liblbr context: lbr_create + lbr_set_geometry (+ lbr_load_cut_links or
+    lbr_set_cut_links) + lbr_build from a case dict.  cut_links: None (cut links
+    from the polylines), the path of a cut-link file, or {level: (n, CUT_STRIDE)
+    array} of precomputed records."""
 
-    def __init__(self, case, storage="f32", device="cuda:0", use_torch_memory=True):
+    def __init__(self, case, storage="f32", device="cuda:0", use_torch_memory=True, cut_links=None):
         import torch
         L = lib()
         if not torch.cuda.is_available():
@@ -234,6 +242,12 @@ class Solver:
         npts = (C.c_int32 * max(1, len(bodies)))(*[len(b) for b in bodies])
         xy = np.ascontiguousarray(np.concatenate(bodies, 0) if bodies else np.zeros((1, 2)))
         self._check(L.lbr_set_geometry(self.h, len(bodies), npts, _dp(xy)))
+        if isinstance(cut_links, (str, os.PathLike)):
+            self._check(L.lbr_load_cut_links(self.h, os.fsencode(cut_links)))
+        elif cut_links is not None:
+            for level, rec in cut_links.items():
+                rec = np.ascontiguousarray(rec, dtype=np.float64).reshape(-1, CUT_STRIDE)
+                self._check(L.lbr_set_cut_links(self.h, int(level), rec.shape[0], _dp(rec)))
         self._check(L.lbr_build(self.h))
         self.n_levels = case["n_levels"]
 

@@ -4,6 +4,8 @@
 #include "lbr_impl.h"
 
 #include <algorithm>
+#include <cctype>
+#include <cstdlib>
 #include <new>
 #include <cmath>
 #include <cstdarg>
@@ -102,6 +104,9 @@ struct lbr_ctx {
     std::vector<int> npts, off;
     double wall_lat[2] = {0, 0};
     std::vector<Level> lv;
+    // precomputed cut-link lists (lbr_set_cut_links), LBR_CUT_STRIDE doubles per
+    // node; an empty list: the level's cut links come from the polylines
+    std::vector<double> cut_in[LBR_MAX_LEVELS];
     int wall_level = -1;
     std::vector<SurfaceBody> surf;
     double* surf_cp = nullptr;
@@ -507,6 +512,104 @@ int build_walls(lbr_ctx* c, Level& L, const std::vector<double>& seg) {
         L.bidx[k] = (int32_t)L.nodes.size();
         L.flag[k] |= F_WALL;
         L.nodes.push_back(nd);
+    }
+    return 0;
+}
+
+// Range checks of one record of a precomputed cut-link list (lbr_set_cut_links);
+// false with the reason in msg.
+bool cut_record_ok(const double* p, char* msg, size_t len) {
+    static const char* name[LBR_CUT_STRIDE] = {"gi", "gj", "IW x", "IW y", "normal x", "normal y", "d_WB",
+                                               "body", "q1", "q2", "q3", "q4", "q5", "q6", "q7", "q8"};
+    for (int j = 0; j < LBR_CUT_STRIDE; ++j)
+        if (!std::isfinite(p[j])) { snprintf(msg, len, "%s is not finite", name[j]); return false; }
+    for (int j : {0, 1, 7})
+        if (p[j] != std::floor(p[j]) || std::fabs(p[j]) > (double)(1 << 30)) {
+            snprintf(msg, len, "%s = %g is not an integer in range", name[j], p[j]);
+            return false;
+        }
+    if (p[7] < -2.0) { snprintf(msg, len, "body = %g is below -2", p[7]); return false; }
+    const double nn = std::hypot(p[4], p[5]);
+    if (std::fabs(nn - 1.0) > 1e-6) { snprintf(msg, len, "|normal| = %.9g is not 1", nn); return false; }
+    if (p[6] < 0.0) { snprintf(msg, len, "d_WB = %g is negative", p[6]); return false; }
+    int cut = 0;
+    for (int o = 1; o < 9; ++o) {
+        const double q = p[7 + o];
+        if (q == -1.0) continue;
+        if (!(q > 0.0 && q <= 1.0)) {
+            snprintf(msg, len, "q%d = %g is neither in (0, 1] nor -1", o, q);
+            return false;
+        }
+        cut++;
+    }
+    if (!cut) { snprintf(msg, len, "no link is cut"); return false; }
+    return true;
+}
+
+// Wall nodes of one level from a precomputed cut-link list (lbr_set_cut_links;
+// records already range-checked): the records take the place of the polyline
+// intersections of build_walls, and are checked against the level's cells.
+int walls_from_list(lbr_ctx* c, Level& L, const std::vector<double>& rec) {
+    const lbr_config& cfg = c->cfg;
+    const int nyd = cfg.ny0 << L.l, nxd = cfg.nx0 << L.l;
+    const bool perx = cfg.bc[0] == LBR_BC_PERIODIC;
+    const int nbody = cfg.body_mode == LBR_BODY_SOLID ? (int)c->npts.size() : 0;
+    const size_t n = rec.size() / LBR_CUT_STRIDE;
+    L.nodes.clear();
+    L.n_cut = 0;
+    for (size_t r = 0; r < n; ++r) {
+        const double* p = &rec[r * LBR_CUT_STRIDE];
+        Node nd{};
+        nd.gi = (int)p[0]; nd.gj = (int)p[1];
+        const long k = L.idx(nd.gi, nd.gj);
+        if (k < 0 || (L.flag[k] & F_TYPE) != T_FLUID)
+            return set_err(c, LBR_ERR_GEOMETRY, "level %d: cut-link record %zu: cell (%d, %d) is not an owned "
+                           "fluid cell", L.l, r, nd.gi, nd.gj);
+        if (L.bidx[k] >= 0)
+            return set_err(c, LBR_ERR_GEOMETRY, "level %d: cut-link record %zu: cell (%d, %d) is listed twice",
+                           L.l, r, nd.gi, nd.gj);
+        // the boundary-node update pulls from owned cells only (as generated
+        // nodes, which the grid keeps away from level interfaces)
+        if (L.flag[k] & (F_NEARGHOST | F_IFACE))
+            return set_err(c, LBR_ERR_GEOMETRY, "level %d: cut-link record %zu: cell (%d, %d) lies next to a "
+                           "level interface", L.l, r, nd.gi, nd.gj);
+        nd.body = (int)p[7];
+        const bool body_ok = nd.body >= 0 ? nd.body < nbody
+                           : L.l == 0 && ((nd.body == -1 && cfg.bc[2] == LBR_BC_WALL) ||
+                                          (nd.body == -2 && cfg.bc[3] == LBR_BC_WALL));
+        if (!body_ok)
+            return set_err(c, LBR_ERR_GEOMETRY, "level %d: cut-link record %zu: body %d names no body or wall "
+                           "side of this level", L.l, r, nd.body);
+        nd.cell = k;
+        nd.iw[0] = p[2]; nd.iw[1] = p[3];
+        nd.nrm[0] = p[4]; nd.nrm[1] = p[5];
+        nd.dwb = p[6];
+        nd.q[0] = -1.0;
+        for (int o = 1; o < 9; ++o) {
+            nd.q[o] = p[7 + o];
+            if (nd.q[o] >= 0.0) L.n_cut++;
+        }
+        L.bidx[k] = (int32_t)L.nodes.size();
+        L.flag[k] |= F_WALL;
+        L.nodes.push_back(nd);
+    }
+    // every link that reaches a solid cell or crosses a wall side must be cut:
+    // the step would otherwise stream from a solid cell
+    for (int32_t k : L.owned) {
+        const int gx = (int)(k % L.box.pitch) + L.box.gx0, gy = (int)(k / L.box.pitch) + L.box.gy0;
+        for (int o = 1; o < 9; ++o) {
+            const int tx = gx + CXH[o], ty = gy + CYH[o];
+            bool solid;
+            if (L.l == 0 && ((ty < 0 && cfg.bc[2] == LBR_BC_WALL) || (ty >= nyd && cfg.bc[3] == LBR_BC_WALL))) {
+                solid = true;
+            } else {
+                const int txx = (L.l == 0 && perx) ? ((tx % nxd) + nxd) % nxd : tx;
+                solid = L.type_at(txx, ty) == T_SOLID;
+            }
+            if (solid && (L.bidx[k] < 0 || L.nodes[L.bidx[k]].q[o] < 0.0))
+                return set_err(c, LBR_ERR_GEOMETRY, "level %d: the link from cell (%d, %d) along c_%d reaches a "
+                               "solid cell or a wall side but is not a cut link of the list", L.l, gx, gy, o);
+        }
     }
     return 0;
 }
@@ -1237,6 +1340,98 @@ int lbr_set_geometry(lbr_ctx* c, int32_t n_bodies, const int32_t* n_pts, const d
     return LBR_OK;
 }
 
+int lbr_set_cut_links(lbr_ctx* c, int32_t level, int64_t n, const double* rec) {
+    if (!c) return LBR_ERR_INVALID_ARG;
+    if (c->built) return set_err(c, LBR_ERR_STATE, "cut-link lists must be set before lbr_build");
+    if (level < 0 || level >= c->cfg.n_levels)
+        return set_err(c, LBR_ERR_INVALID_ARG, "level %d outside 0..%d", level, c->cfg.n_levels - 1);
+    if (n < 0 || n > ((int64_t)1 << 28) || (n > 0 && !rec))
+        return set_err(c, LBR_ERR_INVALID_ARG, "invalid cut-link list arguments");
+    char msg[200];
+    for (int64_t r = 0; r < n; ++r)
+        if (!cut_record_ok(rec + r * LBR_CUT_STRIDE, msg, sizeof msg))
+            return set_err(c, LBR_ERR_INVALID_ARG, "level %d, cut-link record %lld: %s", level, (long long)r, msg);
+    c->cut_in[level].assign(rec, rec + n * LBR_CUT_STRIDE);
+    return LBR_OK;
+}
+
+int lbr_load_cut_links(lbr_ctx* c, const char* path) {
+    if (!c || !path) return LBR_ERR_INVALID_ARG;
+    if (c->built) return set_err(c, LBR_ERR_STATE, "cut-link lists must be set before lbr_build");
+    FILE* fp = fopen(path, "rb");
+    if (!fp) return set_err(c, LBR_ERR_IO, "cannot open %s", path);
+    std::string text;
+    char buf[1 << 16];
+    size_t got;
+    while ((got = fread(buf, 1, sizeof buf, fp)) > 0) text.append(buf, got);
+    const bool failed = ferror(fp) != 0;
+    fclose(fp);
+    if (failed) return set_err(c, LBR_ERR_IO, "cannot read %s", path);
+    // white-space separated tokens; '#' comments to the end of the line
+    size_t i = 0;
+    int line = 1;
+    std::string tok;
+    auto next = [&]() -> bool {
+        for (;;) {
+            while (i < text.size() && std::isspace((unsigned char)text[i])) {
+                if (text[i] == '\n') ++line;
+                ++i;
+            }
+            if (i < text.size() && text[i] == '#') {
+                while (i < text.size() && text[i] != '\n') ++i;
+                continue;
+            }
+            break;
+        }
+        if (i >= text.size()) return false;
+        size_t j = i;
+        while (j < text.size() && !std::isspace((unsigned char)text[j]) && text[j] != '#') ++j;
+        tok.assign(text, i, j - i);
+        i = j;
+        return true;
+    };
+    auto number = [&](double* v) -> bool {
+        tok.clear();
+        if (!next()) return false;
+        char* end = nullptr;
+        *v = std::strtod(tok.c_str(), &end);
+        return end && *end == 0;
+    };
+    if (!next() || tok != "lbr-cut-links" || !next() || tok != "1")
+        return set_err(c, LBR_ERR_INVALID_ARG, "%s: not a cut-link file (header \"lbr-cut-links 1\")", path);
+    std::vector<double> lists[LBR_MAX_LEVELS];
+    bool seen[LBR_MAX_LEVELS] = {};
+    char msg[200];
+    while (next()) {
+        if (tok != "level")
+            return set_err(c, LBR_ERR_INVALID_ARG, "%s:%d: expected \"level\", found \"%s\"", path, line, tok.c_str());
+        double lv = -1, cnt = -1;
+        if (!number(&lv) || lv != std::floor(lv) || lv < 0 || lv >= c->cfg.n_levels)
+            return set_err(c, LBR_ERR_INVALID_ARG, "%s:%d: bad level", path, line);
+        if (!number(&cnt) || cnt != std::floor(cnt) || cnt < 0 || cnt > (double)(1 << 28))
+            return set_err(c, LBR_ERR_INVALID_ARG, "%s:%d: bad record count", path, line);
+        const int l = (int)lv;
+        if (seen[l]) return set_err(c, LBR_ERR_INVALID_ARG, "%s:%d: level %d listed twice", path, line, l);
+        seen[l] = true;
+        const size_t nrec = (size_t)cnt;
+        lists[l].resize(nrec * LBR_CUT_STRIDE);
+        for (size_t k = 0; k < lists[l].size(); ++k)
+            if (!number(&lists[l][k])) {
+                if (tok.empty())
+                    return set_err(c, LBR_ERR_INVALID_ARG, "%s: level %d: truncated after %zu of %zu values",
+                                   path, l, k, lists[l].size());
+                return set_err(c, LBR_ERR_INVALID_ARG, "%s:%d: level %d: \"%s\" is not a number", path, line, l,
+                               tok.c_str());
+            }
+        for (size_t r = 0; r < nrec; ++r)
+            if (!cut_record_ok(&lists[l][r * LBR_CUT_STRIDE], msg, sizeof msg))
+                return set_err(c, LBR_ERR_INVALID_ARG, "%s: level %d, cut-link record %zu: %s", path, l, r, msg);
+    }
+    for (int l = 0; l < LBR_MAX_LEVELS; ++l)
+        if (seen[l]) c->cut_in[l] = std::move(lists[l]);
+    return LBR_OK;
+}
+
 int lbr_build(lbr_ctx* c) {
     if (!c) return LBR_ERR_INVALID_ARG;
     if (c->built) return set_err(c, LBR_ERR_STATE, "already built");
@@ -1260,8 +1455,10 @@ int lbr_build(lbr_ctx* c) {
     if (int r = build_levels(c, poly_dev, off_dev)) return r;
     if (int r = check_levels(c)) return r;
     for (Level& L : c->lv) finish_level(c, L);
-    for (Level& L : c->lv)
-        if (int r = build_walls(c, L, seg)) return r;
+    for (Level& L : c->lv) {
+        const std::vector<double>& given = c->cut_in[L.l];
+        if (int r = given.empty() ? build_walls(c, L, seg) : walls_from_list(c, L, given)) return r;
+    }
     for (Level& L : c->lv) {
         // a tile is addressed by 15-bit column and row indices (for every tile
         // height the tuner may pick)

@@ -13,6 +13,17 @@ def gpu_solver(case, storage):
     return P.Solver(case, storage=storage)
 
 
+def gpu_solver_links(case, storage, cut_links):
+    """A library context whose cut links come from a file path or {level: records}."""
+    import paper_2601_18443_amd as P
+    return P.Solver(case, storage=storage, cut_links=cut_links)
+
+
+def dptr(a):
+    import ctypes as C
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
 def channel_init(case, sims):
     ux, uy = LI.channel_initial_velocity(case)
     rho = np.ones_like(ux)

@@ -159,6 +159,74 @@ def test_set_geometry_checks_the_polylines_on_the_host():
     assert set_geo(bad)[0] == -4
 
 
+def _cut_record(**kw):
+    """One valid cut-link record (gi, gj, IW, normal, d_WB, body, q1..q8)."""
+    import numpy as np
+    r = np.array([10, 3, 10.5, 2.9, 0.0, 1.0, 0.6, 0] + [-1.0] * 8)
+    r[8 + 3] = 0.6                                  # q4: the link along (0, -1)
+    for k, v in kw.items():
+        r[int(k[1:])] = v
+    return r
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="liblbr.so not built")
+def test_cut_link_input_checks_its_records_on_the_host(tmp_path):
+    """lbr_set_cut_links and lbr_load_cut_links are host work: they range-check
+    every record (finite, integral indices and body, a unit normal, d_WB >= 0,
+    q in (0, 1] or -1, at least one cut link) and refuse malformed files with
+    nothing set, before any device call."""
+    import numpy as np
+    import paper_2601_18443_amd as P
+    import lbr_inputs as LI
+    L = P.lib()
+    case = LI.case_airfoil_small()
+    cfg = P.make_config(case, "f32")
+    h = ctypes.c_void_p()
+    assert L.lbr_create(ctypes.byref(cfg), ctypes.byref(h)) == 0
+    dp = ctypes.POINTER(ctypes.c_double)
+
+    def put(level, rows):
+        a = np.ascontiguousarray(np.atleast_2d(rows), dtype=np.float64)
+        rc = L.lbr_set_cut_links(h, level, len(a), a.ctypes.data_as(dp))
+        return rc, L.lbr_last_error(h).decode()
+
+    try:
+        assert put(2, _cut_record())[0] == 0
+        assert put(2, np.zeros((0, 16)))[0] == 0                        # withdraws the list
+        for bad, word in ((_cut_record(c0=10.5), "gi"), (_cut_record(c7=-3), "body"),
+                          (_cut_record(c4=0.5), "normal"), (_cut_record(c6=-0.1), "d_WB"),
+                          (_cut_record(c11=0.0), "q4"), (_cut_record(c11=1.25), "q4"),
+                          (_cut_record(c11=-0.5), "q4"), (_cut_record(c11=-1.0), "no link"),
+                          (_cut_record(c3=np.inf), "not finite")):
+            rc, msg = put(2, bad)
+            assert rc == -1 and word in msg, (rc, msg)
+        assert put(3, _cut_record())[0] == -1                           # 3 levels: 0..2
+        assert put(-1, _cut_record())[0] == -1
+        assert L.lbr_set_cut_links(h, 2, 1, None) == -1
+        # files
+        good = tmp_path / "good.cut"
+        LI.write_cut_links(good, {2: np.stack([_cut_record(), _cut_record(c0=11)])}, comment="two nodes")
+        assert L.lbr_load_cut_links(h, str(good).encode()) == 0
+        text = open(good).read()
+        for name, body, code, word in (
+                ("missing", None, -7, "cannot open"),
+                ("header", "lbr-cut-links 2\n", -1, "header"),
+                ("keyword", "lbr-cut-links 1\nlevels 2 1\n", -1, "expected"),
+                ("level", "lbr-cut-links 1\nlevel 9 0\n", -1, "bad level"),
+                ("twice", "lbr-cut-links 1\nlevel 2 0\nlevel 2 0\n", -1, "twice"),
+                ("truncated", text[: len(text) - 12], -1, "truncated"),
+                ("token", text.replace(" 0.59999999999999998", " 0.6x", 1), -1, "not a number"),
+                ("range", text.replace("-1 -1 -1 -1", "-1 -1 -1 7", 1), -1, "q")):
+            p = tmp_path / (name + ".cut")
+            if body is not None:
+                open(p, "w").write(body)
+            rc = L.lbr_load_cut_links(h, str(p).encode())
+            msg = L.lbr_last_error(h).decode()
+            assert rc == code and word in msg, (name, rc, msg)
+    finally:
+        L.lbr_destroy(h)
+
+
 C_CLIENT = r"""
 #include "lbr.h"
 #include <stdio.h>
