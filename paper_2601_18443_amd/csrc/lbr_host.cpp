@@ -19,6 +19,12 @@ using namespace lbr;
 namespace {
 
 constexpr int G = 2;   // guard ring of every storage box
+// the restriction reads each 2 x 2 block from the LDS rows and columns of its
+// lower-left cell and the next ones: block anchors must sit at even local
+// coordinates (even box origins, even tile heights)
+static_assert(G % 2 == 0, "storage boxes keep 2 x 2 blocks aligned");
+static_assert(TILE_X % 2 == 0 && TILE_YS[0] % 2 == 0 && TILE_YS[1] % 2 == 0 && TILE_YS[2] % 2 == 0 &&
+                  TILE_YS[3] % 2 == 0, "tiles hold whole 2 x 2 blocks");
 // a timed advance attaches start / stop events to its first launches only
 constexpr size_t MAX_TIMED_LAUNCHES = 1 << 16;
 constexpr int CXH[9] = {0, 1, -1, 0, 0, 1, -1, 1, -1};
@@ -817,6 +823,9 @@ int alloc_level(lbr_ctx* c, Level& L) {
             if (Pp && t == T_FLUID && !(gx & 1) && !(gy & 1)) {
                 const long pk = Pp->idx(gx >> 1, gy >> 1);
                 if (pk >= 0 && (Pp->flag[pk] & F_COVB)) {
+                    if (((gx - L.box.gx0) | (gy - L.box.gy0)) & 1)
+                        return set_err(c, LBR_ERR_GEOMETRY, "level %d: restriction block at (%d, %d) is not aligned "
+                                       "with the storage box", L.l, gx, gy);
                     // the 2 x 2 block is averaged by the k_step workgroup that updates it
                     for (int b = 0; b < 2; ++b)
                         for (int a2 = 0; a2 < 2; ++a2) {
@@ -2174,35 +2183,52 @@ bool shares_launch(Prec a, Prec b) {
 }
 
 // Launch groups of items [begin, end), in order.  An item of a virtual level at
-// least three below the finest is deferred and joins the next launch of a
-// finer level (whose format it shares), one deferred item per launch, first in
-// first out.
-// This keeps every dependency of the recursive cycle: a deferred level w is
-// read by its child w + 1 (explosion, ghost values) and by its parent w - 1
-// (coalescence, restriction), and it writes only level w and the restriction
-// into w - 1; its partner is a level of at least w + 2, which touches none of
-// these, and before any later item of level w + 1 the pending items up to the
-// last one of level w are launched on their own.  Deferred items of the chain
-// w, w - 1, ... keep their order.  The buffers each item addresses are those
-// of its place in the unmerged cycle, which the merged order preserves.
+// least three below the finest is deferred and joins a later launch of a finer
+// level (whose format it shares), at most one deferred item per launch: a
+// launch of the finest level takes a deferred item of the level three below
+// it, a launch of the level below the finest one of a level at least four
+// below the finest.  The second kind of launch fills only part of the device,
+// so the coarse work it takes costs little there.
+// This keeps every dependency of the recursive cycle: an item of level w reads
+// its parent w - 1 (explosion, ghost values) and its child w + 1
+// (coalescence, restriction) and writes only level w and the restriction into
+// w - 1, so two items of levels at least two apart may run in either order or
+// together.  A deferred item joins a launch of a level at least w + 2, and it
+// may pass earlier deferred items only if it is independent of each of them;
+// before any later item of level w + 1, the pending items up to the last one
+// of level w are launched on their own, in order.  The buffers each item
+// addresses are those of its place in the unmerged cycle, which the merged
+// order preserves.
 std::vector<std::vector<int>> batch_groups(const lbr_batch* b, const std::vector<Item>& it, int begin, int end) {
     std::vector<std::vector<int>> g;
-    std::vector<int> pend;                                   // FIFO
-    size_t head = 0;
+    std::vector<int> pend;                                   // deferred items, in order
     for (int k = begin; k < end; ++k) {
         const Item& x = it[k];
         if (b->merge && x.v <= b->lmax - 3) {
             pend.push_back(k);
             continue;
         }
-        size_t last = head;
-        for (size_t j = head; j < pend.size(); ++j)
+        size_t last = 0;
+        for (size_t j = 0; j < pend.size(); ++j)
             if (it[pend[j]].v == x.v - 1) last = j + 1;
-        for (; head < last; ++head) g.push_back({pend[head]});
-        if (head < pend.size() && shares_launch(it[pend[head]].st, x.st)) g.push_back({k, pend[head++]});
-        else g.push_back({k});
+        for (size_t j = 0; j < last; ++j) g.push_back({pend[j]});
+        pend.erase(pend.begin(), pend.begin() + last);
+        int pick = -1;
+        for (size_t j = 0; j < pend.size() && pick < 0; ++j) {
+            const int w = it[pend[j]].v;
+            const bool kind = x.v == b->lmax - 1 ? w == b->lmax - 3 : w <= x.v - 2;
+            bool free = kind && shares_launch(it[pend[j]].st, x.st);
+            for (size_t i = 0; i < j && free; ++i) free = std::abs(it[pend[i]].v - w) >= 2;
+            if (free) pick = (int)j;
+        }
+        if (pick >= 0) {
+            g.push_back({k, pend[pick]});
+            pend.erase(pend.begin() + pick);
+        } else {
+            g.push_back({k});
+        }
     }
-    for (; head < pend.size(); ++head) g.push_back({pend[head]});
+    for (int k : pend) g.push_back({k});
     return g;
 }
 

@@ -938,6 +938,9 @@ __device__ __forceinline__ void step_block(const StepArgs<ST, CT>& a, const int 
     }
     __syncthreads();
     if (lm >> 31) {
+        // the block's lower-left cell sits at an even local row and column (the
+        // host keeps box origins and tile heights even), so wy + 1 < TY and
+        // lane + 1 < TILE_X
         const long q = (long)((gy >> 1) - a.cbox.gy0) * a.cbox.pitch + ((gx >> 1) - a.cbox.gx0);
         CT m[4];
 #pragma unroll

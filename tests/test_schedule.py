@@ -102,3 +102,17 @@ def test_invalid_level_counts_are_refused():
     L = P.lib()
     assert L.lbr_schedule(0, 1, None, 0) < 0
     assert L.lbr_schedule(13, 1, None, 0) < 0
+
+
+def test_deep_levels_ride_with_the_level_below_the_finest():
+    """Eight levels: every sub-step of levels 0-4 shares a launch of level 6 (which
+    fills only part of the device), level 5 shares launches of level 7, and no
+    coarse sub-step runs alone except the last coarse level-0 step of the table."""
+    groups = P.schedule(8, merge=True)
+    pairs = {}
+    for g in groups:
+        if len(g) == 2:
+            pairs.setdefault(g[1][0], set()).add(g[0][0])
+    assert pairs == {0: {6}, 1: {6}, 2: {6}, 3: {6}, 4: {6}, 5: {7}}
+    alone = [g[0] for g in groups if len(g) == 1 and g[0][0] <= 5]
+    assert len(alone) <= 6
