@@ -194,6 +194,7 @@ def three_element_roofline(steps=10):
            "traffic": None if traffic is None else round(traffic, 0)}
     if traffic is not None:
         out["hbm_GBps"] = round(traffic / (kt[0] * 1e-6) / 1e9, 1)
+        out["hbm_frac_measured"] = round(out["hbm_GBps"] / HBM_PEAK_GBS, 4)
     s.close()
     log(f"three-element FP32: {out['ms_per_step']} ms per step, frac {out['frac']}")
     return out
@@ -590,6 +591,9 @@ def main():
         if traffic is not None:
             hbm = traffic / (kt[0] * 1e-6) / 1e9
             roof["hbm_GBps"] = round(hbm, 1)
+            # the counted (L2-miss) traffic against the peak: an upper bound on the
+            # DRAM fraction here, since part of it may be served by the Infinity Cache
+            roof["hbm_frac_measured"] = round(hbm / HBM_PEAK_GBS, 4)
             roof["hbm_over_copy"] = round(hbm / copy, 4)
         log(f"device copy {copy:.0f} GB/s")
     # the same workload with 16-bit population storage (FP32 arithmetic), same timing

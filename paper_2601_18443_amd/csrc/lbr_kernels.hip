@@ -815,6 +815,9 @@ __device__ __forceinline__ void step_block(const StepArgs<ST, CT>& a, const int 
         s[i] = unshift<ST, CT>(bld<ST, CT>(rf, e * SS, (uint32_t)(i * P - CX[i] - CY[i] * pitch) * SS), a.dsh, i);
     const CT dist = bld<CT, CT>(rd, e * CS, 0);
     const uint8_t fl = __builtin_amdgcn_raw_buffer_load_b8(rg, e, 0, 0);
+    // link mask: only cells of the ghost band, next to it, or anchoring a
+    // restriction block use it (most tiles have none)
+    const uint32_t lm = ((fl & F_TYPE) == T_GHOST || (fl & F_NEARGHOST) || restrict_tile) ? a.lmask[c] : 0u;
     CT own_n = bld<CT, CT>(rc, e * CS, 0), own_u = bld<CT, CT>(rm, e * CS, (uint32_t)P * CS),
        own_v = bld<CT, CT>(rm, e * CS, 2u * (uint32_t)P * CS);
     // halo cells: the row below, the row above, the left and the right column
@@ -840,15 +843,26 @@ __device__ __forceinline__ void step_block(const StepArgs<ST, CT>& a, const int 
             hv[k] = bld<CT, CT>(rm, he * CS, 2u * (uint32_t)P * CS);
         }
     }
-    // link mask: only cells of the ghost band, next to it, or anchoring a
-    // restriction block use it (most tiles have none); read after every load
-    // above is issued, so that waiting for the flag byte holds none of them back
-    const uint32_t lm = ((fl & F_TYPE) == T_GHOST || (fl & F_NEARGHOST) || restrict_tile) ? a.lmask[c] : 0u;
     const int type = fl & F_TYPE;
-    // the populations that come from the neighbouring levels (the ghost band,
-    // coalescence, explosion next to the band) are gathered before the stencil
-    // staging, so that their loads overlap the barrier
+    if (type == T_GHOST) ghost_fill(a.cmac, a.cchi, a.cbox, gx, gy, own_n, own_u, own_v);
+    sh_n[wy + 1][lane + 1] = own_n;
+    sh_u[wy + 1][lane + 1] = own_u;
+    sh_v[wy + 1][lane + 1] = own_v;
+#pragma unroll
+    for (int k = 0; k < NS; ++k)
+        if (halo[k]) {
+            if ((hfl[k] & F_TYPE) == T_GHOST)
+                ghost_fill(a.cmac, a.cchi, a.cbox, a.box.gx0 + tx0 + hx[k], a.box.gy0 + ty0 + hy[k], hn[k], hu[k],
+                           hv[k]);
+            sh_n[hy[k] + 1][hx[k] + 1] = hn[k];
+            sh_u[hy[k] + 1][hx[k] + 1] = hu[k];
+            sh_v[hy[k] + 1][hx[k] + 1] = hv[k];
+        }
+    __syncthreads();
+
     const Rsrc rfo = make_rsrc(a.fdst - pad, 9 * P + 2 * pad);
+    bool update = false;
+    CT m_rho = CT(0), m_ux = CT(0), m_uy = CT(0), m_chi = CT(0);
     if (type == T_GHOST) {
         // fine band over a coarse interface cell: carries exploded coarse populations
         // (first sub-step) and fine populations one cell per sub-step, no collision
@@ -861,7 +875,8 @@ __device__ __forceinline__ void step_block(const StepArgs<ST, CT>& a, const int 
                 w = coarse_val(a, i, gx - k * CX[i], gy - k * CY[i]);
             bst<ST, CT>(rfo, e * SS, (uint32_t)(i * P) * SS, toshift<ST, CT>(w, a.dsh, i));
         }
-    } else if (type == T_FLUID && !(fl & (F_WALL | F_EDGE))) {
+    } else if (type == T_FLUID && !(fl & (F_WALL | F_EDGE))) {   // others: side-stream kernels
+        update = true;
         if (fl & F_IFACE) {
             // coalescence: mean of the four children of the finer band
             const long f0 = (long)(2 * gy - a.fbox.gy0) * a.fbox.pitch + (2 * gx - a.fbox.gx0);
@@ -881,27 +896,6 @@ __device__ __forceinline__ void step_block(const StepArgs<ST, CT>& a, const int 
             for (int i = 0; i < 9; ++i)
                 if ((lm >> (16 + i)) & 1u) s[i] = coarse_val(a, i, gx - CX[i], gy - CY[i]);
         }
-    }
-    if (type == T_GHOST) ghost_fill(a.cmac, a.cchi, a.cbox, gx, gy, own_n, own_u, own_v);
-    sh_n[wy + 1][lane + 1] = own_n;
-    sh_u[wy + 1][lane + 1] = own_u;
-    sh_v[wy + 1][lane + 1] = own_v;
-#pragma unroll
-    for (int k = 0; k < NS; ++k)
-        if (halo[k]) {
-            if ((hfl[k] & F_TYPE) == T_GHOST)
-                ghost_fill(a.cmac, a.cchi, a.cbox, a.box.gx0 + tx0 + hx[k], a.box.gy0 + ty0 + hy[k], hn[k], hu[k],
-                           hv[k]);
-            sh_n[hy[k] + 1][hx[k] + 1] = hn[k];
-            sh_u[hy[k] + 1][hx[k] + 1] = hu[k];
-            sh_v[hy[k] + 1][hx[k] + 1] = hv[k];
-        }
-    __syncthreads();
-
-    bool update = false;
-    CT m_rho = CT(0), m_ux = CT(0), m_uy = CT(0), m_chi = CT(0);
-    if (type == T_FLUID && !(fl & (F_WALL | F_EDGE))) {   // others: side-stream kernels
-        update = true;
         // SA-neg: chi at the new time level
         CT chi_new;
         if (a.frozen) {
