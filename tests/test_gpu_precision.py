@@ -69,6 +69,23 @@ def test_converged_fields_element_by_element(converged_oracle, storage, tol, chi
     for l, e in errs.items():
         assert e["ux"] <= tol and e["uy"] <= tol and e["rho"] <= rho_tol and e[chi_key] <= chi_tol, (l, e)
     U.assert_walls_match(g, o, case["n_levels"] - 1, tol, rho_tol, U.reference_speed(case))
+    # relative L2 differences per level (the form in which a converged-field
+    # tolerance is often stated): the velocity vector within the velocity bound;
+    # chi within its element-wise bound (FP32 measured 1.1e-5 to 3.0e-5: the
+    # converged chi carries the FP32 rounding of the SA sources, see above)
+    for l in range(case["n_levels"]):
+        du = dn = dc = nc = 0.0
+        for fg, fo in ((1, oracle.F_UX), (2, oracle.F_UY)):
+            a, b = g.field(l, fg), o.field(l, fo)
+            m = np.isfinite(b)
+            du += float(np.sum((a[m] - b[m]) ** 2))
+            dn += float(np.sum(b[m] ** 2))
+        a, b = g.field(l, 3), o.field(l, oracle.F_CHI)
+        m = np.isfinite(b)
+        dc, nc = float(np.sum((a[m] - b[m]) ** 2)), float(np.sum(b[m] ** 2))
+        ru, rc = np.sqrt(du / dn), np.sqrt(dc / nc)
+        print(storage, "level", l, f"relative L2: u {ru:.2e} chi {rc:.2e}")
+        assert ru <= tol and rc <= chi_tol, (l, ru, rc)
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16", "mixed", "f16s", "bf16s", "mixeds"])
