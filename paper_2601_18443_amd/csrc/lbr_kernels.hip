@@ -755,6 +755,49 @@ __device__ __forceinline__ TileShared<CT, TY>& tile_shared() {
     return sh;
 }
 
+// Populations a tile cell takes from the neighbouring levels.  A cell of the
+// fine ghost band carries exploded coarse populations (first sub-step) and fine
+// ones one cell per sub-step, with no collision: stored here.
+template <class ST, class CT>
+__device__ __forceinline__ void ghost_band_cell(const StepArgs<ST, CT>& a, uint32_t lm, int gx, int gy,
+                                                const CT s[9], Rsrc rfo, uint32_t e, long P) {
+    constexpr uint32_t SS = sizeof(ST);
+    const int k = (a.substep == 1) ? 1 : 2;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const bool src_fluid = (lm >> i) & 1u, src_ghost = (lm >> (16 + i)) & 1u;
+        CT w = s[i];
+        if (!(src_fluid || (src_ghost && a.substep == 2)))
+            w = coarse_val(a, i, gx - k * CX[i], gy - k * CY[i]);
+        bst<ST, CT>(rfo, e * SS, (uint32_t)(i * P) * SS, toshift<ST, CT>(w, a.dsh, i));
+    }
+}
+
+// A coarse interface cell takes the mean of its four children (coalescence); a
+// fine cell next to the ghost band takes exploded coarse populations on the
+// first sub-step.  Other cells keep what they pulled.
+template <class ST, class CT>
+__device__ __forceinline__ void band_neighbour_cell(const StepArgs<ST, CT>& a, uint8_t fl, uint32_t lm, int gx, int gy,
+                                                    CT s[9]) {
+    if (fl & F_IFACE) {
+        const long f0 = (long)(2 * gy - a.fbox.gy0) * a.fbox.pitch + (2 * gx - a.fbox.gx0);
+        if constexpr (std::is_same<CT, float>::value) {
+            if (a.fst == P_F16)
+                coalesce<__half, CT>(static_cast<const __half*>(a.ffine), a.fbox.plane, a.fbox.pitch, f0, a.dsh, s);
+            else if (a.fst == P_F32)
+                coalesce<float, CT>(static_cast<const float*>(a.ffine), a.fbox.plane, a.fbox.pitch, f0, a.dsh, s);
+            else
+                coalesce<ST, CT>(static_cast<const ST*>(a.ffine), a.fbox.plane, a.fbox.pitch, f0, a.dsh, s);
+        } else {
+            coalesce<ST, CT>(static_cast<const ST*>(a.ffine), a.fbox.plane, a.fbox.pitch, f0, a.dsh, s);
+        }
+    } else if ((fl & F_NEARGHOST) && a.substep == 1) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+            if ((lm >> (16 + i)) & 1u) s[i] = coarse_val(a, i, gx - CX[i], gy - CY[i]);
+    }
+}
+
 template <class ST, class CT, int TY>
 __device__ __forceinline__ void step_block(const StepArgs<ST, CT>& a, const int blk) {
     constexpr int NT = TILE_X * TY;                        // threads of the workgroup
@@ -844,6 +887,17 @@ __device__ __forceinline__ void step_block(const StepArgs<ST, CT>& a, const int 
         }
     }
     const int type = fl & F_TYPE;
+    // 16-bit storage takes the neighbouring levels' populations before the
+    // stencil staging, so that those loads overlap the barrier; wider formats
+    // take them after it (each order measured the faster for its formats; the
+    // order changes no result)
+    constexpr bool early = sizeof(ST) == 2;
+    if constexpr (early) {
+        if (type == T_GHOST)
+            ghost_band_cell<ST, CT>(a, lm, gx, gy, s, make_rsrc(a.fdst - pad, 9 * P + 2 * pad), e, P);
+        else if (type == T_FLUID && !(fl & (F_WALL | F_EDGE)))
+            band_neighbour_cell<ST, CT>(a, fl, lm, gx, gy, s);
+    }
     if (type == T_GHOST) ghost_fill(a.cmac, a.cchi, a.cbox, gx, gy, own_n, own_u, own_v);
     sh_n[wy + 1][lane + 1] = own_n;
     sh_u[wy + 1][lane + 1] = own_u;
@@ -864,38 +918,10 @@ __device__ __forceinline__ void step_block(const StepArgs<ST, CT>& a, const int 
     bool update = false;
     CT m_rho = CT(0), m_ux = CT(0), m_uy = CT(0), m_chi = CT(0);
     if (type == T_GHOST) {
-        // fine band over a coarse interface cell: carries exploded coarse populations
-        // (first sub-step) and fine populations one cell per sub-step, no collision
-        const int k = (a.substep == 1) ? 1 : 2;
-#pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            const bool src_fluid = (lm >> i) & 1u, src_ghost = (lm >> (16 + i)) & 1u;
-            CT w = s[i];
-            if (!(src_fluid || (src_ghost && a.substep == 2)))
-                w = coarse_val(a, i, gx - k * CX[i], gy - k * CY[i]);
-            bst<ST, CT>(rfo, e * SS, (uint32_t)(i * P) * SS, toshift<ST, CT>(w, a.dsh, i));
-        }
+        if constexpr (!early) ghost_band_cell<ST, CT>(a, lm, gx, gy, s, rfo, e, P);
     } else if (type == T_FLUID && !(fl & (F_WALL | F_EDGE))) {   // others: side-stream kernels
         update = true;
-        if (fl & F_IFACE) {
-            // coalescence: mean of the four children of the finer band
-            const long f0 = (long)(2 * gy - a.fbox.gy0) * a.fbox.pitch + (2 * gx - a.fbox.gx0);
-            if constexpr (std::is_same<CT, float>::value) {
-                if (a.fst == P_F16)
-                    coalesce<__half, CT>(static_cast<const __half*>(a.ffine), a.fbox.plane, a.fbox.pitch, f0, a.dsh, s);
-                else if (a.fst == P_F32)
-                    coalesce<float, CT>(static_cast<const float*>(a.ffine), a.fbox.plane, a.fbox.pitch, f0, a.dsh, s);
-                else
-                    coalesce<ST, CT>(static_cast<const ST*>(a.ffine), a.fbox.plane, a.fbox.pitch, f0, a.dsh, s);
-            } else {
-                coalesce<ST, CT>(static_cast<const ST*>(a.ffine), a.fbox.plane, a.fbox.pitch, f0, a.dsh, s);
-            }
-        } else if ((fl & F_NEARGHOST) && a.substep == 1) {
-            // next to the fine band on the first sub-step: exploded coarse populations
-#pragma unroll
-            for (int i = 0; i < 9; ++i)
-                if ((lm >> (16 + i)) & 1u) s[i] = coarse_val(a, i, gx - CX[i], gy - CY[i]);
-        }
+        if constexpr (!early) band_neighbour_cell<ST, CT>(a, fl, lm, gx, gy, s);
         // SA-neg: chi at the new time level
         CT chi_new;
         if (a.frozen) {
