@@ -272,6 +272,24 @@ def run_sweep(args):
     batch.advance(args.steps)
     batch.synchronize()
     kt = batch.profile(False)
+    # the same super steps as one cooperative grid per two super steps, with
+    # grid-wide barriers in place of the launch boundaries (one format only)
+    persistent = None
+    if args.storage not in ("mixed", "mixeds"):
+        batch.use_persistent(True)
+        batch.advance(2)
+        batch.synchronize()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        batch.advance(args.steps)
+        batch.synchronize()
+        torch.cuda.synchronize()
+        dtp = time.perf_counter() - t0
+        batch.use_persistent(False)
+        persistent = {"value": round(batch.lups_per_super_step() * args.steps / dtp / 1e6, 1), "unit": "MLUPS",
+                      "ms_per_step": round(1000 * dtp / args.steps, 4),
+                      "launches_over_persistent": round(dtp / dt, 3), "tile_rows": 4}
+        log(f"persistent grid: {args.steps} super steps in {dtp:.3f} s ({dtp / dt:.3f} x the launches)")
     batch.close()
     launches = kt[3] if kt[3] > 0 else 2 ** lmax - 1            # per super step
     log(f"batched: {args.steps} super steps in {dt:.3f} s; k_step_batch {kt[0]:.2f} us/launch, "
@@ -336,6 +354,7 @@ def run_sweep(args):
         "one_after_another": {"value": round(lups * args.steps / seq / 1e6, 1), "unit": "MLUPS",
                               "ms_per_step": round(1000 * seq / args.steps, 4)},
         "batched_over_one_after_another": round(seq / dt, 3),
+        "persistent": persistent,
         "one_after_another_f32": None if seq32 is None else
         {"value": round(lups * args.steps / seq32 / 1e6, 1), "unit": "MLUPS",
          "ms_per_step": round(1000 * seq32 / args.steps, 4)},

@@ -494,6 +494,22 @@ int lbr_batch_use_graph(lbr_batch* batch, int32_t enable);
    rebuilt. */
 int lbr_batch_tune(lbr_batch* batch, int32_t trials, int32_t* rows);
 
+/* Persistent mode of a batch: every table of the merged schedule (one or two
+   super steps) runs as a single cooperative grid of co-resident workgroups,
+   which take the blocks of each launch in turn and meet at a grid-wide
+   barrier where the launch boundaries were (workgroups grouped by XCD: one
+   L2 writeback per XCD, then every workgroup discards its stale lines).
+   Results are bit-identical to the launches (64 x 4 tiles everywhere in this
+   mode).  On MI355X it is slower than the launches replayed from a graph (a
+   barrier across 2,048 workgroups costs more than a launch boundary); it is
+   off by default.  Every level of every case must hold one
+   population format (no mixed storage).  Each advance waits for its grid and
+   reports a barrier wait that ran out (LBR_ERR_HIP; only a grid that is not
+   co-resident can reach it).  Profiling (lbr_batch_profile) times the
+   launches of the merged schedule and is refused in this mode.  Errors:
+   LBR_ERR_INVALID_ARG for mixed formats, LBR_ERR_STATE while profiling. */
+int lbr_batch_use_persistent(lbr_batch* batch, int32_t enable);
+
 /* As lbr_profile, for the batched launches: out[0] all launches, out[1] the
    launches of the finest virtual level, out[2] virtual level 0, out[3]
    launches per super step. */

@@ -114,6 +114,7 @@ def lib():
         L.lbr_batch_create.argtypes = [i32, C.POINTER(p), C.POINTER(p)]
         L.lbr_batch_advance.argtypes = [p, i64]
         L.lbr_batch_use_graph.argtypes = [p, i32]
+        L.lbr_batch_use_persistent.argtypes = [p, i32]
         L.lbr_batch_run_to_steady.argtypes = [p, C.c_double, i64, i64, C.POINTER(i64),
                                               C.POINTER(C.c_double)]
         L.lbr_batch_profile.argtypes = [p, i32, C.POINTER(C.c_double)]
@@ -446,6 +447,10 @@ class Batch:
 
     def use_graph(self, enable=True):
         self._check(lib().lbr_batch_use_graph(self.h, 1 if enable else 0))
+
+    def use_persistent(self, enable=True):
+        """Each table of the merged schedule as one cooperative grid (lbr_batch_use_persistent)."""
+        self._check(lib().lbr_batch_use_persistent(self.h, 1 if enable else 0))
 
     def run_to_steady(self, tol, max_super_steps, check_every=100):
         """Returns (coarse steps taken per case, last residual per case)."""

@@ -2136,6 +2136,13 @@ struct lbr_batch {
     std::vector<int> cur0;             // level-0 buffer index of each covered case at parity 0
     std::vector<hipEvent_t> ev;        // ordering between the case streams and the batch stream
     bool use_graph = false;
+    // persistent mode (lbr_batch_use_persistent): each table runs as one cooperative
+    // grid with barriers between its launches; tables built with 64 x PERSISTENT_TY tiles
+    bool persistent = false;
+    PLaunch* plaunch_dev = nullptr;    // one entry per launch of the tables, in order
+    unsigned* bar_dev = nullptr;       // grid barrier counters (BAR_WORDS words) and time-out flag
+    int pgrid = 0;                     // co-resident workgroups of the persistent grid
+    Prec pst = P_F32;                  // the one population format of a persistent batch
     bool ready = false;                // launch tables built and uploaded
     hipGraphExec_t graph = nullptr;    // table 2
     bool prof = false;                 // start / stop events on every launch
@@ -2317,8 +2324,9 @@ int batch_build(lbr_batch* b) {
     for (int t = 0; t < 3; ++t) {
         const auto groups = batch_groups(b, items, range[t][0], range[t][1]);
         std::vector<int> tk(2 * per, TILE_Y_DEFAULT);
-        for (const auto& grp : groups)
-            for (int k : grp) tk[k] = tyv[items[grp[0]].v];
+        if (!b->persistent)
+            for (const auto& grp : groups)
+                for (int k : grp) tk[k] = tyv[items[grp[0]].v];
         if (int r = batch_fill(b, items, range[t][0], range[t][1], tk, seq2)) return r;
         b->table[t][0] = (int)b->launches.size();
         for (const auto& grp : groups) {
@@ -2347,6 +2355,29 @@ int batch_build(lbr_batch* b) {
     if (hipMemcpy(b->parts_dev, parts.data(), parts.size(), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(b->start_dev, starts.data(), starts.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
         return bset_err(b, LBR_ERR_HIP, "batch tables: copy failed");
+    if (b->persistent) {
+        static_assert(TILE_YS[TILE_Y_DEFAULT] == PERSISTENT_TY, "persistent tables use the default tile height");
+        const Prec st = b->launches.empty() ? P_F32 : b->launches[0].st;
+        std::vector<PLaunch> pl;
+        for (const lbr_batch::Launch& ln : b->launches) {
+            if (ln.st != st || st == P_MIXED)
+                return bset_err(b, LBR_ERR_INVALID_ARG, "a persistent batch needs one population format on every level");
+            const size_t sz = st == P_F64 ? sizeof(StepArgs<double, double>) : sizeof(StepArgs<float, float>);
+            pl.push_back({(int)(ln.off / sz), ln.part0, ln.nparts, ln.nblocks});
+        }
+        b->pst = st;
+        b->plaunch_dev = static_cast<PLaunch*>(dalloc(c0, std::max<size_t>(pl.size(), 1) * sizeof(PLaunch)));
+        if (!b->plaunch_dev) return bset_err(b, LBR_ERR_OOM, "batch tables: out of device memory");
+        if (hipMemcpy(b->plaunch_dev, pl.data(), pl.size() * sizeof(PLaunch), hipMemcpyHostToDevice) != hipSuccess)
+            return bset_err(b, LBR_ERR_HIP, "batch tables: copy failed");
+        if (!b->bar_dev) {
+            b->bar_dev = static_cast<unsigned*>(dalloc(c0, BAR_WORDS * sizeof(unsigned)));
+            if (!b->bar_dev || hipMemset(b->bar_dev, 0, BAR_WORDS * sizeof(unsigned)) != hipSuccess)
+                return bset_err(b, LBR_ERR_OOM, "persistent grid barrier: out of device memory");
+        }
+        if (persistent_grid(st, &b->pgrid) != hipSuccess)
+            return bset_err(b, LBR_ERR_HIP, "persistent grid: occupancy query failed");
+    }
     b->ready = true;
     return 0;
 }
@@ -2359,8 +2390,10 @@ int batch_cover(lbr_batch* b, const std::vector<lbr_ctx*>& cases) {
     b->graph = nullptr;
     dfree(b->all[0], b->parts_dev);
     dfree(b->all[0], b->start_dev);
+    dfree(b->all[0], b->plaunch_dev);
     b->parts_dev = nullptr;
     b->start_dev = nullptr;
+    b->plaunch_dev = nullptr;
     b->ready = false;
     b->cases = cases;
     b->lmax = 0;
@@ -2446,8 +2479,42 @@ int batch_release_cases(lbr_batch* b) {
     return 0;
 }
 
+// One table as one cooperative grid (persistent mode).
+int batch_table_persistent(lbr_batch* b, int t) {
+    const int n = b->table[t][1] - b->table[t][0];
+    if (launch_step_persistent(b->pst, b->parts_dev, b->start_dev, b->plaunch_dev + b->table[t][0], n, b->pgrid,
+                               b->bar_dev, b->stream) != hipSuccess)
+        return bset_err(b, LBR_ERR_HIP, "persistent k_step launch failed");
+    return 0;
+}
+
 int batch_run(lbr_batch* b, int64_t n) {
     int64_t k = 0;
+    if (b->persistent) {
+        for (; k < n && b->parity == 1; ++k) {
+            if (int r = batch_table_persistent(b, 1)) return r;
+            batch_account(b);
+        }
+        for (; k + 2 <= n; k += 2) {
+            if (int r = batch_table_persistent(b, 2)) return r;
+            batch_account(b);
+            batch_account(b);
+        }
+        if (k < n) {
+            if (int r = batch_table_persistent(b, 0)) return r;
+            batch_account(b);
+        }
+        // a barrier wait that ran out (a grid that was not co-resident) is an error
+        unsigned flag = 0;
+        if (hipMemcpyAsync(&flag, b->bar_dev + 2, sizeof flag, hipMemcpyDeviceToHost, b->stream) != hipSuccess ||
+            hipStreamSynchronize(b->stream) != hipSuccess)
+            return bset_err(b, LBR_ERR_HIP, "persistent run: synchronize failed");
+        if (flag) {
+            (void)hipMemset(b->bar_dev, 0, BAR_WORDS * sizeof(unsigned));   // counters left mid-way
+            return bset_err(b, LBR_ERR_HIP, "persistent run: a grid barrier wait ran out");
+        }
+        return 0;
+    }
     if (k < n && b->parity == 1) {
         if (int r = batch_table(b, 1)) return r;
         batch_account(b);
@@ -2602,8 +2669,23 @@ int lbr_batch_use_graph(lbr_batch* b, int32_t enable) {
     return LBR_OK;
 }
 
+int lbr_batch_use_persistent(lbr_batch* b, int32_t enable) {
+    if (!b) return LBR_ERR_INVALID_ARG;
+    if ((enable != 0) == b->persistent) return LBR_OK;
+    if (enable && b->prof) return bset_err(b, LBR_ERR_STATE, "profiling times the launches of the merged schedule");
+    b->persistent = enable != 0;
+    if (int r = batch_cover(b, b->cases)) {
+        b->persistent = false;
+        (void)batch_cover(b, b->cases);
+        return r;
+    }
+    return LBR_OK;
+}
+
 int lbr_batch_profile(lbr_batch* b, int32_t enable, double out[4]) {
     if (!b) return LBR_ERR_INVALID_ARG;
+    if (enable && b->persistent)
+        return bset_err(b, LBR_ERR_STATE, "profiling times the launches of the merged schedule (persistent mode is on)");
     b->prof = enable != 0;
     if (out)
         for (int f = 0; f < 4; ++f) out[f] = b->prof_out[f];
@@ -2641,6 +2723,8 @@ void lbr_batch_destroy(lbr_batch* b) {
     if (!b->all.empty()) {
         dfree(b->all[0], b->parts_dev);
         dfree(b->all[0], b->start_dev);
+        dfree(b->all[0], b->plaunch_dev);
+        dfree(b->all[0], b->bar_dev);
     }
     delete b;
 }

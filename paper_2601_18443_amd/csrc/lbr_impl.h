@@ -176,6 +176,22 @@ hipError_t launch_step(Prec p, const void* args, hipStream_t s, const Timing& tm
 // array of the first block of each part (multiples of 8); nblocks_total: grid size
 hipError_t launch_step_batch(Prec p, const void* parts, const int* start, int nparts, int nblocks_total, int ty,
                              hipStream_t s, const Timing& tm = Timing{});
+// Persistent batched run (lbr_batch_use_persistent): the launches of a table
+// as sub-launches of one cooperative grid, separated by a grid-wide barrier.
+// part: index of the launch's first StepArgs in the parts array (all of one
+// format); part0: index of its first part start; nparts; nblocks.
+struct PLaunch { int part, part0, nparts, nblocks; };
+constexpr int PERSISTENT_TY = 4;                 // tile height of every sub-launch
+// bar: BAR_WORDS device words, zero before the first grid (grid and per-XCD
+// barrier counters; word 2 is a flag set when a barrier wait ran out of its spin
+// limit, which only a grid that is not co-resident reaches)
+constexpr int BAR_XCC = 16;                      // XCC ids are four bits
+constexpr int BAR_STRIDE = 32;                   // one 128-byte line per counter group
+constexpr int BAR_WORDS = BAR_STRIDE * (BAR_XCC + 1);
+hipError_t launch_step_persistent(Prec p, const void* parts, const int* start, const PLaunch* launches, int nlaunches,
+                                  int grid, unsigned* bar, hipStream_t s);
+// largest co-resident grid of the persistent kernel of format p (a multiple of 8)
+hipError_t persistent_grid(Prec p, int* grid);
 hipError_t launch_wall(Prec p, const void* args, hipStream_t s);
 hipError_t launch_fill(Prec p, const FillArgs& a, hipStream_t s);
 hipError_t launch_restrict(Prec p, const RestrictArgs& a, hipStream_t s);

@@ -1017,6 +1017,129 @@ __global__ __launch_bounds__(TILE_X * TY, 8) void k_step_batch_mixed(const StepA
         step_block<float, float, TY>(parts[p], blk);
 }
 
+// Grid-wide barrier of a co-resident grid, in two levels.  A launch boundary
+// writes back and invalidates each XCD's L2 once; a barrier in which every
+// workgroup made its writes visible at device scope would do so once per
+// workgroup, about 250 times per XCD.  So the workgroups of one XCD (grouped by
+// the hardware's XCC id, read at the start of the grid) count themselves in at
+// the group's counter once their stores have reached the XCD's L2; the last of
+// the group writes that L2 back to memory and counts the group in at the grid
+// counter; the last group opens the grid's next generation; each group's last
+// workgroup then opens its group, and every workgroup discards its stale cache
+// lines.  The waits poll with relaxed loads (an acquire on every poll would
+// invalidate the L2 under the workgroups still computing) and are bounded:
+// past spin_limit polls a wait sets the flag word and gives up, which only a
+// grid that is not co-resident can reach (the cooperative launch refuses such
+// grids).
+//
+// Words of bar (zero before the first grid): [0] group arrivals at the grid
+// counter, [1] grid generation, [2] time-out flag, [3] workgroups registered,
+// [4] groups; group x at BAR_STRIDE * (x + 1): [0] arrivals, [1] generation,
+// [2] members.
+constexpr unsigned BARRIER_SPIN_LIMIT = 1u << 20;   // far beyond any sub-launch of the batch
+
+__device__ __forceinline__ unsigned xcc_id() {
+    return __builtin_amdgcn_s_getreg((3 << 11) | 20) & (BAR_XCC - 1);   // HW_REG_XCC_ID, bits 0-3
+}
+
+__device__ __forceinline__ unsigned ld_relaxed(unsigned* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void st_relaxed(unsigned* p, unsigned v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ unsigned add_relaxed(unsigned* p, unsigned v) {
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Polls *p until it differs from old (want_equal = false) or equals old (true).
+__device__ __forceinline__ void bounded_wait(unsigned* p, unsigned old, bool want_equal, unsigned* flag,
+                                             unsigned spin_limit) {
+    unsigned n = 0;
+    while ((ld_relaxed(p) == old) != want_equal) {
+        if (++n > spin_limit) {
+            st_relaxed(flag, 1u);
+            return;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+}
+
+// First thread of each workgroup: join the group of its XCD and wait until the
+// whole grid has; returns the group size and sets *x to the group.
+__device__ __forceinline__ unsigned grid_register(unsigned* bar, unsigned nblocks, unsigned* x, unsigned spin_limit) {
+    *x = xcc_id();
+    unsigned* g = bar + BAR_STRIDE * (*x + 1);
+    if (add_relaxed(g + 2, 1u) == 0) add_relaxed(bar + 4, 1u);
+    add_relaxed(bar + 3, 1u);
+    bounded_wait(bar + 3, nblocks, true, bar + 2, spin_limit);
+    return ld_relaxed(g + 2);
+}
+
+__device__ __forceinline__ void grid_barrier(unsigned* bar, unsigned x, unsigned members, unsigned ngroups,
+                                             unsigned spin_limit) {
+    __builtin_amdgcn_s_waitcnt(0);   // this wave's stores have reached the XCD's L2
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned* g = bar + BAR_STRIDE * (x + 1);
+        const unsigned ggen = ld_relaxed(g + 1);
+        if (add_relaxed(g, 1u) == members - 1) {
+            st_relaxed(g, 0u);
+            const unsigned gen = ld_relaxed(bar + 1);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");   // the XCD's L2 (the whole group's writes) to memory
+            if (add_relaxed(bar, 1u) == ngroups - 1) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                st_relaxed(bar, 0u);
+                __hip_atomic_fetch_add(bar + 1, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                bounded_wait(bar + 1, gen, false, bar + 2, spin_limit);
+            }
+            add_relaxed(g + 1, 1u);
+        } else {
+            bounded_wait(g + 1, ggen, false, bar + 2, spin_limit);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // drop stale L1 and L2 lines
+    }
+    __syncthreads();
+}
+
+// The launches of a batch table run by one cooperative grid: each workgroup
+// takes the blocks b = blockIdx.x, blockIdx.x + gridDim.x, ... of every
+// sub-launch (the grid is a multiple of 8 workgroups, so each block keeps the
+// XCD the direct launch gives it), and a grid-wide barrier separates the
+// sub-launches as the launch boundaries of the merged schedule do.  The
+// registration words are cleared after the first barrier, when every
+// workgroup has read its group size, for the next grid on the same words.
+template <class ST, class CT>
+__global__ __launch_bounds__(TILE_X * PERSISTENT_TY, 8) void k_step_persistent(
+        const StepArgs<ST, CT>* __restrict__ parts, const int* __restrict__ start, const PLaunch* __restrict__ launches,
+        int nlaunches, unsigned* bar) {
+    unsigned x = 0, members = 0, ngroups = 0;
+    if (nlaunches > 1 && threadIdx.x == 0) {
+        members = grid_register(bar, gridDim.x, &x, BARRIER_SPIN_LIMIT);
+        ngroups = ld_relaxed(bar + 4);
+    }
+    for (int L = 0; L < nlaunches; ++L) {
+        const PLaunch ln = launches[L];
+        for (int b = (int)blockIdx.x; b < ln.nblocks; b += (int)gridDim.x) {
+            int p = 0;
+            while (p + 1 < ln.nparts && b >= start[ln.part0 + p + 1]) ++p;
+            step_block<ST, CT, PERSISTENT_TY>(parts[ln.part + p], b - start[ln.part0 + p]);
+            __syncthreads();   // the next block reuses the LDS
+        }
+        if (L + 1 < nlaunches) {
+            grid_barrier(bar, x, members, ngroups, BARRIER_SPIN_LIMIT);
+            if (L == 0 && blockIdx.x == 0 && threadIdx.x == 0) {
+                st_relaxed(bar + 3, 0u);
+                st_relaxed(bar + 4, 0u);
+                for (int k = 0; k < BAR_XCC; ++k) st_relaxed(bar + BAR_STRIDE * (k + 1) + 2, 0u);
+            }
+        }
+    }
+}
+
 // Wall model on the current state, for output.
 template <class CT>
 __global__ __launch_bounds__(64) void k_wall(const WallArgs<CT> a) {
@@ -1359,6 +1482,49 @@ hipError_t launch_step_batch(Prec p, const void* parts, const int* start, int np
         case P_F32: return batch_t<float, float>(parts, start, nparts, nblocks_total, ty, s, tm);
         case P_F16: return batch_t<__half, float>(parts, start, nparts, nblocks_total, ty, s, tm);
         default: return batch_t<__hip_bfloat16, float>(parts, start, nparts, nblocks_total, ty, s, tm);
+    }
+}
+
+template <class ST, class CT>
+static hipError_t persistent_t(const void* parts, const int* start, const PLaunch* launches, int nlaunches, int grid,
+                               unsigned* bar, hipStream_t s) {
+    const StepArgs<ST, CT>* pa = static_cast<const StepArgs<ST, CT>*>(parts);
+    void* args[] = {(void*)&pa, (void*)&start, (void*)&launches, (void*)&nlaunches, (void*)&bar};
+    return hipLaunchCooperativeKernel((const void*)k_step_persistent<ST, CT>, dim3(grid),
+                                      dim3(TILE_X * PERSISTENT_TY), args, 0, s);
+}
+
+hipError_t launch_step_persistent(Prec p, const void* parts, const int* start, const PLaunch* launches, int nlaunches,
+                                  int grid, unsigned* bar, hipStream_t s) {
+    if (nlaunches == 0) return hipSuccess;
+    switch (p) {
+        case P_F64: return persistent_t<double, double>(parts, start, launches, nlaunches, grid, bar, s);
+        case P_F32: return persistent_t<float, float>(parts, start, launches, nlaunches, grid, bar, s);
+        case P_F16: return persistent_t<__half, float>(parts, start, launches, nlaunches, grid, bar, s);
+        case P_BF16: return persistent_t<__hip_bfloat16, float>(parts, start, launches, nlaunches, grid, bar, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <class ST, class CT>
+static hipError_t grid_t(int* grid) {
+    int per_cu = 0, dev = 0, cus = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_persistent<ST, CT>,
+                                                                TILE_X * PERSISTENT_TY, 0);
+    if (e == hipSuccess) e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    *grid = per_cu * cus / 8 * 8;
+    return *grid > 0 ? hipSuccess : hipErrorInvalidConfiguration;
+}
+
+hipError_t persistent_grid(Prec p, int* grid) {
+    switch (p) {
+        case P_F64: return grid_t<double, double>(grid);
+        case P_F32: return grid_t<float, float>(grid);
+        case P_F16: return grid_t<__half, float>(grid);
+        case P_BF16: return grid_t<__hip_bfloat16, float>(grid);
+        default: return hipErrorInvalidValue;
     }
 }
 

@@ -157,3 +157,75 @@ def test_batch_run_to_steady_drops_converged_cases():
         twin = P.Solver(cases[k], storage="f32")
         twin.advance(steps[k])
         _assert_same(batched[k], twin, cases[k]["n_levels"], f"steady case {k}")
+
+
+@pytest.mark.parametrize("storage", ["f32", "f64", "f16s"])
+def test_persistent_grid_matches_the_launches(storage):
+    """Persistent mode (lbr_batch_use_persistent): each table of the merged
+    schedule runs as one cooperative grid whose workgroups take the blocks of
+    each launch in turn and meet at a grid-wide barrier where the launch
+    boundaries were.  Advanced 1 + 4 + 3 super steps (odd counts start and end
+    in the middle of a two-step table) it must match the same batch run by
+    launches (graph replay) bit for bit: fields, wall records and forces of
+    every case."""
+    import paper_2601_18443_amd as P
+    cases = _cases()
+    by_launch = [P.Solver(c, storage=storage) for c in cases]
+    by_grid = [P.Solver(c, storage=storage) for c in cases]
+    ba, bb = P.Batch(by_launch), P.Batch(by_grid)
+    try:
+        ba.use_graph(True)
+        bb.use_persistent(True)
+        for n in (1, 4, 3):
+            ba.advance(n)
+            bb.advance(n)
+        for k, c in enumerate(cases):
+            _assert_same(by_grid[k], by_launch[k], c["n_levels"], f"persistent case {k}")
+        with pytest.raises(P.LbrError):
+            bb.profile(True)                  # the launches it would time do not exist
+        bb.use_persistent(False)
+        ba.advance(2)
+        bb.advance(2)
+        for k, c in enumerate(cases):
+            _assert_same(by_grid[k], by_launch[k], c["n_levels"], f"back to launches, case {k}")
+    finally:
+        ba.close()
+        bb.close()
+
+
+def test_persistent_mode_needs_one_population_format():
+    import paper_2601_18443_amd as P
+    solvers = [P.Solver(c, storage="mixeds") for c in _cases()]
+    b = P.Batch(solvers)
+    try:
+        with pytest.raises(P.LbrError):
+            b.use_persistent(True)
+        b.advance(2)                          # still usable by launches
+    finally:
+        b.close()
+
+
+def test_persistent_grid_on_full_size_sweep_cases():
+    """Two cases of the 16-case sweep at full size (finest c/512, four and five
+    levels): the finest virtual level alone has more tiles than the persistent
+    grid has workgroups (2,048 on MI355X: 8 per CU), so workgroups take several
+    blocks of one sub-launch in turn.  One plus two super steps must match the
+    launches bit for bit on every level of both cases."""
+    import paper_2601_18443_amd as P
+    cases = [LI.case_sweep(k) for k in (1, 2)]
+    by_launch = [P.Solver(c, storage="f32") for c in cases]
+    by_grid = [P.Solver(c, storage="f32") for c in cases]
+    finest_tiles = sum(s.level_info(c["n_levels"] - 1)["n_tiles"] for s, c in zip(by_launch, cases))
+    assert finest_tiles > 2048, finest_tiles
+    ba, bb = P.Batch(by_launch), P.Batch(by_grid)
+    try:
+        ba.use_graph(True)
+        bb.use_persistent(True)
+        for n in (1, 2):
+            ba.advance(n)
+            bb.advance(n)
+        for k, c in enumerate(cases):
+            _assert_same(by_grid[k], by_launch[k], c["n_levels"], f"full-size case {k}")
+    finally:
+        ba.close()
+        bb.close()
