@@ -275,7 +275,7 @@ def run_sweep(args):
     # the same super steps as one cooperative grid per two super steps, with
     # grid-wide barriers in place of the launch boundaries (one format only)
     persistent = None
-    if args.storage not in ("mixed", "mixeds"):
+    if args.persistent and args.storage not in ("mixed", "mixeds"):
         batch.use_persistent(True)
         batch.advance(2)
         batch.synchronize()
@@ -497,6 +497,8 @@ def main():
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the FP16 / BF16 storage runs reported beside the main line")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--persistent", type=int, default=1,
+                    help="sweep: also time the persistent mode (one cooperative grid per launch table)")
     ap.add_argument("--tune", type=int, default=1,
                     help="choose each level's tile height by timing (the library's tuner) before the warm-up")
     ap.add_argument("--workload", default="airfoil",
