@@ -122,7 +122,8 @@ def test_batch_refuses_cases_inside_the_start_up_ramp():
     P.Batch([s]).close()
 
 
-def test_batch_run_to_steady_drops_converged_cases():
+@pytest.mark.parametrize("mode", ["graph", "persistent"])
+def test_batch_run_to_steady_drops_converged_cases(mode):
     """A case whose residual falls below the tolerance leaves the launches; the
     others go on.  The threshold is placed between the residuals the cases reach
     at the first check (a deterministic quantity: the same run repeated), so the
@@ -144,7 +145,10 @@ def test_batch_run_to_steady_drops_converged_cases():
 
     batched = [P.Solver(c, storage="f32") for c in cases]
     batch = P.Batch(batched)
-    batch.use_graph(True)
+    if mode == "graph":
+        batch.use_graph(True)
+    else:
+        batch.use_persistent(True)   # the tables are rebuilt when a case drops out
     steps, res = batch.run_to_steady(tol, max_super, check)
     assert batch.lups_per_super_step() == sum(s.lups_per_coarse_step() * p for s, p in zip(batched, per))
     batch.synchronize()
