@@ -1026,7 +1026,12 @@ __global__ __launch_bounds__(TILE_X * TY, 8) void k_step_batch_mixed(const StepA
 // the group writes that L2 back to memory and counts the group in at the grid
 // counter; the last group opens the grid's next generation; each group's last
 // workgroup then opens its group, and every workgroup discards its stale cache
-// lines.  The waits poll with relaxed loads (an acquire on every poll would
+// lines.  The step inside a group rests on the hardware, not on the language's
+// memory model: the vector L1 writes through, a store has reached the XCD's L2
+// when the wave's memory counter has drained, and one L2 serves every compute
+// unit of the XCD, so the writeback of the group's last workgroup carries the
+// stores of the whole group.  Between groups, release and acquire at device
+// scope order everything.  The waits poll with relaxed loads (an acquire on every poll would
 // invalidate the L2 under the workgroups still computing) and are bounded:
 // past spin_limit polls a wait sets the flag word and gives up, which only a
 // grid that is not co-resident can reach (the cooperative launch refuses such
@@ -1073,8 +1078,10 @@ __device__ __forceinline__ unsigned grid_register(unsigned* bar, unsigned nblock
     *x = xcc_id();
     unsigned* g = bar + BAR_STRIDE * (*x + 1);
     if (add_relaxed(g + 2, 1u) == 0) add_relaxed(bar + 4, 1u);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");   // the two counts above before the registration
     add_relaxed(bar + 3, 1u);
     bounded_wait(bar + 3, nblocks, true, bar + 2, spin_limit);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // every workgroup's counts after it
     return ld_relaxed(g + 2);
 }
 
@@ -1096,7 +1103,8 @@ __device__ __forceinline__ void grid_barrier(unsigned* bar, unsigned x, unsigned
             } else {
                 bounded_wait(bar + 1, gen, false, bar + 2, spin_limit);
             }
-            add_relaxed(g + 1, 1u);
+            // release: the reset of the group's count before a member's next arrival
+            __hip_atomic_fetch_add(g + 1, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         } else {
             bounded_wait(g + 1, ggen, false, bar + 2, spin_limit);
         }
