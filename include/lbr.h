@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define LBR_ABI_VERSION 5
+#define LBR_ABI_VERSION 6
 #define LBR_MAX_LEVELS 12
 
 enum lbr_status {
@@ -168,6 +168,14 @@ typedef struct lbr_config {
                                       0.2 sigma keeps it there where a large eddy viscosity on a
                                       fine level would not.  Below the limit the scheme is
                                       unchanged, bit for bit. */
+    double alpha_deg;              /* angle of attack in degrees (the incidence of the free
+                                      stream, Section 3.1.1): lbr_set_geometry turns every body
+                                      by -alpha_deg about alpha_pivot, so that the stream along
+                                      +x meets it at incidence alpha (nose up for alpha > 0);
+                                      C_D and C_L stay along and across +x.  0 for bodies given
+                                      at their incidence.  |alpha_deg| <= 90. */
+    double alpha_pivot[2];         /* physical point the bodies turn about (e.g. the
+                                      quarter chord) */
     lbr_alloc_fn alloc_fn;         /* optional device allocator */
     lbr_free_fn free_fn;
     void* alloc_user;
@@ -210,7 +218,10 @@ int lbr_create(const lbr_config* cfg, lbr_ctx** out);
 
 /* Wall geometry (Section 2.3: surface segments in 2D): n_bodies closed
    polylines, counter-clockwise (fluid on the right), given as consecutive
-   (x, y) pairs without repeating the first point; n_pts[b] >= 3.
+   (x, y) pairs without repeating the first point; n_pts[b] >= 3.  With a
+   non-zero lbr_config.alpha_deg each point is first turned by -alpha_deg
+   about alpha_pivot (x' = p + R(-alpha)(x - p), one rounding per product and
+   per sum).  The arrays are copied.
    Must be called before lbr_build (it may be called with n_bodies = 0).
    Errors: LBR_ERR_GEOMETRY for fewer than 3 points, a non-finite point or a
    body whose signed area is not positive (clockwise); LBR_ERR_STATE after

@@ -37,6 +37,7 @@ class Config(C.Structure):
         ("sponge_width", C.c_double), ("sponge_strength", C.c_double),
         ("ramp_steps", C.c_double), ("ramp_start", C.c_double),
         ("sa_mu_cap", C.c_double),
+        ("alpha_deg", C.c_double), ("alpha_pivot", C.c_double * 2),
     ]
 
 
@@ -200,6 +201,10 @@ def make_config(case) -> Config:
     c.ramp_steps = case.get("ramp_steps", 0.0)
     c.ramp_start = case.get("ramp_start", 0.0)
     c.sa_mu_cap = case.get("sa_mu_cap", 0.0)
+    # angle of attack turned by the oracle itself (the recipes' bodies come at
+    # their incidence; their "alpha_deg" entry only records it)
+    c.alpha_deg = case.get("config_alpha_deg", 0.0)
+    c.alpha_pivot[0], c.alpha_pivot[1] = case.get("config_alpha_pivot", (0.0, 0.0))
     return c
 
 

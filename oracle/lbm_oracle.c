@@ -1009,13 +1009,25 @@ int lbro_create(const lbro_config* cfg, int32_t n_bodies, const int32_t* n_pts, 
     return lbro_create_with_links(cfg, n_bodies, n_pts, xy, NULL, out);
 }
 
+/* Angle of attack (Section 3.1.1 gives the incidence of the free stream, which
+   runs along +x here): a body point x is turned by -alpha about the pivot p,
+   x' = p + R(-alpha) (x - p), R the rotation matrix. */
+static void turn_point(const lbro_config* cfg, double x, double y, double* xo, double* yo) {
+    const double a = -(cfg->alpha_deg * (3.14159265358979323846 / 180.0));
+    const double c = cos(a), s = sin(a);
+    const double dx = x - cfg->alpha_pivot[0], dy = y - cfg->alpha_pivot[1];
+    *xo = (c * dx - s * dy) + cfg->alpha_pivot[0];
+    *yo = (s * dx + c * dy) + cfg->alpha_pivot[1];
+}
+
 int lbro_create_with_links(const lbro_config* cfg, int32_t n_bodies, const int32_t* n_pts,
                            const double* xy, const char* links_path, lbro_sim** out) {
     *out = NULL;
     if (!cfg || cfg->n_levels < 1 || cfg->n_levels > LBRO_MAX_LEVELS || cfg->nx0 < 4 ||
         cfg->ny0 < 4 || !(cfg->dx0 > 0.0) || cfg->outlet < 0 || cfg->outlet > 2 ||
         cfg->sponge_width < 0.0 || cfg->sponge_strength < 0.0 || cfg->sponge_strength > 1.0 ||
-        cfg->ramp_steps < 0.0 || cfg->ramp_start < 0.0 || cfg->ramp_start > 1.0)
+        cfg->ramp_steps < 0.0 || cfg->ramp_start < 0.0 || cfg->ramp_start > 1.0 ||
+        !(fabs(cfg->alpha_deg) <= 90.0) || !isfinite(cfg->alpha_pivot[0]) || !isfinite(cfg->alpha_pivot[1]))
         return fail("invalid configuration");
     if ((cfg->bc[0] == LBRO_BC_PERIODIC) != (cfg->bc[1] == LBRO_BC_PERIODIC) ||
         (cfg->bc[2] == LBRO_BC_PERIODIC) != (cfg->bc[3] == LBRO_BC_PERIODIC))
@@ -1043,8 +1055,10 @@ int lbro_create_with_links(const lbro_config* cfg, int32_t n_bodies, const int32
         s->npts[b] = n_pts[b];
         s->poly[b] = malloc(2 * n_pts[b] * sizeof(double));
         for (int k = 0; k < n_pts[b]; ++k) {
-            s->poly[b][2 * k] = (p[2 * k] - cfg->origin[0]) / cfg->dx0;
-            s->poly[b][2 * k + 1] = (p[2 * k + 1] - cfg->origin[1]) / cfg->dx0;
+            double x = p[2 * k], y = p[2 * k + 1];
+            if (cfg->alpha_deg != 0.0) turn_point(cfg, p[2 * k], p[2 * k + 1], &x, &y);
+            s->poly[b][2 * k] = (x - cfg->origin[0]) / cfg->dx0;
+            s->poly[b][2 * k + 1] = (y - cfg->origin[1]) / cfg->dx0;
         }
         p += 2 * n_pts[b];
     }

@@ -65,6 +65,10 @@ typedef struct {
     double ramp_start;            /* initial fraction of u_ref under a start-up ramp */
     double sa_mu_cap;             /* SA face diffusivity limit in lattice units (not part of
                                      the method; <= 0: none, the scheme of eqs (12), (16)) */
+    double alpha_deg;             /* angle of attack in degrees: the bodies are turned by
+                                     -alpha about alpha_pivot before use (0: given at their
+                                     incidence); |alpha| <= 90 */
+    double alpha_pivot[2];        /* physical point they turn about */
 } lbro_config;
 
 typedef struct lbro_sim lbro_sim;

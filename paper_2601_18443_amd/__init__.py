@@ -17,7 +17,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbr.so")
 
-ABI_VERSION = 5
+ABI_VERSION = 6
 MAX_LEVELS = 12
 WALL_STRIDE = 28
 CUT_STRIDE = 16
@@ -50,6 +50,7 @@ class lbr_config(C.Structure):
         ("sponge_width", C.c_double), ("sponge_strength", C.c_double),
         ("ramp_steps", C.c_double), ("ramp_start", C.c_double), ("shift16", C.c_int32),
         ("health_every", C.c_int32), ("sa_mu_cap", C.c_double),
+        ("alpha_deg", C.c_double), ("alpha_pivot", C.c_double * 2),
         ("alloc_fn", ALLOC_FN), ("free_fn", FREE_FN), ("alloc_user", C.c_void_p),
         ("stream", C.c_void_p),
     ]
@@ -209,6 +210,10 @@ def make_config(case, storage="f32", stream=None, allocator=None) -> lbr_config:
     c.shift16 = 1 if shift else int(case.get("shift16", 0))
     c.sa_mu_cap = float(case.get("sa_mu_cap", 0.0))
     c.health_every = int(case.get("health_every", 0))
+    # angle of attack applied by the library (the recipes' bodies come at their
+    # incidence already; their "alpha_deg" entry only records it)
+    c.alpha_deg = float(case.get("config_alpha_deg", 0.0))
+    c.alpha_pivot[0], c.alpha_pivot[1] = case.get("config_alpha_pivot", (0.0, 0.0))
     if allocator is not None:
         c.alloc_fn, c.free_fn = allocator.alloc_cb, allocator.free_cb
     c.stream = stream

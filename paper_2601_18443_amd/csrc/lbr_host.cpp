@@ -1269,7 +1269,9 @@ int lbr_create(const lbr_config* cfg, lbr_ctx** out) {
         !std::isfinite(cfg->chi_inlet) || !std::isfinite(cfg->chi_init) || !std::isfinite(cfg->force[0]) ||
         !std::isfinite(cfg->force[1]) || !std::isfinite(cfg->origin[0]) || !std::isfinite(cfg->origin[1]) ||
         !std::isfinite(cfg->u_ref) || !std::isfinite(cfg->nu0) || !std::isfinite(cfg->dx0) ||
-        !std::isfinite(cfg->sponge_width) || !std::isfinite(cfg->ramp_steps) || !std::isfinite(cfg->sa_mu_cap))
+        !std::isfinite(cfg->sponge_width) || !std::isfinite(cfg->ramp_steps) || !std::isfinite(cfg->sa_mu_cap) ||
+        !(std::fabs(cfg->alpha_deg) <= 90.0) || !std::isfinite(cfg->alpha_pivot[0]) ||
+        !std::isfinite(cfg->alpha_pivot[1]))
         return LBR_ERR_INVALID_ARG;
     // side conditions the step implements: the inlet rule on x-lo, the outlet rules on
     // x-hi, symmetry and channel walls on the y sides (any other pairing would leave
@@ -1324,17 +1326,33 @@ int lbr_set_geometry(lbr_ctx* c, int32_t n_bodies, const int32_t* n_pts, const d
     c->npts.clear();
     c->off.assign(1, 0);
     c->polyflat.clear();
+    // angle of attack: each point turned by -alpha about the pivot, one product per
+    // statement (no fused multiply-add), then mapped to level-0 lattice units
+    const double a = -(c->cfg.alpha_deg * (M_PI / 180.0));
+    const double ca = std::cos(a), sa = std::sin(a);
+    const double px = c->cfg.alpha_pivot[0], py = c->cfg.alpha_pivot[1];
+    const bool turn = c->cfg.alpha_deg != 0.0;
+    std::vector<double> pt;
     const double* p = xy;
     for (int b = 0; b < n_bodies; ++b) {
         if (n_pts[b] < 3) return set_err(c, LBR_ERR_GEOMETRY, "body %d has fewer than 3 points", b);
+        pt.assign(p, p + 2 * n_pts[b]);
+        if (turn)
+            for (int k = 0; k < n_pts[b]; ++k) {
+                const double dx = pt[2 * k] - px, dy = pt[2 * k + 1] - py;
+                const double xc = ca * dx, ys = sa * dy, xs = sa * dx, yc = ca * dy;
+                const double rx = xc - ys, ry = xs + yc;
+                pt[2 * k] = rx + px;
+                pt[2 * k + 1] = ry + py;
+            }
         double area2 = 0.0;                       // twice the signed area (shoelace)
         for (int k = 0; k < n_pts[b]; ++k) {
-            const double x = (p[2 * k] - c->cfg.origin[0]) / c->cfg.dx0;
-            const double y = (p[2 * k + 1] - c->cfg.origin[1]) / c->cfg.dx0;
+            const double x = (pt[2 * k] - c->cfg.origin[0]) / c->cfg.dx0;
+            const double y = (pt[2 * k + 1] - c->cfg.origin[1]) / c->cfg.dx0;
             if (!std::isfinite(x) || !std::isfinite(y))
                 return set_err(c, LBR_ERR_GEOMETRY, "body %d has a non-finite point", b);
             const int k1 = (k + 1) % n_pts[b];
-            area2 += p[2 * k] * p[2 * k1 + 1] - p[2 * k1] * p[2 * k + 1];
+            area2 += pt[2 * k] * pt[2 * k1 + 1] - pt[2 * k1] * pt[2 * k + 1];
             c->polyflat.push_back(x);
             c->polyflat.push_back(y);
         }

@@ -78,6 +78,7 @@ def test_config_validation_without_gpu():
     ("omega_b", 0.0), ("omega_b", 2.0),                      # bulk rate in (0, 2)
     ("d_wr", 0.0), ("d_wv", -1.0), ("chi_init", float("inf")),
     ("u_ref", float("nan")), ("sponge_width", float("inf")), ("sa_mu_cap", float("nan")), ("health_every", -1),
+    ("alpha_deg", 90.5), ("alpha_deg", float("nan")),        # angle of attack within +-90 degrees
 ])
 def test_create_refuses_out_of_range_config(field, value):
     import paper_2601_18443_amd as P

@@ -110,6 +110,31 @@ def test_airfoil_small_fp64():
         _check64(g, o, case)
 
 
+def test_angle_of_attack_from_the_config_fp64():
+    """Incidence set in the configuration (alpha 10 degrees about the quarter
+    chord; Section 3.1.1) on an unturned body: the library turns the body as the
+    oracle does (same grid, fields, wall records, surface data and forces after
+    one and four coarse steps within the FP64 bounds), and its result is that of
+    the recipe's turned body bit for bit (FP32)."""
+    flat = LI.case_airfoil_small(alpha_deg=0.0)
+    flat.update(config_alpha_deg=10.0, config_alpha_pivot=(0.25, 0.0))
+    o, g = _pair(flat, "f64")
+    assert U.structure_mismatch(g, o, flat["n_levels"]) == []
+    for steps in (1, 3):
+        o.advance(steps)
+        g.advance(steps)
+        _check64(g, o, flat)
+    a = U.gpu_solver(LI.case_airfoil_small(alpha_deg=10.0), "f32")
+    b = U.gpu_solver(flat, "f32")
+    a.advance(2)
+    b.advance(2)
+    for l in range(flat["n_levels"]):
+        assert a.level_info(l) == b.level_info(l)
+        for f in range(4):
+            np.testing.assert_array_equal(a.field(l, f), b.field(l, f))
+    np.testing.assert_array_equal(a.forces(), b.forces())
+
+
 @pytest.mark.parametrize("levels", [1, 2])
 def test_airfoil_with_one_or_two_levels_fp64(levels):
     """Degenerate depths of the recursion: one level (wall nodes, domain edges

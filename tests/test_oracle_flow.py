@@ -485,3 +485,39 @@ def test_start_up_ramp_of_the_inlet_velocity():
         s.advance(1)
         expect = 0.05 * (0.5 - 0.5 * math.cos(math.pi * min(n, 4) / 4.0))
         np.testing.assert_allclose(s.field(0, oracle.F_UX)[:, 0], expect, rtol=0, atol=1e-15)
+
+
+def test_angle_of_attack_in_the_config_is_the_turned_body():
+    """Section 3.1.1 sets the incidence of the free stream (along +x here).  An
+    unturned body with alpha_deg = 10 and pivot (0.25, 0) in the configuration
+    must be the recipe's body turned by the recipe's own rotation (lbr_inputs.rotate,
+    written separately): the same grid, wall records and, two coarse steps
+    later, the same fields bit for bit.  Nose up for alpha > 0: the leftmost
+    wall point lies above the axis, near 0.25 sin(alpha)."""
+    turned = LI.case_airfoil_small(alpha_deg=10.0)
+    flat = LI.case_airfoil_small(alpha_deg=0.0)
+    flat.update(config_alpha_deg=10.0, config_alpha_pivot=(0.25, 0.0))
+    a, b = oracle.Sim(turned), oracle.Sim(flat)
+    n = turned["n_levels"]
+    for l in range(n):
+        assert a.level_info(l) == b.level_info(l)
+    np.testing.assert_array_equal(a.wall(n - 1), b.wall(n - 1))
+    a.advance(2)
+    b.advance(2)
+    for l in range(n):
+        for f in (oracle.F_RHO, oracle.F_UX, oracle.F_UY, oracle.F_CHI):
+            np.testing.assert_array_equal(a.field(l, f), b.field(l, f))
+    np.testing.assert_array_equal(a.forces(), b.forces())
+    w = b.wall(n - 1)
+    dx = flat["dx0"] / 2 ** (n - 1)                  # wall points are in finest-level cells
+    x = flat["origin"][0] + w[:, 2] * dx
+    y = flat["origin"][1] + w[:, 3] * dx
+    k = int(np.argmin(x))
+    assert 0.0 < y[k] < 2 * 0.25 * math.sin(math.radians(10.0)), (x[k], y[k])
+
+
+def test_angle_of_attack_outside_the_range_is_refused():
+    c = LI.case_airfoil_small(alpha_deg=0.0)
+    c.update(config_alpha_deg=91.0)
+    with pytest.raises(RuntimeError, match="invalid configuration"):
+        oracle.Sim(c)
