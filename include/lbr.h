@@ -363,6 +363,14 @@ int lbr_rake_noalloc(lbr_ctx* ctx, double x0, double y0, double x1, double y1, i
    n_pts[body] doubles each. */
 int lbr_surface(lbr_ctx* ctx, int32_t body, double* cp, double* cf);
 
+/* y+ of the virtual node V at the same segment centroids (the quantity of
+   Section 3.1.3 and Figure 6 along the surface): u_tau d_WV / nu of each wall
+   node (as in lbr_wall_yplus), interpolated to the centroids with the nodes and
+   weights that lbr_surface uses for Cp and Cf.  yplus_v holds n_pts[body]
+   doubles; 0 for wall models without a wall function.  Waits for the context's
+   stream.  Errors: LBR_ERR_INVALID_ARG (no build, bad body, null output). */
+int lbr_surface_yplus(lbr_ctx* ctx, int32_t body, double* yplus_v);
+
 /* Integrated coefficients of eq. (30) for one body (body = -1: all bodies):
    out = {C_Df, C_Dp, C_D, C_L (pressure only, as in eq. (30)), C_F . e_y}.
    Sums are FP64 and deterministic. */

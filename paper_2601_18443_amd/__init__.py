@@ -90,6 +90,7 @@ def lib():
         L.lbr_wall_count.argtypes = [p, i32]
         L.lbr_read_wall.argtypes = [p, i32, dp]
         L.lbr_surface.argtypes = [p, i32, dp, dp]
+        L.lbr_surface_yplus.argtypes = [p, i32, dp]
         L.lbr_forces.argtypes = [p, i32, dp]
         L.lbr_residual.argtypes = [p, dp]
         L.lbr_run_to_steady.argtypes = [p, C.c_double, i64, i64, C.POINTER(C.c_int64), dp]
@@ -341,6 +342,12 @@ class Solver:
         cp, cf = np.zeros(n), np.zeros(n)
         self._check(lib().lbr_surface(self.h, body, _dp(cp), _dp(cf)))
         return cp, cf
+
+    def surface_yplus(self, body=0):
+        """y+ of the virtual node at the segment centroids of one body."""
+        yv = np.zeros(len(self.case["bodies"][body]))
+        self._check(lib().lbr_surface_yplus(self.h, body, _dp(yv)))
+        return yv
 
     def residual(self):
         r = C.c_double()

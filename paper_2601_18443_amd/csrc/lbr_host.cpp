@@ -94,6 +94,8 @@ struct SurfaceBody {
     double* seg = nullptr;
     int32_t* near = nullptr;
     double* wgt = nullptr;
+    std::vector<int32_t> near_h;   // host copies of near and wgt (per-segment y+)
+    std::vector<double> wgt_h;
 };
 
 }  // namespace
@@ -1187,7 +1189,9 @@ int build_surface(lbr_ctx* c, const std::vector<double>& seg) {
         sb.nseg = n;
         if (int r = upload(c, &sb.seg, sg, nullptr)) return r;
         if (int r = upload(c, &sb.near, near, nullptr)) return r;
+        sb.near_h = near;
         if (int r = upload(c, &sb.wgt, wgt, nullptr)) return r;
+        sb.wgt_h = wgt;
     }
     c->surf_cp = static_cast<double*>(dalloc(c, (size_t)maxseg * sizeof(double)));
     c->surf_cf = static_cast<double*>(dalloc(c, (size_t)maxseg * sizeof(double)));
@@ -2015,6 +2019,36 @@ int lbr_surface(lbr_ctx* c, int32_t body, double* cp, double* cf) {
         return set_err(c, LBR_ERR_INVALID_ARG, "bad body %d", body);
     double sums[4];
     return surface_eval(c, body, cp, cf, sums);
+}
+
+int lbr_surface_yplus(lbr_ctx* c, int32_t body, double* yplus_v) {
+    if (!c || !c->built || !yplus_v) return LBR_ERR_INVALID_ARG;
+    if (body < 0 || body >= (int)c->surf.size() || c->wall_level < 0)
+        return set_err(c, LBR_ERR_INVALID_ARG, "bad body %d", body);
+    const SurfaceBody& sb = c->surf[body];
+    Level& L = c->lv[c->wall_level];
+    const int nb = (int)L.nodes.size();
+    std::vector<double> st((size_t)std::max(nb, 1) * 8, 0.0);
+    if (nb > 0) {
+        if (int r = eval_wall(c, c->wall_level)) return r;
+        HIPCHK(c, hipMemcpyAsync(st.data(), L.bout, (size_t)nb * 8 * sizeof(double), hipMemcpyDeviceToHost,
+                                 c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    // y+ of V at each node, then the weights and order of the Cp / Cf interpolation
+    const double dwv = c->cfg.d_wv;
+    for (int k = 0; k < sb.nseg; ++k) {
+        double sw = 0.0, sy = 0.0;
+        for (int m = 0; m < 2; ++m) {
+            const int b = sb.near_h[2 * k + m];
+            if (b < 0) continue;
+            const double w = sb.wgt_h[2 * k + m];
+            sw += w;
+            sy += w * (st[8 * b] / L.nu * dwv);
+        }
+        yplus_v[k] = sw > 0.0 ? sy / sw : 0.0;
+    }
+    return LBR_OK;
 }
 
 int lbr_forces(lbr_ctx* c, int32_t body, double out[5]) {

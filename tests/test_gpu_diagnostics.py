@@ -53,6 +53,36 @@ def test_wall_yplus_of_r_b_and_v(pair):
     assert seen > 0
 
 
+def test_surface_yplus_of_v_at_the_segment_centroids(pair):
+    """lbr_surface_yplus: y+ of V along the surface (Section 3.1.3, Figure 6) at
+    the segment centroids, interpolated as Cp and Cf are after eq (30): from the
+    two wall nodes nearest to the centroid, weighted by inverse squared distance
+    (a node on the centroid alone).  Rebuilt here from the oracle's wall records
+    (u_tau, IW, body) and the body's polyline."""
+    case, g, o = pair
+    lf = case["n_levels"] - 1
+    U = case["mach"] / math.sqrt(3.0)
+    nu = U * (case["ref_length"] / case["dx0"]) / case["reynolds"] * 2 ** lf
+    wo = o.wall(lf)
+    mine = wo[wo[:, 15] == 0]                       # column 15: the body
+    yv_node = mine[:, 8] * case["d_wv"] / nu
+    dx = case["dx0"] / 2 ** lf
+    xy = (np.asarray(case["bodies"][0]) - np.asarray(case["origin"])) / dx
+    mid = 0.5 * (xy + np.roll(xy, -1, axis=0))
+    expect = np.empty(len(mid))
+    for k, (mx, my) in enumerate(mid):
+        d2 = (mine[:, 2] - mx) ** 2 + (mine[:, 3] - my) ** 2
+        a, b = np.argsort(d2, kind="stable")[:2]
+        if d2[a] < 1e-24:
+            expect[k] = yv_node[a]
+        else:
+            expect[k] = (yv_node[a] / d2[a] + yv_node[b] / d2[b]) / (1.0 / d2[a] + 1.0 / d2[b])
+    got = g.surface_yplus(0)
+    assert got.shape == expect.shape
+    np.testing.assert_allclose(got, expect, rtol=1e-9, atol=1e-12)
+    assert np.all(got > 0)
+
+
 def _oracle_rake(case, o, p0, p1, n):
     out = np.full((n, 5), np.nan)
     out[:, 0] = -1
