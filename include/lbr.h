@@ -250,7 +250,9 @@ int lbr_set_geometry(lbr_ctx* ctx, int32_t n_bodies, const int32_t* n_pts, const
                  cut.
    lbr_build then takes these nodes for level l instead of intersecting the
    links with the polylines; the cell types, the wall-distance field and the
-   surface segments of Cp and Cf still come from the polylines.  The
+   surface segments of Cp and Cf still come from the polylines.  The records
+   are in the frame of the grid: with a non-zero alpha_deg they describe the
+   turned bodies.  The
    reference-point stencils are derived from IW and the normal as for
    generated nodes.  Call after lbr_create and before lbr_build; a second call
    for a level replaces its list, n = 0 withdraws it.  The records are copied.
