@@ -50,7 +50,7 @@ struct Level {
     std::vector<uint8_t> inside;
     std::vector<int32_t> bidx;
     std::vector<Node> nodes;
-    std::vector<uint32_t> rows[NTY]; // k_step tiles of each height (x, y, restriction bit)
+    std::vector<uint32_t> rows[NTY]; // k_step tiles of each height (x, y, ghost and restriction bits)
     int ty = TILE_Y_DEFAULT;         // index of the tile height k_step uses on this level
     std::vector<int32_t> owned, ghosts, covb, edge;
     int64_t n_fluid = 0, n_ghost = 0, n_cut = 0;
@@ -761,6 +761,25 @@ void mark_restriction_tiles(lbr_ctx* c, Level& L) {
                           (L.flag[(long)(ty * H + y) * L.box.pitch + tx * TILE_X + x] & F_TYPE) == T_FLUID;
                 }
             if (any) tl |= 1u << 31;
+        }
+    }
+}
+
+// Marks (bit 15 of the tile word) the tiles whose cells or one-cell halo ring
+// hold ghost cells: the step stages the parent's chi, u, v under them in LDS.
+void mark_ghost_tiles(Level& L) {
+    for (int k = 0; k < NTY; ++k) {
+        const int H = TILE_YS[k];
+        for (uint32_t& tl : L.rows[k]) {
+            const int tx = tl & 0x7fff, ty = (tl >> 16) & 0x7fff;
+            bool any = false;
+            for (int y = -1; y <= H && !any; ++y)
+                for (int x = -1; x <= TILE_X && !any; ++x) {
+                    const int ly = ty * H + y, lx = tx * TILE_X + x;
+                    if (ly < 0 || ly >= L.box.ny || lx < 0 || lx >= L.box.pitch) continue;
+                    any = (L.flag[(long)ly * L.box.pitch + lx] & F_TYPE) == T_GHOST;
+                }
+            if (any) tl |= 1u << 15;
         }
     }
 }
@@ -1499,6 +1518,7 @@ int lbr_build(lbr_ctx* c) {
                            0x7fff * TILE_YS[0]);
         make_rows(L);
         mark_restriction_tiles(c, L);
+        mark_ghost_tiles(L);
         if (int r = alloc_level(c, L)) return r;
         L.dbody.clear();
         L.dbody.shrink_to_fit();

@@ -80,7 +80,7 @@ struct StepArgs {
     const uint32_t* lmask;           // per cell: bit i, source c - c_i is owned fluid;
                                      // bit 16 + i, source is a ghost; bit 31, lower-left
                                      // child of a covered coarse cell next to coarse fluid
-    const uint32_t* tiles;           // active 64 x ty tiles, (tx | ty << 16 | restriction << 31)
+    const uint32_t* tiles;           // active 64 x ty tiles, (tx | ghost << 15 | ty << 16 | restriction << 31)
     int ntiles;
     const int32_t* edge;             // level-0 domain-edge cells that are not wall nodes
     int nedge;

@@ -744,15 +744,45 @@ __device__ __forceinline__ void boundary_node(const StepArgs<ST, CT>& a, int b) 
 // LDS of a tile workgroup: the 3 x 3 stencil values of the tile and its halo,
 // and the restriction staging.  Keyed on the arithmetic type and tile height
 // only, so that the storage formats of a mixed launch share one allocation.
+constexpr int GC_W = TILE_X / 2 + 4;   // parent columns under a tile and its halo, with the fill stencil
+
 template <class CT, int TY>
 struct TileShared {
     CT n[TY + 2][TILE_X + 2], u[TY + 2][TILE_X + 2], v[TY + 2][TILE_X + 2];
-    CT r[4][TY][TILE_X];
+    union {
+        CT r[4][TY][TILE_X];                // restriction, after the update
+        CT gc[3][TY / 2 + 4][GC_W];         // the parent's chi, u, v under a ghost tile, before it
+    };
 };
 template <class CT, int TY>
 __device__ __forceinline__ TileShared<CT, TY>& tile_shared() {
     __shared__ TileShared<CT, TY> sh;
     return sh;
+}
+
+// ghost_fill from the parent's chi, u, v staged in LDS (gc[.][0][0] holds the
+// parent cell (cpx0, cpy0)): the same arithmetic in the same order, so the same
+// values bit for bit
+template <class CT, int TY>
+__device__ __forceinline__ void ghost_fill_lds(const TileShared<CT, TY>& sh, int cpx0, int cpy0, int gx, int gy,
+                                               CT& n, CT& u, CT& v) {
+    const int px = gx >> 1, py = gy >> 1;
+    const CT ox = (gx & 1) ? CT(0.25) : CT(-0.25), oy = (gy & 1) ? CT(0.25) : CT(-0.25);
+    CT sn = 0, su = 0, sv = 0, xn = 0, xu = 0, xv = 0, yn = 0, yu = 0, yv = 0;
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+            const int r = py + dy - cpy0, w = px + dx - cpx0;
+            const CT a = sh.gc[0][r][w], b = sh.gc[1][r][w], c = sh.gc[2][r][w];
+            sn += a; su += b; sv += c;
+            xn += CT(dx) * a; xu += CT(dx) * b; xv += CT(dx) * c;
+            yn += CT(dy) * a; yu += CT(dy) * b; yv += CT(dy) * c;
+        }
+    const CT k9 = CT(1.0 / 9.0), k6 = CT(1.0 / 6.0);
+    n = sn * k9 + (ox * xn + oy * yn) * k6;
+    u = su * k9 + (ox * xu + oy * yu) * k6;
+    v = sv * k9 + (ox * xv + oy * yv) * k6;
 }
 
 // Populations a tile cell takes from the neighbouring levels.  A cell of the
@@ -834,6 +864,9 @@ __device__ __forceinline__ void step_block(const StepArgs<ST, CT>& a, const int 
     const int lane = threadIdx.x & 63, wy = threadIdx.x >> 6;
     const int tx0 = (int)(tile & 0x7fffu) * TILE_X, ty0 = (int)((tile >> 16) & 0x7fffu) * TY;
     const bool restrict_tile = (tile >> 31) && a.substep == 2;   // uniform over the workgroup
+    // ghost tiles (cells or halo hold ghost cells) of the wider formats stage the
+    // parent's chi, u, v in LDS (for 16-bit storage it measured slower)
+    const bool ghost_tile = sizeof(ST) >= 4 && ((tile >> 15) & 1u);
     const int lx = tx0 + lane, ly = ty0 + wy;
     const long c = (long)ly * pitch + lx;
     const int gx = lx + a.box.gx0, gy = ly + a.box.gy0;
@@ -886,6 +919,27 @@ __device__ __forceinline__ void step_block(const StepArgs<ST, CT>& a, const int 
             hv[k] = bld<CT, CT>(rm, he * CS, 2u * (uint32_t)P * CS);
         }
     }
+    // The ghost fill of a ghost tile reads the parent's chi, u, v from LDS, staged
+    // here from the first round of loads, instead of 27 scattered loads per ghost
+    // cell issued once the flags have come (the tiles that end the latency-bound
+    // launches).  Reads are bounds-checked: what lies outside the parent's box
+    // reads 0, and no ghost cell's stencil reaches it.
+    constexpr int GR = TY / 2 + 4;
+    const int cpx0 = ((a.box.gx0 + tx0 - 1) >> 1) - 1, cpy0 = ((a.box.gy0 + ty0 - 1) >> 1) - 1;
+    if (ghost_tile) {
+        const Rsrc rcn = make_rsrc(a.cchi, a.cbox.plane);
+        const Rsrc rcu = make_rsrc(a.cmac + a.cbox.plane, a.cbox.plane);
+        const Rsrc rcv = make_rsrc(a.cmac + 2 * a.cbox.plane, a.cbox.plane);
+        for (int k = (int)threadIdx.x; k < GR * GC_W; k += NT) {
+            const int r = k / GC_W, w = k - r * GC_W;
+            const long q = (long)(cpy0 + r - a.cbox.gy0) * a.cbox.pitch + (cpx0 + w - a.cbox.gx0);
+            const uint32_t o = (uint32_t)q * CS;
+            lds.gc[0][r][w] = bld<CT, CT>(rcn, o, 0);
+            lds.gc[1][r][w] = bld<CT, CT>(rcu, o, 0);
+            lds.gc[2][r][w] = bld<CT, CT>(rcv, o, 0);
+        }
+        __syncthreads();
+    }
     const int type = fl & F_TYPE;
     // 16-bit storage takes the neighbouring levels' populations before the
     // stencil staging, so that those loads overlap the barrier; wider formats
@@ -898,16 +952,21 @@ __device__ __forceinline__ void step_block(const StepArgs<ST, CT>& a, const int 
         else if (type == T_FLUID && !(fl & (F_WALL | F_EDGE)))
             band_neighbour_cell<ST, CT>(a, fl, lm, gx, gy, s);
     }
-    if (type == T_GHOST) ghost_fill(a.cmac, a.cchi, a.cbox, gx, gy, own_n, own_u, own_v);
+    if (type == T_GHOST) {
+        if (ghost_tile) ghost_fill_lds<CT, TY>(lds, cpx0, cpy0, gx, gy, own_n, own_u, own_v);
+        else ghost_fill(a.cmac, a.cchi, a.cbox, gx, gy, own_n, own_u, own_v);
+    }
     sh_n[wy + 1][lane + 1] = own_n;
     sh_u[wy + 1][lane + 1] = own_u;
     sh_v[wy + 1][lane + 1] = own_v;
 #pragma unroll
     for (int k = 0; k < NS; ++k)
         if (halo[k]) {
-            if ((hfl[k] & F_TYPE) == T_GHOST)
-                ghost_fill(a.cmac, a.cchi, a.cbox, a.box.gx0 + tx0 + hx[k], a.box.gy0 + ty0 + hy[k], hn[k], hu[k],
-                           hv[k]);
+            if ((hfl[k] & F_TYPE) == T_GHOST) {
+                const int hgx = a.box.gx0 + tx0 + hx[k], hgy = a.box.gy0 + ty0 + hy[k];
+                if (ghost_tile) ghost_fill_lds<CT, TY>(lds, cpx0, cpy0, hgx, hgy, hn[k], hu[k], hv[k]);
+                else ghost_fill(a.cmac, a.cchi, a.cbox, hgx, hgy, hn[k], hu[k], hv[k]);
+            }
             sh_n[hy[k] + 1][hx[k] + 1] = hn[k];
             sh_u[hy[k] + 1][hx[k] + 1] = hu[k];
             sh_v[hy[k] + 1][hx[k] + 1] = hv[k];
