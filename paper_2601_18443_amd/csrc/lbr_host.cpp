@@ -784,6 +784,47 @@ void mark_ghost_tiles(Level& L) {
     }
 }
 
+// Orders each XCD's share of a short tile list so that the slow tiles start
+// first: tiles holding ghost cells, then tiles with other neighbouring-level
+// work (near-ghost and coalescence cells, restriction anchors, ghost cells in
+// the halo), then the rest, each group in its original order.  The step maps
+// block b to tile (b mod 8) * per + b / 8, so each XCD keeps its tiles.  Only
+// lists of at most four generations of resident workgroups are reordered: there
+// the last generation's tail sets the launch time; longer launches run at the
+// memory system's rate and keep the row order, whose neighbouring tiles share
+// halo rows in the XCD's L2.  Tiles of one launch are independent, so the order
+// changes no result.
+void order_tiles(Level& L, int cus) {
+    for (int k = 0; k < NTY; ++k) {
+        const int H = TILE_YS[k];
+        std::vector<uint32_t>& rows = L.rows[k];
+        const int n = (int)rows.size(), per = (n + 7) >> 3;
+        const long resident = (long)cus * 32 / H;       // 8 waves per SIMD, 4 SIMDs; H waves per workgroup
+        if (resident <= 0 || n > 4 * resident) continue;
+        std::vector<std::pair<int, uint32_t>> keyed(n);
+        for (int t = 0; t < n; ++t) {
+            const uint32_t tl = rows[t];
+            const int tx = tl & 0x7fff, ty = (tl >> 16) & 0x7fff;
+            bool ghost = false, other = (tl >> 31) || ((tl >> 15) & 1u);
+            for (int y = 0; y < H; ++y)
+                for (int x = 0; x < TILE_X; ++x) {
+                    const uint8_t f = L.flag[(long)(ty * H + y) * L.box.pitch + tx * TILE_X + x];
+                    ghost = ghost || (f & F_TYPE) == T_GHOST;
+                    other = other || (f & (F_NEARGHOST | F_IFACE));
+                }
+            keyed[t] = {ghost ? 0 : (other ? 1 : 2), tl};
+        }
+        for (int x = 0; x < 8; ++x) {
+            const int a = std::min(n, x * per), b = std::min(n, (x + 1) * per);
+            std::stable_sort(keyed.begin() + a, keyed.begin() + b,
+                             [](const std::pair<int, uint32_t>& p, const std::pair<int, uint32_t>& q) {
+                                 return p.first < q.first;
+                             });
+        }
+        for (int t = 0; t < n; ++t) rows[t] = keyed[t].second;
+    }
+}
+
 Prec level_storage(const lbr_ctx* c, int l) {
     if (c->cfg.storage != LBR_STORE_MIXED) return c->prec;
     return l >= c->cfg.n_levels - 2 ? P_F32 : P_F16;
@@ -1509,6 +1550,9 @@ int lbr_build(lbr_ctx* c) {
         const std::vector<double>& given = c->cut_in[L.l];
         if (int r = given.empty() ? build_walls(c, L, seg) : walls_from_list(c, L, given)) return r;
     }
+    int cus = 0, dev = 0;                            // compute units, for the tile order
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        cus = 0;
     for (Level& L : c->lv) {
         // a tile is addressed by 15-bit column and row indices (for every tile
         // height the tuner may pick)
@@ -1519,6 +1563,7 @@ int lbr_build(lbr_ctx* c) {
         make_rows(L);
         mark_restriction_tiles(c, L);
         mark_ghost_tiles(L);
+        order_tiles(L, cus);
         if (int r = alloc_level(c, L)) return r;
         L.dbody.clear();
         L.dbody.shrink_to_fit();
