@@ -2415,6 +2415,9 @@ int batch_fill(lbr_batch* b, std::vector<Item>& it, int a, int e, const std::vec
 // groups decide the tile height of every item (a merged launch takes its main
 // part's); the arguments are then filled for that table.
 int batch_build(lbr_batch* b) {
+    int cus = 0, dev = 0;                            // compute units, for the part order
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        cus = 0;
     std::vector<std::pair<int, int>> seq;
     batch_schedule(b, 0, 0, seq);
     const int per = (int)seq.size();
@@ -2452,7 +2455,17 @@ int batch_build(lbr_batch* b) {
             for (int k : grp)
                 if (items[k].st != m.st) st = P_MIXED;
             lbr_batch::Launch ln{parts.size(), (int)starts.size(), 0, 0, m.v, st, TILE_YS[tk[grp[0]]]};
-            for (int k : grp) {
+            // a short launch (its main part at most four generations of resident
+            // workgroups) lays out the merged coarser parts first, so that their
+            // slow ghost-band tiles do not start in its tail; parts are
+            // independent, so the order changes no result
+            long main_blocks = 0;
+            for (int nb : m.blocks) main_blocks += nb;
+            const long resident = (long)cus * 32 / TILE_YS[tk[grp[0]]];
+            const bool coarse_first = grp.size() > 1 && main_blocks <= 4 * resident;
+            std::vector<int> order(grp.begin(), grp.end());
+            if (coarse_first) std::rotate(order.begin(), order.begin() + 1, order.end());
+            for (int k : order) {
                 const Item& x = items[k];
                 parts.insert(parts.end(), x.args.begin(), x.args.end());
                 for (int nb : x.blocks) {
