@@ -785,46 +785,49 @@ __device__ __forceinline__ void ghost_fill_lds(const TileShared<CT, TY>& sh, int
     v = sv * k9 + (ox * xv + oy * yv) * k6;
 }
 
-// Populations a tile cell takes from the neighbouring levels.  A cell of the
-// fine ghost band carries exploded coarse populations (first sub-step) and fine
-// ones one cell per sub-step, with no collision: stored here.
+// The parent populations a ghost cell (explosion: every direction whose source is
+// not fluid, or not a ghost on the second sub-step, from k cells back) and a fine
+// cell next to the ghost band (first sub-step: the directions whose source is a
+// ghost) take, in one predicated pass for both kinds of cell, so that a wave
+// holding both issues all its loads before one wait.
 template <class ST, class CT>
-__device__ __forceinline__ void ghost_band_cell(const StepArgs<ST, CT>& a, uint32_t lm, int gx, int gy,
-                                                const CT s[9], Rsrc rfo, uint32_t e, long P) {
-    constexpr uint32_t SS = sizeof(ST);
-    const int k = (a.substep == 1) ? 1 : 2;
+__device__ __forceinline__ void parent_pops(const StepArgs<ST, CT>& a, int type, uint8_t fl, uint32_t lm, int gx,
+                                            int gy, CT s[9]) {
+    const bool ghost = type == T_GHOST;
+    const bool near = type == T_FLUID && !(fl & (F_WALL | F_EDGE | F_IFACE)) && (fl & F_NEARGHOST) && a.substep == 1;
+    if (!(ghost || near)) return;
+    const int k = (ghost && a.substep == 2) ? 2 : 1;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
         const bool src_fluid = (lm >> i) & 1u, src_ghost = (lm >> (16 + i)) & 1u;
-        CT w = s[i];
-        if (!(src_fluid || (src_ghost && a.substep == 2)))
-            w = coarse_val(a, i, gx - k * CX[i], gy - k * CY[i]);
-        bst<ST, CT>(rfo, e * SS, (uint32_t)(i * P) * SS, toshift<ST, CT>(w, a.dsh, i));
+        const bool need = ghost ? !(src_fluid || (src_ghost && a.substep == 2)) : src_ghost;
+        if (need) s[i] = coarse_val(a, i, gx - k * CX[i], gy - k * CY[i]);
     }
 }
 
-// A coarse interface cell takes the mean of its four children (coalescence); a
-// fine cell next to the ghost band takes exploded coarse populations on the
-// first sub-step.  Other cells keep what they pulled.
+// A ghost cell stores what it carries (after parent_pops), with no collision.
 template <class ST, class CT>
-__device__ __forceinline__ void band_neighbour_cell(const StepArgs<ST, CT>& a, uint8_t fl, uint32_t lm, int gx, int gy,
-                                                    CT s[9]) {
-    if (fl & F_IFACE) {
-        const long f0 = (long)(2 * gy - a.fbox.gy0) * a.fbox.pitch + (2 * gx - a.fbox.gx0);
-        if constexpr (std::is_same<CT, float>::value) {
-            if (a.fst == P_F16)
-                coalesce<__half, CT>(static_cast<const __half*>(a.ffine), a.fbox.plane, a.fbox.pitch, f0, a.dsh, s);
-            else if (a.fst == P_F32)
-                coalesce<float, CT>(static_cast<const float*>(a.ffine), a.fbox.plane, a.fbox.pitch, f0, a.dsh, s);
-            else
-                coalesce<ST, CT>(static_cast<const ST*>(a.ffine), a.fbox.plane, a.fbox.pitch, f0, a.dsh, s);
-        } else {
-            coalesce<ST, CT>(static_cast<const ST*>(a.ffine), a.fbox.plane, a.fbox.pitch, f0, a.dsh, s);
-        }
-    } else if ((fl & F_NEARGHOST) && a.substep == 1) {
+__device__ __forceinline__ void ghost_band_store(const StepArgs<ST, CT>& a, const CT s[9], Rsrc rfo, uint32_t e,
+                                                 long P) {
+    constexpr uint32_t SS = sizeof(ST);
 #pragma unroll
-        for (int i = 0; i < 9; ++i)
-            if ((lm >> (16 + i)) & 1u) s[i] = coarse_val(a, i, gx - CX[i], gy - CY[i]);
+    for (int i = 0; i < 9; ++i) bst<ST, CT>(rfo, e * SS, (uint32_t)(i * P) * SS, toshift<ST, CT>(s[i], a.dsh, i));
+}
+
+// A coarse interface cell takes the mean of its four children (coalescence).
+template <class ST, class CT>
+__device__ __forceinline__ void iface_cell(const StepArgs<ST, CT>& a, uint8_t fl, int gx, int gy, CT s[9]) {
+    if (!(fl & F_IFACE)) return;
+    const long f0 = (long)(2 * gy - a.fbox.gy0) * a.fbox.pitch + (2 * gx - a.fbox.gx0);
+    if constexpr (std::is_same<CT, float>::value) {
+        if (a.fst == P_F16)
+            coalesce<__half, CT>(static_cast<const __half*>(a.ffine), a.fbox.plane, a.fbox.pitch, f0, a.dsh, s);
+        else if (a.fst == P_F32)
+            coalesce<float, CT>(static_cast<const float*>(a.ffine), a.fbox.plane, a.fbox.pitch, f0, a.dsh, s);
+        else
+            coalesce<ST, CT>(static_cast<const ST*>(a.ffine), a.fbox.plane, a.fbox.pitch, f0, a.dsh, s);
+    } else {
+        coalesce<ST, CT>(static_cast<const ST*>(a.ffine), a.fbox.plane, a.fbox.pitch, f0, a.dsh, s);
     }
 }
 
@@ -947,10 +950,11 @@ __device__ __forceinline__ void step_block(const StepArgs<ST, CT>& a, const int 
     // order changes no result)
     constexpr bool early = sizeof(ST) == 2;
     if constexpr (early) {
+        parent_pops<ST, CT>(a, type, fl, lm, gx, gy, s);
         if (type == T_GHOST)
-            ghost_band_cell<ST, CT>(a, lm, gx, gy, s, make_rsrc(a.fdst - pad, 9 * P + 2 * pad), e, P);
+            ghost_band_store<ST, CT>(a, s, make_rsrc(a.fdst - pad, 9 * P + 2 * pad), e, P);
         else if (type == T_FLUID && !(fl & (F_WALL | F_EDGE)))
-            band_neighbour_cell<ST, CT>(a, fl, lm, gx, gy, s);
+            iface_cell<ST, CT>(a, fl, gx, gy, s);
     }
     if (type == T_GHOST) {
         if (ghost_tile) ghost_fill_lds<CT, TY>(lds, cpx0, cpy0, gx, gy, own_n, own_u, own_v);
@@ -976,11 +980,12 @@ __device__ __forceinline__ void step_block(const StepArgs<ST, CT>& a, const int 
     const Rsrc rfo = make_rsrc(a.fdst - pad, 9 * P + 2 * pad);
     bool update = false;
     CT m_rho = CT(0), m_ux = CT(0), m_uy = CT(0), m_chi = CT(0);
+    if constexpr (!early) parent_pops<ST, CT>(a, type, fl, lm, gx, gy, s);
     if (type == T_GHOST) {
-        if constexpr (!early) ghost_band_cell<ST, CT>(a, lm, gx, gy, s, rfo, e, P);
+        if constexpr (!early) ghost_band_store<ST, CT>(a, s, rfo, e, P);
     } else if (type == T_FLUID && !(fl & (F_WALL | F_EDGE))) {   // others: side-stream kernels
         update = true;
-        if constexpr (!early) band_neighbour_cell<ST, CT>(a, fl, lm, gx, gy, s);
+        if constexpr (!early) iface_cell<ST, CT>(a, fl, gx, gy, s);
         // SA-neg: chi at the new time level
         CT chi_new;
         if (a.frozen) {
