@@ -429,7 +429,8 @@ int lbr_use_graph(lbr_ctx* ctx, int32_t enable);
    bit-identical for any choice.  lbr_tune times each height on every level
    with that level's first sub-step from the current state (trials launches
    each; the step's outputs are overwritten by the next real step and the wall
-   nodes' Newton state is restored) and keeps the fastest; rows, if not NULL,
+   nodes' Newton state is restored) and keeps the fastest, where a height other
+   than 4 must beat 4 by 3 % (near-equal times swap from run to run); rows, if not NULL,
    receives n_levels heights.  lbr_set_tile_rows sets one level's height
    (level -1: all levels); other values of rows are LBR_ERR_INVALID_ARG. */
 int lbr_tune(lbr_ctx* ctx, int32_t trials, int32_t* rows);

@@ -2873,6 +2873,8 @@ namespace {
 // the next real step overwrites, and the wall nodes' friction velocities, which
 // are restored afterwards; every cell's result is independent of the tile
 // height.
+constexpr float TUNE_MARGIN = 0.97f;   // another tile height must beat the default by 3 %
+
 int tune_levels(const std::vector<lbr_ctx*>& cases, int lmax, int trials, std::vector<int>& best,
                 std::string& err) {
     lbr_ctx* c0 = cases[0];
@@ -2899,7 +2901,7 @@ int tune_levels(const std::vector<lbr_ctx*>& cases, int lmax, int trials, std::v
     size_t cap = 0;
     alignas(16) unsigned char buf[sizeof(StepArgs<double, double>)];
     for (int v = 0; v < lmax && !rc; ++v) {
-        float best_ms = 0.0f;
+        float ms_k[NTY] = {};
         for (int k = 0; k < NTY && !rc; ++k) {
             std::vector<unsigned char> parts;
             std::vector<int> starts;
@@ -2947,8 +2949,17 @@ int tune_levels(const std::vector<lbr_ctx*>& cases, int lmax, int trials, std::v
             ok = ok && hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
                  hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
             if (!ok) { err = "tuner: launch failed"; rc = LBR_ERR_HIP; break; }
-            if (k == 0 || ms < best_ms) { best_ms = ms; best[v] = k; }
+            ms_k[k] = ms;
         }
+        // another height replaces the default only when it is clearly faster:
+        // near-equal times swap from run to run, and a level timed alone does not
+        // see the tile order and part order of the merged schedule
+        float pick_ms = ms_k[TILE_Y_DEFAULT];
+        for (int k = 0; k < NTY && !rc; ++k)
+            if (ms_k[k] < TUNE_MARGIN * ms_k[TILE_Y_DEFAULT] && ms_k[k] < pick_ms) {
+                pick_ms = ms_k[k];
+                best[v] = k;
+            }
     }
     if (hipStreamSynchronize(s) != hipSuccess && !rc) { err = "synchronize failed"; rc = LBR_ERR_HIP; }
     for (auto& sv : saved)

@@ -944,18 +944,12 @@ __device__ __forceinline__ void step_block(const StepArgs<ST, CT>& a, const int 
         __syncthreads();
     }
     const int type = fl & F_TYPE;
-    // 16-bit storage takes the neighbouring levels' populations before the
-    // stencil staging, so that those loads overlap the barrier; wider formats
-    // take them after it (each order measured the faster for its formats; the
-    // order changes no result)
+    // 16-bit storage issues the parent-level loads of ghost and near-ghost cells
+    // before the stencil staging, so that they overlap the barrier; wider formats
+    // after it (each order measured the faster for its formats; the order changes
+    // no result).  The ghost cells' stores and the coalescence follow the barrier.
     constexpr bool early = sizeof(ST) == 2;
-    if constexpr (early) {
-        parent_pops<ST, CT>(a, type, fl, lm, gx, gy, s);
-        if (type == T_GHOST)
-            ghost_band_store<ST, CT>(a, s, make_rsrc(a.fdst - pad, 9 * P + 2 * pad), e, P);
-        else if (type == T_FLUID && !(fl & (F_WALL | F_EDGE)))
-            iface_cell<ST, CT>(a, fl, gx, gy, s);
-    }
+    if constexpr (early) parent_pops<ST, CT>(a, type, fl, lm, gx, gy, s);
     if (type == T_GHOST) {
         if (ghost_tile) ghost_fill_lds<CT, TY>(lds, cpx0, cpy0, gx, gy, own_n, own_u, own_v);
         else ghost_fill(a.cmac, a.cchi, a.cbox, gx, gy, own_n, own_u, own_v);
@@ -982,10 +976,10 @@ __device__ __forceinline__ void step_block(const StepArgs<ST, CT>& a, const int 
     CT m_rho = CT(0), m_ux = CT(0), m_uy = CT(0), m_chi = CT(0);
     if constexpr (!early) parent_pops<ST, CT>(a, type, fl, lm, gx, gy, s);
     if (type == T_GHOST) {
-        if constexpr (!early) ghost_band_store<ST, CT>(a, s, rfo, e, P);
+        ghost_band_store<ST, CT>(a, s, rfo, e, P);
     } else if (type == T_FLUID && !(fl & (F_WALL | F_EDGE))) {   // others: side-stream kernels
         update = true;
-        if constexpr (!early) iface_cell<ST, CT>(a, fl, gx, gy, s);
+        iface_cell<ST, CT>(a, fl, gx, gy, s);
         // SA-neg: chi at the new time level
         CT chi_new;
         if (a.frozen) {
