@@ -335,7 +335,10 @@ __device__ double friction_velocity(double ut, double d, double nu, double guess
         double un = u - step;
         if (!(un > 0.0)) un = 0.5 * u;
         u = un;
-        if (fabs(step) <= 1e-14 * u) break;
+        // Newton converges quadratically here: after a step of at most 1e-9 u the
+        // remaining error is of order 1e-18 u, below FP64 resolution, so no
+        // further iteration is needed to confirm it
+        if (fabs(step) <= 1e-9 * u) break;
     }
     if (!(u > 0.0) || !isfinite(u)) {
         double lo = 0.0, hi = ut * 1e3;
