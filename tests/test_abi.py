@@ -284,3 +284,30 @@ def test_binding_binds_liblbr_to_pytorchs_hip_runtime():
     assert len(libs) == 1, libs
     import torch
     assert os.path.dirname(libs[0]) == os.path.join(os.path.dirname(torch.__file__), "lib")
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="liblbr.so not built")
+def test_new_entry_points_refuse_missing_handles_on_the_host():
+    """lbr_surface_yplus and lbr_batch_use_persistent check their arguments on
+    the host: a null context or batch, or a context that was never built, is
+    LBR_ERR_INVALID_ARG with no device call; the turned geometry of a non-zero
+    alpha_deg is accepted by lbr_set_geometry (host work only)."""
+    import numpy as np
+    import paper_2601_18443_amd as P
+    import lbr_inputs as LI
+    L = P.lib()
+    out = np.zeros(8)
+    dp = out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    assert L.lbr_surface_yplus(None, 0, dp) == P.ERR_INVALID_ARG
+    assert L.lbr_batch_use_persistent(None, 1) == P.ERR_INVALID_ARG
+    case = dict(LI.case_airfoil_small(alpha_deg=0.0), config_alpha_deg=10.0, config_alpha_pivot=(0.25, 0.0))
+    cfg = P.make_config(case, "f32")
+    h = ctypes.c_void_p()
+    assert L.lbr_create(ctypes.byref(cfg), ctypes.byref(h)) == 0
+    try:
+        assert L.lbr_surface_yplus(h, 0, dp) == P.ERR_INVALID_ARG          # not built
+        body = np.ascontiguousarray(case["bodies"][0], dtype=np.float64)
+        n = (ctypes.c_int32 * 1)(len(body))
+        assert L.lbr_set_geometry(h, 1, n, body.ctypes.data_as(ctypes.POINTER(ctypes.c_double))) == 0
+    finally:
+        L.lbr_destroy(h)
