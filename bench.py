@@ -151,7 +151,7 @@ def equal_cf(case, steps):
     return out
 
 
-def three_element_roofline(steps=10):
+def three_element_roofline(steps=10, tune=False):
     """The FP32 step on the 19.5M-cell three-element case, whose working set
     (about 5 GB) is far beyond the 256 MB Infinity Cache: the HBM fraction of the
     step without cache help.  The start-up ramp is shortened to one coarse step,
@@ -165,7 +165,7 @@ def three_element_roofline(steps=10):
     s = P.Solver(case, storage="f32")
     s.synchronize()
     log(f"three-element grid built in {time.perf_counter() - t0:.1f} s")
-    rows = s.tune(trials=3)
+    rows = s.tune(trials=3) if tune else [4] * case["n_levels"]
     s.use_graph(True)
     s.advance(3)
     s.synchronize()
@@ -499,8 +499,10 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--persistent", type=int, default=1,
                     help="sweep: also time the persistent mode (one cooperative grid per launch table)")
-    ap.add_argument("--tune", type=int, default=1,
-                    help="choose each level's tile height by timing (the library's tuner) before the warm-up")
+    ap.add_argument("--tune", type=int, default=0,
+                    help="choose each level's tile height with the library's tuner before the warm-up (default: "
+                         "the library's 64 x 4 tiles; the tuner times each level's sub-step alone and has picked "
+                         "heights that are slower in the merged schedule)")
     ap.add_argument("--workload", default="airfoil",
                     choices=["airfoil", "three_element", "sweep", "sweep_steady", "precision"],
                     help="airfoil: the benchmark line (8 levels, 2.0M cells); three_element: the "
@@ -553,7 +555,7 @@ def main():
     log(f"build {time.perf_counter() - t0:.1f} s")
     lups = sim.lups_per_coarse_step()
     finest = sim.level_info(case["n_levels"] - 1)
-    rows = None
+    rows = [4] * case["n_levels"]                    # the library's default tile height
     if args.tune:
         rows = sim.tune(trials=5)
         log(f"tile heights per level (tuned): {rows}")
@@ -669,7 +671,7 @@ def main():
                                               else round(eq[best]["mlups"] / eq["f32"]["mlups"], 3))
     te = None
     if args.workload == "airfoil" and args.storage == "f32" and not args.no_three_element:
-        te = three_element_roofline()
+        te = three_element_roofline(tune=bool(args.tune))
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on the same workload")
