@@ -486,7 +486,7 @@ def run_precision(args):
     print(json.dumps(line), flush=True)
 
 
-def main():
+def make_parser():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
@@ -519,7 +519,11 @@ def main():
                     help="coarse steps of the equal-Cf check of the default line (0: skip it)")
     ap.add_argument("--no-three-element", action="store_true",
                     help="skip the three-element FP32 roofline record of the default line")
-    args = ap.parse_args()
+    return ap
+
+
+def main():
+    args = make_parser().parse_args()
 
     if args.gpus != 1:
         print("bench.py measures one GPU: running the step over several GPUs is not implemented",

@@ -121,3 +121,15 @@ def test_gap_summary_of_a_dispatch_stream(tmp_path):
     assert "gaps_inside_us_per_super_step = 4.00" in out
     assert "gap_between_super_steps_us = 5.00" in out
     assert "gaps_over_span = 0.1781" in out          # (2 x 4 + 5) / (2 x 34 + 5)
+
+
+def test_default_line_runs_the_library_tiles_on_one_gpu():
+    """With no flags the benchmark line is the 8-level airfoil in FP32 on one
+    GPU, replayed from a graph, with the library's default tile height (the
+    tuner only on request), the equal-Cf check, the three-element record and
+    the CPU baseline; the sweep also times the persistent mode."""
+    import bench
+    a = bench.make_parser().parse_args([])
+    assert (a.gpus, a.workload, a.storage, a.graph, a.tune, a.persistent) == (1, "airfoil", "f32", 1, 0, 1)
+    assert a.equal_cf_steps > 0 and not a.no_three_element and not a.no_cpu_baseline
+    assert bench.make_parser().parse_args(["--tune", "1"]).tune == 1
