@@ -14,13 +14,18 @@
  *
  * Parity status per part (pins live in tests/):
  *   wall function, Newton, slip velocity, equilibrium, collision, SA-neg
- *   source terms, LSQ/IDW, half-way and interpolated bounce-back, periodic
- *   conservation, force integral: pinned against closed forms and invariants.
- *   Coarse/fine transfer: pinned by exact mass conservation and uniform-flow
- *   preservation only (the paper gives no formulas for it).
- *   Second-order 2D Lax-Wendroff form of the SA convection, the reference-point
- *   stencil rule and the centroid interpolation rule: parity unpinned beyond
- *   the invariants above (the paper prints no values for them).
+ *   source terms and negative branch, LSQ/IDW, the Lax-Wendroff convection
+ *   (quadratic fields and the bilinear cross term advected exactly), half-way
+ *   and interpolated bounce-back, periodic conservation, force integral and
+ *   the friction sign rule, the angle-of-attack turn of the bodies, the
+ *   precomputed cut-link reader: pinned against closed forms, invariants and
+ *   independently computed inputs.
+ *   Coarse/fine transfer: pinned by exact mass conservation, uniform-flow
+ *   preservation and a Poiseuille profile through a refined block that
+ *   converges under refinement (the paper gives no formulas for it).
+ *   The reference-point stencil rule, the centroid interpolation rule and the
+ *   transfer's own first-order terms: parity unpinned beyond the invariants
+ *   above (the paper prints no values for them).
  */
 #include "oracle.h"
 
