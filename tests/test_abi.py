@@ -246,8 +246,16 @@ int main(void) {
     if (lbr_create(&cfg, &ctx) != LBR_OK || !ctx) return 2;
     if (lbr_set_geometry(ctx, 0, NULL, NULL) != LBR_OK) return 3;
     if (lbr_advance(ctx, 1) != LBR_ERR_STATE) return 4;      /* not built yet */
+    {
+        double yv[4];
+        if (lbr_surface_yplus(ctx, 0, yv) != LBR_ERR_INVALID_ARG) return 5;   /* not built */
+        if (lbr_surface_yplus(NULL, 0, yv) != LBR_ERR_INVALID_ARG) return 6;
+        if (lbr_batch_use_persistent(NULL, 1) != LBR_ERR_INVALID_ARG) return 7;
+    }
     printf("%s\n", lbr_last_error(ctx));
     lbr_destroy(ctx);
+    cfg.alpha_deg = 120.0;                                    /* beyond +-90 degrees */
+    if (lbr_create(&cfg, &ctx) != LBR_ERR_INVALID_ARG || ctx) return 8;
     return 0;
 }
 """
